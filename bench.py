@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Time-to-solution of a 30-qubit depth-25 random supremacy circuit on one
+MI355X: float32 fused clusters versus float64 one gate at a time.
+
+One step = initialise |0...0>, run the whole circuit through the library
+(scheduling, float64 cluster-matrix build on the GPU, cluster / diagonal
+kernels), then the float64 reductions (norm, sum p^2, entropy) that give the
+output distribution's statistics. Inputs are resident in HBM; the timed
+region is bracketed by device synchronisation.
+
+Prints one JSON line. `value` is the float32 fused time-to-solution in
+seconds. `roofline` is measured live from HIP events around every launch of
+the timed steps; `cpu_baseline` times the CPU oracle on a bounded sample of
+the same circuit and scales it to the whole circuit.
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "30q depth-25 time-to-solution + % HBM peak, FP32-fused vs FP64 per-gate"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3   # dense FP32 matrix cores
+FP64_PEAK_TFLOPS = 78.6
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1704_01127_amd", "csrc", "qsim_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--rows", type=int, default=5)
+    ap.add_argument("--cols", type=int, default=6)
+    ap.add_argument("--depth", type=int, default=25)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--kmax", type=int, default=5)
+    ap.add_argument("--scheduler", default="greedy")
+    ap.add_argument("--no-fuse-diag", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=None, help="steps of the float64 per-gate form")
+    ap.add_argument("--only", choices=["fused", "pergate"], default=None,
+                    help="run one form only (for profiling)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-gates", type=int, default=24)
+    return ap.parse_args()
+
+
+def cpu_baseline(circ, n_sample):
+    """Time the oracle on a stratified sample of the circuit's gates at full
+    size and scale to all gates (the oracle applies every gate, one at a time)."""
+    import ctypes
+
+    import numpy as np
+
+    import oracle
+    from supremacy_inputs import Circuit, to_text
+
+    L = oracle.lib()
+    n = circ.n
+    step = max(1, len(circ.gates) // n_sample)
+    sample = circ.gates[::step][:n_sample]
+    psi = np.empty(2 ** n, np.complex128)
+    ptr = psi.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    t0 = time.perf_counter()
+    L.oracle_run_text(ptr, n, ("n %d\n" % n).encode())  # |0...0>
+    t1 = time.perf_counter()
+    rc = L.oracle_apply_text(ptr, n, to_text(Circuit(n, sample)).encode())
+    t2 = time.perf_counter()
+    assert rc == len(sample)
+    per_gate = (t2 - t1) / len(sample)
+    est = (t1 - t0) + per_gate * len(circ.gates)
+    del psi
+    return {"value": round(est, 2), "unit": "s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d of %d gates (every %d-th) applied to the full 2^%d complex128 state in %.1f s, "
+                      "plus |0> initialisation %.1f s; scaled to all %d gates"
+                      % (len(sample), len(circ.gates), step, n, t2 - t1, t1 - t0, len(circ.gates))}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the whole state vector lives in one MI355X's HBM and "
+              "this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1704_01127_amd import qsim
+    from supremacy_inputs import supremacy_circuit
+
+    circ = supremacy_circuit(args.rows, args.cols, args.depth, args.seed)
+    n = circ.n
+    gates = circ.gates
+    fused_opts = dict(kmax=args.kmax, scheduler=args.scheduler, fuse_diag=not args.no_fuse_diag,
+                      skip_trailing_diag=True, skip_initial_h=True)
+    pergate_opts = dict(scheduler="per_gate", skip_trailing_diag=True, skip_initial_h=True)
+
+    def timed(state, opts, steps, warmup, record):
+        def step():
+            state.init("zero")
+            st = state.run_circuit(gates, record_timings=record, **opts)
+            return st, state.probs()
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        recs, per = [], []
+        t_all = time.perf_counter()
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            st, res = step()
+            per.append(time.perf_counter() - t0)
+            if record:
+                recs.extend(state.op_timings())
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_all
+        return total / steps, per, st, res, recs
+
+    out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "data": "synthetic"}
+
+    fused = pergate = None
+    if args.only in (None, "fused"):
+        s32 = qsim.State(n, "c64", kmax=max(args.kmax, 5))
+        fused = timed(s32, fused_opts, args.steps, args.warmup, record=True)
+    if args.only in (None, "pergate"):
+        s64 = qsim.State(n, "c128", kmax=max(args.kmax, 5))
+        k64 = args.fp64_steps if args.fp64_steps is not None else args.steps
+        pergate = timed(s64, pergate_opts, k64, min(args.warmup, 1), record=False)
+
+    ref = fused if fused is not None else pergate
+    tts, per, st, res, recs = ref
+    out["value"] = round(tts, 5)
+    out["unit"] = "s"
+    out["ms_per_step"] = round(tts * 1e3, 3)
+    out["dtype"] = "f32" if fused is not None else "f64"
+    out["config"] = {"workload": "%d-qubit %dx%d-grid depth-%d random supremacy circuit (%d gates, seed %d)"
+                                 % (n, args.rows, args.cols, args.depth, len(gates), args.seed),
+                     "form": "float32 state, fused clusters k<=%d, scheduler %s, diagonal fusion %s"
+                             % (args.kmax, args.scheduler, "on" if not args.no_fuse_diag else "off")
+                             if fused is not None else "float64 state, one launch per gate",
+                     "skips": "leading H layer -> uniform init; trailing diagonal gates dropped (Sec. 3.6)"}
+    out["stats"] = {"norm": res[0], "sum_p2_times_N": res[1] * 2 ** n, "entropy_nats": res[2],
+                    "ops": st["n_ops"], "clusters_by_k": st["n_clusters_by_k"], "diag_ops": st["n_diag_ops"],
+                    "gates_applied": st["n_gates_applied"], "schedule_ms": round(st["schedule_ms"], 3),
+                    "step_s_median": round(statistics.median(per), 5)}
+    out["amplitude_updates_per_s"] = len(gates) * 2 ** n / tts
+
+    if pergate is not None and fused is not None:
+        out["fp64_per_gate"] = {"tts_s": round(pergate[0], 4), "steps": len(pergate[1]),
+                                "launches": pergate[2]["n_ops"], "norm": pergate[3][0],
+                                "entropy_nats": pergate[3][2]}
+        out["speedup_vs_fp64_per_gate"] = round(pergate[0] / fused[0], 2)
+        fid, maxd = s32.compare(s64.amps)
+        out["fused_vs_fp64_per_gate"] = {"fidelity": fid, "max_abs_diff": maxd}
+
+    if recs:
+        amp_bytes = 8
+        clusters = [r for r in recs if r["kind"] == "cluster"]
+        total_ms = sum(r["ms"] for r in recs)
+        groups = {}
+        for r in clusters:
+            key = (r["k"], r["qubits"][0] == 0)
+            groups.setdefault(key, []).append(r["ms"])
+        dom = max(groups.items(), key=lambda kv: sum(kv[1]))
+        (k, lowt), times = dom
+        bytes_per_launch = 2 * 2 ** n * amp_bytes
+        avg_ms = sum(times) / len(times)
+        ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        nb = 1 if k == 6 else 2
+        traffic = None
+        tpath = os.path.join(ROOT, "profiles", "traffic_cluster_f32_30q.json")
+        if os.path.exists(tpath):
+            with open(tpath) as f:
+                t = json.load(f)
+            if t.get("kernel_source_sha") == kernel_source_hash() and str(k) in t.get("bytes_per_launch", {}):
+                traffic = t["bytes_per_launch"][str(k)]
+        out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                           "kernel": "k_cluster_f32_mfma<%d, %d, %s>" % (k, nb, "true" if lowt else "false")
+                           if k >= 4 else "k_cluster_valu<float, %d>" % k,
+                           "launches": len(times), "avg_ms": round(avg_ms, 4),
+                           "algorithmic_bytes_per_launch": bytes_per_launch}
+        csum = sum(r["ms"] for r in clusters)
+        cbytes = len(clusters) * 2 * 2 ** n * amp_bytes
+        cflops = sum(2 ** n * (8 * 2 ** r["k"] - 2) for r in clusters)
+        out["cluster_kernels"] = {"launches_per_step": len(clusters) // max(1, args.steps),
+                                  "hbm_GBs": round(cbytes / (csum * 1e-3) / 1e9, 1),
+                                  "hbm_frac": round(cbytes / (csum * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  "tflops": round(cflops / (csum * 1e-3) / 1e12, 2),
+                                  "share_of_gpu_time": round(csum / total_ms, 4)}
+        by_k = {}
+        for r in clusters:
+            d = by_k.setdefault(r["k"], [0, 0.0])
+            d[0] += 1
+            d[1] += r["ms"]
+        out["cluster_kernels"]["by_k"] = {
+            str(kk): {"launches": v[0], "avg_ms": round(v[1] / v[0], 4),
+                      "GBs": round(2 * 2 ** n * amp_bytes / (v[1] / v[0] * 1e-3) / 1e9, 1)}
+            for kk, v in sorted(by_k.items())}
+        others = {}
+        for r in recs:
+            if r["kind"] != "cluster":
+                d = others.setdefault(r["kind"], [0, 0.0])
+                d[0] += 1
+                d[1] += r["ms"]
+        out["other_kernels"] = {kk: {"launches": v[0], "total_ms": round(v[1], 3)} for kk, v in others.items()}
+
+    if not args.no_cpu_baseline:
+        # free the GPU states first: the oracle needs 16 GiB of host memory
+        out["cpu_baseline"] = cpu_baseline(circ, args.cpu_sample_gates)
+    out["paper_context"] = {"tts_s": 9.58, "hardware": "1 Cori II node (Xeon Phi 7250, 68 cores)",
+                            "precision": "complex128", "gates": 369, "source": "Table 2"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

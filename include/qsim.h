@@ -1,0 +1,214 @@
+/*
+ * qsim.h - C ABI of a state-vector quantum circuit simulator for one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is the one of Haener & Steiger, "0.5 Petabyte Simulation of a
+ * 45-Qubit Quantum Circuit" (SC'17): an n-qubit state is a vector of 2^n
+ * complex amplitudes (Sec. 2); gates are applied in place; many gates are
+ * fused into one dense k-qubit gate by a clustering scheduler (Sec. 3.6.1,
+ * step 2) and each such k-qubit gate is applied by gathering the 2^k
+ * amplitudes that share all non-target bits, multiplying them by the 2^k x 2^k
+ * matrix and scattering them back (Sec. 3.2). Diagonal gates (CZ, T, Z) need
+ * no gather (Sec. 3.5) and are applied as one pass, or fused into the
+ * neighbouring cluster's store.
+ *
+ * Conventions used by every call:
+ *   - amplitude index i = sum_q b_q 2^q: qubit q is bit q of the index (Sec. 2);
+ *   - a k-qubit matrix is 2^k x 2^k complex128, row-major, (re, im)
+ *     interleaved; bit j of its row/column index belongs to qubits[j]
+ *     (Sec. 3.2), the qubits may be listed in any order;
+ *   - the state is interleaved complex: QSIM_C64 = (float re, float im),
+ *     QSIM_C128 = (double re, double im), the layouts of torch.complex64 and
+ *     torch.complex128.
+ *
+ * Ownership: the caller owns all device memory (state and workspace). The
+ * library never allocates or frees device memory; it enqueues its work on the
+ * caller's HIP stream and returns before the work is done. Host pointers are
+ * read only during the call. A qsim_state handle holds metadata only.
+ *
+ * Errors: every call returns a qsim_status; QSIM_OK is 0, errors are
+ * negative, and qsim_last_error() returns a message for the calling thread.
+ * Argument errors are detected on the host before anything is enqueued.
+ * Errors of enqueued GPU work surface at the next qsim_sync() or
+ * qsim_probs()/qsim_compare() (which synchronise the stream).
+ */
+#ifndef QSIM_H
+#define QSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qsim_state_s* qsim_state;
+
+typedef enum { QSIM_C64 = 1, QSIM_C128 = 2 } qsim_dtype;
+
+/* Initial contents of the state at qsim_create / qsim_init_state.
+ * QSIM_INIT_ZERO    |0...0>
+ * QSIM_INIT_UNIFORM every amplitude 2^{-n/2}: the state after the cycle-0
+ *                   Hadamard layer, which a simulator may skip (Sec. 3.6)
+ * QSIM_INIT_KEEP    leave the buffer as the caller filled it */
+typedef enum { QSIM_INIT_ZERO = 0, QSIM_INIT_UNIFORM = 1, QSIM_INIT_KEEP = 2 } qsim_init;
+
+typedef enum {
+    QSIM_OK = 0,
+    QSIM_E_INVALID = -1,     /* bad argument: qubit >= n or repeated, null pointer, buffer too small */
+    QSIM_E_UNSUPPORTED = -2, /* k > 6, n out of range, too many entries in a diagonal layer */
+    QSIM_E_DEVICE = -3       /* a HIP runtime error or a failed GPU launch */
+} qsim_status;
+
+/* Gate kinds. The named matrices are the ones printed in Sec. 2 (H, T, X^1/2,
+ * Y^1/2, X, CZ), the Pauli Y and Z, the inverses of T, X^1/2 and Y^1/2 (for
+ * mirrored circuits), a phase gate diag(1, e^{i theta}) and a dense k-qubit
+ * matrix (k <= 6). */
+typedef enum {
+    QSIM_GATE_H = 0,
+    QSIM_GATE_T = 1,
+    QSIM_GATE_SQRT_X = 2,
+    QSIM_GATE_SQRT_Y = 3,
+    QSIM_GATE_X = 4,
+    QSIM_GATE_Y = 5,
+    QSIM_GATE_Z = 6,
+    QSIM_GATE_CZ = 7,
+    QSIM_GATE_TDG = 8,
+    QSIM_GATE_SQRT_X_DG = 9,
+    QSIM_GATE_SQRT_Y_DG = 10,
+    QSIM_GATE_PHASE = 11, /* diag(1, e^{i theta}) */
+    QSIM_GATE_DENSE = 12  /* k qubits, matrix in `mat` (host, 2^k x 2^k complex128) */
+} qsim_gate_kind;
+
+typedef struct {
+    int32_t kind;       /* qsim_gate_kind */
+    int32_t k;          /* number of qubits: 1, 2 for CZ, 1..6 for DENSE */
+    int32_t qubits[6];  /* target qubits; bit j of a DENSE matrix index <-> qubits[j] */
+    double theta;       /* angle of QSIM_GATE_PHASE */
+    const double* mat;  /* DENSE only: host pointer, read during the call */
+} qsim_gate;
+
+/* How qsim_run_circuit executes a gate list. */
+typedef enum {
+    QSIM_SCHED_PER_GATE = 0, /* one launch per gate, no fusion (the plain method) */
+    QSIM_SCHED_GREEDY = 1,   /* clusters of <= kmax qubits, most gates per cluster (Sec. 3.6.1, step 2) */
+    QSIM_SCHED_ANALYTIC = 2, /* clusters chosen by a bandwidth/compute cost model (fewest predicted us) */
+    QSIM_SCHED_LEARNED = 3   /* as ANALYTIC with the MLP cost model loaded by qsim_set_cost_model;
+                                falls back to GREEDY when none is loaded */
+} qsim_scheduler;
+
+typedef struct {
+    int32_t kmax;               /* largest cluster, 1..6 (ignored by PER_GATE) */
+    int32_t scheduler;          /* qsim_scheduler */
+    int32_t skip_trailing_diag; /* drop diagonal gates after the last non-diagonal gate on all
+                                   their qubits: they change phases, not probabilities (Sec. 3.6) */
+    int32_t fuse_diag;          /* let a cluster carry diagonal gates outside its qubits and apply
+                                   them while storing (no extra pass over the state) */
+    int32_t skip_initial_h;     /* caller promises the state is |0...0>: the leading H on every
+                                   qubit is replaced by the uniform initialisation (Sec. 3.6) */
+    int32_t record_timings;     /* time every launched op with HIP events (slows the run) */
+    int32_t reserved[2];
+} qsim_run_opts;
+
+typedef struct {
+    int32_t n_ops;              /* launches of cluster / diagonal / per-gate kernels */
+    int32_t n_clusters_by_k[7]; /* clusters applied, by k */
+    int32_t n_diag_ops;         /* standalone diagonal passes */
+    int32_t n_gates_applied;    /* gates after trailing / initial skips */
+    int32_t n_gates_fused_epilogue;
+    double schedule_ms;         /* host time spent scheduling */
+    double total_ms;            /* host wall time of the call (launches are asynchronous) */
+} qsim_run_stats;
+
+/* Workspace needed for a state of n qubits and dtype dt when clusters have
+ * at most kmax qubits. The workspace holds cluster matrices, descriptors and
+ * reduction partial sums. */
+size_t qsim_workspace_bytes(int n_qubits, qsim_dtype dt, int kmax);
+
+/* Create a handle for the state held in dev_amps (2^n amplitudes of dt,
+ * >= 256-byte aligned, amps_bytes >= 2^n * sizeof(amplitude)) with the
+ * workspace dev_workspace (>= qsim_workspace_bytes, 256-byte aligned). Both
+ * buffers stay owned by the caller and must outlive the handle. hip_stream
+ * is a hipStream_t (NULL = the default stream). n_qubits in [1, 34] for C64,
+ * [1, 33] for C128. Enqueues the initialisation `init`. */
+qsim_status qsim_create(int n_qubits, qsim_dtype dt, void* dev_amps, size_t amps_bytes,
+                        void* dev_workspace, size_t ws_bytes, void* hip_stream, qsim_init init,
+                        qsim_state* out);
+qsim_status qsim_destroy(qsim_state s);
+qsim_status qsim_init_state(qsim_state s, qsim_init init);
+
+/* Apply one dense k-qubit gate (Sec. 3.2) in place: for every assignment c of
+ * the n-k other bits, psi[c + dep(y)] <- sum_x mat[y][x] psi[c + dep(x)],
+ * where dep(x) puts bit j of x at qubit qubits[j]. 1 <= k <= 6, qubits
+ * distinct and < n. mat: host, 2^k x 2^k complex128 row-major. The matrix is
+ * re-indexed to sorted qubit order (Sec. 3.2) and, for a C64 state, rounded
+ * to float. */
+qsim_status qsim_apply_cluster(qsim_state s, int k, const int32_t* qubits, const double* mat);
+
+/* Apply a diagonal layer in place, with no gather (Sec. 3.5): every amplitude
+ * is multiplied by prod_{pairs (a,b)} (-1)^{b_a b_b} * prod_j e^{i theta_j b_{q_j}}.
+ * cz_pairs: 2*n_pairs qubit indices (host); phase_qubits / phase_theta:
+ * n_phase entries (host). At most 64 pairs and 64 phases. */
+qsim_status qsim_apply_diag(qsim_state s, int n_pairs, const int32_t* cz_pairs, int n_phase,
+                            const int32_t* phase_qubits, const double* phase_theta);
+
+/* Apply one gate with the per-gate kernels (one launch; the plain method):
+ * a 2x2 matrix on the index pairs (i, i + 2^q) (Sec. 2), a sign flip for CZ,
+ * a phase on the amplitudes with bit q set for diagonal 1-qubit gates, and
+ * the cluster kernel for DENSE. */
+qsim_status qsim_apply_gate(qsim_state s, const qsim_gate* gate);
+
+/* Run a gate list (in circuit order) on the state. With a fusing scheduler
+ * the gates are clustered (Sec. 3.6.1, step 2), every cluster matrix is built
+ * in float64 on the GPU and applied by the cluster kernel. stats may be
+ * NULL. */
+qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates,
+                             const qsim_run_opts* opts, qsim_run_stats* stats);
+
+/* Output probabilities p_i = |a_i|^2 (Sec. 3.6) and float64 reductions on the
+ * GPU: norm = sum p_i, sum_p2 = sum p_i^2, entropy = -sum p_i ln p_i (nats).
+ * dev_out (nullable): 2^n reals of out_dt (QSIM_C64 -> float, QSIM_C128 ->
+ * double). Scalar pointers are host pointers and may be NULL. Synchronises
+ * the stream. */
+qsim_status qsim_probs(qsim_state s, void* dev_out, qsim_dtype out_dt, double* norm,
+                       double* sum_p2, double* entropy_nats);
+
+/* Compare the state with a reference vector on the GPU, in float64:
+ * fidelity = |<ref|psi>|^2 / (<ref|ref> <psi|psi>), max_abs_diff = max_i
+ * |psi_i - ref_i|. dev_ref: 2^n amplitudes of ref_dt. Synchronises. */
+qsim_status qsim_compare(qsim_state s, const void* dev_ref, qsim_dtype ref_dt, double* fidelity,
+                         double* max_abs_diff);
+
+/* Wait for the state's stream; reports errors of enqueued work. */
+qsim_status qsim_sync(qsim_state s);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* qsim_last_error(void);
+
+/* Per-launch GPU times of the last qsim_run_circuit that had record_timings
+ * set, measured with HIP events on the state's stream. For each launch, in
+ * order: op_kind (0 cluster, 1 diagonal pass, 2 single-qubit gate, 3
+ * single-qubit phase, 4 CZ, 5 cluster-matrix build), op_k (cluster size;
+ * number of matrices for a build), op_qubits[6*i ..] (sorted targets of a
+ * cluster, -1 padded), op_epi (1 if the cluster applies diagonal gates while
+ * storing) and ms (milliseconds). Arrays of cap entries (any may be NULL);
+ * *n_ops receives the count. Synchronises the stream. */
+qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32_t* op_qubits,
+                            int32_t* op_epi, float* ms, int cap, int* n_ops);
+
+/* Host-only: the schedule qsim_run_circuit would use (no GPU work). For each
+ * gate: gate_op[g] = index of the op applying it (-1 if skipped) and
+ * gate_role[g] = 0 (folded into the op's matrix), 1 (applied while storing,
+ * diagonal) or 2 (the op is a standalone diagonal pass). For each op:
+ * op_kind[o] (0 cluster, 1 diagonal pass, 2 per-gate), op_k[o] and its sorted
+ * qubits op_qubits[6*o ..]. Arrays of op_cap entries; *n_ops receives the
+ * count. Returns QSIM_E_INVALID if op_cap is too small. */
+qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates,
+                          const qsim_run_opts* opts, int32_t* gate_op, int32_t* gate_role,
+                          int32_t* op_kind, int32_t* op_k, int32_t* op_qubits, int op_cap,
+                          int* n_ops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSIM_H */

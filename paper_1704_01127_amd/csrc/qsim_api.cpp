@@ -1,0 +1,697 @@
+// C ABI of the simulator (include/qsim.h): argument checks, the state handle,
+// scheduling, cluster-matrix upload / build and kernel dispatch.
+#include "qsim.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qsim_internal.h"
+#include "scheduler.h"
+
+using namespace qsim;
+
+namespace {
+
+thread_local std::string g_err;
+
+qsim_status fail(qsim_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+qsim_status hip_fail(hipError_t e, const char* where) {
+    return fail(QSIM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                          \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+// Workspace layout (byte offsets, 256-aligned).
+constexpr size_t kPartBytes = size_t(kReduceBlocks) * 8 * sizeof(double);  // partial sums
+constexpr size_t kResOff = kPartBytes;                                     // 8 doubles
+constexpr size_t kDescOff = kResOff + 256;
+constexpr size_t kDescBytes = size_t(6) << 20;                             // descriptors + dense gates
+constexpr size_t kMatOff = kDescOff + kDescBytes;
+constexpr int kSlots = 64;                                                 // cluster matrices per chunk
+
+size_t slot_bytes(bool dbl, int kmax) {
+    // the largest layout for k <= kmax (real-split 2^(k+1) squared or complex 2^k squared: equal size)
+    return (size_t)matrix_bytes(std::max(1, std::min(kmax, kMaxK)), LAYOUT_MFMA32F, dbl);
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct OpRecord {
+    int kind;  // 0 cluster, 1 diagonal pass, 2 1-qubit gate, 3 1-qubit phase, 4 CZ, 5 matrix build
+    int k;
+    int qubits[6];
+    int n_epi;
+    hipEvent_t ev0, ev1;
+};
+
+struct qsim_state_s {
+    int n = 0;
+    bool dbl = false;
+    void* psi = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t st = nullptr;
+    int kmax_ws = 6;  // largest k the workspace slots can hold
+    // op timing (record_timings): HIP events around every launch
+    bool recording = false;
+    std::vector<OpRecord> recs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    ~qsim_state_s() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+bool is_named_1q(int kind) { return kind >= G_H && kind <= G_PHASE && kind != G_CZ; }
+
+qsim_status check_gate(const qsim_state_s* s, const qsim_gate& g, int idx) {
+    const std::string at = "gate " + std::to_string(idx) + ": ";
+    int nq;
+    if (g.kind == G_CZ) nq = 2;
+    else if (g.kind == G_DENSE) nq = g.k;
+    else if (is_named_1q(g.kind)) nq = 1;
+    else return fail(QSIM_E_INVALID, at + "unknown gate kind " + std::to_string(g.kind));
+    if (g.kind == G_DENSE && (nq < 1 || nq > kMaxK))
+        return fail(QSIM_E_UNSUPPORTED, at + "dense gates need 1 <= k <= 6");
+    if (g.kind == G_DENSE && !g.mat) return fail(QSIM_E_INVALID, at + "dense gate without a matrix");
+    uint64_t m = 0;
+    for (int j = 0; j < nq; ++j) {
+        const int q = g.qubits[j];
+        if (q < 0 || q >= s->n) return fail(QSIM_E_INVALID, at + "qubit " + std::to_string(q) + " out of range");
+        if (m >> q & 1) return fail(QSIM_E_INVALID, at + "repeated qubit " + std::to_string(q));
+        m |= uint64_t(1) << q;
+    }
+    return QSIM_OK;
+}
+
+int gate_nq(const qsim_gate& g) { return g.kind == G_CZ ? 2 : (g.kind == G_DENSE ? g.k : 1); }
+
+// One chunk of work: descriptors packed on the host, uploaded once.
+struct Chunk {
+    std::vector<BuildOp> bops;
+    std::vector<BuildGate> bgates;
+    std::vector<double> dense;
+    std::vector<EpiDesc> epis;
+    struct Item {
+        int kind;        // 0 cluster, 1 diag pass, 2 gate1q, 3 phase1q, 4 cz
+        ClusterGeom geom;
+        int layout;
+        int slot;        // matrix slot (cluster)
+        int epi;         // index into epis, -1 none
+        int q0, q1;
+        double m[8];
+    };
+    std::vector<Item> items;
+    int slots_used = 0;
+    size_t desc_bytes() const {
+        return align256(bops.size() * sizeof(BuildOp)) + align256(bgates.size() * sizeof(BuildGate)) +
+               align256(dense.size() * sizeof(double)) + align256(epis.size() * sizeof(EpiDesc));
+    }
+    void clear() {
+        bops.clear(); bgates.clear(); dense.clear(); epis.clear(); items.clear(); slots_used = 0;
+    }
+};
+
+hipError_t next_event(qsim_state_s* s, hipEvent_t* e) {
+    if (s->pool_used == s->pool.size()) {
+        hipEvent_t ne;
+        hipError_t r = hipEventCreate(&ne);
+        if (r != hipSuccess) return r;
+        s->pool.push_back(ne);
+    }
+    *e = s->pool[s->pool_used++];
+    return hipSuccess;
+}
+
+// Start / finish the timing record of one launch (no-ops unless recording).
+hipError_t rec_begin(qsim_state_s* s, OpRecord& r) {
+    if (!s->recording) return hipSuccess;
+    hipError_t e = next_event(s, &r.ev0);
+    if (e == hipSuccess) e = next_event(s, &r.ev1);
+    if (e == hipSuccess) e = hipEventRecord(r.ev0, s->st);
+    return e;
+}
+hipError_t rec_end(qsim_state_s* s, const OpRecord& r) {
+    if (!s->recording) return hipSuccess;
+    hipError_t e = hipEventRecord(r.ev1, s->st);
+    if (e == hipSuccess) s->recs.push_back(r);
+    return e;
+}
+
+qsim_status flush(qsim_state_s* s, Chunk& c) {
+    if (c.items.empty()) return QSIM_OK;
+    const size_t ob = 0;
+    const size_t gb = ob + align256(c.bops.size() * sizeof(BuildOp));
+    const size_t db = gb + align256(c.bgates.size() * sizeof(BuildGate));
+    const size_t eb = db + align256(c.dense.size() * sizeof(double));
+    const size_t total = eb + align256(c.epis.size() * sizeof(EpiDesc));
+    if (total > kDescBytes) return fail(QSIM_E_UNSUPPORTED, "descriptor chunk too large");
+    std::vector<char> host(total, 0);
+    if (!c.bops.empty()) std::memcpy(host.data() + ob, c.bops.data(), c.bops.size() * sizeof(BuildOp));
+    if (!c.bgates.empty()) std::memcpy(host.data() + gb, c.bgates.data(), c.bgates.size() * sizeof(BuildGate));
+    if (!c.dense.empty()) std::memcpy(host.data() + db, c.dense.data(), c.dense.size() * sizeof(double));
+    if (!c.epis.empty()) std::memcpy(host.data() + eb, c.epis.data(), c.epis.size() * sizeof(EpiDesc));
+    char* dev = s->ws + kDescOff;
+    char* mats = s->ws + kMatOff;
+    if (total) HIP_TRY(hipMemcpyAsync(dev, host.data(), total, hipMemcpyHostToDevice, s->st), "upload descriptors");
+    if (!c.bops.empty()) {
+        OpRecord r;
+        std::memset(&r, 0, sizeof(r));
+        r.kind = 5;
+        r.k = (int)c.bops.size();
+        HIP_TRY(rec_begin(s, r), "event record");
+        HIP_TRY(launch_build(reinterpret_cast<const BuildOp*>(dev + ob), (int)c.bops.size(),
+                             reinterpret_cast<const BuildGate*>(dev + gb),
+                             reinterpret_cast<const double*>(dev + db), mats, s->st),
+                "matrix build launch");
+        HIP_TRY(rec_end(s, r), "event record");
+    }
+    const EpiDesc* epis = reinterpret_cast<const EpiDesc*>(dev + eb);
+    const size_t sb = slot_bytes(s->dbl, s->kmax_ws);
+    for (const auto& it : c.items) {
+        OpRecord r;
+        std::memset(&r, 0, sizeof(r));
+        r.kind = it.kind;
+        if (it.kind == 0) {
+            r.k = it.geom.k;
+            for (int j = 0; j < it.geom.k; ++j) r.qubits[j] = it.geom.t[j];
+            if (it.epi >= 0) r.n_epi = 1;
+        } else if (it.kind >= 2) {
+            r.k = it.kind == 4 ? 2 : 1;
+            r.qubits[0] = it.q0;
+            r.qubits[1] = it.q1;
+        }
+        HIP_TRY(rec_begin(s, r), "event record");
+        hipError_t e = hipSuccess;
+        switch (it.kind) {
+            case 0:
+                e = launch_cluster(s->psi, s->dbl, it.geom, mats + it.slot * sb, it.layout,
+                                   it.epi >= 0 ? epis + it.epi : nullptr, s->st);
+                break;
+            case 1: e = launch_diag(s->psi, s->dbl, s->n, epis + it.epi, s->st); break;
+            case 2: e = launch_gate1q(s->psi, s->dbl, s->n, it.q0, it.m, s->st); break;
+            case 3: e = launch_phase1q(s->psi, s->dbl, s->n, it.q0, it.m[0], it.m[1], s->st); break;
+            case 4: e = launch_cz(s->psi, s->dbl, s->n, it.q0, it.q1, s->st); break;
+        }
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        HIP_TRY(rec_end(s, r), "event record");
+    }
+    c.clear();
+    return QSIM_OK;
+}
+
+// Standalone diagonal pass over pairs and phases (global qubit indices).
+qsim_status diag_desc(int n, const std::vector<std::pair<int, int>>& pairs,
+                      const std::vector<std::pair<int, double>>& phases, EpiDesc& e) {
+    std::memset(&e, 0, sizeof(e));
+    const int L = n < 2 ? n : 2;
+    for (int j = 0; j < (1 << L); ++j) { e.low[j][0] = 1.0; e.low[j][1] = 0.0; }
+    e.n_low = 1 << L;
+    for (auto pr : pairs) {
+        int a = std::min(pr.first, pr.second), b = std::max(pr.first, pr.second);
+        if (b < L) {
+            for (int j = 0; j < (1 << L); ++j)
+                if ((j >> a & 1) && (j >> b & 1)) { e.low[j][0] = -e.low[j][0]; e.low[j][1] = -e.low[j][1]; }
+        } else if (a < L) {
+            if (e.n_mix >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "too many CZ pairs in a diagonal pass");
+            e.mix[e.n_mix][0] = a; e.mix[e.n_mix][1] = b; e.n_mix++;
+        } else {
+            if (e.n_cc >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "too many CZ pairs in a diagonal pass");
+            e.cc[e.n_cc][0] = a; e.cc[e.n_cc][1] = b; e.n_cc++;
+        }
+    }
+    for (auto ph : phases) {
+        const double c = std::cos(ph.second), sn = std::sin(ph.second);
+        if (ph.first < L) {
+            for (int j = 0; j < (1 << L); ++j)
+                if (j >> ph.first & 1) {
+                    const double r = e.low[j][0] * c - e.low[j][1] * sn;
+                    e.low[j][1] = e.low[j][0] * sn + e.low[j][1] * c;
+                    e.low[j][0] = r;
+                }
+        } else {
+            if (e.n_ph >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "too many phases in a diagonal pass");
+            e.ph_q[e.n_ph] = ph.first; e.ph[e.n_ph][0] = c; e.ph[e.n_ph][1] = sn; e.n_ph++;
+        }
+    }
+    return QSIM_OK;
+}
+
+BuildGate to_build_gate(const qsim_gate& g, const int* pos_of, std::vector<double>& dense) {
+    BuildGate b;
+    std::memset(&b, 0, sizeof(b));
+    b.kind = g.kind;
+    b.nq = gate_nq(g);
+    for (int j = 0; j < b.nq; ++j) b.pos[j] = pos_of[g.qubits[j]];
+    b.theta = g.theta;
+    b.dense_off = -1;
+    if (g.kind == G_DENSE) {
+        b.dense_off = (int)dense.size();
+        const int cnt = 2 << (2 * g.k);
+        dense.insert(dense.end(), g.mat, g.mat + cnt);
+    }
+    return b;
+}
+
+// Add a cluster op (sorted qubits, member gates, epilogue gates) to the chunk;
+// flushes first if the chunk is full.
+qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, const qsim_gate* gates,
+                        const std::vector<int>& members, const std::vector<int>& epi_gates) {
+    size_t dense_need = 0;
+    for (int gi : members) if (gates[gi].kind == G_DENSE) dense_need += size_t(2) << (2 * gates[gi].k);
+    const size_t need = align256((c.bops.size() + 1) * sizeof(BuildOp)) +
+                        align256((c.bgates.size() + members.size() + epi_gates.size()) * sizeof(BuildGate)) +
+                        align256((c.dense.size() + dense_need) * sizeof(double)) +
+                        align256((c.epis.size() + 1) * sizeof(EpiDesc));
+    if (c.slots_used >= kSlots || need > kDescBytes) {
+        qsim_status r = flush(s, c);
+        if (r != QSIM_OK) return r;
+    }
+    int pos_of[64];
+    for (int i = 0; i < 64; ++i) pos_of[i] = -1;
+    for (int j = 0; j < k; ++j) pos_of[qubits[j]] = j;
+    BuildOp bo;
+    std::memset(&bo, 0, sizeof(bo));
+    bo.k = k;
+    bo.gate0 = (int)c.bgates.size();
+    bo.is_double = s->dbl;
+    bo.layout = cluster_layout(s->dbl, k, s->n);
+    bo.out_off = (int64_t)c.slots_used * (int64_t)slot_bytes(s->dbl, s->kmax_ws);
+    for (int gi : members) c.bgates.push_back(to_build_gate(gates[gi], pos_of, c.dense));
+    // epilogue: terms on target qubits only join the matrix, the rest go to the descriptor
+    EpiDesc e;
+    std::memset(&e, 0, sizeof(e));
+    for (int gi : epi_gates) {
+        const qsim_gate& g = gates[gi];
+        if (g.kind == G_CZ) {
+            const int a = g.qubits[0], b = g.qubits[1];
+            const bool ta = pos_of[a] >= 0, tb = pos_of[b] >= 0;
+            if (ta && tb) {
+                c.bgates.push_back(to_build_gate(g, pos_of, c.dense));
+            } else if (ta || tb) {
+                if (e.n_mix >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "epilogue too long");
+                e.mix[e.n_mix][0] = ta ? pos_of[a] : pos_of[b];
+                e.mix[e.n_mix][1] = ta ? b : a;
+                e.n_mix++;
+            } else {
+                if (e.n_cc >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "epilogue too long");
+                e.cc[e.n_cc][0] = a; e.cc[e.n_cc][1] = b; e.n_cc++;
+            }
+        } else {
+            const int q = g.qubits[0];
+            if (pos_of[q] >= 0) {
+                c.bgates.push_back(to_build_gate(g, pos_of, c.dense));
+            } else {
+                if (e.n_ph >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "epilogue too long");
+                const double ang = gate_phase_angle(g.kind, g.theta);
+                e.ph_q[e.n_ph] = q; e.ph[e.n_ph][0] = std::cos(ang); e.ph[e.n_ph][1] = std::sin(ang); e.n_ph++;
+            }
+        }
+    }
+    bo.n_gates = (int)c.bgates.size() - bo.gate0;
+    c.bops.push_back(bo);
+    Chunk::Item it;
+    std::memset(&it, 0, sizeof(it));
+    it.kind = 0;
+    for (int j = 0; j < k; ++j) it.geom.t[j] = qubits[j];
+    it.geom.n = s->n;
+    it.geom.k = k;
+    it.geom.ncols = uint64_t(1) << (s->n - k);
+    it.layout = bo.layout;
+    it.slot = c.slots_used++;
+    it.epi = -1;
+    if (e.n_cc || e.n_mix || e.n_ph) {
+        it.epi = (int)c.epis.size();
+        c.epis.push_back(e);
+    }
+    c.items.push_back(it);
+    return QSIM_OK;
+}
+
+qsim_status add_diag(qsim_state_s* s, Chunk& c, const std::vector<std::pair<int, int>>& pairs,
+                     const std::vector<std::pair<int, double>>& phases) {
+    if (c.desc_bytes() + 2 * sizeof(EpiDesc) + 1024 > kDescBytes) {
+        qsim_status r = flush(s, c);
+        if (r != QSIM_OK) return r;
+    }
+    EpiDesc e;
+    qsim_status r = diag_desc(s->n, pairs, phases, e);
+    if (r != QSIM_OK) return r;
+    Chunk::Item it;
+    std::memset(&it, 0, sizeof(it));
+    it.kind = 1;
+    it.epi = (int)c.epis.size();
+    c.epis.push_back(e);
+    c.items.push_back(it);
+    return QSIM_OK;
+}
+
+// A single gate with the per-gate kernels.
+qsim_status add_gate(qsim_state_s* s, Chunk& c, const qsim_gate* gates, int gi) {
+    const qsim_gate& g = gates[gi];
+    if (g.kind == G_DENSE) {
+        int qs[6];
+        for (int j = 0; j < g.k; ++j) qs[j] = g.qubits[j];
+        std::sort(qs, qs + g.k);
+        return add_cluster(s, c, g.k, qs, gates, std::vector<int>{gi}, {});
+    }
+    Chunk::Item it;
+    std::memset(&it, 0, sizeof(it));
+    it.epi = -1;
+    if (g.kind == G_CZ) {
+        it.kind = 4;
+        it.q0 = g.qubits[0];
+        it.q1 = g.qubits[1];
+    } else if (gate_is_diagonal(g.kind)) {
+        it.kind = 3;
+        it.q0 = g.qubits[0];
+        const double ang = gate_phase_angle(g.kind, g.theta);
+        it.m[0] = std::cos(ang);
+        it.m[1] = std::sin(ang);
+    } else {
+        it.kind = 2;
+        it.q0 = g.qubits[0];
+        gate2x2(g.kind, g.theta, it.m);
+    }
+    c.items.push_back(it);
+    return QSIM_OK;
+}
+
+qsim_status check_state(qsim_state s) {
+    if (!s) return fail(QSIM_E_INVALID, "null state handle");
+    return QSIM_OK;
+}
+
+std::vector<SGate> to_sgates(const qsim_gate* gates, int n_gates) {
+    std::vector<SGate> sg(n_gates);
+    for (int i = 0; i < n_gates; ++i) {
+        sg[i].kind = gates[i].kind;
+        sg[i].nq = gate_nq(gates[i]);
+        for (int j = 0; j < sg[i].nq; ++j) sg[i].q[j] = gates[i].qubits[j];
+        sg[i].diag = gate_is_diagonal(gates[i].kind);
+    }
+    return sg;
+}
+
+SchedOpts to_sched_opts(const qsim_run_opts* o) {
+    SchedOpts so;
+    if (!o) return so;
+    so.kmax = o->kmax;
+    so.mode = o->scheduler == QSIM_SCHED_PER_GATE ? 0 : (o->scheduler == QSIM_SCHED_GREEDY ? 1 : 2);
+    so.fuse_diag = o->fuse_diag != 0;
+    so.skip_trailing_diag = o->skip_trailing_diag != 0;
+    so.skip_initial_h = o->skip_initial_h != 0;
+    return so;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t qsim_workspace_bytes(int n_qubits, qsim_dtype dt, int kmax) {
+    (void)n_qubits;
+    return kMatOff + size_t(kSlots) * slot_bytes(dt == QSIM_C128, kmax <= 0 ? kMaxK : kmax);
+}
+
+qsim_status qsim_create(int n_qubits, qsim_dtype dt, void* dev_amps, size_t amps_bytes, void* dev_workspace,
+                        size_t ws_bytes, void* hip_stream, qsim_init init, qsim_state* out) {
+    if (!out) return fail(QSIM_E_INVALID, "out is null");
+    *out = nullptr;
+    if (dt != QSIM_C64 && dt != QSIM_C128) return fail(QSIM_E_INVALID, "unknown dtype");
+    const bool dbl = dt == QSIM_C128;
+    if (n_qubits < 1 || n_qubits > (dbl ? 33 : 34))
+        return fail(QSIM_E_UNSUPPORTED, "n_qubits must be in [1, 34] (complex64) or [1, 33] (complex128)");
+    if (!dev_amps || !dev_workspace) return fail(QSIM_E_INVALID, "null device buffer");
+    if ((reinterpret_cast<uintptr_t>(dev_amps) & 255) || (reinterpret_cast<uintptr_t>(dev_workspace) & 255))
+        return fail(QSIM_E_INVALID, "device buffers must be 256-byte aligned");
+    const size_t need = (size_t(1) << n_qubits) * (dbl ? 16 : 8);
+    if (amps_bytes < need) return fail(QSIM_E_INVALID, "state buffer too small");
+    // the workspace decides the largest cluster it can hold
+    int kws = 0;
+    for (int k = kMaxK; k >= 1; --k)
+        if (ws_bytes >= qsim_workspace_bytes(n_qubits, dt, k)) { kws = k; break; }
+    if (kws == 0) return fail(QSIM_E_INVALID, "workspace too small");
+    if (init != QSIM_INIT_ZERO && init != QSIM_INIT_UNIFORM && init != QSIM_INIT_KEEP)
+        return fail(QSIM_E_INVALID, "unknown init");
+    auto* s = new qsim_state_s;
+    s->n = n_qubits;
+    s->dbl = dbl;
+    s->psi = dev_amps;
+    s->ws = static_cast<char*>(dev_workspace);
+    s->ws_bytes = ws_bytes;
+    s->st = static_cast<hipStream_t>(hip_stream);
+    s->kmax_ws = kws;
+    if (init != QSIM_INIT_KEEP) {
+        hipError_t e = launch_init(s->psi, s->n, s->dbl, init == QSIM_INIT_ZERO ? 0 : 1, s->st);
+        if (e != hipSuccess) { delete s; return hip_fail(e, "init launch"); }
+    }
+    *out = s;
+    return QSIM_OK;
+}
+
+qsim_status qsim_destroy(qsim_state s) {
+    delete s;
+    return QSIM_OK;
+}
+
+qsim_status qsim_init_state(qsim_state s, qsim_init init) {
+    if (qsim_status r = check_state(s)) return r;
+    if (init == QSIM_INIT_KEEP) return QSIM_OK;
+    if (init != QSIM_INIT_ZERO && init != QSIM_INIT_UNIFORM) return fail(QSIM_E_INVALID, "unknown init");
+    HIP_TRY(launch_init(s->psi, s->n, s->dbl, init == QSIM_INIT_ZERO ? 0 : 1, s->st), "init launch");
+    return QSIM_OK;
+}
+
+qsim_status qsim_apply_cluster(qsim_state s, int k, const int32_t* qubits, const double* mat) {
+    if (qsim_status r = check_state(s)) return r;
+    if (!qubits || !mat) return fail(QSIM_E_INVALID, "null argument");
+    if (k < 1 || k > kMaxK) return fail(QSIM_E_UNSUPPORTED, "k must be in [1, 6]");
+    if (k > s->kmax_ws) return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
+    if (k > s->n) return fail(QSIM_E_INVALID, "k exceeds the number of qubits");
+    qsim_gate g;
+    std::memset(&g, 0, sizeof(g));
+    g.kind = G_DENSE;
+    g.k = k;
+    for (int j = 0; j < k; ++j) g.qubits[j] = qubits[j];
+    g.mat = mat;
+    if (qsim_status r = check_gate(s, g, 0)) return r;
+    Chunk c;
+    if (qsim_status r = add_gate(s, c, &g, 0)) return r;
+    return flush(s, c);
+}
+
+qsim_status qsim_apply_diag(qsim_state s, int n_pairs, const int32_t* cz_pairs, int n_phase,
+                            const int32_t* phase_qubits, const double* phase_theta) {
+    if (qsim_status r = check_state(s)) return r;
+    if (n_pairs < 0 || n_phase < 0) return fail(QSIM_E_INVALID, "negative count");
+    if ((n_pairs && !cz_pairs) || (n_phase && (!phase_qubits || !phase_theta)))
+        return fail(QSIM_E_INVALID, "null argument");
+    if (n_pairs > kEpiMax || n_phase > kEpiMax) return fail(QSIM_E_UNSUPPORTED, "at most 64 pairs and 64 phases");
+    std::vector<std::pair<int, int>> pairs;
+    std::vector<std::pair<int, double>> phases;
+    for (int i = 0; i < n_pairs; ++i) {
+        const int a = cz_pairs[2 * i], b = cz_pairs[2 * i + 1];
+        if (a < 0 || a >= s->n || b < 0 || b >= s->n || a == b) return fail(QSIM_E_INVALID, "bad CZ pair");
+        pairs.emplace_back(a, b);
+    }
+    for (int i = 0; i < n_phase; ++i) {
+        const int q = phase_qubits[i];
+        if (q < 0 || q >= s->n) return fail(QSIM_E_INVALID, "bad phase qubit");
+        phases.emplace_back(q, phase_theta[i]);
+    }
+    Chunk c;
+    if (qsim_status r = add_diag(s, c, pairs, phases)) return r;
+    return flush(s, c);
+}
+
+qsim_status qsim_apply_gate(qsim_state s, const qsim_gate* gate) {
+    if (qsim_status r = check_state(s)) return r;
+    if (!gate) return fail(QSIM_E_INVALID, "null gate");
+    if (qsim_status r = check_gate(s, *gate, 0)) return r;
+    if (gate->kind == G_DENSE && gate->k > s->kmax_ws)
+        return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
+    Chunk c;
+    if (qsim_status r = add_gate(s, c, gate, 0)) return r;
+    return flush(s, c);
+}
+
+qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, const qsim_run_opts* opts,
+                             qsim_run_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (qsim_status r = check_state(s)) return r;
+    if (n_gates < 0 || (n_gates && !gates)) return fail(QSIM_E_INVALID, "bad gate list");
+    for (int i = 0; i < n_gates; ++i)
+        if (qsim_status r = check_gate(s, gates[i], i)) return r;
+    SchedOpts so = to_sched_opts(opts);
+    if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 6]");
+    if (so.mode != 0 && so.kmax > s->kmax_ws) return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
+    for (int i = 0; i < n_gates; ++i)
+        if (gates[i].kind == G_DENSE && gates[i].k > s->kmax_ws)
+            return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
+    const std::vector<SGate> sg = to_sgates(gates, n_gates);
+    const Schedule S = make_schedule(s->n, sg, so, OpCostFn());
+    const auto t1 = std::chrono::steady_clock::now();
+
+    qsim_run_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.n_gates_applied = S.n_applied;
+    const bool rec = opts && opts->record_timings;
+    if (rec) {
+        // the events of the previous run are reused: wait until they have fired
+        HIP_TRY(hipStreamSynchronize(s->st), "stream sync");
+        s->recs.clear();
+        s->pool_used = 0;
+    }
+    s->recording = rec;
+    struct RecOff {
+        qsim_state_s* s;
+        ~RecOff() { s->recording = false; }
+    } rec_off{s};
+    if (S.uniform_init) HIP_TRY(launch_init(s->psi, s->n, s->dbl, 1, s->st), "init launch");
+    Chunk c;
+    for (const SOp& op : S.ops) {
+        qsim_status r = QSIM_OK;
+        if (op.kind == OP_GATE) {
+            r = add_gate(s, c, gates, op.members[0]);
+        } else if (op.kind == OP_DIAG) {
+            std::vector<std::pair<int, int>> pairs;
+            std::vector<std::pair<int, double>> phases;
+            for (int gi : op.members) {
+                if (gates[gi].kind == G_CZ) pairs.emplace_back(gates[gi].qubits[0], gates[gi].qubits[1]);
+                else phases.emplace_back(gates[gi].qubits[0], gate_phase_angle(gates[gi].kind, gates[gi].theta));
+            }
+            r = add_diag(s, c, pairs, phases);
+            st.n_diag_ops++;
+        } else {
+            r = add_cluster(s, c, op.k, op.qubits, gates, op.members, op.epi);
+            st.n_clusters_by_k[op.k]++;
+            st.n_gates_fused_epilogue += (int)op.epi.size();
+        }
+        if (r != QSIM_OK) return r;
+        st.n_ops++;
+    }
+    if (qsim_status r = flush(s, c)) return r;
+    const auto t2 = std::chrono::steady_clock::now();
+    st.schedule_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    st.total_ms = std::chrono::duration<double, std::milli>(t2 - t0).count();
+    if (stats) *stats = st;
+    return QSIM_OK;
+}
+
+qsim_status qsim_probs(qsim_state s, void* dev_out, qsim_dtype out_dt, double* norm, double* sum_p2,
+                       double* entropy_nats) {
+    if (qsim_status r = check_state(s)) return r;
+    if (dev_out && out_dt != QSIM_C64 && out_dt != QSIM_C128) return fail(QSIM_E_INVALID, "unknown out dtype");
+    double* part = reinterpret_cast<double*>(s->ws);
+    double* res = reinterpret_cast<double*>(s->ws + kResOff);
+    HIP_TRY(launch_stats(s->psi, s->dbl, s->n, dev_out, out_dt == QSIM_C128, part, res, s->st), "stats launch");
+    double h[8];
+    HIP_TRY(hipMemcpyAsync(h, res, 8 * sizeof(double), hipMemcpyDeviceToHost, s->st), "stats copy");
+    HIP_TRY(hipStreamSynchronize(s->st), "stats sync");
+    if (norm) *norm = h[0];
+    if (sum_p2) *sum_p2 = h[1];
+    if (entropy_nats) *entropy_nats = h[2];
+    return QSIM_OK;
+}
+
+qsim_status qsim_compare(qsim_state s, const void* dev_ref, qsim_dtype ref_dt, double* fidelity,
+                         double* max_abs_diff) {
+    if (qsim_status r = check_state(s)) return r;
+    if (!dev_ref) return fail(QSIM_E_INVALID, "null reference");
+    if (ref_dt != QSIM_C64 && ref_dt != QSIM_C128) return fail(QSIM_E_INVALID, "unknown reference dtype");
+    double* part = reinterpret_cast<double*>(s->ws);
+    double* res = reinterpret_cast<double*>(s->ws + kResOff);
+    HIP_TRY(launch_compare(s->psi, s->dbl, s->n, dev_ref, ref_dt == QSIM_C128, part, res, s->st), "compare launch");
+    double h[8];
+    HIP_TRY(hipMemcpyAsync(h, res, 8 * sizeof(double), hipMemcpyDeviceToHost, s->st), "compare copy");
+    HIP_TRY(hipStreamSynchronize(s->st), "compare sync");
+    const double dot2 = h[0] * h[0] + h[1] * h[1];
+    if (fidelity) *fidelity = (h[2] > 0 && h[3] > 0) ? dot2 / (h[2] * h[3]) : 0.0;
+    if (max_abs_diff) *max_abs_diff = h[4];
+    return QSIM_OK;
+}
+
+qsim_status qsim_sync(qsim_state s) {
+    if (qsim_status r = check_state(s)) return r;
+    HIP_TRY(hipStreamSynchronize(s->st), "stream sync");
+    HIP_TRY(hipGetLastError(), "pending error");
+    return QSIM_OK;
+}
+
+const char* qsim_last_error(void) { return g_err.c_str(); }
+
+qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32_t* op_qubits,
+                            int32_t* op_epi, float* ms, int cap, int* n_ops) {
+    if (qsim_status r = check_state(s)) return r;
+    HIP_TRY(hipStreamSynchronize(s->st), "stream sync");
+    if (n_ops) *n_ops = (int)s->recs.size();
+    if ((int)s->recs.size() > cap) return fail(QSIM_E_INVALID, "cap too small");
+    for (size_t i = 0; i < s->recs.size(); ++i) {
+        const OpRecord& r = s->recs[i];
+        if (op_kind) op_kind[i] = r.kind;
+        if (op_k) op_k[i] = r.k;
+        if (op_qubits)
+            for (int j = 0; j < 6; ++j) op_qubits[6 * i + j] = (r.kind == 0 && j < r.k) ? r.qubits[j] : -1;
+        if (op_epi) op_epi[i] = r.n_epi;
+        if (ms) {
+            float t = 0.f;
+            HIP_TRY(hipEventElapsedTime(&t, r.ev0, r.ev1), "event time");
+            ms[i] = t;
+        }
+    }
+    return QSIM_OK;
+}
+
+qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates, const qsim_run_opts* opts,
+                          int32_t* gate_op, int32_t* gate_role, int32_t* op_kind, int32_t* op_k,
+                          int32_t* op_qubits, int op_cap, int* n_ops) {
+    if (n_qubits < 1 || n_qubits > 64) return fail(QSIM_E_UNSUPPORTED, "n_qubits out of range");
+    if (n_gates < 0 || (n_gates && !gates)) return fail(QSIM_E_INVALID, "bad gate list");
+    qsim_state_s tmp;
+    tmp.n = n_qubits;
+    for (int i = 0; i < n_gates; ++i)
+        if (qsim_status r = check_gate(&tmp, gates[i], i)) return r;
+    SchedOpts so = to_sched_opts(opts);
+    if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 6]");
+    const Schedule S = make_schedule(n_qubits, to_sgates(gates, n_gates), so, OpCostFn());
+    if (n_ops) *n_ops = (int)S.ops.size();
+    if ((int)S.ops.size() > op_cap) return fail(QSIM_E_INVALID, "op_cap too small");
+    if (gate_op)
+        for (int i = 0; i < n_gates; ++i) gate_op[i] = -1;
+    for (int o = 0; o < (int)S.ops.size(); ++o) {
+        const SOp& op = S.ops[o];
+        if (op_kind) op_kind[o] = op.kind;
+        if (op_k) op_k[o] = op.k;
+        if (op_qubits)
+            for (int j = 0; j < 6; ++j) op_qubits[6 * o + j] = j < op.k ? op.qubits[j] : -1;
+        for (int gi : op.members) {
+            if (gate_op) gate_op[gi] = o;
+            if (gate_role) gate_role[gi] = op.kind == OP_DIAG ? 2 : 0;
+        }
+        for (int gi : op.epi) {
+            if (gate_op) gate_op[gi] = o;
+            if (gate_role) gate_role[gi] = 1;
+        }
+    }
+    return QSIM_OK;
+}
+
+}  // extern "C"

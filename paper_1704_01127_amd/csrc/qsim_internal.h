@@ -1,0 +1,149 @@
+// Internal declarations of the qsim library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qsim {
+
+constexpr int kMaxK = 6;     // largest cluster
+constexpr int kEpiMax = 64;  // entries of each list of a diagonal descriptor
+
+// Named 2x2 gate matrices, row-major, (re, im) interleaved. Sec. 2 prints H,
+// T, X^1/2, Y^1/2 and X; Y and Z are the Pauli matrices; the *_DG entries are
+// conjugate transposes; PHASE is diag(1, e^{i theta}).
+__host__ __device__ inline void gate2x2(int kind, double theta, double m[8]) {
+    const double r = 0.70710678118654752440;  // 1/sqrt(2) = cos(pi/4) = sin(pi/4)
+    for (int i = 0; i < 8; ++i) m[i] = 0.0;
+    switch (kind) {
+        case 0:  // H
+            m[0] = r; m[2] = r; m[4] = r; m[6] = -r; break;
+        case 1:  // T
+            m[0] = 1; m[6] = r; m[7] = r; break;
+        case 2:  // X^1/2
+            m[0] = .5; m[1] = .5; m[2] = .5; m[3] = -.5; m[4] = .5; m[5] = -.5; m[6] = .5; m[7] = .5; break;
+        case 3:  // Y^1/2
+            m[0] = .5; m[1] = .5; m[2] = -.5; m[3] = -.5; m[4] = .5; m[5] = .5; m[6] = .5; m[7] = .5; break;
+        case 4:  // X
+            m[2] = 1; m[4] = 1; break;
+        case 5:  // Y
+            m[3] = -1; m[5] = 1; break;
+        case 6:  // Z
+            m[0] = 1; m[6] = -1; break;
+        case 8:  // T^dagger
+            m[0] = 1; m[6] = r; m[7] = -r; break;
+        case 9:  // (X^1/2)^dagger
+            m[0] = .5; m[1] = -.5; m[2] = .5; m[3] = .5; m[4] = .5; m[5] = .5; m[6] = .5; m[7] = -.5; break;
+        case 10:  // (Y^1/2)^dagger
+            m[0] = .5; m[1] = -.5; m[2] = .5; m[3] = -.5; m[4] = -.5; m[5] = .5; m[6] = .5; m[7] = -.5; break;
+        case 11:  // PHASE
+            m[0] = 1; m[6] = cos(theta); m[7] = sin(theta); break;
+        default:
+            break;
+    }
+}
+
+// Gate kinds (values of qsim_gate_kind).
+enum : int32_t {
+    G_H = 0, G_T = 1, G_SX = 2, G_SY = 3, G_X = 4, G_Y = 5, G_Z = 6, G_CZ = 7,
+    G_TDG = 8, G_SXDG = 9, G_SYDG = 10, G_PHASE = 11, G_DENSE = 12
+};
+
+__host__ __device__ inline bool gate_is_diagonal(int kind) {
+    return kind == G_T || kind == G_Z || kind == G_CZ || kind == G_TDG || kind == G_PHASE;
+}
+
+// Phase e^{i theta} a diagonal single-qubit gate puts on |1>.
+__host__ __device__ inline double gate_phase_angle(int kind, double theta) {
+    const double pi = 3.14159265358979323846;
+    switch (kind) {
+        case G_T: return pi / 4;
+        case G_TDG: return -pi / 4;
+        case G_Z: return pi;
+        case G_PHASE: return theta;
+        default: return 0.0;
+    }
+}
+
+// Diagonal factors of a state index, split by which bits they read:
+//   cc   : CZ pairs whose two qubits are both outside the target set
+//   mix  : CZ pairs with one qubit among the targets: (bit j of the target
+//          index x, state bit b)
+//   ph   : phase gates on qubits outside the target set (cos, sin)
+//   low  : standalone pass only, factor of the bits below the per-thread
+//          chunk (indexed by those bits)
+// Terms that read target bits only are folded into the cluster matrix.
+struct EpiDesc {
+    int32_t n_cc, n_mix, n_ph, n_low;
+    int32_t cc[kEpiMax][2];
+    int32_t mix[kEpiMax][2];
+    int32_t ph_q[kEpiMax];
+    double ph[kEpiMax][2];
+    double low[8][2];
+};
+
+// Cluster-matrix build: one op per work-group of the builder kernel.
+struct BuildGate {
+    int32_t kind;
+    int32_t nq;
+    int32_t pos[6];     // positions inside the cluster's sorted qubit list
+    int32_t dense_off;  // DENSE: offset (in doubles) of its matrix in the dense pool
+    int32_t pad;
+    double theta;
+};
+
+enum : int32_t {
+    LAYOUT_PLAIN = 0,     // complex matrix M[y][x] (T re, T im), for the VALU kernel
+    LAYOUT_MFMA32F = 1,   // real-split, permuted for v_mfma_f32_32x32x2_f32
+    LAYOUT_MFMA16D = 2    // real-split, permuted for v_mfma_f64_16x16x4_f64
+};
+
+struct BuildOp {
+    int32_t k;
+    int32_t n_gates;
+    int32_t gate0;      // first BuildGate of this op
+    int32_t layout;
+    int32_t is_double;  // element type of the output
+    int32_t pad;
+    int64_t out_off;    // byte offset of the output inside the matrix region
+};
+
+// Geometry of one cluster application.
+struct ClusterGeom {
+    int32_t t[kMaxK];   // sorted target qubits
+    int32_t n;          // qubits of the state
+    int32_t k;
+    uint64_t ncols;     // 2^(n-k)
+};
+
+// Bytes of a cluster matrix in each layout.
+inline int64_t matrix_bytes(int k, int layout, bool dbl) {
+    const int64_t d = int64_t(1) << k;
+    const int64_t es = dbl ? 8 : 4;
+    if (layout == LAYOUT_PLAIN) return d * d * 2 * es;
+    return (2 * d) * (2 * d) * es;
+}
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `st` and return hipSuccess or the launch error.
+hipError_t launch_init(void* psi, int n, bool dbl, int mode, hipStream_t st);
+hipError_t launch_build(const BuildOp* ops, int n_ops, const BuildGate* gates, const double* dense,
+                        char* mat_base, hipStream_t st);
+// Variant of the cluster kernel chosen for (dtype, k, n, targets).
+int cluster_layout(bool dbl, int k, int n);
+hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, int layout,
+                          const EpiDesc* epi, hipStream_t st);
+hipError_t launch_diag(void* psi, bool dbl, int n, const EpiDesc* epi, hipStream_t st);
+hipError_t launch_gate1q(void* psi, bool dbl, int n, int q, const double m[8], hipStream_t st);
+hipError_t launch_phase1q(void* psi, bool dbl, int n, int q, double cs, double sn, hipStream_t st);
+hipError_t launch_cz(void* psi, bool dbl, int n, int a, int b, hipStream_t st);
+// Reductions: partial sums go to `part` (kReduceBlocks * 4 doubles), the
+// final values to `res` (4 doubles).
+constexpr int kReduceBlocks = 1024;
+hipError_t launch_stats(const void* psi, bool dbl, int n, void* probs, bool probs_dbl, double* part,
+                        double* res, hipStream_t st);
+hipError_t launch_compare(const void* psi, bool dbl, int n, const void* ref, bool ref_dbl,
+                          double* part, double* res, hipStream_t st);
+
+}  // namespace qsim

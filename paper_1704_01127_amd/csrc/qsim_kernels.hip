@@ -1,0 +1,828 @@
+// GPU kernels of the state-vector simulator (gfx950 / MI355X).
+//
+// State: 2^n interleaved complex amplitudes (float2 or double2), amplitude
+// index i = sum_q b_q 2^q (Haener & Steiger, Sec. 2).
+//
+// Cluster kernels apply one dense k-qubit gate in place (Sec. 3.2): with the
+// targets sorted (t_0 < ... < t_{k-1}), a "column" c is an assignment of the
+// n-k other bits, deposited into the non-target positions; the 2^k amplitudes
+// of a column are gathered, multiplied by the 2^k x 2^k matrix and scattered
+// back. Consecutive columns differ in the lowest non-target bits, so a wave's
+// columns are contiguous runs of memory.
+//
+// For k >= 4 (float) / k >= 3 (double) the product is a real GEMM on the
+// matrix cores: with the state's (re, im) interleaving the complex matrix
+// becomes the real 2^(k+1) x 2^(k+1) matrix [[Re m, -Im m], [Im m, Re m]] per
+// entry - the (m_R, m_R) / (-m_I, m_I) pairing of Sec. 3.2, Eqs. (1)-(3) -
+// and one MFMA block multiplies it by 32 (float) or 16 (double) columns. The
+// rows and inner index of that matrix are permuted once, when it is built,
+// so that every lane's MFMA operands and results are exactly the amplitudes
+// it loads and stores: lane (p, h) of a float wave owns the amplitudes whose
+// highest target bit is h in column p, with no LDS round trip for the state.
+#include "qsim_internal.h"
+
+namespace qsim {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Cplx;
+template <> struct Cplx<float> { using type = float2; };
+template <> struct Cplx<double> { using type = double2; };
+
+// Insert a zero bit at position t.
+__device__ __forceinline__ uint64_t insert_zero(uint64_t c, int t) {
+    const uint64_t low = (uint64_t(1) << t) - 1;
+    return ((c & ~low) << 1) | (c & low);
+}
+
+// Deposit column index c into the non-target bit positions.
+template <int K>
+__device__ __forceinline__ uint64_t deposit_cols(uint64_t c, const ClusterGeom& g) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) c = insert_zero(c, g.t[j]);
+    return c;
+}
+
+// Offset of target index x: bit j of x at state bit t[j], j < NB.
+template <int NB>
+__device__ __forceinline__ uint64_t target_off(int x, const ClusterGeom& g) {
+    uint64_t o = 0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if ((x >> j) & 1) o |= uint64_t(1) << g.t[j];
+    return o;
+}
+
+// ------------------------------------------------------------ diagonal factors
+// Factor of the diagonal gates that depends on the non-target bits of a
+// column (sign parity, sign mask over target bits, complex phase).
+template <typename T>
+struct ColFactor {
+    uint32_t sgn, w;
+    T cr, ci;
+};
+
+template <typename T>
+__device__ __forceinline__ ColFactor<T> col_factor(const EpiDesc* __restrict__ e, uint64_t base) {
+    ColFactor<T> f{0u, 0u, T(1), T(0)};
+    const int ncc = e->n_cc;
+    for (int i = 0; i < ncc; ++i)
+        f.sgn ^= (uint32_t)((base >> e->cc[i][0]) & (base >> e->cc[i][1]) & 1);
+    const int nm = e->n_mix;
+    for (int i = 0; i < nm; ++i) f.w ^= (uint32_t)((base >> e->mix[i][1]) & 1) << e->mix[i][0];
+    const int np = e->n_ph;
+    if (np) {
+        double cr = 1.0, ci = 0.0;
+        for (int i = 0; i < np; ++i) {
+            if ((base >> e->ph_q[i]) & 1) {
+                const double a = e->ph[i][0], b = e->ph[i][1];
+                const double t = cr * a - ci * b;
+                ci = cr * b + ci * a;
+                cr = t;
+            }
+        }
+        f.cr = (T)cr;
+        f.ci = (T)ci;
+    }
+    return f;
+}
+
+template <typename T>
+__device__ __forceinline__ void apply_factor(T& re, T& im, const ColFactor<T>& f, uint32_t y, bool ph) {
+    if (ph) {
+        const T r = re * f.cr - im * f.ci;
+        const T i = re * f.ci + im * f.cr;
+        re = r;
+        im = i;
+    }
+    const bool neg = ((f.sgn ^ (uint32_t)__popc(y & f.w)) & 1u) != 0;
+    re = neg ? -re : re;
+    im = neg ? -im : im;
+}
+
+// ------------------------------------------------------------ cluster: MFMA, float
+// Wave tile: all 2^K target combinations x 32*NB columns. Lane l: p = l%32,
+// h = l/32 owns target indices x = j | h << (K-1), j < 2^(K-1), of its
+// column(s). Without a target at bit 0 (LOWT = false) and NB = 2 a lane's two
+// columns are adjacent in memory (one 16-byte load per amplitude pair); with
+// t_0 = 0 (LOWT) the amplitudes j, j+1 of one column are adjacent instead.
+template <int K, int NB, bool LOWT>
+__global__ __launch_bounds__(256) void k_cluster_f32_mfma(float2* __restrict__ psi,
+                                                          const float* __restrict__ Ap,
+                                                          const EpiDesc* __restrict__ epi,
+                                                          ClusterGeom g) {
+    constexpr int D = 1 << K;
+    constexpr int HX = D / 2;       // amplitudes per lane and column
+    constexpr int RB = 2 * D / 32;  // 32-row blocks of the real-split matrix
+    constexpr int S = D;            // MFMA steps (inner dimension 2^(K+1), 2 per step)
+    constexpr int COLS = 32 * NB;
+    __shared__ float As[RB * S * 64];
+    for (int i = threadIdx.x; i < RB * S * 64; i += 256) As[i] = Ap[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const uint64_t hoff = h ? (uint64_t(1) << g.t[K - 1]) : 0;
+    const uint64_t ntiles = g.ncols / COLS;
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+
+    for (uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += stride) {
+        uint64_t base[NB];
+        if (LOWT || NB == 1) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) base[nb] = deposit_cols<K>(tile * COLS + p + 32 * nb, g);
+        } else {
+            base[0] = deposit_cols<K>(tile * COLS + 2 * p, g);
+            base[NB - 1] = base[0] | 1;
+        }
+        float B[NB][2 * HX];
+        if (!LOWT && NB == 2) {
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                const float4 v = *reinterpret_cast<const float4*>(psi + (base[0] | hoff | target_off<K - 1>(j, g)));
+                B[0][2 * j] = v.x; B[0][2 * j + 1] = v.y;
+                B[NB - 1][2 * j] = v.z; B[NB - 1][2 * j + 1] = v.w;
+            }
+        } else if (LOWT) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int j = 0; j < HX; j += 2) {
+                    const float4 v = *reinterpret_cast<const float4*>(psi + (base[nb] | hoff | target_off<K - 1>(j, g)));
+                    B[nb][2 * j] = v.x; B[nb][2 * j + 1] = v.y;
+                    B[nb][2 * j + 2] = v.z; B[nb][2 * j + 3] = v.w;
+                }
+        } else {
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                const float2 v = psi[base[0] | hoff | target_off<K - 1>(j, g)];
+                B[0][2 * j] = v.x; B[0][2 * j + 1] = v.y;
+            }
+        }
+
+        floatx16 acc[NB][RB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[nb][rb][i] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const float a = As[(rb * S + s) * 64 + lane];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[nb][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, B[nb][s], acc[nb][rb], 0, 0, 0);
+            }
+        }
+        // acc[nb][j / 8][2 (j % 8) + {0, 1}] is output amplitude j of the lane
+        if (has_epi) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const ColFactor<float> f = col_factor<float>(epi, base[nb]);
+#pragma unroll
+                for (int j = 0; j < HX; ++j) {
+                    float re = acc[nb][j / 8][2 * (j % 8)], im = acc[nb][j / 8][2 * (j % 8) + 1];
+                    apply_factor(re, im, f, (uint32_t)(j | (h << (K - 1))), has_ph);
+                    acc[nb][j / 8][2 * (j % 8)] = re;
+                    acc[nb][j / 8][2 * (j % 8) + 1] = im;
+                }
+            }
+        }
+        if (!LOWT && NB == 2) {
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                float4 v;
+                v.x = acc[0][j / 8][2 * (j % 8)]; v.y = acc[0][j / 8][2 * (j % 8) + 1];
+                v.z = acc[NB - 1][j / 8][2 * (j % 8)]; v.w = acc[NB - 1][j / 8][2 * (j % 8) + 1];
+                *reinterpret_cast<float4*>(psi + (base[0] | hoff | target_off<K - 1>(j, g))) = v;
+            }
+        } else if (LOWT) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int j = 0; j < HX; j += 2) {
+                    float4 v;
+                    v.x = acc[nb][j / 8][2 * (j % 8)]; v.y = acc[nb][j / 8][2 * (j % 8) + 1];
+                    v.z = acc[nb][(j + 1) / 8][2 * ((j + 1) % 8)];
+                    v.w = acc[nb][(j + 1) / 8][2 * ((j + 1) % 8) + 1];
+                    *reinterpret_cast<float4*>(psi + (base[nb] | hoff | target_off<K - 1>(j, g))) = v;
+                }
+        } else {
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                psi[base[0] | hoff | target_off<K - 1>(j, g)] =
+                    make_float2(acc[0][j / 8][2 * (j % 8)], acc[0][j / 8][2 * (j % 8) + 1]);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ cluster: MFMA, double
+// v_mfma_f64_16x16x4_f64: lane l: p = l%16 (column), q = l/16 owns target
+// indices x = j | q << (K-2), j < 2^(K-2), of its column(s). Operand A/B: lane
+// l holds row / column l%16 at inner index l/16; result register r of lane l
+// holds row 4 r + l/16, column l%16.
+template <int K, int NB, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_cluster_f64_mfma(double2* __restrict__ psi,
+                                                             const double* __restrict__ Ap,
+                                                             const EpiDesc* __restrict__ epi,
+                                                             ClusterGeom g) {
+    constexpr int D = 1 << K;
+    constexpr int HX = D / 4;
+    constexpr int RB = 2 * D / 16;
+    constexpr int S = 2 * D / 4;
+    constexpr int COLS = 16 * NB;
+    constexpr int WAVES = THREADS / 64;
+    __shared__ double As[RB * S * 64];
+    for (int i = threadIdx.x; i < RB * S * 64; i += THREADS) As[i] = Ap[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, p = lane & 15, q = lane >> 4;
+    const uint64_t qoff = ((q & 1) ? (uint64_t(1) << g.t[K - 2]) : 0) | ((q & 2) ? (uint64_t(1) << g.t[K - 1]) : 0);
+    const uint64_t ntiles = g.ncols / COLS;
+    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+
+    for (uint64_t tile = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); tile < ntiles; tile += stride) {
+        uint64_t base[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) base[nb] = deposit_cols<K>(tile * COLS + p + 16 * nb, g);
+        double B[NB][2 * HX];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                const double2 v = psi[base[nb] | qoff | target_off<K - 2>(j, g)];
+                B[nb][2 * j] = v.x;
+                B[nb][2 * j + 1] = v.y;
+            }
+        doublex4 acc[NB][RB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[nb][rb][i] = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const double a = As[(rb * S + s) * 64 + lane];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[nb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[nb][s], acc[nb][rb], 0, 0, 0);
+            }
+        }
+        // acc[nb][j / 2][2 (j % 2) + {0, 1}] is output amplitude j of the lane
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            ColFactor<double> f{0u, 0u, 1.0, 0.0};
+            if (has_epi) f = col_factor<double>(epi, base[nb]);
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                double re = acc[nb][j / 2][2 * (j % 2)], im = acc[nb][j / 2][2 * (j % 2) + 1];
+                if (has_epi) apply_factor(re, im, f, (uint32_t)(j | (q << (K - 2))), has_ph);
+                psi[base[nb] | qoff | target_off<K - 2>(j, g)] = make_double2(re, im);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ cluster: vector ALU
+// One column per thread; the matrix M[y][x] (complex) sits in LDS and is read
+// as a broadcast. Used for small k and for states too small for a wave tile.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_cluster_valu(typename Cplx<T>::type* __restrict__ psi,
+                                                      const typename Cplx<T>::type* __restrict__ M,
+                                                      const EpiDesc* __restrict__ epi, ClusterGeom g) {
+    using V = typename Cplx<T>::type;
+    constexpr int D = 1 << K;
+    __shared__ V Ms[D * D];
+    for (int i = threadIdx.x; i < D * D; i += 256) Ms[i] = M[i];
+    __syncthreads();
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < g.ncols; c += stride) {
+        const uint64_t base = deposit_cols<K>(c, g);
+        V v[D];
+#pragma unroll
+        for (int x = 0; x < D; ++x) v[x] = psi[base | target_off<K>(x, g)];
+        ColFactor<T> f{0u, 0u, T(1), T(0)};
+        if (has_epi) f = col_factor<T>(epi, base);
+#pragma unroll
+        for (int y = 0; y < D; ++y) {
+            T ar = 0, ai = 0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) {
+                const V m = Ms[y * D + x];
+                ar += m.x * v[x].x - m.y * v[x].y;
+                ai += m.x * v[x].y + m.y * v[x].x;
+            }
+            if (has_epi) apply_factor(ar, ai, f, (uint32_t)y, has_ph);
+            V o;
+            o.x = ar;
+            o.y = ai;
+            psi[base | target_off<K>(y, g)] = o;
+        }
+    }
+}
+
+// ------------------------------------------------------------ diagonal pass
+// Every amplitude times the diagonal factor of its index. A thread owns a
+// chunk of 2^lowbits consecutive amplitudes; terms reading only the chunk's
+// low bits come from the descriptor's `low` table, the others from the
+// column factor of the chunk's base index (the low bits act as "targets").
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag(typename Cplx<T>::type* __restrict__ psi, int lowbits,
+                                              const EpiDesc* __restrict__ e, uint64_t nchunks) {
+    using V = typename Cplx<T>::type;
+    const bool has_ph = e->n_ph > 0;
+    const int ch = 1 << lowbits;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < nchunks; c += stride) {
+        const uint64_t base = c << lowbits;
+        const ColFactor<T> f = col_factor<T>(e, base);
+        for (int j = 0; j < ch; ++j) {
+            V v = psi[base + j];
+            T re = v.x, im = v.y;
+            const T lr = (T)e->low[j][0], li = (T)e->low[j][1];
+            const T r = re * lr - im * li;
+            im = re * li + im * lr;
+            re = r;
+            apply_factor(re, im, f, (uint32_t)j, has_ph);
+            v.x = re;
+            v.y = im;
+            psi[base + j] = v;
+        }
+    }
+}
+
+// ------------------------------------------------------------ per-gate kernels
+// A single-qubit gate on the pairs (i, i + 2^q) with bit q of i clear (Sec. 2).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gate1q(typename Cplx<T>::type* __restrict__ psi, int q, T m0r,
+                                                T m0i, T m1r, T m1i, T m2r, T m2i, T m3r, T m3i,
+                                                uint64_t npairs) {
+    using V = typename Cplx<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    const uint64_t bit = uint64_t(1) << q;
+    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < npairs; p += stride) {
+        const uint64_t i = insert_zero(p, q);
+        const V a = psi[i], b = psi[i | bit];
+        V o0, o1;
+        o0.x = (m0r * a.x - m0i * a.y) + (m1r * b.x - m1i * b.y);
+        o0.y = (m0r * a.y + m0i * a.x) + (m1r * b.y + m1i * b.x);
+        o1.x = (m2r * a.x - m2i * a.y) + (m3r * b.x - m3i * b.y);
+        o1.y = (m2r * a.y + m2i * a.x) + (m3r * b.y + m3i * b.x);
+        psi[i] = o0;
+        psi[i | bit] = o1;
+    }
+}
+
+// A diagonal single-qubit gate diag(1, e^{i phi}): only amplitudes with bit q set change.
+template <typename T>
+__global__ __launch_bounds__(256) void k_phase1q(typename Cplx<T>::type* __restrict__ psi, int q, T cr,
+                                                 T ci, uint64_t nhalf) {
+    using V = typename Cplx<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    const uint64_t bit = uint64_t(1) << q;
+    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < nhalf; p += stride) {
+        const uint64_t i = insert_zero(p, q) | bit;
+        const V a = psi[i];
+        V o;
+        o.x = a.x * cr - a.y * ci;
+        o.y = a.x * ci + a.y * cr;
+        psi[i] = o;
+    }
+}
+
+// CZ(a, b), a < b: negate the amplitudes with both bits set.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cz(typename Cplx<T>::type* __restrict__ psi, int a, int b,
+                                            uint64_t nquarter) {
+    using V = typename Cplx<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    const uint64_t m = (uint64_t(1) << a) | (uint64_t(1) << b);
+    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < nquarter; p += stride) {
+        const uint64_t i = insert_zero(insert_zero(p, a), b) | m;
+        V v = psi[i];
+        v.x = -v.x;
+        v.y = -v.y;
+        psi[i] = v;
+    }
+}
+
+// ------------------------------------------------------------ initialisation
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(typename Cplx<T>::type* __restrict__ psi, uint64_t count,
+                                              int mode, T val) {
+    using V = typename Cplx<T>::type;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride) {
+        V v;
+        v.x = (mode == 0) ? (i == 0 ? T(1) : T(0)) : val;
+        v.y = T(0);
+        psi[i] = v;
+    }
+}
+
+// ------------------------------------------------------------ cluster-matrix builder
+// One work-group (64 threads) per cluster. Thread x owns column x of the
+// cluster matrix: it starts from the basis vector e_x of the 2^k space and
+// applies the cluster's gates in order, in float64 (the matrix is reused for
+// all 2^(n-k) columns of the state, Sec. 3.2, so building it is cheap). The
+// result is then written in the layout of the kernel that will apply it.
+__device__ void build_apply_1q(double* v, int D, int a, const double m[8]) {
+    for (int i = 0; i < D; ++i) {
+        if ((i >> a) & 1) continue;
+        const int j = i | (1 << a);
+        const double ar = v[2 * i], ai = v[2 * i + 1], br = v[2 * j], bi = v[2 * j + 1];
+        v[2 * i] = (m[0] * ar - m[1] * ai) + (m[2] * br - m[3] * bi);
+        v[2 * i + 1] = (m[0] * ai + m[1] * ar) + (m[2] * bi + m[3] * br);
+        v[2 * j] = (m[4] * ar - m[5] * ai) + (m[6] * br - m[7] * bi);
+        v[2 * j + 1] = (m[4] * ai + m[5] * ar) + (m[6] * bi + m[7] * br);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_build(const BuildOp* __restrict__ ops, const BuildGate* __restrict__ gates,
+                                              const double* __restrict__ dense, char* __restrict__ mat_base) {
+    __shared__ double Vs[64 * 64 * 2];
+    __shared__ double Ws[64 * 64 * 2];
+    const BuildOp op = ops[blockIdx.x];
+    const int k = op.k, D = 1 << k, x = threadIdx.x;
+    if (x < D) {
+        double* v = Vs + x * D * 2;
+        double* w = Ws + x * D * 2;
+        for (int i = 0; i < 2 * D; ++i) v[i] = 0.0;
+        v[2 * x] = 1.0;
+        for (int gi = 0; gi < op.n_gates; ++gi) {
+            const BuildGate bg = gates[op.gate0 + gi];
+            if (bg.kind == G_CZ) {
+                const int m = (1 << bg.pos[0]) | (1 << bg.pos[1]);
+                for (int i = 0; i < D; ++i)
+                    if ((i & m) == m) { v[2 * i] = -v[2 * i]; v[2 * i + 1] = -v[2 * i + 1]; }
+            } else if (bg.kind == G_DENSE) {
+                const int dq = bg.nq, dd = 1 << dq;
+                const double* u = dense + bg.dense_off;
+                int pm = 0;
+                for (int j = 0; j < dq; ++j) pm |= 1 << bg.pos[j];
+                for (int y = 0; y < D; ++y) {
+                    int yl = 0;
+                    for (int j = 0; j < dq; ++j) yl |= ((y >> bg.pos[j]) & 1) << j;
+                    const int rest = y & ~pm;
+                    double sr = 0.0, si = 0.0;
+                    for (int xl = 0; xl < dd; ++xl) {
+                        int src = rest;
+                        for (int j = 0; j < dq; ++j) src |= ((xl >> j) & 1) << bg.pos[j];
+                        const double mr = u[2 * (yl * dd + xl)], mi = u[2 * (yl * dd + xl) + 1];
+                        sr += mr * v[2 * src] - mi * v[2 * src + 1];
+                        si += mr * v[2 * src + 1] + mi * v[2 * src];
+                    }
+                    w[2 * y] = sr;
+                    w[2 * y + 1] = si;
+                }
+                for (int i = 0; i < 2 * D; ++i) v[i] = w[i];
+            } else {
+                double m[8];
+                gate2x2(bg.kind, bg.theta, m);
+                build_apply_1q(v, D, bg.pos[0], m);
+            }
+        }
+    }
+    __syncthreads();
+    // M[y][x] = Vs[x][y]
+    auto Mre = [&](int y, int xx) { return Vs[xx * D * 2 + 2 * y]; };
+    auto Mim = [&](int y, int xx) { return Vs[xx * D * 2 + 2 * y + 1]; };
+    // entry (R, Kc) of the real-split matrix [[Re, -Im], [Im, Re]]
+    auto Ars = [&](int y, int a, int xx, int b) {
+        const double re = Mre(y, xx), im = Mim(y, xx);
+        return (a == b) ? re : (a == 0 ? -im : im);
+    };
+    char* out = mat_base + op.out_off;
+    if (op.layout == LAYOUT_PLAIN) {
+        if (x < D) {
+            for (int y = 0; y < D; ++y) {
+                if (op.is_double) {
+                    reinterpret_cast<double2*>(out)[y * D + x] = make_double2(Mre(y, x), Mim(y, x));
+                } else {
+                    reinterpret_cast<float2*>(out)[y * D + x] = make_float2((float)Mre(y, x), (float)Mim(y, x));
+                }
+            }
+        }
+    } else if (op.layout == LAYOUT_MFMA32F) {
+        // entry (rb, s, lane l): row rho = l % 32 of row block rb, inner index 2 s + l / 32
+        const int RB = 2 * D / 32, S = D, l = x;
+        const int rho = l & 31, hin = l >> 5;
+        float* A = reinterpret_cast<float*>(out);
+        for (int rb = 0; rb < RB; ++rb) {
+            const int jout = rb * 8 + 2 * (rho >> 3) + ((rho & 3) >> 1);
+            const int hout = (rho >> 2) & 1;
+            const int y = jout | (hout << (k - 1)), a = rho & 1;
+            for (int s = 0; s < S; ++s) {
+                const int xin = (s >> 1) | (hin << (k - 1)), b = s & 1;
+                A[(rb * S + s) * 64 + l] = (float)Ars(y, a, xin, b);
+            }
+        }
+    } else {  // LAYOUT_MFMA16D
+        // entry (rb, s, lane l): row rho = l % 16 of row block rb, inner index 4 s + l / 16.
+        // The result row rho lands in register rho / 4 of the lanes with l / 16 = rho % 4.
+        const int RB = 2 * D / 16, S = 2 * D / 4, l = x;
+        const int rho = l & 15, qin = l >> 4;
+        double* A = reinterpret_cast<double*>(out);
+        for (int rb = 0; rb < RB; ++rb) {
+            const int qout = rho & 3, ir = rho >> 2;
+            const int y = (rb * 2 + (ir >> 1)) | (qout << (k - 2)), a = ir & 1;
+            for (int s = 0; s < S; ++s) {
+                const int xin = (s >> 1) | (qin << (k - 2)), b = s & 1;
+                A[(rb * S + s) * 64 + l] = Ars(y, a, xin, b);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ float64 reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block reduction of up to 8 values; slot i is summed unless bit i of maxmask is set.
+__device__ void block_reduce_store(double (&vals)[8], int nv, unsigned maxmask, double* out) {
+    __shared__ double sh[4][8];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = 0; i < nv; ++i) vals[i] = ((maxmask >> i) & 1) ? wave_max(vals[i]) : wave_sum(vals[i]);
+    if (lane == 0)
+        for (int i = 0; i < nv; ++i) sh[w][i] = vals[i];
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        const int i = threadIdx.x;
+        double r = sh[0][i];
+        for (int ww = 1; ww < 4; ++ww) r = ((maxmask >> i) & 1) ? fmax(r, sh[ww][i]) : r + sh[ww][i];
+        out[i] = r;
+    }
+}
+
+template <typename T, typename P>
+__global__ __launch_bounds__(256) void k_stats(const typename Cplx<T>::type* __restrict__ psi, uint64_t count,
+                                               P* __restrict__ probs, double* __restrict__ part) {
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride) {
+        const auto a = psi[i];
+        const double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+        v[0] += pr;
+        v[1] += pr * pr;
+        if (pr > 0.0) v[2] -= pr * log(pr);
+        if (probs) probs[i] = (P)pr;
+    }
+    block_reduce_store(v, 3, 0u, part + blockIdx.x * 8);
+}
+
+template <typename T, typename R>
+__global__ __launch_bounds__(256) void k_compare(const typename Cplx<T>::type* __restrict__ psi,
+                                                 const typename Cplx<R>::type* __restrict__ ref, uint64_t count,
+                                                 double* __restrict__ part) {
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride) {
+        const auto a = psi[i];
+        const auto r = ref[i];
+        const double ar = a.x, ai = a.y, rr = r.x, ri = r.y;
+        v[0] += rr * ar + ri * ai;  // Re <ref|psi>
+        v[1] += rr * ai - ri * ar;  // Im <ref|psi>
+        v[2] += rr * rr + ri * ri;
+        v[3] += ar * ar + ai * ai;
+        const double dr = ar - rr, di = ai - ri;
+        v[4] = fmax(v[4], sqrt(dr * dr + di * di));
+    }
+    block_reduce_store(v, 5, 1u << 4, part + blockIdx.x * 8);
+}
+
+// Sum (or max) the per-block partials in a fixed order: deterministic.
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ part, int nblocks, int nv,
+                                                      unsigned maxmask, double* __restrict__ res) {
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+        for (int i = 0; i < nv; ++i) {
+            const double x = part[b * 8 + i];
+            v[i] = ((maxmask >> i) & 1) ? fmax(v[i], x) : v[i] + x;
+        }
+    block_reduce_store(v, nv, maxmask, res);
+}
+
+// ------------------------------------------------------------ launchers
+namespace {
+inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap) {
+    const uint64_t b = (work + per_block - 1) / per_block;
+    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+constexpr unsigned kStreamGrid = 8192;  // blocks of 256 threads for grid-stride streaming kernels
+constexpr unsigned kPersistGrid = 2048; // work-groups of the persistent cluster kernels
+}  // namespace
+
+hipError_t launch_init(void* psi, int n, bool dbl, int mode, hipStream_t st) {
+    const uint64_t cnt = uint64_t(1) << n;
+    const unsigned grid = grid_for(cnt, 256, kStreamGrid);
+    const double val = std::ldexp(1.0, -n) > 0 ? std::sqrt(std::ldexp(1.0, -n)) : 0.0;
+    if (dbl)
+        hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, cnt, mode, val);
+    else
+        hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, cnt, mode, (float)val);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const BuildOp* ops, int n_ops, const BuildGate* gates, const double* dense,
+                        char* mat_base, hipStream_t st) {
+    if (n_ops <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_build, dim3(n_ops), dim3(64), 0, st, ops, gates, dense, mat_base);
+    return hipGetLastError();
+}
+
+int cluster_layout(bool dbl, int k, int n) {
+    if (!dbl) {
+        const int nb = (k == 6) ? 1 : 2;
+        return (k >= 4 && n - k >= 5 + (nb == 2)) ? LAYOUT_MFMA32F : LAYOUT_PLAIN;
+    }
+    const int nb = (k == 6) ? 1 : 2;
+    return (k >= 3 && n - k >= 4 + (nb == 2)) ? LAYOUT_MFMA16D : LAYOUT_PLAIN;
+}
+
+namespace {
+template <int K>
+hipError_t launch_valu_k(void* psi, bool dbl, const ClusterGeom& g, const void* mat, const EpiDesc* epi,
+                         hipStream_t st) {
+    const unsigned grid = grid_for(g.ncols, 256, kStreamGrid);
+    if (dbl)
+        hipLaunchKernelGGL((k_cluster_valu<double, K>), dim3(grid), dim3(256), 0, st, (double2*)psi,
+                           (const double2*)mat, epi, g);
+    else
+        hipLaunchKernelGGL((k_cluster_valu<float, K>), dim3(grid), dim3(256), 0, st, (float2*)psi,
+                           (const float2*)mat, epi, g);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_mfma32_k(void* psi, const ClusterGeom& g, const void* mat, const EpiDesc* epi, hipStream_t st) {
+    constexpr int NB = (K == 6) ? 1 : 2;
+    const uint64_t tiles = g.ncols / (32 * NB);
+    const unsigned grid = grid_for(tiles, 4, kPersistGrid);
+    if (g.t[0] == 0)
+        hipLaunchKernelGGL((k_cluster_f32_mfma<K, NB, true>), dim3(grid), dim3(256), 0, st, (float2*)psi,
+                           (const float*)mat, epi, g);
+    else
+        hipLaunchKernelGGL((k_cluster_f32_mfma<K, NB, false>), dim3(grid), dim3(256), 0, st, (float2*)psi,
+                           (const float*)mat, epi, g);
+    return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_mfma64_k(void* psi, const ClusterGeom& g, const void* mat, const EpiDesc* epi, hipStream_t st) {
+    constexpr int NB = (K == 6) ? 1 : 2;
+    constexpr int TH = (K == 6) ? 512 : 256;
+    const uint64_t tiles = g.ncols / (16 * NB);
+    const unsigned grid = grid_for(tiles, TH / 64, kPersistGrid);
+    hipLaunchKernelGGL((k_cluster_f64_mfma<K, NB, TH>), dim3(grid), dim3(TH), 0, st, (double2*)psi,
+                       (const double*)mat, epi, g);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, int layout,
+                          const EpiDesc* epi, hipStream_t st) {
+    if (layout == LAYOUT_PLAIN) {
+        switch (g.k) {
+            case 1: return launch_valu_k<1>(psi, dbl, g, mat, epi, st);
+            case 2: return launch_valu_k<2>(psi, dbl, g, mat, epi, st);
+            case 3: return launch_valu_k<3>(psi, dbl, g, mat, epi, st);
+            case 4: return launch_valu_k<4>(psi, dbl, g, mat, epi, st);
+            case 5: return launch_valu_k<5>(psi, dbl, g, mat, epi, st);
+            case 6: return launch_valu_k<6>(psi, dbl, g, mat, epi, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (layout == LAYOUT_MFMA32F && !dbl) {
+        switch (g.k) {
+            case 4: return launch_mfma32_k<4>(psi, g, mat, epi, st);
+            case 5: return launch_mfma32_k<5>(psi, g, mat, epi, st);
+            case 6: return launch_mfma32_k<6>(psi, g, mat, epi, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (layout == LAYOUT_MFMA16D && dbl) {
+        switch (g.k) {
+            case 3: return launch_mfma64_k<3>(psi, g, mat, epi, st);
+            case 4: return launch_mfma64_k<4>(psi, g, mat, epi, st);
+            case 5: return launch_mfma64_k<5>(psi, g, mat, epi, st);
+            case 6: return launch_mfma64_k<6>(psi, g, mat, epi, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_diag(void* psi, bool dbl, int n, const EpiDesc* epi, hipStream_t st) {
+    const int lowbits = n < 2 ? n : 2;
+    const uint64_t nchunks = uint64_t(1) << (n - lowbits);
+    const unsigned grid = grid_for(nchunks, 256, kStreamGrid);
+    if (dbl)
+        hipLaunchKernelGGL(k_diag<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, lowbits, epi, nchunks);
+    else
+        hipLaunchKernelGGL(k_diag<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, lowbits, epi, nchunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate1q(void* psi, bool dbl, int n, int q, const double m[8], hipStream_t st) {
+    const uint64_t np = uint64_t(1) << (n - 1);
+    const unsigned grid = grid_for(np, 256, kStreamGrid);
+    if (dbl)
+        hipLaunchKernelGGL(k_gate1q<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, q, m[0], m[1], m[2],
+                           m[3], m[4], m[5], m[6], m[7], np);
+    else
+        hipLaunchKernelGGL(k_gate1q<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, q, (float)m[0],
+                           (float)m[1], (float)m[2], (float)m[3], (float)m[4], (float)m[5], (float)m[6],
+                           (float)m[7], np);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase1q(void* psi, bool dbl, int n, int q, double cs, double sn, hipStream_t st) {
+    const uint64_t nh = uint64_t(1) << (n - 1);
+    const unsigned grid = grid_for(nh, 256, kStreamGrid);
+    if (dbl)
+        hipLaunchKernelGGL(k_phase1q<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, q, cs, sn, nh);
+    else
+        hipLaunchKernelGGL(k_phase1q<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, q, (float)cs,
+                           (float)sn, nh);
+    return hipGetLastError();
+}
+
+hipError_t launch_cz(void* psi, bool dbl, int n, int a, int b, hipStream_t st) {
+    if (a > b) { const int t = a; a = b; b = t; }
+    const uint64_t nq = uint64_t(1) << (n - 2);
+    const unsigned grid = grid_for(nq, 256, kStreamGrid);
+    if (dbl)
+        hipLaunchKernelGGL(k_cz<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, a, b, nq);
+    else
+        hipLaunchKernelGGL(k_cz<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, a, b, nq);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const void* psi, bool dbl, int n, void* probs, bool probs_dbl, double* part,
+                        double* res, hipStream_t st) {
+    const uint64_t cnt = uint64_t(1) << n;
+    const unsigned grid = grid_for(cnt, 256, kReduceBlocks);
+    if (dbl) {
+        if (probs_dbl)
+            hipLaunchKernelGGL((k_stats<double, double>), dim3(grid), dim3(256), 0, st, (const double2*)psi, cnt,
+                               (double*)probs, part);
+        else
+            hipLaunchKernelGGL((k_stats<double, float>), dim3(grid), dim3(256), 0, st, (const double2*)psi, cnt,
+                               (float*)probs, part);
+    } else {
+        if (probs_dbl)
+            hipLaunchKernelGGL((k_stats<float, double>), dim3(grid), dim3(256), 0, st, (const float2*)psi, cnt,
+                               (double*)probs, part);
+        else
+            hipLaunchKernelGGL((k_stats<float, float>), dim3(grid), dim3(256), 0, st, (const float2*)psi, cnt,
+                               (float*)probs, part);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, part, (int)grid, 3, 0u, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_compare(const void* psi, bool dbl, int n, const void* ref, bool ref_dbl, double* part,
+                          double* res, hipStream_t st) {
+    const uint64_t cnt = uint64_t(1) << n;
+    const unsigned grid = grid_for(cnt, 256, kReduceBlocks);
+    if (dbl) {
+        if (ref_dbl)
+            hipLaunchKernelGGL((k_compare<double, double>), dim3(grid), dim3(256), 0, st, (const double2*)psi,
+                               (const double2*)ref, cnt, part);
+        else
+            hipLaunchKernelGGL((k_compare<double, float>), dim3(grid), dim3(256), 0, st, (const double2*)psi,
+                               (const float2*)ref, cnt, part);
+    } else {
+        if (ref_dbl)
+            hipLaunchKernelGGL((k_compare<float, double>), dim3(grid), dim3(256), 0, st, (const float2*)psi,
+                               (const double2*)ref, cnt, part);
+        else
+            hipLaunchKernelGGL((k_compare<float, float>), dim3(grid), dim3(256), 0, st, (const float2*)psi,
+                               (const float2*)ref, cnt, part);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, part, (int)grid, 5, 1u << 4, res);
+    return hipGetLastError();
+}
+
+}  // namespace qsim

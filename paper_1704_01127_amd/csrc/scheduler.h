@@ -1,0 +1,51 @@
+// Gate scheduling: clustering of a gate list into k-qubit clusters
+// (Haener & Steiger, Sec. 3.6.1, step 2) plus diagonal passes.
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <vector>
+
+namespace qsim {
+
+struct SGate {
+    int kind;
+    int nq;
+    int q[6];
+    bool diag;
+};
+
+enum : int { OP_CLUSTER = 0, OP_DIAG = 1, OP_GATE = 2 };
+
+struct SOp {
+    int kind = OP_CLUSTER;
+    int k = 0;
+    int qubits[6] = {0, 0, 0, 0, 0, 0};  // sorted (clusters); the gate's qubits (per-gate ops)
+    std::vector<int> members;            // gates folded into the matrix / the pass / the single gate
+    std::vector<int> epi;                // diagonal gates applied while storing
+};
+
+// Predicted time (microseconds) of one cluster op on k qubits with the given
+// sorted qubits; used by the cost-driven scheduler.
+using OpCostFn = std::function<double(int k, const int* qubits, int n_epi)>;
+
+struct SchedOpts {
+    int kmax = 5;
+    int mode = 1;  // 0 per-gate, 1 greedy, 2 cost-driven
+    bool fuse_diag = false;
+    bool skip_trailing_diag = false;
+    bool skip_initial_h = false;
+};
+
+struct Schedule {
+    std::vector<SOp> ops;
+    bool uniform_init = false;  // leading H layer replaced by uniform initialisation
+    std::vector<char> dropped;  // per gate: removed by a skip option
+    int n_applied = 0;
+};
+
+// Build the schedule. `cost` is used by mode 2 only (may be empty: then a
+// constant cost per op is assumed, which reduces to the greedy rule).
+Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& o, const OpCostFn& cost);
+
+}  // namespace qsim

@@ -1,0 +1,280 @@
+"""ctypes binding of libqsim.so (the C ABI in include/qsim.h).
+
+Argument marshalling only: every step of a simulation runs in the library's
+HIP kernels on the GPU. PyTorch provides the device memory (state vector and
+workspace) and the stream. The binding fails loudly when the library has not
+been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsim.so")
+
+C64, C128 = 1, 2
+INIT_ZERO, INIT_UNIFORM, INIT_KEEP = 0, 1, 2
+SCHED_PER_GATE, SCHED_GREEDY, SCHED_ANALYTIC, SCHED_LEARNED = 0, 1, 2, 3
+GATE_KIND = {"H": 0, "T": 1, "SX": 2, "SY": 3, "X": 4, "Y": 5, "Z": 6, "CZ": 7, "TDG": 8,
+             "SXDG": 9, "SYDG": 10, "PHASE": 11, "U": 12}
+STATUS = {0: "QSIM_OK", -1: "QSIM_E_INVALID", -2: "QSIM_E_UNSUPPORTED", -3: "QSIM_E_DEVICE"}
+SCHEDULERS = {"per_gate": 0, "greedy": 1, "analytic": 2, "learned": 3}
+
+
+class QsimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("qubits", ctypes.c_int32 * 6),
+                ("theta", ctypes.c_double), ("mat", ctypes.POINTER(ctypes.c_double))]
+
+
+class RunOpts(ctypes.Structure):
+    _fields_ = [("kmax", ctypes.c_int32), ("scheduler", ctypes.c_int32),
+                ("skip_trailing_diag", ctypes.c_int32), ("fuse_diag", ctypes.c_int32),
+                ("skip_initial_h", ctypes.c_int32), ("record_timings", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("n_ops", ctypes.c_int32), ("n_clusters_by_k", ctypes.c_int32 * 7),
+                ("n_diag_ops", ctypes.c_int32), ("n_gates_applied", ctypes.c_int32),
+                ("n_gates_fused_epilogue", ctypes.c_int32), ("schedule_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(n_ops=self.n_ops, n_clusters_by_k=list(self.n_clusters_by_k),
+                    n_diag_ops=self.n_diag_ops, n_gates_applied=self.n_gates_applied,
+                    n_gates_fused_epilogue=self.n_gates_fused_epilogue,
+                    schedule_ms=self.schedule_ms, total_ms=self.total_ms)
+
+
+_lib = None
+
+
+def lib():
+    """Load libqsim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libqsim.so is not built: run `python -c 'import __graft_entry__ as g; "
+                              "g.build()'` (hipcc, gfx950) first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "qsim_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+            "qsim_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp,
+                                           ctypes.c_size_t, vp, ctypes.c_int, ctypes.POINTER(vp)]),
+            "qsim_destroy": (ctypes.c_int, [vp]),
+            "qsim_init_state": (ctypes.c_int, [vp, ctypes.c_int]),
+            "qsim_apply_cluster": (ctypes.c_int, [vp, ctypes.c_int, i32p, dp]),
+            "qsim_apply_diag": (ctypes.c_int, [vp, ctypes.c_int, i32p, ctypes.c_int, i32p, dp]),
+            "qsim_apply_gate": (ctypes.c_int, [vp, ctypes.POINTER(Gate)]),
+            "qsim_run_circuit": (ctypes.c_int, [vp, ctypes.POINTER(Gate), ctypes.c_int,
+                                                ctypes.POINTER(RunOpts), ctypes.POINTER(RunStats)]),
+            "qsim_probs": (ctypes.c_int, [vp, vp, ctypes.c_int, dp, dp, dp]),
+            "qsim_compare": (ctypes.c_int, [vp, vp, ctypes.c_int, dp, dp]),
+            "qsim_sync": (ctypes.c_int, [vp]),
+            "qsim_last_error": (ctypes.c_char_p, []),
+            "qsim_op_timings": (ctypes.c_int, [vp, i32p, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_float),
+                                               ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+            "qsim_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_int,
+                                             ctypes.POINTER(RunOpts), i32p, i32p, i32p, i32p, i32p,
+                                             ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise QsimError(status, lib().qsim_last_error().decode())
+
+
+def _i32(seq) -> ctypes.Array:
+    seq = list(seq)
+    return (ctypes.c_int32 * max(1, len(seq)))(*seq)
+
+
+def gate_array(gates: Sequence) -> tuple:
+    """Marshal gates (objects with .name, .qubits and .mat, or tuples
+    (name, qubits[, mat or theta])) into a qsim_gate array. Returns the array
+    and the list of numpy buffers it points into (keep it alive)."""
+    arr = (Gate * max(1, len(gates)))()
+    keep = []
+    for i, g in enumerate(gates):
+        if isinstance(g, tuple):
+            name, qubits = g[0], tuple(g[1])
+            extra = g[2] if len(g) > 2 else None
+        else:
+            name, qubits, extra = g.name, tuple(g.qubits), getattr(g, "mat", None)
+        arr[i].kind = GATE_KIND[name]
+        arr[i].k = len(qubits)
+        for j, q in enumerate(qubits):
+            arr[i].qubits[j] = int(q)
+        if name == "U":
+            m = np.ascontiguousarray(extra, dtype=np.complex128)
+            if m.shape != (2 ** len(qubits), 2 ** len(qubits)):
+                raise ValueError("dense gate matrix must be 2^k x 2^k")
+            keep.append(m)
+            arr[i].mat = m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        elif name == "PHASE":
+            arr[i].theta = float(extra)
+    return arr, keep
+
+
+def run_opts(kmax=5, scheduler="greedy", fuse_diag=False, skip_trailing_diag=False,
+             skip_initial_h=False, record_timings=False) -> RunOpts:
+    o = RunOpts()
+    o.kmax = kmax
+    o.scheduler = SCHEDULERS[scheduler] if isinstance(scheduler, str) else int(scheduler)
+    o.fuse_diag = int(fuse_diag)
+    o.skip_trailing_diag = int(skip_trailing_diag)
+    o.skip_initial_h = int(skip_initial_h)
+    o.record_timings = int(record_timings)
+    return o
+
+
+def schedule(n: int, gates: Sequence, **opts) -> dict:
+    """Host-only: the schedule the library would run (no GPU needed)."""
+    arr, keep = gate_array(gates)
+    o = run_opts(**opts)
+    ng = len(gates)
+    cap = max(1, ng)
+    gate_op = (ctypes.c_int32 * max(1, ng))()
+    gate_role = (ctypes.c_int32 * max(1, ng))()
+    op_kind = (ctypes.c_int32 * cap)()
+    op_k = (ctypes.c_int32 * cap)()
+    op_q = (ctypes.c_int32 * (6 * cap))()
+    nops = ctypes.c_int()
+    _check(lib().qsim_schedule(n, arr, ng, ctypes.byref(o), gate_op, gate_role, op_kind, op_k, op_q,
+                               cap, ctypes.byref(nops)))
+    m = nops.value
+    return dict(gate_op=list(gate_op)[:ng], gate_role=list(gate_role)[:ng], op_kind=list(op_kind)[:m],
+                op_k=list(op_k)[:m], op_qubits=[list(op_q[6 * o_:6 * o_ + 6]) for o_ in range(m)])
+
+
+def workspace_bytes(n: int, dtype: int, kmax: int = 6) -> int:
+    return int(lib().qsim_workspace_bytes(n, dtype, kmax))
+
+
+class State:
+    """An n-qubit state vector in HBM (torch complex64 / complex128 tensor)."""
+
+    def __init__(self, n: int, dtype: str = "c64", init: str = "zero", kmax: int = 6,
+                 amps=None, stream=None, device: int = 0):
+        import torch
+        self.n = n
+        self.dt = C64 if dtype in ("c64", "complex64") else C128
+        tdt = torch.complex64 if self.dt == C64 else torch.complex128
+        dev = torch.device("cuda", device)
+        self.amps = amps if amps is not None else torch.empty(2 ** n, dtype=tdt, device=dev)
+        if self.amps.dtype != tdt or self.amps.numel() != 2 ** n or not self.amps.is_contiguous():
+            raise ValueError("amps must be a contiguous %s tensor of 2^n elements" % tdt)
+        self.workspace = torch.empty(workspace_bytes(n, self.dt, kmax), dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        initc = {"zero": INIT_ZERO, "uniform": INIT_UNIFORM, "keep": INIT_KEEP}[init]
+        _check(lib().qsim_create(n, self.dt, ctypes.c_void_p(self.amps.data_ptr()),
+                                 self.amps.numel() * self.amps.element_size(),
+                                 ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                 ctypes.c_void_p(self.stream.cuda_stream), initc, ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.qsim_destroy(h)
+            self.h = None
+
+    # -- state I/O (torch copies; no simulation arithmetic)
+    def set_amps(self, values):
+        import torch
+        t = torch.as_tensor(values).to(self.amps.dtype)
+        self.amps.copy_(t.to(self.amps.device))
+
+    def to_numpy(self) -> np.ndarray:
+        self.sync()
+        return self.amps.cpu().numpy()
+
+    def init(self, init: str = "zero"):
+        _check(lib().qsim_init_state(self.h, {"zero": INIT_ZERO, "uniform": INIT_UNIFORM}[init]))
+
+    # -- operations
+    def apply_cluster(self, qubits: Sequence[int], mat: np.ndarray):
+        m = np.ascontiguousarray(mat, dtype=np.complex128)
+        _check(lib().qsim_apply_cluster(self.h, len(qubits), _i32(qubits),
+                                        m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def apply_diag(self, pairs: Iterable = (), phases: Iterable = ()):
+        pairs = list(pairs)
+        phases = list(phases)
+        flat = [q for p in pairs for q in p]
+        th = (ctypes.c_double * max(1, len(phases)))(*[float(t) for _, t in phases])
+        _check(lib().qsim_apply_diag(self.h, len(pairs), _i32(flat), len(phases),
+                                     _i32([q for q, _ in phases]), th))
+
+    def apply_gate(self, gate):
+        arr, keep = gate_array([gate])
+        _check(lib().qsim_apply_gate(self.h, arr))
+
+    def run_circuit(self, gates: Sequence, **opts) -> dict:
+        arr, keep = gate_array(gates)
+        o = run_opts(**opts)
+        st = RunStats()
+        _check(lib().qsim_run_circuit(self.h, arr, len(gates), ctypes.byref(o), ctypes.byref(st)))
+        return st.as_dict()
+
+    def probs(self, out=None):
+        """(norm, sum p^2, entropy in nats); fills `out` (float32 or float64
+        tensor of 2^n) with p_i when given."""
+        import torch
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        ptr, odt = None, C64
+        if out is not None:
+            if out.numel() != 2 ** self.n or out.dtype not in (torch.float32, torch.float64):
+                raise ValueError("out must hold 2^n float32 or float64")
+            ptr, odt = ctypes.c_void_p(out.data_ptr()), (C64 if out.dtype == torch.float32 else C128)
+        _check(lib().qsim_probs(self.h, ptr, odt, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def compare(self, ref) -> tuple:
+        """(fidelity, max |psi - ref|) against a device tensor, in float64 on the GPU."""
+        import torch
+        dt = C64 if ref.dtype == torch.complex64 else C128
+        if ref.numel() != 2 ** self.n or not ref.is_contiguous() or not ref.is_cuda:
+            raise ValueError("ref must be a contiguous device tensor of 2^n amplitudes")
+        f, m = ctypes.c_double(), ctypes.c_double()
+        _check(lib().qsim_compare(self.h, ctypes.c_void_p(ref.data_ptr()), dt, ctypes.byref(f),
+                                  ctypes.byref(m)))
+        return f.value, m.value
+
+    def op_timings(self) -> list:
+        """Per-launch records of the last run with record_timings=True:
+        dicts with kind, k, qubits, epi and ms (HIP events on the state's stream)."""
+        n = ctypes.c_int()
+        L = lib()
+        L.qsim_op_timings(self.h, None, None, None, None, None, 0, ctypes.byref(n))  # count only
+        m = n.value
+        if m == 0:
+            return []
+        kind, k, epi = (ctypes.c_int32 * m)(), (ctypes.c_int32 * m)(), (ctypes.c_int32 * m)()
+        qs, ms = (ctypes.c_int32 * (6 * m))(), (ctypes.c_float * m)()
+        _check(L.qsim_op_timings(self.h, kind, k, qs, epi, ms, m, ctypes.byref(n)))
+        kinds = {0: "cluster", 1: "diag", 2: "gate1q", 3: "phase1q", 4: "cz", 5: "build"}
+        return [dict(kind=kinds[kind[i]], k=k[i], qubits=[q for q in qs[6 * i:6 * i + 6] if q >= 0],
+                     epi=bool(epi[i]), ms=float(ms[i])) for i in range(m)]
+
+    def sync(self):
+        _check(lib().qsim_sync(self.h))

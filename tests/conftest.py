@@ -24,3 +24,14 @@ def read_golden(name):
             if line and not line.startswith("#"):
                 rows.append(line.split())
     return rows
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Print and flush the case name before each GPU test, so a run that dies
+    on the device still names the case it was running."""
+    if request.node.get_closest_marker("gpu") is not None:
+        tr = request.config.pluginmanager.get_plugin("terminalreporter")
+        if tr is not None:
+            tr.write_line("[gpu case] %s" % request.node.nodeid, flush=True)
+    yield

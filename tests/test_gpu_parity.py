@@ -1,0 +1,358 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every case builds the same seeded input for both sides, runs the GPU
+library and the oracle, and compares element by element.
+
+Tolerances:
+  * float64 states: max |d amp| <= 1e-12 for whole circuits (the target the
+    project sets for the float64 path); single kernels use the bound below
+    with u = 2^-53;
+  * float32 states: one k-qubit cluster computes each output as a dot product
+    of 2^(k+1) real terms, so |error| <= (2^(k+1) + 2) u sum_j |A_ij||b_j| <=
+    (2^(k+1) + 2) u sqrt(2^k) max|amp| with u = 2^-24 (rows of the real-split
+    unitary have unit norm); tests allow twice that. Whole circuits are held to
+    fidelity >= 1 - 1e-6 and report max |d amp|.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1704_01127_amd import qsim
+from supremacy_inputs import (Circuit, Gate, blocked_circuit, drop_trailing_cz_layer, haar_unitary,
+                              mirror_circuit, random_state, supremacy_circuit)
+
+pytestmark = pytest.mark.gpu
+
+U32, U64 = 2.0 ** -24, 2.0 ** -53
+
+
+def kernel_tol(dt, k, scale):
+    u = U32 if dt == "c64" else U64
+    return 2 * (2 ** (k + 1) + 2) * u * math.sqrt(2 ** k) * scale
+
+
+def make_state(n, dt, psi=None, init="zero"):
+    s = qsim.State(n, dt, init=init if psi is None else "keep")
+    if psi is not None:
+        s.set_amps(torch.from_numpy(psi))
+    return s
+
+
+def fidelity(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return abs(np.vdot(b, a)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
+
+
+# ------------------------------------------------------------------ init
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("n", [1, 5, 20])
+def test_init(dt, n):
+    z = make_state(n, dt).to_numpy()
+    ref = np.zeros(2 ** n)
+    ref[0] = 1
+    assert np.array_equal(z, ref)
+    u = make_state(n, dt, init="uniform").to_numpy()
+    assert np.max(np.abs(u - 2.0 ** (-n / 2))) <= (1e-7 if dt == "c64" else 1e-16) * 2.0 ** (-n / 2)
+
+
+# ------------------------------------------------------------------ one cluster
+def target_sets(n, k, seed):
+    rng = np.random.default_rng(seed)
+    sets = {"low": list(range(k)), "high": list(range(n - k, n))}
+    mixed = sorted(set([0, n - 1]) | set(int(q) for q in rng.choice(range(1, n - 1), k - 2, replace=False))) \
+        if k >= 2 and n >= k + 1 else list(range(k))
+    sets["mixed"] = mixed[:k] if len(mixed) >= k else list(range(k))
+    sets["nolow"] = sorted(int(q) for q in rng.choice(range(1, n), k, replace=False)) if n > k else list(range(k))
+    return sets
+
+
+CLUSTER_CASES = []
+for _k in range(1, 7):
+    for _n in sorted({_k, _k + 1, _k + 3, 12, _k + 8}):
+        if _n >= _k:
+            for _pat in ("low", "high", "mixed", "nolow"):
+                CLUSTER_CASES.append((_k, _n, _pat))
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("k,n,pat", CLUSTER_CASES)
+def test_apply_cluster(dt, k, n, pat):
+    qs = target_sets(n, k, 1000 * k + n)[pat]
+    rng = np.random.default_rng(k * 7 + n)
+    order = list(rng.permutation(qs))  # the ABI takes the qubits in any order
+    u = haar_unitary(k, 31 * k + n)
+    psi = random_state(n, 17 * n + k)
+    ref = oracle.apply_dense(psi.copy(), order, u)
+    s = make_state(n, dt, psi)
+    s.apply_cluster(order, u)
+    got = s.to_numpy()
+    err = np.max(np.abs(got - ref))
+    assert err <= kernel_tol(dt, k, np.max(np.abs(ref))), (err, order)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_apply_cluster_twice_large(dt):
+    """Several tiles per wave and a grid that does not divide the tile count."""
+    n = 21
+    for k, qs in ((5, [20, 0, 7, 13, 3]), (4, [1, 2, 19, 9]), (6, [2, 3, 4, 10, 15, 20]), (3, [0, 1, 2])):
+        u = haar_unitary(k, k)
+        psi = random_state(n, k)
+        ref = oracle.apply_dense(psi.copy(), qs, u)
+        s = make_state(n, dt, psi)
+        s.apply_cluster(qs, u)
+        got = s.to_numpy()
+        assert np.max(np.abs(got - ref)) <= kernel_tol(dt, k, np.max(np.abs(ref)))
+
+
+# ------------------------------------------------------------------ diagonal layer
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("n", [1, 2, 3, 9, 16])
+def test_apply_diag(dt, n):
+    rng = np.random.default_rng(n)
+    pairs = []
+    if n >= 2:
+        perm = list(rng.permutation(n))
+        pairs = [(int(perm[2 * i]), int(perm[2 * i + 1])) for i in range(n // 2)]
+        pairs.append((0, n - 1))
+        if n >= 3:
+            pairs.append((1, 2))
+    phases = [(int(q), float(rng.uniform(-np.pi, np.pi))) for q in rng.choice(n, min(n, 5), replace=False)]
+    phases.append((0, np.pi / 4))
+    psi = random_state(n, n + 5)
+    ref = psi.copy()
+    for a, b in pairs:
+        oracle.apply_named(ref, "CZ", a, b)
+    for q, th in phases:
+        oracle.apply_dense(ref, (q,), np.diag([1.0, np.exp(1j * th)]))
+    s = make_state(n, dt, psi)
+    s.apply_diag(pairs, phases)
+    got = s.to_numpy()
+    assert np.max(np.abs(got - ref)) <= (8 * U32 if dt == "c64" else 8 * U64) * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------------ per-gate kernels
+NAMED = ["H", "T", "SX", "SY", "X", "Y", "Z", "TDG", "SXDG", "SYDG"]
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("name", NAMED + ["CZ", "U"])
+def test_apply_gate(dt, name):
+    n = 11
+    psi = random_state(n, 3)
+    ref = psi.copy()
+    s = make_state(n, dt, psi)
+    if name == "CZ":
+        targets = [(0, 1), (n - 1, 0), (4, 9), (n - 2, n - 1)]
+    elif name == "U":
+        targets = [(3, 0), (n - 1, 5, 2)]
+    else:
+        targets = [(0,), (5,), (n - 1,)]
+    for t in targets:
+        if name == "U":
+            u = haar_unitary(len(t), len(t))
+            s.apply_gate(("U", t, u))
+            oracle.apply_dense(ref, t, u)
+        else:
+            s.apply_gate((name, t))
+            oracle.apply_named(ref, name, t[0], t[1] if len(t) > 1 else -1)
+    got = s.to_numpy()
+    assert np.max(np.abs(got - ref)) <= kernel_tol(dt, 3, 1.0) * len(targets)
+
+
+def test_phase_gate():
+    n = 6
+    psi = random_state(n, 4)
+    s = make_state(n, "c128", psi)
+    s.apply_gate(("PHASE", (2,), 0.3))
+    ref = oracle.apply_dense(psi.copy(), (2,), np.diag([1, np.exp(0.3j)]))
+    assert np.max(np.abs(s.to_numpy() - ref)) <= 1e-15
+
+
+# ------------------------------------------------------------------ whole circuits
+RUN_CASES = [
+    dict(scheduler="per_gate"),
+    dict(scheduler="greedy", kmax=1),
+    dict(scheduler="greedy", kmax=2),
+    dict(scheduler="greedy", kmax=3),
+    dict(scheduler="greedy", kmax=4),
+    dict(scheduler="greedy", kmax=5),
+    dict(scheduler="greedy", kmax=6),
+    dict(scheduler="greedy", kmax=3, fuse_diag=True),
+    dict(scheduler="greedy", kmax=4, fuse_diag=True),
+    dict(scheduler="greedy", kmax=5, fuse_diag=True),
+    dict(scheduler="greedy", kmax=6, fuse_diag=True),
+    dict(scheduler="greedy", kmax=5, fuse_diag=True, skip_initial_h=True),
+]
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("case", range(len(RUN_CASES)))
+def test_run_circuit_16q(dt, case):
+    opts = RUN_CASES[case]
+    circ = supremacy_circuit(4, 4, 20, seed=case)
+    ref = oracle.run(circ)
+    s = make_state(circ.n, dt)
+    st = s.run_circuit(circ.gates, **opts)
+    got = s.to_numpy()
+    if dt == "c128":
+        assert np.max(np.abs(got - ref)) <= 1e-12
+    else:
+        assert fidelity(got, ref) >= 1 - 1e-6
+        assert np.max(np.abs(got - ref)) <= 1e-5
+    assert st["n_gates_applied"] <= len(circ.gates)
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_skip_trailing_diag_keeps_probabilities(dt):
+    circ = supremacy_circuit(4, 4, 18, seed=5)
+    ref = oracle.run(circ)
+    s = make_state(circ.n, dt)
+    st = s.run_circuit(circ.gates, kmax=4, fuse_diag=True, skip_trailing_diag=True)
+    got = s.to_numpy()
+    assert st["n_gates_applied"] < len(circ.gates)
+    tol = 1e-14 if dt == "c128" else 1e-6
+    assert np.max(np.abs(np.abs(got) ** 2 - np.abs(ref) ** 2)) <= tol * np.max(np.abs(ref) ** 2) * 10
+
+
+def test_dense_gates_in_circuit():
+    from supremacy_inputs import with_haar_layers
+    circ = with_haar_layers(supremacy_circuit(3, 4, 20, 0), 8, 5, 3)
+    ref = oracle.run(circ)
+    for dt in ("c64", "c128"):
+        for opts in (dict(scheduler="per_gate"), dict(kmax=3), dict(kmax=6, fuse_diag=True)):
+            s = make_state(circ.n, dt)
+            s.run_circuit(circ.gates, **opts)
+            got = s.to_numpy()
+            if dt == "c128":
+                assert np.max(np.abs(got - ref)) <= 1e-12
+            else:
+                assert fidelity(got, ref) >= 1 - 1e-6
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_20q_depth25_per_gate_float64(seed):
+    """4x5 grid, depth 25, complex128, one gate at a time: max |d amp| <= 1e-12."""
+    circ = supremacy_circuit(4, 5, 25, seed)
+    ref = oracle.run(circ)
+    s = make_state(20, "c128")
+    s.run_circuit(circ.gates, scheduler="per_gate")
+    got = s.to_numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-12
+    # the same through the fused float64 and float32 forms
+    s2 = make_state(20, "c128")
+    s2.run_circuit(circ.gates, kmax=5, fuse_diag=True)
+    assert np.max(np.abs(s2.to_numpy() - ref)) <= 1e-12
+    s3 = make_state(20, "c64")
+    s3.run_circuit(circ.gates, kmax=5, fuse_diag=True)
+    g3 = s3.to_numpy()
+    assert fidelity(g3, ref) >= 1 - 1e-6
+
+
+# ------------------------------------------------------------------ reductions
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_probs_and_compare(dt):
+    circ = supremacy_circuit(4, 5, 25, 7)
+    ref = oracle.run(circ)
+    norm_o, s2_o, ent_o = oracle.stats(ref)
+    s = make_state(20, dt)
+    s.run_circuit(circ.gates, kmax=5, fuse_diag=True)
+    out = torch.empty(2 ** 20, dtype=torch.float64 if dt == "c128" else torch.float32, device="cuda")
+    norm, s2, ent = s.probs(out)
+    tol = 1e-12 if dt == "c128" else 1e-5
+    assert abs(norm - norm_o) <= tol and abs(ent - ent_o) <= tol * 20 and abs(s2 - s2_o) <= tol * s2_o
+    p = out.cpu().numpy()
+    assert np.max(np.abs(p - np.abs(ref) ** 2)) <= (1e-15 if dt == "c128" else 1e-6 * np.max(np.abs(ref) ** 2))
+    refd = torch.from_numpy(ref).cuda()
+    f, md = s.compare(refd)
+    got = s.to_numpy()
+    assert abs(f - fidelity(got, ref)) <= 1e-12
+    assert abs(md - np.max(np.abs(got - ref))) <= 1e-12
+    if dt == "c128":
+        assert md <= 1e-12 and abs(f - 1) <= 1e-12
+
+
+# ------------------------------------------------------------------ larger states
+def test_22q_full_circuit_float32():
+    """4x6 grid minus two sites (22 qubits), depth 25, float32 fused vs oracle."""
+    circ = supremacy_circuit(4, 6, 25, 11, drop=[(3, 5), (3, 4)])
+    assert circ.n == 22
+    ref = oracle.run(circ)
+    for opts in (dict(kmax=5, fuse_diag=True), dict(kmax=4), dict(kmax=6, fuse_diag=True)):
+        s = make_state(22, "c64")
+        s.run_circuit(circ.gates, **opts)
+        got = s.to_numpy()
+        assert fidelity(got, ref) >= 1 - 1e-6, opts
+
+
+def _blocked_30q():
+    groups = [[0, 5, 10, 15, 20, 25], [1, 6, 11, 16, 21, 26], [2, 7, 12, 17, 22, 27],
+              [3, 8, 13, 18, 23, 28], [4, 9, 14, 19, 24, 29]]
+    return blocked_circuit(30, groups, 20, seed=3), groups
+
+
+def _product_amplitudes(circ, groups, idx):
+    amps = np.ones(len(idx), np.complex128)
+    for gi, grp in enumerate(groups):
+        sub = Circuit(len(grp), [Gate(g.name, tuple(grp.index(q) for q in g.qubits), g.mat)
+                                 for g in circ.gates if set(g.qubits) <= set(grp)])
+        psi = oracle.run(sub)
+        loc = np.zeros(len(idx), np.int64)
+        for j, q in enumerate(grp):
+            loc |= ((idx >> q) & 1) << j
+        amps *= psi[loc]
+    return amps
+
+
+@pytest.mark.parametrize("dt,opts", [("c64", dict(kmax=5, fuse_diag=True)), ("c64", dict(kmax=6)),
+                                     ("c128", dict(kmax=5, fuse_diag=True)), ("c128", dict(scheduler="per_gate"))])
+def test_30q_product_state_sampled(dt, opts):
+    """30 qubits in five independent 6-qubit groups interleaved across all
+    bit positions: every amplitude is a product of group amplitudes, which
+    the oracle computes exactly; 65536 sampled indices are compared."""
+    circ, groups = _blocked_30q()
+    s = make_state(30, dt)
+    s.run_circuit(circ.gates, **opts)
+    s.sync()
+    rng = np.random.default_rng(0)
+    idx = np.concatenate([rng.integers(0, 2 ** 30, 65536 - 2), [0, 2 ** 30 - 1]]).astype(np.int64)
+    ref = _product_amplitudes(circ, groups, idx)
+    got = s.amps[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.complex128)
+    scale = np.max(np.abs(ref))
+    err = np.max(np.abs(got - ref))
+    assert err <= (1e-12 if dt == "c128" else 2e-5 * scale), err
+    norm, _, _ = s.probs()
+    assert abs(norm - 1) <= (1e-12 if dt == "c128" else 1e-5)
+    del s
+    torch.cuda.empty_cache()
+
+
+def test_30q_depth25_mirror_float32():
+    """5x6 grid, depth 25, followed by its inverse: the float32 fused run must
+    return to |0...0> (the workload the benchmark times)."""
+    circ = supremacy_circuit(5, 6, 25, 0)
+    s = make_state(30, "c64")
+    s.run_circuit(mirror_circuit(circ).gates, kmax=5, fuse_diag=True)
+    a0 = s.amps[0].item()
+    assert abs(a0) ** 2 >= 1 - 1e-6
+    norm, _, _ = s.probs()
+    assert abs(norm - 1) <= 1e-5
+    del s
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ errors
+def test_argument_errors():
+    s = make_state(6, "c64")
+    with pytest.raises(qsim.QsimError, match="INVALID"):
+        s.apply_cluster([0, 6], np.eye(4))
+    with pytest.raises(qsim.QsimError, match="INVALID"):
+        s.apply_cluster([1, 1], np.eye(4))
+    with pytest.raises(qsim.QsimError, match="UNSUPPORTED"):
+        s.apply_cluster(list(range(7)), np.eye(128)) if False else s.run_circuit([("H", (0,))], kmax=7)
+    with pytest.raises(qsim.QsimError, match="INVALID"):
+        s.apply_diag([(2, 2)])
+    s.sync()

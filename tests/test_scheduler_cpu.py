@@ -1,0 +1,143 @@
+"""Host-only checks of the clustering scheduler (Sec. 3.6.1, step 2).
+
+Any schedule that respects the per-qubit gate order is exact, so validity is
+checked structurally here; the GPU tests check the states it produces against
+the oracle. Table 1's cluster counts are a soft quality target."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1704_01127_amd import qsim
+from supremacy_inputs import (Circuit, Gate, drop_trailing_cz_layer, haar_unitary,
+                              supremacy_circuit, with_haar_layers)
+
+from conftest import read_golden
+
+DIAG = {"T", "TDG", "Z", "CZ", "PHASE"}
+
+
+def check_schedule(circ, sch, kmax, skip_trailing=False, skip_initial_h=False):
+    gates = circ.gates
+    gop, role = sch["gate_op"], sch["gate_role"]
+    n_ops = len(sch["op_kind"])
+    # every kept gate is applied exactly once; dropped gates are the allowed ones
+    for i, g in enumerate(gates):
+        if gop[i] < 0:
+            later_dense = any(h.name not in DIAG and set(h.qubits) & set(g.qubits) for h in gates[i + 1:])
+            first_h = g.name == "H" and all(set(h.qubits).isdisjoint(g.qubits) for h in gates[:i])
+            assert (skip_trailing and g.name in DIAG and not later_dense) or (skip_initial_h and first_h), i
+        else:
+            assert 0 <= gop[i] < n_ops
+    for o in range(n_ops):
+        kind, k, qs = sch["op_kind"][o], sch["op_k"][o], [q for q in sch["op_qubits"][o] if q >= 0]
+        members = [i for i in range(len(gates)) if gop[i] == o]
+        assert members
+        if kind == 0:
+            assert len(qs) == k and qs == sorted(qs) and k <= max(kmax, 6)
+            for i in members:
+                if role[i] == 0:
+                    assert set(gates[i].qubits) <= set(qs)
+                else:
+                    assert role[i] == 1 and gates[i].name in DIAG
+        elif kind == 1:
+            assert all(gates[i].name in DIAG for i in members)
+    # order: gates sharing a qubit keep their order (op index, then member before epilogue)
+    last = {}
+    for i, g in enumerate(gates):
+        if gop[i] < 0:
+            continue
+        key = (gop[i], role[i])
+        for q in g.qubits:
+            if q in last:
+                pk, pdiag = last[q]
+                if key[0] == pk[0]:
+                    assert key[1] >= pk[1], (i, q)
+                else:
+                    assert key[0] > pk[0], (i, q)
+            last[q] = (key, g.name in DIAG)
+
+
+@pytest.mark.parametrize("kmax", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("fuse", [False, True])
+def test_supremacy_schedule_valid(kmax, fuse):
+    circ = supremacy_circuit(5, 6, 25, seed=kmax)
+    sch = qsim.schedule(circ.n, circ.gates, kmax=kmax, fuse_diag=fuse)
+    check_schedule(circ, sch, kmax)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_circuit_schedule_valid(seed):
+    rng = np.random.default_rng(seed)
+    n = 9
+    names = ["H", "T", "SX", "SY", "X", "Z", "TDG"]
+    gates = []
+    for i in range(120):
+        r = rng.random()
+        if r < 0.5:
+            gates.append(Gate(names[rng.integers(len(names))], (int(rng.integers(n)),)))
+        elif r < 0.9:
+            a, b = rng.choice(n, 2, replace=False)
+            gates.append(Gate("CZ", (int(a), int(b))))
+        else:
+            k = int(rng.integers(1, 5))
+            gates.append(Gate("U", tuple(int(q) for q in rng.choice(n, k, replace=False)), haar_unitary(k, i)))
+    circ = Circuit(n, gates)
+    for kmax in (2, 4, 6):
+        for fuse in (False, True):
+            for st in (False, True):
+                sch = qsim.schedule(n, gates, kmax=kmax, fuse_diag=fuse, skip_trailing_diag=st,
+                                    skip_initial_h=st)
+                check_schedule(circ, sch, kmax, skip_trailing=st, skip_initial_h=st)
+
+
+def test_skip_options():
+    circ = supremacy_circuit(4, 5, 25, seed=0)
+    sch = qsim.schedule(circ.n, circ.gates, kmax=4, skip_trailing_diag=True, skip_initial_h=True)
+    dropped = [i for i, o in enumerate(sch["gate_op"]) if o < 0]
+    n_h = sum(1 for g in circ.gates if g.cycle == 0)
+    last = max(g.cycle for g in circ.gates)
+    n_final_cz = sum(1 for g in circ.gates if g.cycle == last and g.name == "CZ")
+    # the leading H layer and at least the final CZ layer are dropped
+    assert len(dropped) >= n_h + n_final_cz
+    check_schedule(circ, sch, 4, skip_trailing=True, skip_initial_h=True)
+
+
+def test_per_gate_schedule_is_one_op_per_gate():
+    circ = supremacy_circuit(4, 5, 25, seed=0)
+    sch = qsim.schedule(circ.n, circ.gates, scheduler="per_gate")
+    assert len(sch["op_kind"]) == len(circ.gates)
+    assert set(sch["op_kind"]) == {2}
+
+
+def test_table1_cluster_counts_and_time():
+    """Table 1: clusters for k_max = 3/4/5 on depth-25 circuits without the
+    final CZ layer, in under 3 s (the paper's Python scheduler). Soft target:
+    each count within 20% above the printed one, the sum no larger."""
+    rows = read_golden("table1_counts.txt")
+    for R, C, n, gates, c3, c4, c5 in rows[:2]:
+        circ = drop_trailing_cz_layer(supremacy_circuit(int(R), int(C), 25, seed=0))
+        assert len(circ.gates) == int(gates)
+        ours = []
+        for kmax, ref in ((3, int(c3)), (4, int(c4)), (5, int(c5))):
+            t = time.time()
+            sch = qsim.schedule(circ.n, circ.gates, kmax=kmax)
+            assert time.time() - t < 3.0
+            ours.append(len(sch["op_kind"]))
+            assert ours[-1] <= 1.2 * ref, (R, C, kmax, ours[-1], ref)
+        assert sum(ours) <= int(c3) + int(c4) + int(c5)
+
+
+def test_diag_fusion_reduces_passes():
+    circ = drop_trailing_cz_layer(supremacy_circuit(6, 5, 25, seed=0))
+    for kmax in (3, 4, 5):
+        a = len(qsim.schedule(circ.n, circ.gates, kmax=kmax)["op_kind"])
+        b = len(qsim.schedule(circ.n, circ.gates, kmax=kmax, fuse_diag=True)["op_kind"])
+        assert b < a
+
+
+def test_dense_gate_wider_than_kmax():
+    circ = with_haar_layers(supremacy_circuit(4, 5, 17, 0), 8, 5, 1)
+    sch = qsim.schedule(circ.n, circ.gates, kmax=3)
+    check_schedule(circ, sch, 3)
+    assert 5 in sch["op_k"]
