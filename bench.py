@@ -35,6 +35,16 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def kernel_name(rec) -> str:
+    """Name (as rocprofv3 reports it) of the float cluster kernel a launch used."""
+    k, lowt = rec["k"], rec["qubits"][0] == 0
+    if not rec.get("mfma"):
+        return "k_cluster_valu<float, %d>" % k
+    if rec.get("staged"):
+        return "k_cluster_f32_stage<%d, 6, %s>" % (k, "true" if lowt else "false")
+    return "k_cluster_f32_mfma<%d, %d, %s>" % (k, 1 if k == 6 else 2, "true" if lowt else "false")
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,27 +180,24 @@ def main():
         total_ms = sum(r["ms"] for r in recs)
         groups = {}
         for r in clusters:
-            key = (r["k"], r["qubits"][0] == 0)
-            groups.setdefault(key, []).append(r["ms"])
-        dom = max(groups.items(), key=lambda kv: sum(kv[1]))
-        (k, lowt), times = dom
+            groups.setdefault(kernel_name(r), []).append(r["ms"])
+        kname, times = max(groups.items(), key=lambda kv: sum(kv[1]))
         bytes_per_launch = 2 * 2 ** n * amp_bytes
         avg_ms = sum(times) / len(times)
         ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        nb = 1 if k == 6 else 2
         traffic = None
         tpath = os.path.join(ROOT, "profiles", "traffic_cluster_f32_30q.json")
         if os.path.exists(tpath):
             with open(tpath) as f:
                 t = json.load(f)
-            if t.get("kernel_source_sha") == kernel_source_hash() and str(k) in t.get("bytes_per_launch", {}):
-                traffic = t["bytes_per_launch"][str(k)]
+            if t.get("kernel_source_sha") == kernel_source_hash() and kname in t.get("kernels", {}):
+                traffic = round(t["kernels"][kname]["bytes_per_launch"])
         out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
-                           "kernel": "k_cluster_f32_mfma<%d, %d, %s>" % (k, nb, "true" if lowt else "false")
-                           if k >= 4 else "k_cluster_valu<float, %d>" % k,
+                           "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                            "launches": len(times), "avg_ms": round(avg_ms, 4),
-                           "algorithmic_bytes_per_launch": bytes_per_launch}
+                           "algorithmic_bytes_per_launch": bytes_per_launch,
+                           "kernel_groups": {k: {"launches": len(v), "avg_ms": round(sum(v) / len(v), 4)}
+                                             for k, v in groups.items()}}
         csum = sum(r["ms"] for r in clusters)
         cbytes = len(clusters) * 2 * 2 ** n * amp_bytes
         cflops = sum(2 ** n * (8 * 2 ** r["k"] - 2) for r in clusters)

@@ -190,11 +190,27 @@ const char* qsim_last_error(void);
  * order: op_kind (0 cluster, 1 diagonal pass, 2 single-qubit gate, 3
  * single-qubit phase, 4 CZ, 5 cluster-matrix build), op_k (cluster size;
  * number of matrices for a build), op_qubits[6*i ..] (sorted targets of a
- * cluster, -1 padded), op_epi (1 if the cluster applies diagonal gates while
- * storing) and ms (milliseconds). Arrays of cap entries (any may be NULL);
+ * cluster, -1 padded), op_epi (flags of a cluster: bit 0 = applies diagonal
+ * gates while storing, bit 1 = LDS-staged kernel variant, bit 2 = matrix-core
+ * kernel) and ms (milliseconds). Arrays of cap entries (any may be NULL);
  * *n_ops receives the count. Synchronises the stream. */
 qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32_t* op_qubits,
                             int32_t* op_epi, float* ms, int cap, int* n_ops);
+
+/* Process-wide tuning (the autotuner's controls).
+ * The matrix-core cluster kernels exist in two variants: 0 gathers each
+ * lane's amplitudes straight from HBM into registers, 1 moves the wave's tile
+ * as linear runs and re-orders it through LDS. The variant is looked up per
+ * (dtype, k, class of the lowest target qubit: 0 | 1-2 | 3-5 | >= 6) in a
+ * tune table, which qsim_set_tune_entry overwrites (the autotuner fills it
+ * from measurements). QSIM_OPT_CLUSTER_VARIANT = 0 or 1 forces one variant
+ * everywhere, -1 (default) uses the table. Errors: QSIM_E_INVALID for an
+ * unknown option or an out-of-range value. */
+typedef enum { QSIM_OPT_CLUSTER_VARIANT = 1 } qsim_option;
+qsim_status qsim_set_option(int option, int value);
+int qsim_get_option(int option);
+qsim_status qsim_set_tune_entry(qsim_dtype dt, int k, int low_class, int variant);
+int qsim_get_tune_entry(qsim_dtype dt, int k, int low_class);
 
 /* Host-only: the schedule qsim_run_circuit would use (no GPU work). For each
  * gate: gate_op[g] = index of the op applying it (-1 if skipped) and

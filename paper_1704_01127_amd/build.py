@@ -55,6 +55,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))
     os.replace(tmp, LIB)
+    # measurement tool: streaming-bandwidth probe and traffic-counter calibration kernel
+    probe = os.path.join(HERE, "stream_probe")
+    cmd = [hipcc(), os.path.join(CSRC, "stream_probe.hip"), "-o", probe + ".tmp"] + common_flags()
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for stream_probe.hip:\n%s\n%s" % (r.stdout, r.stderr))
+    os.replace(probe + ".tmp", probe)
     return LIB
 
 

@@ -52,11 +52,32 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+// ------------------------------------------------------------ kernel-variant policy
+namespace qsim {
+namespace {
+int g_cluster_variant = -1;
+// [dtype][k][lowest-target class]: the LDS-staged variant unless the lowest
+// target is above the column bits' first run (then a direct gather is coalesced)
+int g_tune[2][kMaxK + 1][kLowClasses] = {
+    {{1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}},
+    {{1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}}};
+}  // namespace
+void set_cluster_variant(int v) { g_cluster_variant = v; }
+int get_cluster_variant() { return g_cluster_variant; }
+void set_tune_entry(bool dbl, int k, int cls, int variant) { g_tune[dbl][k][cls] = variant; }
+int get_tune_entry(bool dbl, int k, int cls) { return g_tune[dbl][k][cls]; }
+int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
+    if (layout == LAYOUT_PLAIN || g.k > 5) return 0;
+    if (g_cluster_variant >= 0) return g_cluster_variant;
+    return g_tune[dbl][g.k][low_class(g.t[0])];
+}
+}  // namespace qsim
+
 struct OpRecord {
     int kind;  // 0 cluster, 1 diagonal pass, 2 1-qubit gate, 3 1-qubit phase, 4 CZ, 5 matrix build
     int k;
     int qubits[6];
-    int n_epi;
+    int flags;  // bit 0: diagonal epilogue, bit 1: LDS-staged kernel, bit 2: matrix-core kernel
     hipEvent_t ev0, ev1;
 };
 
@@ -190,10 +211,11 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
         OpRecord r;
         std::memset(&r, 0, sizeof(r));
         r.kind = it.kind;
+        const int variant = it.kind == 0 ? cluster_variant_for(s->dbl, it.geom, it.layout) : 0;
         if (it.kind == 0) {
             r.k = it.geom.k;
             for (int j = 0; j < it.geom.k; ++j) r.qubits[j] = it.geom.t[j];
-            if (it.epi >= 0) r.n_epi = 1;
+            r.flags = (it.epi >= 0 ? 1 : 0) | (variant == 1 ? 2 : 0) | (it.layout != LAYOUT_PLAIN ? 4 : 0);
         } else if (it.kind >= 2) {
             r.k = it.kind == 4 ? 2 : 1;
             r.qubits[0] = it.q0;
@@ -204,7 +226,7 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
         switch (it.kind) {
             case 0:
                 e = launch_cluster(s->psi, s->dbl, it.geom, mats + it.slot * sb, it.layout,
-                                   it.epi >= 0 ? epis + it.epi : nullptr, s->st);
+                                   it.epi >= 0 ? epis + it.epi : nullptr, variant, s->st);
                 break;
             case 1: e = launch_diag(s->psi, s->dbl, s->n, epis + it.epi, s->st); break;
             case 2: e = launch_gate1q(s->psi, s->dbl, s->n, it.q0, it.m, s->st); break;
@@ -638,6 +660,34 @@ qsim_status qsim_sync(qsim_state s) {
 
 const char* qsim_last_error(void) { return g_err.c_str(); }
 
+qsim_status qsim_set_option(int option, int value) {
+    if (option == QSIM_OPT_CLUSTER_VARIANT) {
+        if (value < -1 || value > 1) return fail(QSIM_E_INVALID, "cluster variant must be -1, 0 or 1");
+        set_cluster_variant(value);
+        return QSIM_OK;
+    }
+    return fail(QSIM_E_INVALID, "unknown option");
+}
+
+qsim_status qsim_set_tune_entry(qsim_dtype dt, int k, int low_class, int variant) {
+    if (dt != QSIM_C64 && dt != QSIM_C128) return fail(QSIM_E_INVALID, "unknown dtype");
+    if (k < 1 || k > kMaxK || low_class < 0 || low_class >= kLowClasses || variant < 0 || variant > 1)
+        return fail(QSIM_E_INVALID, "tune entry out of range");
+    set_tune_entry(dt == QSIM_C128, k, low_class, variant);
+    return QSIM_OK;
+}
+
+int qsim_get_tune_entry(qsim_dtype dt, int k, int low_class) {
+    if ((dt != QSIM_C64 && dt != QSIM_C128) || k < 1 || k > kMaxK || low_class < 0 || low_class >= kLowClasses)
+        return -1;
+    return get_tune_entry(dt == QSIM_C128, k, low_class);
+}
+
+int qsim_get_option(int option) {
+    if (option == QSIM_OPT_CLUSTER_VARIANT) return get_cluster_variant();
+    return -1;
+}
+
 qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32_t* op_qubits,
                             int32_t* op_epi, float* ms, int cap, int* n_ops) {
     if (qsim_status r = check_state(s)) return r;
@@ -650,7 +700,7 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
         if (op_k) op_k[i] = r.k;
         if (op_qubits)
             for (int j = 0; j < 6; ++j) op_qubits[6 * i + j] = (r.kind == 0 && j < r.k) ? r.qubits[j] : -1;
-        if (op_epi) op_epi[i] = r.n_epi;
+        if (op_epi) op_epi[i] = r.flags;
         if (ms) {
             float t = 0.f;
             HIP_TRY(hipEventElapsedTime(&t, r.ev0, r.ev1), "event time");

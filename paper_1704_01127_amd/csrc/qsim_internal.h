@@ -117,6 +117,20 @@ struct ClusterGeom {
     uint64_t ncols;     // 2^(n-k)
 };
 
+// Geometry of the LDS-staged cluster kernels. A wave tile is the set of
+// amplitudes whose "tile bits" (the k targets and the C lowest non-target
+// bits, the columns) vary while all other bits are fixed; tau is the index of
+// an amplitude inside its tile (the tile bits in ascending order). The tile is
+// read and written as linear runs of tau (coalesced) and re-ordered through LDS.
+struct StageGeom {
+    int32_t nt;          // tile bits (k + C)
+    int32_t tb[16];      // their state-bit positions, ascending
+    int32_t tpos[6];     // tau bit of target m
+    int32_t cpos[6];     // tau bit of column bit b
+    int32_t pad;
+    uint64_t ioff[32];   // state offset of linear chunk i (tau = i << lane_bits ...)
+};
+
 // Bytes of a cluster matrix in each layout.
 inline int64_t matrix_bytes(int k, int layout, bool dbl) {
     const int64_t d = int64_t(1) << k;
@@ -132,8 +146,20 @@ hipError_t launch_build(const BuildOp* ops, int n_ops, const BuildGate* gates, c
                         char* mat_base, hipStream_t st);
 // Variant of the cluster kernel chosen for (dtype, k, n, targets).
 int cluster_layout(bool dbl, int k, int n);
+// variant (matrix-core layouts, k <= 5): 0 = direct register gather, 1 = LDS-staged.
 hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, int layout,
-                          const EpiDesc* epi, hipStream_t st);
+                          const EpiDesc* epi, int variant, hipStream_t st);
+// Kernel variant of the matrix-core cluster path: 0 = direct register
+// gather, 1 = LDS-staged linear loads. Chosen per (dtype, k, class of the
+// lowest target bit) from a process-wide tune table; a forced variant (>= 0)
+// overrides the table.
+constexpr int kLowClasses = 4;  // lowest target bit: 0 | 1..2 | 3..5 | >= 6
+inline int low_class(int t0) { return t0 == 0 ? 0 : (t0 <= 2 ? 1 : (t0 <= 5 ? 2 : 3)); }
+void set_cluster_variant(int v);  // -1 = use the tune table
+int get_cluster_variant();
+void set_tune_entry(bool dbl, int k, int cls, int variant);
+int get_tune_entry(bool dbl, int k, int cls);
+int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout);
 hipError_t launch_diag(void* psi, bool dbl, int n, const EpiDesc* epi, hipStream_t st);
 hipError_t launch_gate1q(void* psi, bool dbl, int n, int q, const double m[8], hipStream_t st);
 hipError_t launch_phase1q(void* psi, bool dbl, int n, int q, double cs, double sn, hipStream_t st);

@@ -21,6 +21,9 @@
 // highest target bit is h in column p, with no LDS round trip for the state.
 #include "qsim_internal.h"
 
+#include <cmath>
+#include <cstring>
+
 namespace qsim {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
@@ -108,28 +111,11 @@ __device__ __forceinline__ void apply_factor(T& re, T& im, const ColFactor<T>& f
 // columns are adjacent in memory (one 16-byte load per amplitude pair); with
 // t_0 = 0 (LOWT) the amplitudes j, j+1 of one column are adjacent instead.
 template <int K, int NB, bool LOWT>
-__global__ __launch_bounds__(256) void k_cluster_f32_mfma(float2* __restrict__ psi,
-                                                          const float* __restrict__ Ap,
-                                                          const EpiDesc* __restrict__ epi,
-                                                          ClusterGeom g) {
-    constexpr int D = 1 << K;
-    constexpr int HX = D / 2;       // amplitudes per lane and column
-    constexpr int RB = 2 * D / 32;  // 32-row blocks of the real-split matrix
-    constexpr int S = D;            // MFMA steps (inner dimension 2^(K+1), 2 per step)
-    constexpr int COLS = 32 * NB;
-    __shared__ float As[RB * S * 64];
-    for (int i = threadIdx.x; i < RB * S * 64; i += 256) As[i] = Ap[i];
-    __syncthreads();
+struct TileF32 {
+    static constexpr int HX = (1 << K) / 2;
+    static constexpr int COLS = 32 * NB;
 
-    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
-    const uint64_t hoff = h ? (uint64_t(1) << g.t[K - 1]) : 0;
-    const uint64_t ntiles = g.ncols / COLS;
-    const uint64_t stride = (uint64_t)gridDim.x * 4;
-    const bool has_epi = epi != nullptr;
-    const bool has_ph = has_epi && epi->n_ph > 0;
-
-    for (uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles; tile += stride) {
-        uint64_t base[NB];
+    __device__ __forceinline__ static void bases(uint64_t tile, int p, const ClusterGeom& g, uint64_t (&base)[NB]) {
         if (LOWT || NB == 1) {
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) base[nb] = deposit_cols<K>(tile * COLS + p + 32 * nb, g);
@@ -137,7 +123,9 @@ __global__ __launch_bounds__(256) void k_cluster_f32_mfma(float2* __restrict__ p
             base[0] = deposit_cols<K>(tile * COLS + 2 * p, g);
             base[NB - 1] = base[0] | 1;
         }
-        float B[NB][2 * HX];
+    }
+    __device__ __forceinline__ static void load(const float2* __restrict__ psi, const uint64_t (&base)[NB],
+                                                uint64_t hoff, const ClusterGeom& g, float (&B)[NB][2 * HX]) {
         if (!LOWT && NB == 2) {
 #pragma unroll
             for (int j = 0; j < HX; ++j) {
@@ -150,7 +138,8 @@ __global__ __launch_bounds__(256) void k_cluster_f32_mfma(float2* __restrict__ p
             for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
                 for (int j = 0; j < HX; j += 2) {
-                    const float4 v = *reinterpret_cast<const float4*>(psi + (base[nb] | hoff | target_off<K - 1>(j, g)));
+                    const float4 v =
+                        *reinterpret_cast<const float4*>(psi + (base[nb] | hoff | target_off<K - 1>(j, g)));
                     B[nb][2 * j] = v.x; B[nb][2 * j + 1] = v.y;
                     B[nb][2 * j + 2] = v.z; B[nb][2 * j + 3] = v.w;
                 }
@@ -161,6 +150,73 @@ __global__ __launch_bounds__(256) void k_cluster_f32_mfma(float2* __restrict__ p
                 B[0][2 * j] = v.x; B[0][2 * j + 1] = v.y;
             }
         }
+    }
+    __device__ __forceinline__ static void store(float2* __restrict__ psi, const uint64_t (&base)[NB], uint64_t hoff,
+                                                 const ClusterGeom& g, const float (&O)[NB][2 * HX]) {
+        if (!LOWT && NB == 2) {
+#pragma unroll
+            for (int j = 0; j < HX; ++j)
+                *reinterpret_cast<float4*>(psi + (base[0] | hoff | target_off<K - 1>(j, g))) =
+                    make_float4(O[0][2 * j], O[0][2 * j + 1], O[NB - 1][2 * j], O[NB - 1][2 * j + 1]);
+        } else if (LOWT) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int j = 0; j < HX; j += 2)
+                    *reinterpret_cast<float4*>(psi + (base[nb] | hoff | target_off<K - 1>(j, g))) =
+                        make_float4(O[nb][2 * j], O[nb][2 * j + 1], O[nb][2 * j + 2], O[nb][2 * j + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < HX; ++j)
+                psi[base[0] | hoff | target_off<K - 1>(j, g)] = make_float2(O[0][2 * j], O[0][2 * j + 1]);
+        }
+    }
+};
+
+// Persistent: each wave walks tiles with a stride of the whole grid and
+// prefetches the next tile's amplitudes into registers before it runs the
+// current tile's MFMA chain, so loads stay in flight under the matrix work.
+template <int K, int NB, bool LOWT>
+__global__ __launch_bounds__(256, 2) void k_cluster_f32_mfma(float2* __restrict__ psi,
+                                                             const float* __restrict__ Ap,
+                                                             const EpiDesc* __restrict__ epi,
+                                                             ClusterGeom g) {
+    using T = TileF32<K, NB, LOWT>;
+    constexpr int D = 1 << K;
+    constexpr int HX = D / 2;       // amplitudes per lane and column
+    constexpr int RB = 2 * D / 32;  // 32-row blocks of the real-split matrix
+    constexpr int S = D;            // MFMA steps (inner dimension 2^(K+1), 2 per step)
+    __shared__ float As[RB * S * 64];
+    for (int i = threadIdx.x; i < RB * S * 64; i += 256) As[i] = Ap[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const uint64_t hoff = h ? (uint64_t(1) << g.t[K - 1]) : 0;
+    const uint64_t ntiles = g.ncols / T::COLS;
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+
+    // The prefetch is unconditional (the last tile is re-read instead of
+    // reading past the end) so the load count per iteration is fixed and the
+    // waits the compiler places for the amplitudes cover only their own loads.
+    uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    const uint64_t last = ntiles - 1;
+    float B[NB][2 * HX];
+    uint64_t base[NB];
+    T::bases(tile, p, g, base);
+    T::load(psi, base, hoff, g, B);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
+    do {
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        float Bn[NB][2 * HX];
+        uint64_t basen[NB];
+        T::bases(nxt, p, g, basen);
+        T::load(psi, basen, hoff, g, Bn);
+        __builtin_amdgcn_sched_barrier(0);
 
         floatx16 acc[NB][RB];
 #pragma unroll
@@ -169,69 +225,54 @@ __global__ __launch_bounds__(256) void k_cluster_f32_mfma(float2* __restrict__ p
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) acc[nb][rb][i] = 0.0f;
+        int aoff = lane;
+        asm volatile("" : "+v"(aoff));  // keep the matrix reads inside the loop (not in registers)
 #pragma unroll
         for (int s = 0; s < S; ++s) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                const float a = As[(rb * S + s) * 64 + lane];
+                const float a = As[(rb * S + s) * 64 + aoff];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     acc[nb][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, B[nb][s], acc[nb][rb], 0, 0, 0);
             }
         }
         // acc[nb][j / 8][2 (j % 8) + {0, 1}] is output amplitude j of the lane
+        float O[NB][2 * HX];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < 2 * HX; ++j) O[nb][j] = acc[nb][j / 16][j % 16];
         if (has_epi) {
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const ColFactor<float> f = col_factor<float>(epi, base[nb]);
 #pragma unroll
-                for (int j = 0; j < HX; ++j) {
-                    float re = acc[nb][j / 8][2 * (j % 8)], im = acc[nb][j / 8][2 * (j % 8) + 1];
-                    apply_factor(re, im, f, (uint32_t)(j | (h << (K - 1))), has_ph);
-                    acc[nb][j / 8][2 * (j % 8)] = re;
-                    acc[nb][j / 8][2 * (j % 8) + 1] = im;
-                }
+                for (int j = 0; j < HX; ++j)
+                    apply_factor(O[nb][2 * j], O[nb][2 * j + 1], f, (uint32_t)(j | (h << (K - 1))), has_ph);
             }
         }
-        if (!LOWT && NB == 2) {
+        T::store(psi, base, hoff, g, O);
 #pragma unroll
-            for (int j = 0; j < HX; ++j) {
-                float4 v;
-                v.x = acc[0][j / 8][2 * (j % 8)]; v.y = acc[0][j / 8][2 * (j % 8) + 1];
-                v.z = acc[NB - 1][j / 8][2 * (j % 8)]; v.w = acc[NB - 1][j / 8][2 * (j % 8) + 1];
-                *reinterpret_cast<float4*>(psi + (base[0] | hoff | target_off<K - 1>(j, g))) = v;
-            }
-        } else if (LOWT) {
+        for (int nb = 0; nb < NB; ++nb) {
+            base[nb] = basen[nb];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-                for (int j = 0; j < HX; j += 2) {
-                    float4 v;
-                    v.x = acc[nb][j / 8][2 * (j % 8)]; v.y = acc[nb][j / 8][2 * (j % 8) + 1];
-                    v.z = acc[nb][(j + 1) / 8][2 * ((j + 1) % 8)];
-                    v.w = acc[nb][(j + 1) / 8][2 * ((j + 1) % 8) + 1];
-                    *reinterpret_cast<float4*>(psi + (base[nb] | hoff | target_off<K - 1>(j, g))) = v;
-                }
-        } else {
-#pragma unroll
-            for (int j = 0; j < HX; ++j) {
-                psi[base[0] | hoff | target_off<K - 1>(j, g)] =
-                    make_float2(acc[0][j / 8][2 * (j % 8)], acc[0][j / 8][2 * (j % 8) + 1]);
-            }
+            for (int j = 0; j < 2 * HX; ++j) B[nb][j] = Bn[nb][j];
         }
-    }
+        tile += stride;
+    } while (tile < ntiles);
 }
 
 // ------------------------------------------------------------ cluster: MFMA, double
 // v_mfma_f64_16x16x4_f64: lane l: p = l%16 (column), q = l/16 owns target
 // indices x = j | q << (K-2), j < 2^(K-2), of its column(s). Operand A/B: lane
 // l holds row / column l%16 at inner index l/16; result register r of lane l
-// holds row 4 r + l/16, column l%16.
+// holds row 4 r + l/16, column l%16. Same prefetching loop as the float kernel.
 template <int K, int NB, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_cluster_f64_mfma(double2* __restrict__ psi,
-                                                             const double* __restrict__ Ap,
-                                                             const EpiDesc* __restrict__ epi,
-                                                             ClusterGeom g) {
+__global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_mfma(double2* __restrict__ psi,
+                                                                           const double* __restrict__ Ap,
+                                                                           const EpiDesc* __restrict__ epi,
+                                                                           ClusterGeom g) {
     constexpr int D = 1 << K;
     constexpr int HX = D / 4;
     constexpr int RB = 2 * D / 16;
@@ -249,19 +290,35 @@ __global__ __launch_bounds__(THREADS) void k_cluster_f64_mfma(double2* __restric
     const bool has_epi = epi != nullptr;
     const bool has_ph = has_epi && epi->n_ph > 0;
 
-    for (uint64_t tile = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6); tile < ntiles; tile += stride) {
-        uint64_t base[NB];
+    auto load = [&](uint64_t t, uint64_t (&bs)[NB], double (&B)[NB][2 * HX]) {
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) base[nb] = deposit_cols<K>(tile * COLS + p + 16 * nb, g);
-        double B[NB][2 * HX];
+        for (int nb = 0; nb < NB; ++nb) bs[nb] = deposit_cols<K>(t * COLS + p + 16 * nb, g);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int j = 0; j < HX; ++j) {
-                const double2 v = psi[base[nb] | qoff | target_off<K - 2>(j, g)];
+                const double2 v = psi[bs[nb] | qoff | target_off<K - 2>(j, g)];
                 B[nb][2 * j] = v.x;
                 B[nb][2 * j + 1] = v.y;
             }
+    };
+
+    uint64_t tile = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    const uint64_t last = ntiles - 1;
+    double B[NB][2 * HX];
+    uint64_t base[NB];
+    load(tile, base, B);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
+    do {
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        double Bn[NB][2 * HX];
+        uint64_t basen[NB];
+        load(nxt, basen, Bn);
+        __builtin_amdgcn_sched_barrier(0);
+
         doublex4 acc[NB][RB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
@@ -269,11 +326,13 @@ __global__ __launch_bounds__(THREADS) void k_cluster_f64_mfma(double2* __restric
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) acc[nb][rb][i] = 0.0;
+        int aoff = lane;
+        asm volatile("" : "+v"(aoff));
 #pragma unroll
         for (int s = 0; s < S; ++s) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
-                const double a = As[(rb * S + s) * 64 + lane];
+                const double a = As[(rb * S + s) * 64 + aoff];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     acc[nb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[nb][s], acc[nb][rb], 0, 0, 0);
@@ -291,7 +350,361 @@ __global__ __launch_bounds__(THREADS) void k_cluster_f64_mfma(double2* __restric
                 psi[base[nb] | qoff | target_off<K - 2>(j, g)] = make_double2(re, im);
             }
         }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            base[nb] = basen[nb];
+#pragma unroll
+            for (int j = 0; j < 2 * HX; ++j) B[nb][j] = Bn[nb][j];
+        }
+        tile += stride;
+    } while (tile < ntiles);
+}
+
+// ------------------------------------------------------------ cluster: MFMA, LDS-staged
+// The same MFMA products, but the wave tile (targets x 2^C columns) is moved
+// between HBM and registers as linear runs of its tile index tau: lane l reads
+// and writes 16 consecutive bytes, so each load / store instruction covers
+// runs of at least 2^C amplitudes whatever the target bits are (targets on
+// the lowest bits scatter a direct register gather across many cache lines).
+// The re-ordering into the MFMA operand layout goes through a private LDS
+// buffer of the wave; the next tile's linear loads are in flight while the
+// current tile's MFMA chain runs.
+
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+
+// LDS exchange between lanes of one wave: LDS operations of a wave execute in
+// order, so only the compiler must be kept from reordering them.
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// State offset of tile t: t deposited into the non-tile bit positions.
+template <int NT>
+__device__ __forceinline__ uint64_t tile_base(uint64_t t, const StageGeom& sg) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) t = insert_zero(t, sg.tb[i]);
+    return t;
+}
+
+// tau of target index x (bits m0 <= m < m1 of x).
+template <int M0, int M1>
+__device__ __forceinline__ int tau_of_targets(int x, const StageGeom& sg) {
+    int t = 0;
+#pragma unroll
+    for (int m = M0; m < M1; ++m)
+        if ((x >> m) & 1) t |= 1 << sg.tpos[m];
+    return t;
+}
+
+template <int C>
+__device__ __forceinline__ int tau_of_column(int c, const StageGeom& sg) {
+    int t = 0;
+#pragma unroll
+    for (int b = 0; b < C; ++b)
+        if ((c >> b) & 1) t |= 1 << sg.cpos[b];
+    return t;
+}
+
+template <int C>
+__device__ __forceinline__ uint64_t state_bits_of_column(int c, const StageGeom& sg) {
+    uint64_t o = 0;
+#pragma unroll
+    for (int b = 0; b < C; ++b)
+        if ((c >> b) & 1) o |= uint64_t(1) << sg.tb[sg.cpos[b]];
+    return o;
+}
+
+// Linear loads and the LDS re-ordering of the float staged kernel.
+template <int K, int C, bool LOWT>
+struct StageF32 {
+    static constexpr int HX = (1 << K) / 2;
+    static constexpr int NB = (1 << C) / 32;
+    static constexpr int NL = (1 << (K + C)) / 128;
+    __device__ __forceinline__ static void load_lin(const float2* __restrict__ psi, uint64_t b0, const StageGeom& sg,
+                                                    vf4 (&R)[NL]) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const vf4*>(psi + (b0 | sg.ioff[i]));
     }
+    __device__ __forceinline__ static void stage_in(vf4* L4, int lane, const int (&tc)[NB], int th,
+                                                    const StageGeom& sg, const vf4 (&R)[NL],
+                                                    float (&B)[NB][2 * HX]) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) L4[i * 64 + lane] = R[i];
+        wave_lds_fence();
+        if (!LOWT) {
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                const vf4 v = L4[(tc[0] | th | tau_of_targets<0, K - 1>(j, sg)) >> 1];
+                B[0][2 * j] = v.x; B[0][2 * j + 1] = v.y;
+                B[1][2 * j] = v.z; B[1][2 * j + 1] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int j = 0; j < HX; j += 2) {
+                    const vf4 v = L4[(tc[nb] | th | tau_of_targets<0, K - 1>(j, sg)) >> 1];
+                    B[nb][2 * j] = v.x; B[nb][2 * j + 1] = v.y;
+                    B[nb][2 * j + 2] = v.z; B[nb][2 * j + 3] = v.w;
+                }
+        }
+        wave_lds_fence();
+    }
+};
+
+// float: lane l covers tau = 2 (i * 64 + l) + {0, 1} in linear order. In MFMA
+// order lane (p, h) owns target indices j | h << (K-1) of columns 2p, 2p+1
+// (tau bit 0 is a column bit) or p, p+32 (tau bit 0 is target 0, LOWT).
+template <int K, int C, bool LOWT>
+__global__ __launch_bounds__(256, 2) void k_cluster_f32_stage(float2* __restrict__ psi,
+                                                              const float* __restrict__ Ap,
+                                                              const EpiDesc* __restrict__ epi, ClusterGeom g,
+                                                              StageGeom sg) {
+    constexpr int D = 1 << K;
+    constexpr int HX = D / 2;
+    constexpr int RB = 2 * D / 32;
+    constexpr int S = D;
+    constexpr int NB = (1 << C) / 32;
+    constexpr int NT = K + C;
+    constexpr int TILE = 1 << NT;
+    constexpr int NL = TILE / 128;
+    static_assert(NB == 2, "two column blocks per lane");
+    __shared__ float As[RB * S * 64];
+    __shared__ vf4 Ls[4][TILE / 2];
+    for (int i = threadIdx.x; i < RB * S * 64; i += 256) As[i] = Ap[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5, w = threadIdx.x >> 6;
+    vf4* L4 = Ls[w];
+    uint64_t lane_off = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if ((lane >> b) & 1) lane_off |= uint64_t(1) << sg.tb[b + 1];
+    int tc[NB];
+    uint64_t cbits[NB];
+    if (!LOWT) {
+        tc[0] = tau_of_column<C>(2 * p, sg);
+        tc[1] = tc[0] | 1;
+        cbits[0] = state_bits_of_column<C>(2 * p, sg);
+        cbits[1] = state_bits_of_column<C>(2 * p + 1, sg);
+    } else {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            tc[nb] = tau_of_column<C>(p + 32 * nb, sg);
+            cbits[nb] = state_bits_of_column<C>(p + 32 * nb, sg);
+        }
+    }
+    const int th = h << sg.tpos[K - 1];
+    const uint64_t ntiles = g.ncols >> C;
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+
+    uint64_t tile = (uint64_t)blockIdx.x * 4 + w;
+    if (tile >= ntiles) return;
+    const uint64_t last = ntiles - 1;
+    vf4 R[NL];
+    StageF32<K, C, LOWT>::load_lin(psi, tile_base<NT>(tile, sg) | lane_off, sg, R);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
+    float B[NB][2 * HX];
+    StageF32<K, C, LOWT>::stage_in(L4, lane, tc, th, sg, R, B);
+    do {
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        StageF32<K, C, LOWT>::load_lin(psi, tile_base<NT>(nxt, sg) | lane_off, sg, R);
+        __builtin_amdgcn_sched_barrier(0);
+
+        floatx16 acc[NB][RB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[nb][rb][i] = 0.0f;
+        int aoff = lane;
+        asm volatile("" : "+v"(aoff));
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const float a = As[(rb * S + s) * 64 + aoff];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[nb][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, B[nb][s], acc[nb][rb], 0, 0, 0);
+            }
+        }
+        float O[NB][2 * HX];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < 2 * HX; ++j) O[nb][j] = acc[nb][j / 16][j % 16];
+        const uint64_t tb0 = tile_base<NT>(tile, sg);
+        if (has_epi) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const ColFactor<float> f = col_factor<float>(epi, tb0 | cbits[nb]);
+#pragma unroll
+                for (int j = 0; j < HX; ++j)
+                    apply_factor(O[nb][2 * j], O[nb][2 * j + 1], f, (uint32_t)(j | (h << (K - 1))), has_ph);
+            }
+        }
+        // MFMA order -> LDS -> linear order -> HBM
+        if (!LOWT) {
+#pragma unroll
+            for (int j = 0; j < HX; ++j)
+                L4[(tc[0] | th | tau_of_targets<0, K - 1>(j, sg)) >> 1] =
+                    vf4{O[0][2 * j], O[0][2 * j + 1], O[1][2 * j], O[1][2 * j + 1]};
+        } else {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int j = 0; j < HX; j += 2)
+                    L4[(tc[nb] | th | tau_of_targets<0, K - 1>(j, sg)) >> 1] =
+                        vf4{O[nb][2 * j], O[nb][2 * j + 1], O[nb][2 * j + 2], O[nb][2 * j + 3]};
+        }
+        wave_lds_fence();
+        {
+            const uint64_t b0 = tb0 | lane_off;
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const vf4 v = L4[i * 64 + lane];
+                *reinterpret_cast<vf4*>(psi + (b0 | sg.ioff[i])) = v;
+            }
+        }
+        wave_lds_fence();
+        StageF32<K, C, LOWT>::stage_in(L4, lane, tc, th, sg, R, B);
+        tile += stride;
+    } while (tile < ntiles);
+}
+
+template <int K, int C>
+struct StageF64 {
+    static constexpr int HX = (1 << K) / 4;
+    static constexpr int NB = (1 << C) / 16;
+    static constexpr int NL = (1 << (K + C)) / 64;
+    __device__ __forceinline__ static void load_lin(const vd2* __restrict__ psi, uint64_t b0,
+                                                    const StageGeom& sg, vd2 (&R)[NL]) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const vd2*>(psi + (b0 | sg.ioff[i]));
+    }
+    __device__ __forceinline__ static void stage_in(vd2* L, int lane, const int (&tc)[NB], int tq,
+                                                    const StageGeom& sg, const vd2 (&R)[NL],
+                                                    double (&B)[NB][2 * HX]) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) L[i * 64 + lane] = R[i];
+        wave_lds_fence();
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                const vd2 v = L[tc[nb] | tq | tau_of_targets<0, K - 2>(j, sg)];
+                B[nb][2 * j] = v.x;
+                B[nb][2 * j + 1] = v.y;
+            }
+        wave_lds_fence();
+    }
+};
+
+// double: lane l covers tau = i * 64 + l in linear order; in MFMA order lane
+// (p, q) owns target indices j | q << (K-2) of columns p and p + 16.
+template <int K, int C, int THREADS>
+__global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd2* __restrict__ psi,
+                                                                            const double* __restrict__ Ap,
+                                                                            const EpiDesc* __restrict__ epi,
+                                                                            ClusterGeom g, StageGeom sg) {
+    constexpr int D = 1 << K;
+    constexpr int HX = D / 4;
+    constexpr int RB = 2 * D / 16;
+    constexpr int S = 2 * D / 4;
+    constexpr int NB = (1 << C) / 16;
+    constexpr int NT = K + C;
+    constexpr int TILE = 1 << NT;
+    constexpr int NL = TILE / 64;
+    constexpr int WAVES = THREADS / 64;
+    __shared__ double As[RB * S * 64];
+    __shared__ vd2 Ls[WAVES][TILE];
+    for (int i = threadIdx.x; i < RB * S * 64; i += THREADS) As[i] = Ap[i];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, p = lane & 15, q = lane >> 4, w = threadIdx.x >> 6;
+    vd2* L = Ls[w];
+    uint64_t lane_off = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if ((lane >> b) & 1) lane_off |= uint64_t(1) << sg.tb[b];
+    int tc[NB];
+    uint64_t cbits[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        tc[nb] = tau_of_column<C>(p + 16 * nb, sg);
+        cbits[nb] = state_bits_of_column<C>(p + 16 * nb, sg);
+    }
+    const int tq = ((q & 1) << sg.tpos[K - 2]) | ((q >> 1) << sg.tpos[K - 1]);
+    const uint64_t ntiles = g.ncols >> C;
+    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+
+    uint64_t tile = (uint64_t)blockIdx.x * WAVES + w;
+    if (tile >= ntiles) return;
+    const uint64_t last = ntiles - 1;
+    vd2 R[NL];
+    StageF64<K, C>::load_lin(psi, tile_base<NT>(tile, sg) | lane_off, sg, R);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
+    double B[NB][2 * HX];
+    StageF64<K, C>::stage_in(L, lane, tc, tq, sg, R, B);
+    do {
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        StageF64<K, C>::load_lin(psi, tile_base<NT>(nxt, sg) | lane_off, sg, R);
+        __builtin_amdgcn_sched_barrier(0);
+
+        doublex4 acc[NB][RB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[nb][rb][i] = 0.0;
+        int aoff = lane;
+        asm volatile("" : "+v"(aoff));
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const double a = As[(rb * S + s) * 64 + aoff];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[nb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, B[nb][s], acc[nb][rb], 0, 0, 0);
+            }
+        }
+        const uint64_t tb0 = tile_base<NT>(tile, sg);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            ColFactor<double> f{0u, 0u, 1.0, 0.0};
+            if (has_epi) f = col_factor<double>(epi, tb0 | cbits[nb]);
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                double re = acc[nb][j / 2][2 * (j % 2)], im = acc[nb][j / 2][2 * (j % 2) + 1];
+                if (has_epi) apply_factor(re, im, f, (uint32_t)(j | (q << (K - 2))), has_ph);
+                L[tc[nb] | tq | tau_of_targets<0, K - 2>(j, sg)] = vd2{re, im};
+            }
+        }
+        wave_lds_fence();
+        {
+            const uint64_t b0 = tb0 | lane_off;
+#pragma unroll
+            for (int i = 0; i < NL; ++i) *reinterpret_cast<vd2*>(psi + (b0 | sg.ioff[i])) = L[i * 64 + lane];
+        }
+        wave_lds_fence();
+        StageF64<K, C>::stage_in(L, lane, tc, tq, sg, R, B);
+        tile += stride;
+    } while (tile < ntiles);
 }
 
 // ------------------------------------------------------------ cluster: vector ALU
@@ -651,6 +1064,36 @@ hipError_t launch_build(const BuildOp* ops, int n_ops, const BuildGate* gates, c
     return hipGetLastError();
 }
 
+// Tile geometry of the staged kernels: the C lowest non-target bits are the
+// columns; chunk i of the linear order starts at tau = i << unit.
+static StageGeom make_stage_geom(const ClusterGeom& g, int C, int unit) {
+    StageGeom sg;
+    std::memset(&sg, 0, sizeof(sg));
+    uint64_t tmask = 0;
+    for (int m = 0; m < g.k; ++m) tmask |= uint64_t(1) << g.t[m];
+    int cols[8], nc = 0;
+    for (int b = 0; b < g.n && nc < C; ++b)
+        if (!(tmask >> b & 1)) cols[nc++] = b;
+    uint64_t tilemask = tmask;
+    for (int b = 0; b < nc; ++b) tilemask |= uint64_t(1) << cols[b];
+    sg.nt = 0;
+    for (int b = 0; b < g.n; ++b)
+        if (tilemask >> b & 1) sg.tb[sg.nt++] = b;
+    for (int r = 0; r < sg.nt; ++r) {
+        for (int m = 0; m < g.k; ++m) if (sg.tb[r] == g.t[m]) sg.tpos[m] = r;
+        for (int c = 0; c < nc; ++c) if (sg.tb[r] == cols[c]) sg.cpos[c] = r;
+    }
+    const int chunks = 1 << (sg.nt - unit);
+    for (int i = 0; i < chunks && i < 32; ++i) {
+        const uint64_t tau = uint64_t(i) << unit;
+        uint64_t off = 0;
+        for (int r = 0; r < sg.nt; ++r)
+            if (tau >> r & 1) off |= uint64_t(1) << sg.tb[r];
+        sg.ioff[i] = off;
+    }
+    return sg;
+}
+
 int cluster_layout(bool dbl, int k, int n) {
     if (!dbl) {
         const int nb = (k == 6) ? 1 : 2;
@@ -675,7 +1118,21 @@ hipError_t launch_valu_k(void* psi, bool dbl, const ClusterGeom& g, const void* 
 }
 
 template <int K>
-hipError_t launch_mfma32_k(void* psi, const ClusterGeom& g, const void* mat, const EpiDesc* epi, hipStream_t st) {
+hipError_t launch_mfma32_k(void* psi, const ClusterGeom& g, const void* mat, const EpiDesc* epi, int variant,
+                           hipStream_t st) {
+    if (K <= 5 && variant == 1) {
+        constexpr int KS = K <= 5 ? K : 5;
+        const StageGeom sg = make_stage_geom(g, 6, 7);
+        const uint64_t tiles = g.ncols >> 6;
+        const unsigned grid = grid_for(tiles, 4, kPersistGrid);
+        if (g.t[0] == 0)
+            hipLaunchKernelGGL((k_cluster_f32_stage<KS, 6, true>), dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const float*)mat, epi, g, sg);
+        else
+            hipLaunchKernelGGL((k_cluster_f32_stage<KS, 6, false>), dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const float*)mat, epi, g, sg);
+        return hipGetLastError();
+    }
     constexpr int NB = (K == 6) ? 1 : 2;
     const uint64_t tiles = g.ncols / (32 * NB);
     const unsigned grid = grid_for(tiles, 4, kPersistGrid);
@@ -689,7 +1146,18 @@ hipError_t launch_mfma32_k(void* psi, const ClusterGeom& g, const void* mat, con
 }
 
 template <int K>
-hipError_t launch_mfma64_k(void* psi, const ClusterGeom& g, const void* mat, const EpiDesc* epi, hipStream_t st) {
+hipError_t launch_mfma64_k(void* psi, const ClusterGeom& g, const void* mat, const EpiDesc* epi, int variant,
+                           hipStream_t st) {
+    if (K <= 5 && variant == 1) {
+        constexpr int KS = K <= 5 ? K : 5;
+        constexpr int TH = KS == 5 ? 512 : 256;
+        const StageGeom sg = make_stage_geom(g, 5, 6);
+        const uint64_t tiles = g.ncols >> 5;
+        const unsigned grid = grid_for(tiles, TH / 64, kPersistGrid);
+        hipLaunchKernelGGL((k_cluster_f64_stage<KS, 5, TH>), dim3(grid), dim3(TH), 0, st, (vd2*)psi,
+                           (const double*)mat, epi, g, sg);
+        return hipGetLastError();
+    }
     constexpr int NB = (K == 6) ? 1 : 2;
     constexpr int TH = (K == 6) ? 512 : 256;
     const uint64_t tiles = g.ncols / (16 * NB);
@@ -701,7 +1169,7 @@ hipError_t launch_mfma64_k(void* psi, const ClusterGeom& g, const void* mat, con
 }  // namespace
 
 hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, int layout,
-                          const EpiDesc* epi, hipStream_t st) {
+                          const EpiDesc* epi, int variant, hipStream_t st) {
     if (layout == LAYOUT_PLAIN) {
         switch (g.k) {
             case 1: return launch_valu_k<1>(psi, dbl, g, mat, epi, st);
@@ -715,18 +1183,18 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
     }
     if (layout == LAYOUT_MFMA32F && !dbl) {
         switch (g.k) {
-            case 4: return launch_mfma32_k<4>(psi, g, mat, epi, st);
-            case 5: return launch_mfma32_k<5>(psi, g, mat, epi, st);
-            case 6: return launch_mfma32_k<6>(psi, g, mat, epi, st);
+            case 4: return launch_mfma32_k<4>(psi, g, mat, epi, variant, st);
+            case 5: return launch_mfma32_k<5>(psi, g, mat, epi, variant, st);
+            case 6: return launch_mfma32_k<6>(psi, g, mat, epi, variant, st);
             default: return hipErrorInvalidValue;
         }
     }
     if (layout == LAYOUT_MFMA16D && dbl) {
         switch (g.k) {
-            case 3: return launch_mfma64_k<3>(psi, g, mat, epi, st);
-            case 4: return launch_mfma64_k<4>(psi, g, mat, epi, st);
-            case 5: return launch_mfma64_k<5>(psi, g, mat, epi, st);
-            case 6: return launch_mfma64_k<6>(psi, g, mat, epi, st);
+            case 3: return launch_mfma64_k<3>(psi, g, mat, epi, variant, st);
+            case 4: return launch_mfma64_k<4>(psi, g, mat, epi, variant, st);
+            case 5: return launch_mfma64_k<5>(psi, g, mat, epi, variant, st);
+            case 6: return launch_mfma64_k<6>(psi, g, mat, epi, variant, st);
             default: return hipErrorInvalidValue;
         }
     }

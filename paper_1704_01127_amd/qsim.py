@@ -66,6 +66,9 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libqsim.so is not built: run `python -c 'import __graft_entry__ as g; "
                               "g.build()'` (hipcc, gfx950) first")
+        # PyTorch ships its own HIP runtime; load it first so that the library
+        # binds to the same runtime instead of mapping a second one.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32p, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
         sig = {
@@ -85,6 +88,10 @@ def lib():
             "qsim_last_error": (ctypes.c_char_p, []),
             "qsim_op_timings": (ctypes.c_int, [vp, i32p, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_float),
                                                ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+            "qsim_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+            "qsim_set_tune_entry": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+            "qsim_get_tune_entry": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+            "qsim_get_option": (ctypes.c_int, [ctypes.c_int]),
             "qsim_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_int,
                                              ctypes.POINTER(RunOpts), i32p, i32p, i32p, i32p, i32p,
                                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -163,6 +170,17 @@ def schedule(n: int, gates: Sequence, **opts) -> dict:
     m = nops.value
     return dict(gate_op=list(gate_op)[:ng], gate_role=list(gate_role)[:ng], op_kind=list(op_kind)[:m],
                 op_k=list(op_k)[:m], op_qubits=[list(op_q[6 * o_:6 * o_ + 6]) for o_ in range(m)])
+
+
+OPT_CLUSTER_VARIANT = 1
+
+
+def set_option(option: int, value: int):
+    _check(lib().qsim_set_option(option, value))
+
+
+def get_option(option: int) -> int:
+    return int(lib().qsim_get_option(option))
 
 
 def workspace_bytes(n: int, dtype: int, kmax: int = 6) -> int:
@@ -274,7 +292,8 @@ class State:
         _check(L.qsim_op_timings(self.h, kind, k, qs, epi, ms, m, ctypes.byref(n)))
         kinds = {0: "cluster", 1: "diag", 2: "gate1q", 3: "phase1q", 4: "cz", 5: "build"}
         return [dict(kind=kinds[kind[i]], k=k[i], qubits=[q for q in qs[6 * i:6 * i + 6] if q >= 0],
-                     epi=bool(epi[i]), ms=float(ms[i])) for i in range(m)]
+                     epi=bool(epi[i] & 1), staged=bool(epi[i] & 2), mfma=bool(epi[i] & 4), ms=float(ms[i]))
+                for i in range(m)]
 
     def sync(self):
         _check(lib().qsim_sync(self.h))

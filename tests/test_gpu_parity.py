@@ -78,9 +78,18 @@ for _k in range(1, 7):
                 CLUSTER_CASES.append((_k, _n, _pat))
 
 
+@pytest.fixture(params=[1, 0], ids=["staged", "direct"])
+def variant(request):
+    """Run with each matrix-core cluster kernel variant, then restore the default."""
+    old = qsim.get_option(qsim.OPT_CLUSTER_VARIANT)
+    qsim.set_option(qsim.OPT_CLUSTER_VARIANT, request.param)
+    yield request.param
+    qsim.set_option(qsim.OPT_CLUSTER_VARIANT, old)
+
+
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("k,n,pat", CLUSTER_CASES)
-def test_apply_cluster(dt, k, n, pat):
+def test_apply_cluster(dt, k, n, pat, variant):
     qs = target_sets(n, k, 1000 * k + n)[pat]
     rng = np.random.default_rng(k * 7 + n)
     order = list(rng.permutation(qs))  # the ABI takes the qubits in any order
@@ -95,7 +104,7 @@ def test_apply_cluster(dt, k, n, pat):
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-def test_apply_cluster_twice_large(dt):
+def test_apply_cluster_twice_large(dt, variant):
     """Several tiles per wave and a grid that does not divide the tile count."""
     n = 21
     for k, qs in ((5, [20, 0, 7, 13, 3]), (4, [1, 2, 19, 9]), (6, [2, 3, 4, 10, 15, 20]), (3, [0, 1, 2])):
@@ -191,7 +200,7 @@ RUN_CASES = [
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("case", range(len(RUN_CASES)))
-def test_run_circuit_16q(dt, case):
+def test_run_circuit_16q(dt, case, variant):
     opts = RUN_CASES[case]
     circ = supremacy_circuit(4, 4, 20, seed=case)
     ref = oracle.run(circ)
