@@ -92,7 +92,8 @@ typedef struct {
 typedef enum {
     QSIM_SCHED_PER_GATE = 0, /* one launch per gate, no fusion (the plain method) */
     QSIM_SCHED_GREEDY = 1,   /* clusters of <= kmax qubits, most gates per cluster (Sec. 3.6.1, step 2) */
-    QSIM_SCHED_ANALYTIC = 2, /* clusters chosen by a bandwidth/compute cost model (fewest predicted us) */
+    QSIM_SCHED_ANALYTIC = 2, /* greedy schedules for every cap <= kmax, the cheapest under the
+                                measured cost table (qsim_set_cost_table) wins */
     QSIM_SCHED_LEARNED = 3   /* as ANALYTIC with the MLP cost model loaded by qsim_set_cost_model;
                                 falls back to GREEDY when none is loaded */
 } qsim_scheduler;
@@ -107,7 +108,8 @@ typedef struct {
     int32_t skip_initial_h;     /* caller promises the state is |0...0>: the leading H on every
                                    qubit is replaced by the uniform initialisation (Sec. 3.6) */
     int32_t record_timings;     /* time every launched op with HIP events (slows the run) */
-    int32_t reserved[2];
+    int32_t reserved[2];        /* reserved[0]: qsim_dtype the cost models assume in
+                                   qsim_schedule (qsim_run_circuit uses the state's); 0 = C64 */
 } qsim_run_opts;
 
 typedef struct {
@@ -201,8 +203,8 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * The matrix-core cluster kernels exist in two variants: 0 gathers each
  * lane's amplitudes straight from HBM into registers, 1 moves the wave's tile
  * as linear runs and re-orders it through LDS. The variant is looked up per
- * (dtype, k, class of the lowest target qubit: 0 | 1-2 | 3-5 | >= 6) in a
- * tune table, which qsim_set_tune_entry overwrites (the autotuner fills it
+ * (dtype, k, low_class = number of targets among qubits 0..5, capped at 3) in
+ * a tune table, which qsim_set_tune_entry overwrites (the autotuner fills it
  * from measurements). QSIM_OPT_CLUSTER_VARIANT = 0 or 1 forces one variant
  * everywhere, -1 (default) uses the table. Errors: QSIM_E_INVALID for an
  * unknown option or an out-of-range value. */
@@ -211,6 +213,61 @@ qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);
 qsim_status qsim_set_tune_entry(qsim_dtype dt, int k, int low_class, int variant);
 int qsim_get_tune_entry(qsim_dtype dt, int k, int low_class);
+
+/* Cost table of QSIM_SCHED_ANALYTIC: us_by_k[k] = measured microseconds of one
+ * op on a state of n_ref qubits (index 0: a diagonal pass, 1..6: a k-qubit
+ * cluster); costs scale as 2^(n - n_ref) because every op streams the whole
+ * state (Sec. 3.1: the kernels are memory bound; a compute-bound k shows up as
+ * a larger entry). The cost-driven schedulers build the greedy schedule for
+ * every cap k <= kmax and keep the one with the smallest predicted total time.
+ * The autotuner measures the table. */
+qsim_status qsim_set_cost_table(qsim_dtype dt, const double* us_by_k, int n_ref);
+
+/* ------------------------------------------------------------------------
+ * Learned cost model (QSIM_SCHED_LEARNED). Not in the paper: the paper picks
+ * k_max per machine by benchmarks (Sec. 3.3, 3.6.1); here a small MLP trained
+ * on the simulator's own recorded kernel times predicts the time of a
+ * candidate op, and the scheduler keeps the candidate schedule with the
+ * smallest predicted total.
+ *
+ * Features of an op (k = 0: a standalone diagonal pass; qubits sorted): a
+ * vector of qsim_cost_feature_count() floats, computed the same way for
+ * training data and for scheduling. */
+int qsim_cost_feature_count(void);
+qsim_status qsim_cost_features(int n_qubits, qsim_dtype dt, int k, const int32_t* qubits, int n_epi,
+                               float* out);
+
+/* MLP in -> H -> H -> 1, ReLU, float32. Parameters in one array:
+ * W1[H][in], b1[H], W2[H][H], b2[H], W3[H], b3[1] (qsim_mlp_param_count).
+ * The prediction y of normalised features x = (f - feat_mean) / feat_std is
+ * ln(microseconds per 2^30 amplitudes) = y * y_std + y_mean. Host copies are
+ * taken; params = NULL unloads the model (LEARNED then falls back to the
+ * fixed-k greedy scheduler). in must equal qsim_cost_feature_count(), H <= 64
+ * for the GPU kernels (256 on the host). */
+size_t qsim_mlp_param_count(int n_in, int n_hidden);
+qsim_status qsim_set_cost_model(const float* params, int n_in, int n_hidden, const float* feat_mean,
+                                const float* feat_std, double y_mean, double y_std);
+/* Predicted microseconds of one op under the loaded model (1.0 if none). */
+double qsim_cost_model_predict_us(int n_qubits, qsim_dtype dt, int k, const int32_t* qubits, int n_epi);
+/* Host forward pass (float32, fused multiply-adds in index order): y[b] for x[batch][in]. */
+qsim_status qsim_mlp_predict_host(const float* params, int n_in, int n_hidden, const float* x, int batch,
+                                  float* y);
+
+/* GPU training kernels (device pointers, enqueued on `stream`, n_in <= 32,
+ * n_hidden <= 64). Forward: y[b] for x[batch][in], the same arithmetic as the
+ * host pass. Backward: gradient of the mean squared error
+ * L = (1/batch) sum_b (y_b - target_b)^2 with respect to every parameter, and
+ * L itself (dev_loss, nullable); dev_scratch holds
+ * qsim_mlp_scratch_floats(n_in, n_hidden, batch) floats. Adam: one step of
+ * Kingma & Ba's update with bias correction at step `step` (>= 1). */
+size_t qsim_mlp_scratch_floats(int n_in, int n_hidden, int batch);
+qsim_status qsim_mlp_forward(int n_in, int n_hidden, const float* dev_params, const float* dev_x, int batch,
+                             float* dev_y, void* stream);
+qsim_status qsim_mlp_backward(int n_in, int n_hidden, const float* dev_params, const float* dev_x,
+                              const float* dev_target, int batch, float* dev_grad, float* dev_loss,
+                              float* dev_scratch, void* stream);
+qsim_status qsim_mlp_adam(int n_params, float* dev_params, const float* dev_grad, float* dev_m, float* dev_v,
+                          int step, float lr, float beta1, float beta2, float eps, void* stream);
 
 /* Host-only: the schedule qsim_run_circuit would use (no GPU work). For each
  * gate: gate_op[g] = index of the op applying it (-1 if skipped) and

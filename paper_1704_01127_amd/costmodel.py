@@ -1,0 +1,212 @@
+"""Learned cost model of the clustering scheduler: record, train, compare.
+
+record   runs seeded random circuits (supremacy circuits of depth 40 with a
+         Haar-random 5-qubit gate after every 8th cycle) under many schedules
+         with per-launch HIP-event timing and stores, per op, the library's
+         feature vector and ln(us per 2^30 amplitudes).
+train    fits the MLP (16 -> 64 -> 64 -> 1, float32) with the library's own
+         GPU forward / backward / Adam kernels and writes cost_model.npz.
+compare  times held-out circuits with the learned scheduler against the
+         fixed-k greedy scheduler (and the analytic one) and checks that the
+         results agree.
+
+    python -m paper_1704_01127_amd.costmodel record --out records.npz
+    python -m paper_1704_01127_amd.costmodel train --data records.npz --out paper_1704_01127_amd/cost_model.npz
+    python -m paper_1704_01127_amd.costmodel compare
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import qsim
+
+N_IN, N_HIDDEN = 16, 64
+
+
+def workload(n: int, depth: int, seed: int):
+    from supremacy_inputs import supremacy_circuit, with_haar_layers
+    from supremacy_inputs.circuits import batch_grid
+    R, C, drop = batch_grid(n)
+    circ = supremacy_circuit(R, C, depth, seed, drop)
+    return with_haar_layers(circ, 8, 5, seed + 77)
+
+
+def op_record_rows(recs, n, dtype_code):
+    feats, ys = [], []
+    for r in recs:
+        if r["kind"] not in ("cluster", "diag"):
+            continue
+        k = r["k"] if r["kind"] == "cluster" else 0
+        qs = r["qubits"] if k else []
+        f = qsim.cost_features(n, dtype_code, qs, n_epi=1 if r.get("epi") else 0)
+        feats.append(f)
+        ys.append(math.log(r["ms"] * 1e3 / 2.0 ** (n - 30)))
+    return feats, ys
+
+
+def cmd_record(args):
+    import torch  # noqa: F401
+    feats, ys, meta = [], [], []
+    configs = [dict(kmax=k, fuse_diag=fd) for k in (2, 3, 4, 5, 6) for fd in (False, True)]
+    t_start = time.time()
+    for dt, ns in (("c64", [27, 28, 29, 30]), ("c128", [27, 28])):
+        code = qsim.C64 if dt == "c64" else qsim.C128
+        for n in ns:
+            state = qsim.State(n, dt, kmax=6)
+            for seed in range(args.seeds):
+                circ = workload(n, args.depth, seed)
+                for ci, cfg in enumerate(configs):
+                    state.init("uniform")
+                    state.run_circuit(circ.gates, record_timings=True, skip_trailing_diag=True, **cfg)
+                    f, y = op_record_rows(state.op_timings(), n, code)
+                    feats += f
+                    ys += y
+                    meta += [(seed, n, code, ci)] * len(y)
+                print("recorded %s n=%d seed=%d: %d records (%.0f s)" % (dt, n, seed, len(ys), time.time() - t_start),
+                      flush=True)
+            del state
+    np.savez(args.out, x=np.array(feats, np.float32), y=np.array(ys, np.float64),
+             meta=np.array(meta, np.int32))
+    print("wrote %d records to %s" % (len(ys), args.out), flush=True)
+
+
+def init_params(rng, n_in=N_IN, h=N_HIDDEN):
+    """He-uniform weights, zero biases, in the library's flat layout."""
+    def u(fan_in, shape):
+        lim = math.sqrt(6.0 / fan_in)
+        return rng.uniform(-lim, lim, shape)
+    return np.concatenate([u(n_in, h * n_in), np.zeros(h), u(h, h * h), np.zeros(h), u(h, h) * 0.1,
+                           np.zeros(1)]).astype(np.float32)
+
+
+def train(x, y, steps=4000, batch=512, lr=2e-3, seed=0, val=None, log=print):
+    """Train on the GPU with the library's kernels. x: [N, in] normalised
+    float32, y: [N] normalised. Returns (params, history)."""
+    import torch
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(seed)
+    p = torch.from_numpy(init_params(rng)).to(dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    xt = torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(dev)
+    yt = torch.from_numpy(np.ascontiguousarray(y, np.float32)).to(dev)
+    hist = []
+    N = x.shape[0]
+    for step in range(1, steps + 1):
+        idx = torch.from_numpy(rng.integers(0, N, batch)).to(dev)
+        xb = xt.index_select(0, idx).contiguous()
+        yb = yt.index_select(0, idx).contiguous()
+        grad, loss = qsim.mlp_backward(p, N_IN, N_HIDDEN, xb, yb)
+        cur_lr = lr * (0.5 * (1 + math.cos(math.pi * step / steps)) * 0.9 + 0.1)
+        qsim.mlp_adam(p, grad, m, v, step, cur_lr)
+        if step % max(1, steps // 10) == 0 or step == 1:
+            rec = {"step": step, "train_mse": float(loss.item())}
+            if val is not None:
+                pv = qsim.mlp_forward(p, N_IN, N_HIDDEN, torch.from_numpy(val[0]).to(dev))
+                rec["val_mse"] = float(((pv.cpu().numpy() - val[1]) ** 2).mean())
+            hist.append(rec)
+            log(json.dumps(rec))
+    return p.cpu().numpy(), hist
+
+
+def cmd_train(args):
+    d = np.load(args.data, allow_pickle=False)
+    x, y, meta = d["x"], d["y"], d["meta"]
+    held = meta[:, 0] % 5 == 4  # every fifth seed is validation
+    mean = x[~held].mean(0)
+    std = x[~held].std(0)
+    std[std < 1e-6] = 1.0
+    y_mean, y_std = float(y[~held].mean()), float(y[~held].std())
+    xn = ((x - mean) / std).astype(np.float32)
+    yn = ((y - y_mean) / y_std).astype(np.float32)
+    params, hist = train(xn[~held], yn[~held], steps=args.steps, val=(xn[held], yn[held]))
+    # validation error in log space -> typical relative error of a time prediction
+    pred = qsim.mlp_predict_host(params, N_IN, N_HIDDEN, xn[held]) * y_std + y_mean
+    rmse = float(np.sqrt(np.mean((pred - y[held]) ** 2)))
+    mae_rel = float(np.mean(np.abs(np.exp(pred - y[held]) - 1)))
+    print("validation: rmse(ln us) = %.4f, mean |relative error| = %.2f%% over %d ops" %
+          (rmse, 100 * mae_rel, int(held.sum())), flush=True)
+    np.savez(args.out, params=params, n_in=N_IN, n_hidden=N_HIDDEN, feat_mean=mean.astype(np.float32),
+             feat_std=std.astype(np.float32), y_mean=y_mean, y_std=y_std, val_rmse_log=rmse,
+             val_mean_rel_err=mae_rel, n_train=int((~held).sum()), n_val=int(held.sum()),
+             history=json.dumps(hist))
+
+
+def time_run(state, circ, opts, reps=3):
+    best, st = None, None
+    for _ in range(reps + 1):
+        state.init("zero")
+        state.sync()
+        t0 = time.perf_counter()
+        st = state.run_circuit(circ.gates, **opts)
+        state.sync()
+        t = time.perf_counter() - t0
+        best = t if best is None or t < best else best
+    return best, st
+
+
+def compare(n_list=(28, 29, 30), seeds=range(100, 104), depth=40, log=print):
+    """Time held-out circuits: learned (k <= 6) vs fixed-k greedy (k = 5) vs analytic."""
+    import torch
+    rows = []
+    for n in n_list:
+        s1 = qsim.State(n, "c64", kmax=6)
+        s2 = qsim.State(n, "c64", kmax=6)
+        for seed in seeds:
+            circ = workload(n, depth, seed)
+            base = dict(fuse_diag=True, skip_trailing_diag=True, skip_initial_h=True)
+            tg, stg = time_run(s1, circ, dict(base, scheduler="greedy", kmax=5))
+            tl, stl = time_run(s2, circ, dict(base, scheduler="learned", kmax=6))
+            fid, maxd = s1.compare(s2.amps)
+            ta, sta = time_run(s1, circ, dict(base, scheduler="analytic", kmax=6))
+            row = dict(n=n, seed=seed, greedy_ms=tg * 1e3, learned_ms=tl * 1e3, analytic_ms=ta * 1e3,
+                       greedy_ops=stg["n_ops"], learned_ops=stl["n_ops"], analytic_ops=sta["n_ops"],
+                       learned_clusters_by_k=stl["n_clusters_by_k"], fidelity_learned_vs_greedy=fid,
+                       max_abs_diff=maxd)
+            rows.append(row)
+            log(json.dumps(row))
+        del s1, s2
+        torch.cuda.empty_cache()
+    g = sum(r["greedy_ms"] for r in rows)
+    lr = sum(r["learned_ms"] for r in rows)
+    log("total: greedy %.1f ms, learned %.1f ms (%.1f%% faster)" % (g, lr, 100 * (g - lr) / g))
+    return rows
+
+
+def cmd_compare(args):
+    import torch  # noqa: F401
+    qsim.load_tuning()
+    rows = compare(n_list=[int(x) for x in args.n.split(",")], seeds=range(args.seed0, args.seed0 + args.seeds))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(rows, f, indent=1)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("record")
+    r.add_argument("--seeds", type=int, default=10)
+    r.add_argument("--depth", type=int, default=40)
+    r.add_argument("--out", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--data", required=True)
+    t.add_argument("--steps", type=int, default=4000)
+    t.add_argument("--out", required=True)
+    c = sub.add_parser("compare")
+    c.add_argument("--n", default="28,29,30")
+    c.add_argument("--seed0", type=int, default=100)
+    c.add_argument("--seeds", type=int, default=4)
+    c.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    {"record": cmd_record, "train": cmd_train, "compare": cmd_compare}[args.cmd](args)
+
+
+if __name__ == "__main__":
+    main()

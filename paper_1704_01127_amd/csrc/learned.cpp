@@ -1,0 +1,168 @@
+// Learned cost model of the scheduler: features of a cluster op and the
+// host-side evaluation of a small MLP (in -> H -> H -> 1, ReLU, float32)
+// trained on the simulator's own recorded kernel times. The prediction is the
+// natural log of the op's time per 2^30 amplitudes in microseconds; the
+// scheduler's cost is exp(prediction) * 2^(n - 30).
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "qsim.h"
+#include "qsim_internal.h"
+
+namespace qsim {
+
+constexpr int kFeatures = 16;
+
+// Features of one op: sizes, FLOP and byte intensity, where the targets sit
+// (low bits break coalescing, high bits stride far), kernel kind and the
+// diagonal epilogue. k = 0 is a standalone diagonal pass.
+void op_features(int n, bool dbl, int k, const int* q, int n_epi, float* f) {
+    std::memset(f, 0, sizeof(float) * kFeatures);
+    int lo = n, hi = -1, below3 = 0, below6 = 0, top3 = 0;
+    for (int j = 0; j < k; ++j) {
+        lo = q[j] < lo ? q[j] : lo;
+        hi = q[j] > hi ? q[j] : hi;
+        below3 += q[j] < 3;
+        below6 += q[j] < 6;
+        top3 += q[j] >= n - 3;
+    }
+    if (k == 0) lo = hi = 0;
+    const int layout = k == 0 ? LAYOUT_PLAIN : cluster_layout(dbl, k, n);
+    ClusterGeom g;
+    std::memset(&g, 0, sizeof(g));
+    for (int j = 0; j < k; ++j) g.t[j] = q[j];
+    g.k = k;
+    g.n = n;
+    const int variant = k == 0 ? 0 : cluster_variant_for(dbl, g, layout);
+    f[0] = k / 6.0f;
+    f[1] = n / 34.0f;
+    f[2] = dbl ? 1.0f : 0.0f;
+    f[3] = k == 0 ? 0.0f : (8.0f * (1 << k) - 2.0f) / 510.0f;
+    f[4] = dbl ? 1.0f : 0.5f;
+    f[5] = (float)lo / n;
+    f[6] = (float)hi / n;
+    f[7] = below3 / 3.0f;
+    f[8] = below6 / 6.0f;
+    f[9] = top3 / 3.0f;
+    f[10] = layout != LAYOUT_PLAIN ? 1.0f : 0.0f;
+    f[11] = variant ? 1.0f : 0.0f;
+    f[12] = n_epi > 0 ? 1.0f : 0.0f;
+    f[13] = std::log2(1.0f + n_epi) / 7.0f;
+    f[14] = k == 6 ? 1.0f : 0.0f;
+    f[15] = k == 0 ? 1.0f : 0.0f;
+}
+
+namespace {
+struct Model {
+    bool loaded = false;
+    int n_in = 0, n_hidden = 0;
+    std::vector<float> p;             // W1 [H][in], b1 [H], W2 [H][H], b2 [H], W3 [H], b3 [1]
+    std::vector<float> mean, inv_std; // feature normalisation
+    float y_mean = 0.f, y_std = 1.f;
+};
+Model g_model;
+std::mutex g_model_mu;
+}  // namespace
+
+size_t mlp_param_count(int n_in, int h) { return (size_t)h * n_in + h + (size_t)h * h + h + h + 1; }
+
+// Plain float32 forward pass of one sample (the same operation order as the
+// GPU forward kernel: dot products accumulated in index order).
+float mlp_forward_host(const float* p, int n_in, int h, const float* x) {
+    const float* W1 = p;
+    const float* b1 = W1 + (size_t)h * n_in;
+    const float* W2 = b1 + h;
+    const float* b2 = W2 + (size_t)h * h;
+    const float* W3 = b2 + h;
+    const float* b3 = W3 + h;
+    float a1[256], a2[256];
+    for (int i = 0; i < h; ++i) {
+        float s = b1[i];
+        for (int j = 0; j < n_in; ++j) s = std::fma(W1[(size_t)i * n_in + j], x[j], s);
+        a1[i] = s > 0.f ? s : 0.f;
+    }
+    for (int i = 0; i < h; ++i) {
+        float s = b2[i];
+        for (int j = 0; j < h; ++j) s = std::fma(W2[(size_t)i * h + j], a1[j], s);
+        a2[i] = s > 0.f ? s : 0.f;
+    }
+    float y = b3[0];
+    for (int j = 0; j < h; ++j) y = std::fma(W3[j], a2[j], y);
+    return y;
+}
+
+bool learned_model_loaded() {
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    return g_model.loaded;
+}
+
+double learned_cost_us(int n, bool dbl, int k, const int* qubits, int n_epi) {
+    float f[kFeatures];
+    op_features(n, dbl, k, qubits, n_epi, f);
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    if (!g_model.loaded) return 1.0;
+    float x[kFeatures];
+    for (int i = 0; i < kFeatures; ++i) x[i] = (f[i] - g_model.mean[i]) * g_model.inv_std[i];
+    const float y = mlp_forward_host(g_model.p.data(), g_model.n_in, g_model.n_hidden, x);
+    const double log_us = (double)y * g_model.y_std + g_model.y_mean;
+    return std::exp(log_us) * std::ldexp(1.0, n - 30);
+}
+
+}  // namespace qsim
+
+using namespace qsim;
+
+extern "C" {
+
+int qsim_cost_feature_count(void) { return kFeatures; }
+
+qsim_status qsim_cost_features(int n_qubits, qsim_dtype dt, int k, const int32_t* qubits, int n_epi,
+                               float* out) {
+    if (!out || k < 0 || k > kMaxK || (k > 0 && !qubits) || n_qubits < 1 || n_qubits > 40)
+        return QSIM_E_INVALID;
+    int q[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < k; ++j) q[j] = qubits[j];
+    op_features(n_qubits, dt == QSIM_C128, k, q, n_epi, out);
+    return QSIM_OK;
+}
+
+qsim_status qsim_set_cost_model(const float* params, int n_in, int n_hidden, const float* feat_mean,
+                                const float* feat_std, double y_mean, double y_std) {
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    if (!params) {  // unload
+        g_model = Model();
+        return QSIM_OK;
+    }
+    if (n_in != kFeatures || n_hidden < 1 || n_hidden > 256 || !feat_mean || !feat_std || !(y_std > 0))
+        return QSIM_E_INVALID;
+    Model m;
+    m.n_in = n_in;
+    m.n_hidden = n_hidden;
+    m.p.assign(params, params + mlp_param_count(n_in, n_hidden));
+    m.mean.assign(feat_mean, feat_mean + n_in);
+    m.inv_std.resize(n_in);
+    for (int i = 0; i < n_in; ++i) m.inv_std[i] = feat_std[i] > 0 ? 1.0f / feat_std[i] : 0.0f;
+    m.y_mean = (float)y_mean;
+    m.y_std = (float)y_std;
+    m.loaded = true;
+    g_model = std::move(m);
+    return QSIM_OK;
+}
+
+qsim_status qsim_mlp_predict_host(const float* params, int n_in, int n_hidden, const float* x, int batch,
+                                  float* y) {
+    if (!params || !x || !y || n_in < 1 || n_hidden < 1 || n_hidden > 256 || batch < 0) return QSIM_E_INVALID;
+    for (int b = 0; b < batch; ++b) y[b] = mlp_forward_host(params, n_in, n_hidden, x + (size_t)b * n_in);
+    return QSIM_OK;
+}
+
+double qsim_cost_model_predict_us(int n_qubits, qsim_dtype dt, int k, const int32_t* qubits, int n_epi) {
+    int q[6] = {0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < k && j < 6; ++j) q[j] = qubits[j];
+    return learned_cost_us(n_qubits, dt == QSIM_C128, k, q, n_epi);
+}
+
+}  // extern "C"

@@ -56,21 +56,32 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 namespace qsim {
 namespace {
 int g_cluster_variant = -1;
-// [dtype][k][lowest-target class]: the LDS-staged variant unless the lowest
-// target is above the column bits' first run (then a direct gather is coalesced)
+// [dtype][k][low_class]: a direct gather when no target is on the low bits,
+// the LDS-staged variant otherwise
 int g_tune[2][kMaxK + 1][kLowClasses] = {
-    {{1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}},
-    {{1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}, {1, 1, 1, 0}}};
+    {{0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}},
+    {{0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}}};
 }  // namespace
 void set_cluster_variant(int v) { g_cluster_variant = v; }
 int get_cluster_variant() { return g_cluster_variant; }
 void set_tune_entry(bool dbl, int k, int cls, int variant) { g_tune[dbl][k][cls] = variant; }
 int get_tune_entry(bool dbl, int k, int cls) { return g_tune[dbl][k][cls]; }
+// Analytic cost model of the cost-driven scheduler: measured microseconds of
+// one op by k (index 0 = diagonal pass) on a state of n_ref qubits, scaled by
+// 2^(n - n_ref) (every op streams the whole state). Defaults: a k-independent
+// cost, which reduces the cost-driven scheduler to "most gates per cluster".
+double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
+int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
     if (layout == LAYOUT_PLAIN || g.k > 5) return 0;
     if (g_cluster_variant >= 0) return g_cluster_variant;
-    return g_tune[dbl][g.k][low_class(g.t[0])];
+    return g_tune[dbl][g.k][low_class(g.t, g.k)];
 }
+}  // namespace qsim
+
+namespace qsim {
+bool learned_model_loaded();
+double learned_cost_us(int n, bool dbl, int k, const int* qubits, int n_epi);
 }  // namespace qsim
 
 struct OpRecord {
@@ -240,39 +251,24 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
     return QSIM_OK;
 }
 
-// Standalone diagonal pass over pairs and phases (global qubit indices).
+// Standalone diagonal pass over pairs and phases (global qubit indices): the
+// kernel itself splits them by which index bits they read.
 qsim_status diag_desc(int n, const std::vector<std::pair<int, int>>& pairs,
                       const std::vector<std::pair<int, double>>& phases, EpiDesc& e) {
+    (void)n;
     std::memset(&e, 0, sizeof(e));
-    const int L = n < 2 ? n : 2;
-    for (int j = 0; j < (1 << L); ++j) { e.low[j][0] = 1.0; e.low[j][1] = 0.0; }
-    e.n_low = 1 << L;
+    if ((int)pairs.size() > kEpiMax) return fail(QSIM_E_UNSUPPORTED, "too many CZ pairs in a diagonal pass");
+    if ((int)phases.size() > kEpiMax) return fail(QSIM_E_UNSUPPORTED, "too many phases in a diagonal pass");
     for (auto pr : pairs) {
-        int a = std::min(pr.first, pr.second), b = std::max(pr.first, pr.second);
-        if (b < L) {
-            for (int j = 0; j < (1 << L); ++j)
-                if ((j >> a & 1) && (j >> b & 1)) { e.low[j][0] = -e.low[j][0]; e.low[j][1] = -e.low[j][1]; }
-        } else if (a < L) {
-            if (e.n_mix >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "too many CZ pairs in a diagonal pass");
-            e.mix[e.n_mix][0] = a; e.mix[e.n_mix][1] = b; e.n_mix++;
-        } else {
-            if (e.n_cc >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "too many CZ pairs in a diagonal pass");
-            e.cc[e.n_cc][0] = a; e.cc[e.n_cc][1] = b; e.n_cc++;
-        }
+        e.cc[e.n_cc][0] = std::min(pr.first, pr.second);
+        e.cc[e.n_cc][1] = std::max(pr.first, pr.second);
+        e.n_cc++;
     }
     for (auto ph : phases) {
-        const double c = std::cos(ph.second), sn = std::sin(ph.second);
-        if (ph.first < L) {
-            for (int j = 0; j < (1 << L); ++j)
-                if (j >> ph.first & 1) {
-                    const double r = e.low[j][0] * c - e.low[j][1] * sn;
-                    e.low[j][1] = e.low[j][0] * sn + e.low[j][1] * c;
-                    e.low[j][0] = r;
-                }
-        } else {
-            if (e.n_ph >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "too many phases in a diagonal pass");
-            e.ph_q[e.n_ph] = ph.first; e.ph[e.n_ph][0] = c; e.ph[e.n_ph][1] = sn; e.n_ph++;
-        }
+        e.ph_q[e.n_ph] = ph.first;
+        e.ph[e.n_ph][0] = std::cos(ph.second);
+        e.ph[e.n_ph][1] = std::sin(ph.second);
+        e.n_ph++;
     }
     return QSIM_OK;
 }
@@ -433,11 +429,23 @@ std::vector<SGate> to_sgates(const qsim_gate* gates, int n_gates) {
     return sg;
 }
 
+// Cost function of the cost-driven schedulers (empty for the others).
+OpCostFn cost_fn(const qsim_run_opts* o, int n, bool dbl) {
+    if (!o || o->scheduler == QSIM_SCHED_PER_GATE || o->scheduler == QSIM_SCHED_GREEDY) return OpCostFn();
+    if (o->scheduler == QSIM_SCHED_LEARNED && learned_model_loaded()) {
+        return [n, dbl](int k, const int* q, int n_epi) { return learned_cost_us(n, dbl, k, q, n_epi); };
+    }
+    const double scale = std::ldexp(1.0, n - g_cost_nref[dbl]);
+    const double* us = g_cost_us[dbl];
+    return [scale, us](int k, const int*, int) { return us[k] * scale; };
+}
+
 SchedOpts to_sched_opts(const qsim_run_opts* o) {
     SchedOpts so;
     if (!o) return so;
     so.kmax = o->kmax;
     so.mode = o->scheduler == QSIM_SCHED_PER_GATE ? 0 : (o->scheduler == QSIM_SCHED_GREEDY ? 1 : 2);
+    if (o->scheduler == QSIM_SCHED_LEARNED && !learned_model_loaded()) so.mode = 1;  // fixed-k greedy fallback
     so.fuse_diag = o->fuse_diag != 0;
     so.skip_trailing_diag = o->skip_trailing_diag != 0;
     so.skip_initial_h = o->skip_initial_h != 0;
@@ -569,7 +577,7 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
         if (gates[i].kind == G_DENSE && gates[i].k > s->kmax_ws)
             return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
     const std::vector<SGate> sg = to_sgates(gates, n_gates);
-    const Schedule S = make_schedule(s->n, sg, so, OpCostFn());
+    const Schedule S = make_schedule(s->n, sg, so, cost_fn(opts, s->n, s->dbl));
     const auto t1 = std::chrono::steady_clock::now();
 
     qsim_run_stats st;
@@ -677,6 +685,16 @@ qsim_status qsim_set_tune_entry(qsim_dtype dt, int k, int low_class, int variant
     return QSIM_OK;
 }
 
+qsim_status qsim_set_cost_table(qsim_dtype dt, const double* us_by_k, int n_ref) {
+    if (dt != QSIM_C64 && dt != QSIM_C128) return fail(QSIM_E_INVALID, "unknown dtype");
+    if (!us_by_k || n_ref < 1 || n_ref > 40) return fail(QSIM_E_INVALID, "bad cost table");
+    for (int k = 0; k <= kMaxK; ++k)
+        if (!(us_by_k[k] > 0.0)) return fail(QSIM_E_INVALID, "costs must be positive");
+    for (int k = 0; k <= kMaxK; ++k) g_cost_us[dt == QSIM_C128][k] = us_by_k[k];
+    g_cost_nref[dt == QSIM_C128] = n_ref;
+    return QSIM_OK;
+}
+
 int qsim_get_tune_entry(qsim_dtype dt, int k, int low_class) {
     if ((dt != QSIM_C64 && dt != QSIM_C128) || k < 1 || k > kMaxK || low_class < 0 || low_class >= kLowClasses)
         return -1;
@@ -721,7 +739,8 @@ qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates, con
         if (qsim_status r = check_gate(&tmp, gates[i], i)) return r;
     SchedOpts so = to_sched_opts(opts);
     if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 6]");
-    const Schedule S = make_schedule(n_qubits, to_sgates(gates, n_gates), so, OpCostFn());
+    const Schedule S = make_schedule(n_qubits, to_sgates(gates, n_gates), so,
+                                     cost_fn(opts, n_qubits, opts && opts->reserved[0] == QSIM_C128));
     if (n_ops) *n_ops = (int)S.ops.size();
     if ((int)S.ops.size() > op_cap) return fail(QSIM_E_INVALID, "op_cap too small");
     if (gate_op)

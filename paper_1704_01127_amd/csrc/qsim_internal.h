@@ -71,16 +71,14 @@ __host__ __device__ inline double gate_phase_angle(int kind, double theta) {
 //   mix  : CZ pairs with one qubit among the targets: (bit j of the target
 //          index x, state bit b)
 //   ph   : phase gates on qubits outside the target set (cos, sin)
-//   low  : standalone pass only, factor of the bits below the per-thread
-//          chunk (indexed by those bits)
-// Terms that read target bits only are folded into the cluster matrix.
+// Terms that read target bits only are folded into the cluster matrix. A
+// standalone diagonal pass lists all its pairs in cc and phases in ph.
 struct EpiDesc {
-    int32_t n_cc, n_mix, n_ph, n_low;
+    int32_t n_cc, n_mix, n_ph, pad;
     int32_t cc[kEpiMax][2];
     int32_t mix[kEpiMax][2];
     int32_t ph_q[kEpiMax];
     double ph[kEpiMax][2];
-    double low[8][2];
 };
 
 // Cluster-matrix build: one op per work-group of the builder kernel.
@@ -150,11 +148,17 @@ int cluster_layout(bool dbl, int k, int n);
 hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, int layout,
                           const EpiDesc* epi, int variant, hipStream_t st);
 // Kernel variant of the matrix-core cluster path: 0 = direct register
-// gather, 1 = LDS-staged linear loads. Chosen per (dtype, k, class of the
-// lowest target bit) from a process-wide tune table; a forced variant (>= 0)
-// overrides the table.
-constexpr int kLowClasses = 4;  // lowest target bit: 0 | 1..2 | 3..5 | >= 6
-inline int low_class(int t0) { return t0 == 0 ? 0 : (t0 <= 2 ? 1 : (t0 <= 5 ? 2 : 3)); }
+// gather, 1 = LDS-staged linear loads. Chosen per (dtype, k, low_class) from a
+// process-wide tune table; a forced variant (>= 0) overrides the table.
+// Class of a target set for the variant choice: how many targets sit on the
+// lowest 6 state bits (0 | 1 | 2 | 3 or more): those bits would otherwise be
+// the contiguous column bits of a direct gather.
+constexpr int kLowClasses = 4;
+inline int low_class(const int32_t* t, int k) {
+    int c = 0;
+    for (int j = 0; j < k; ++j) c += t[j] < 6;
+    return c < 3 ? c : 3;
+}
 void set_cluster_variant(int v);  // -1 = use the tune table
 int get_cluster_variant();
 void set_tune_entry(bool dbl, int k, int cls, int variant);

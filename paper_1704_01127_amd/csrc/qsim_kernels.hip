@@ -748,32 +748,79 @@ __global__ __launch_bounds__(256) void k_cluster_valu(typename Cplx<T>::type* __
 }
 
 // ------------------------------------------------------------ diagonal pass
-// Every amplitude times the diagonal factor of its index. A thread owns a
-// chunk of 2^lowbits consecutive amplitudes; terms reading only the chunk's
-// low bits come from the descriptor's `low` table, the others from the
-// column factor of the chunk's base index (the low bits act as "targets").
+// Every amplitude times the diagonal factor of its index (Sec. 3.5: diagonal
+// gates need no gather). A wave covers one window of 128 consecutive
+// amplitudes per step (2 per lane, 16-byte accesses). The index splits into
+// lo (bits 0..6, fixed per lane) and hi (the window, uniform per wave): terms
+// of lo bits only are per-lane constants, terms of hi bits only are computed
+// once per window, and CZ pairs with one bit in each half give a sign mask
+// over lo. The descriptor lists the pairs in `cc` and the phases in `ph`.
 template <typename T>
-__global__ __launch_bounds__(256) void k_diag(typename Cplx<T>::type* __restrict__ psi, int lowbits,
-                                              const EpiDesc* __restrict__ e, uint64_t nchunks) {
+__global__ __launch_bounds__(256) void k_diag(typename Cplx<T>::type* __restrict__ psi, int n,
+                                              const EpiDesc* __restrict__ e) {
     using V = typename Cplx<T>::type;
-    const bool has_ph = e->n_ph > 0;
-    const int ch = 1 << lowbits;
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
-    for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < nchunks; c += stride) {
-        const uint64_t base = c << lowbits;
-        const ColFactor<T> f = col_factor<T>(e, base);
-        for (int j = 0; j < ch; ++j) {
-            V v = psi[base + j];
-            T re = v.x, im = v.y;
-            const T lr = (T)e->low[j][0], li = (T)e->low[j][1];
-            const T r = re * lr - im * li;
-            im = re * li + im * lr;
-            re = r;
-            apply_factor(re, im, f, (uint32_t)j, has_ph);
-            v.x = re;
-            v.y = im;
-            psi[base + j] = v;
+    constexpr int LO = 7;
+    const int lane = threadIdx.x & 63;
+    const int np = e->n_cc, nph = e->n_ph;
+    // per-lane constants: the factor of the two lo indices of this lane
+    uint32_t sgn_lo[2] = {0u, 0u};
+    double plr[2] = {1.0, 1.0}, pli[2] = {0.0, 0.0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t lo = 2 * lane + h;
+        for (int i = 0; i < np; ++i) {
+            const int a = e->cc[i][0], b = e->cc[i][1];
+            if (a < LO && b < LO) sgn_lo[h] ^= (lo >> a) & (lo >> b) & 1u;
         }
+        for (int i = 0; i < nph; ++i) {
+            const int q = e->ph_q[i];
+            if (q < LO && ((lo >> q) & 1u)) {
+                const double c = e->ph[i][0], sn = e->ph[i][1];
+                const double r = plr[h] * c - pli[h] * sn;
+                pli[h] = plr[h] * sn + pli[h] * c;
+                plr[h] = r;
+            }
+        }
+    }
+    const uint64_t nwin = (n >= LO) ? (uint64_t(1) << (n - LO)) : 1;
+    const uint64_t wstride = (uint64_t)gridDim.x * 4;
+    for (uint64_t win = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); win < nwin; win += wstride) {
+        const uint64_t hi = win << LO;
+        uint32_t sgn_hi = 0u, wmask = 0u;
+        double phr = 1.0, phi = 0.0;
+        for (int i = 0; i < np; ++i) {
+            const int a = e->cc[i][0], b = e->cc[i][1];
+            if (a >= LO && b >= LO) sgn_hi ^= (uint32_t)((hi >> a) & (hi >> b) & 1);
+            else if (a < LO && b >= LO) wmask ^= (uint32_t)((hi >> b) & 1) << a;
+            else if (b < LO && a >= LO) wmask ^= (uint32_t)((hi >> a) & 1) << b;
+        }
+        for (int i = 0; i < nph; ++i) {
+            const int q = e->ph_q[i];
+            if (q >= LO && ((hi >> q) & 1)) {
+                const double c = e->ph[i][0], sn = e->ph[i][1];
+                const double r = phr * c - phi * sn;
+                phi = phr * sn + phi * c;
+                phr = r;
+            }
+        }
+        const uint64_t i0 = hi | (uint64_t)(2 * lane);
+        if (i0 >= (uint64_t(1) << n)) continue;  // states of fewer than 7 qubits: lanes past the end
+        V v[2];
+        v[0] = psi[i0];
+        v[1] = psi[i0 + 1];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t lo = 2 * lane + h;
+            const bool neg = ((sgn_lo[h] ^ sgn_hi ^ (uint32_t)__popc(lo & wmask)) & 1u) != 0;
+            const T fr = (T)(phr * plr[h] - phi * pli[h]);
+            const T fi = (T)(phr * pli[h] + phi * plr[h]);
+            const T re = v[h].x * fr - v[h].y * fi;
+            const T im = v[h].x * fi + v[h].y * fr;
+            v[h].x = neg ? -re : re;
+            v[h].y = neg ? -im : im;
+        }
+        psi[i0] = v[0];
+        psi[i0 + 1] = v[1];
     }
 }
 
@@ -1202,13 +1249,12 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
 }
 
 hipError_t launch_diag(void* psi, bool dbl, int n, const EpiDesc* epi, hipStream_t st) {
-    const int lowbits = n < 2 ? n : 2;
-    const uint64_t nchunks = uint64_t(1) << (n - lowbits);
-    const unsigned grid = grid_for(nchunks, 256, kStreamGrid);
+    const uint64_t nwin = n >= 7 ? (uint64_t(1) << (n - 7)) : 1;
+    const unsigned grid = grid_for(nwin, 4, kStreamGrid);
     if (dbl)
-        hipLaunchKernelGGL(k_diag<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, lowbits, epi, nchunks);
+        hipLaunchKernelGGL(k_diag<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, n, epi);
     else
-        hipLaunchKernelGGL(k_diag<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, lowbits, epi, nchunks);
+        hipLaunchKernelGGL(k_diag<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, n, epi);
     return hipGetLastError();
 }
 

@@ -8,6 +8,12 @@
 // search tries every ready gate as the seed and keeps the cluster with the
 // most gates, before the remaining gates are assigned to further clusters.
 //
+// Cost-driven mode (analytic or learned cost model): the complete greedy
+// schedule is built for every cap k <= kmax and the one with the smallest
+// predicted total time is kept (per-cluster "gates per microsecond" choices
+// are myopic: a wide cluster can look cheap per gate and still leave more
+// total work).
+//
 // Extensions for the GPU kernels (both exact, as diagonal gates commute):
 //   * a cluster made only of diagonal gates becomes a diagonal pass, which
 //     then absorbs every ready diagonal gate;
@@ -18,6 +24,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <future>
 
 #include "qsim_internal.h"
 
@@ -115,6 +122,74 @@ bool all_diag(const std::vector<SGate>& G, const Grown& c) {
     return true;
 }
 
+// Greedy clustering with at most kcap qubits per cluster (gates with more
+// qubits form a cluster of their own width).
+std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::vector<char>& dropped, int n_applied,
+                            int kcap_in, bool fuse_diag) {
+    const int ng = (int)gates.size();
+    std::vector<SOp> out;
+    Dag d;
+    d.n = n;
+    d.g = &gates;
+    d.queue.assign(n, {});
+    d.mask.assign(ng, 0);
+    for (int i = 0; i < ng; ++i) {
+        for (int j = 0; j < gates[i].nq; ++j) d.mask[i] |= uint64_t(1) << gates[i].q[j];
+        if (dropped[i]) continue;
+        for (int j = 0; j < gates[i].nq; ++j) d.queue[gates[i].q[j]].push_back(i);
+    }
+    std::vector<int> head(n, 0);
+    int remaining = n_applied;
+    std::vector<int> rl;
+    const int kmax = kcap_in;
+
+    while (remaining > 0) {
+        d.ready_list(head, rl);
+        Grown best;
+        int best_score = -1;
+        for (int seed : rl) {
+            // a gate wider than kmax (a dense gate) forms a cluster of its own width
+            const int khi = std::max(kmax, popc(d.mask[seed]));
+            Grown c = grow(d, head, seed, khi, fuse_diag);
+            if (c.n_gates() > best_score) { best_score = c.n_gates(); best = std::move(c); }
+        }
+        SOp op;
+        if (all_diag(gates, best)) {
+            // a diagonal pass: take every ready diagonal gate, repeatedly
+            op.kind = OP_DIAG;
+            int ncz = 0, nph = 0;
+            for (;;) {
+                d.ready_list(head, rl);
+                bool took = false;
+                for (int gi : rl) {
+                    if (!gates[gi].diag) continue;
+                    const bool cz = gates[gi].kind == G_CZ;
+                    if ((cz && ncz >= kEpiMax) || (!cz && nph >= kEpiMax)) continue;
+                    (cz ? ncz : nph)++;
+                    op.members.push_back(gi);
+                    d.pop(head, gi);
+                    took = true;
+                }
+                if (!took) break;
+            }
+            std::sort(op.members.begin(), op.members.end());
+            remaining -= (int)op.members.size();
+        } else {
+            op.kind = OP_CLUSTER;
+            for (int q = 0; q < n; ++q)
+                if (best.Q >> q & 1) op.qubits[op.k++] = q;
+            op.members = best.members;
+            op.epi = best.epi;
+            std::sort(op.members.begin(), op.members.end());
+            std::sort(op.epi.begin(), op.epi.end());
+            head = best.head;
+            remaining -= best.n_gates();
+        }
+        out.push_back(std::move(op));
+    }
+    return out;
+}
+
 }  // namespace
 
 Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& o, const OpCostFn& cost) {
@@ -165,74 +240,30 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
         return S;
     }
 
-    Dag d;
-    d.n = n;
-    d.g = &gates;
-    d.queue.assign(n, {});
-    d.mask.assign(ng, 0);
-    for (int i = 0; i < ng; ++i) {
-        for (int j = 0; j < gates[i].nq; ++j) d.mask[i] |= uint64_t(1) << gates[i].q[j];
-        if (S.dropped[i]) continue;
-        for (int j = 0; j < gates[i].nq; ++j) d.queue[gates[i].q[j]].push_back(i);
-    }
-    std::vector<int> head(n, 0);
-    int remaining = S.n_applied;
-    std::vector<int> rl;
     const int kmax = std::max(1, std::min(o.kmax, kMaxK));
-
-    while (remaining > 0) {
-        d.ready_list(head, rl);
-        Grown best;
-        double best_score = -1.0;
-        for (int seed : rl) {
-            // a gate wider than kmax (a dense gate) forms a cluster of its own width
-            const int kseed = popc(d.mask[seed]);
-            const int khi = std::max(kmax, kseed);
-            const int klo = (o.mode == 2) ? kseed : khi;
-            for (int kc = klo; kc <= khi; ++kc) {
-                Grown c = grow(d, head, seed, kc, o.fuse_diag);
-                double score = c.n_gates();
-                if (o.mode == 2 && cost) {
-                    int qs[6], k = 0;
-                    for (int q = 0; q < n; ++q) if (c.Q >> q & 1) qs[k++] = q;
-                    score = c.n_gates() / std::max(1e-3, cost(k, qs, (int)c.epi.size()));
-                }
-                if (score > best_score) { best_score = score; best = std::move(c); }
-            }
+    if (o.mode == 1 || !cost) {
+        S.ops = greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag);
+        return S;
+    }
+    // cost-driven: the complete greedy schedule for every cap, the one with
+    // the smallest predicted total time wins (schedules built in parallel)
+    std::vector<std::future<std::vector<SOp>>> futs;
+    for (int kc = 1; kc <= kmax; ++kc)
+        futs.push_back(std::async(std::launch::async, [&, kc]() {
+            return greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag);
+        }));
+    double best_cost = 0.0;
+    for (int kc = 1; kc <= kmax; ++kc) {
+        std::vector<SOp> ops = futs[kc - 1].get();
+        double total = 0.0;
+        for (const SOp& op : ops) {
+            if (op.kind == OP_DIAG) total += cost(0, op.qubits, 0);
+            else total += cost(op.k, op.qubits, (int)op.epi.size());
         }
-        SOp op;
-        if (all_diag(gates, best)) {
-            // a diagonal pass: take every ready diagonal gate, repeatedly
-            op.kind = OP_DIAG;
-            int ncz = 0, nph = 0;
-            for (;;) {
-                d.ready_list(head, rl);
-                bool took = false;
-                for (int gi : rl) {
-                    if (!gates[gi].diag) continue;
-                    const bool cz = gates[gi].kind == G_CZ;
-                    if ((cz && ncz >= kEpiMax) || (!cz && nph >= kEpiMax)) continue;
-                    (cz ? ncz : nph)++;
-                    op.members.push_back(gi);
-                    d.pop(head, gi);
-                    took = true;
-                }
-                if (!took) break;
-            }
-            std::sort(op.members.begin(), op.members.end());
-            remaining -= (int)op.members.size();
-        } else {
-            op.kind = OP_CLUSTER;
-            for (int q = 0; q < n; ++q)
-                if (best.Q >> q & 1) op.qubits[op.k++] = q;
-            op.members = best.members;
-            op.epi = best.epi;
-            std::sort(op.members.begin(), op.members.end());
-            std::sort(op.epi.begin(), op.epi.end());
-            head = best.head;
-            remaining -= best.n_gates();
+        if (kc == 1 || total < best_cost) {
+            best_cost = total;
+            S.ops = std::move(ops);
         }
-        S.ops.push_back(std::move(op));
     }
     return S;
 }

@@ -44,8 +44,9 @@ struct Schedule {
     int n_applied = 0;
 };
 
-// Build the schedule. `cost` is used by mode 2 only (may be empty: then a
-// constant cost per op is assumed, which reduces to the greedy rule).
+// Build the schedule. `cost` is used by mode 2 only: the greedy schedule of
+// every cap k <= kmax is built and the cheapest by predicted total wins
+// (empty cost: the greedy schedule with cap kmax).
 Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& o, const OpCostFn& cost);
 
 }  // namespace qsim

@@ -89,6 +89,22 @@ def lib():
             "qsim_op_timings": (ctypes.c_int, [vp, i32p, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_float),
                                                ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
             "qsim_set_option": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+            "qsim_set_cost_table": (ctypes.c_int, [ctypes.c_int, dp, ctypes.c_int]),
+            "qsim_cost_feature_count": (ctypes.c_int, []),
+            "qsim_cost_features": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int,
+                                                  ctypes.POINTER(ctypes.c_float)]),
+            "qsim_mlp_param_count": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+            "qsim_set_cost_model": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_double,
+                                                   ctypes.c_double]),
+            "qsim_cost_model_predict_us": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, ctypes.c_int, i32p,
+                                                             ctypes.c_int]),
+            "qsim_mlp_predict_host": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, vp]),
+            "qsim_mlp_scratch_floats": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+            "qsim_mlp_forward": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp]),
+            "qsim_mlp_backward": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.c_int, vp, vp, vp,
+                                                 vp]),
+            "qsim_mlp_adam": (ctypes.c_int, [ctypes.c_int, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float,
+                                             ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]),
             "qsim_set_tune_entry": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
             "qsim_get_tune_entry": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
             "qsim_get_option": (ctypes.c_int, [ctypes.c_int]),
@@ -153,10 +169,11 @@ def run_opts(kmax=5, scheduler="greedy", fuse_diag=False, skip_trailing_diag=Fal
     return o
 
 
-def schedule(n: int, gates: Sequence, **opts) -> dict:
+def schedule(n: int, gates: Sequence, dtype: int = C64, **opts) -> dict:
     """Host-only: the schedule the library would run (no GPU needed)."""
     arr, keep = gate_array(gates)
     o = run_opts(**opts)
+    o.reserved[0] = dtype
     ng = len(gates)
     cap = max(1, ng)
     gate_op = (ctypes.c_int32 * max(1, ng))()
@@ -183,8 +200,136 @@ def get_option(option: int) -> int:
     return int(lib().qsim_get_option(option))
 
 
+def set_cost_table(dtype: int, us_by_k, n_ref: int):
+    """Analytic scheduler costs: us_by_k[k] microseconds per op at n_ref qubits (k = 0: diagonal pass)."""
+    a = (ctypes.c_double * 7)(*[float(x) for x in us_by_k])
+    _check(lib().qsim_set_cost_table(dtype, a, n_ref))
+
+
+def cost_features(n: int, dtype: int, qubits, n_epi: int = 0) -> np.ndarray:
+    """Feature vector of an op as the library computes it (k = len(qubits), sorted)."""
+    L = lib()
+    out = np.zeros(L.qsim_cost_feature_count(), np.float32)
+    qs = sorted(int(q) for q in qubits)
+    _check(L.qsim_cost_features(n, dtype, len(qs), _i32(qs), n_epi,
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+def _fp(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def set_cost_model(params=None, n_in=0, n_hidden=0, feat_mean=None, feat_std=None, y_mean=0.0, y_std=1.0):
+    """Load (or with params=None unload) the learned cost model into the scheduler."""
+    if params is None:
+        _check(lib().qsim_set_cost_model(None, 0, 0, None, None, 0.0, 1.0))
+        return
+    p = np.ascontiguousarray(params, np.float32)
+    m = np.ascontiguousarray(feat_mean, np.float32)
+    sd = np.ascontiguousarray(feat_std, np.float32)
+    _check(lib().qsim_set_cost_model(_fp(p), n_in, n_hidden, _fp(m), _fp(sd), float(y_mean), float(y_std)))
+
+
+def cost_model_predict_us(n: int, dtype: int, qubits, n_epi: int = 0) -> float:
+    qs = sorted(int(q) for q in qubits)
+    return float(lib().qsim_cost_model_predict_us(n, dtype, len(qs), _i32(qs), n_epi))
+
+
+def mlp_param_count(n_in: int, n_hidden: int) -> int:
+    return int(lib().qsim_mlp_param_count(n_in, n_hidden))
+
+
+def mlp_predict_host(params: np.ndarray, n_in: int, n_hidden: int, x: np.ndarray) -> np.ndarray:
+    p = np.ascontiguousarray(params, np.float32)
+    xx = np.ascontiguousarray(x, np.float32)
+    y = np.zeros(xx.shape[0], np.float32)
+    _check(lib().qsim_mlp_predict_host(_fp(p), n_in, n_hidden, _fp(xx), xx.shape[0], _fp(y)))
+    return y
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_forward(params, n_in: int, n_hidden: int, x, stream=None):
+    """GPU forward pass (torch float32 device tensors); returns y [batch]."""
+    import torch
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    _check(lib().qsim_mlp_forward(n_in, n_hidden, _dptr(params), _dptr(x), x.shape[0], _dptr(y),
+                                  ctypes.c_void_p(st.cuda_stream)))
+    return y
+
+
+def mlp_backward(params, n_in: int, n_hidden: int, x, target, stream=None):
+    """GPU gradient of the mean squared error; returns (grad [P], loss [1])."""
+    import torch
+    P = mlp_param_count(n_in, n_hidden)
+    grad = torch.empty(P, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    scratch = torch.empty(int(lib().qsim_mlp_scratch_floats(n_in, n_hidden, x.shape[0])), dtype=torch.float32,
+                          device=x.device)
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    _check(lib().qsim_mlp_backward(n_in, n_hidden, _dptr(params), _dptr(x), _dptr(target), x.shape[0],
+                                   _dptr(grad), _dptr(loss), _dptr(scratch), ctypes.c_void_p(st.cuda_stream)))
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(params.device)
+    _check(lib().qsim_mlp_adam(params.numel(), _dptr(params), _dptr(grad), _dptr(m), _dptr(v), step, lr, beta1,
+                               beta2, eps, ctypes.c_void_p(st.cuda_stream)))
+
+
 def workspace_bytes(n: int, dtype: int, kmax: int = 6) -> int:
     return int(lib().qsim_workspace_bytes(n, dtype, kmax))
+
+
+TUNE_PATH = os.path.join(_HERE, "tune_table.json")
+COST_MODEL_PATH = os.path.join(_HERE, "cost_model.npz")
+_tuning = {"loaded": False, "table": None, "model": None}
+
+
+def load_tuning(path: Optional[str] = None, model_path: Optional[str] = None) -> dict:
+    """Apply the autotuner's table (kernel variants, analytic costs) and the
+    learned cost model, if their files exist. Called once by State()."""
+    import json
+    path = path or TUNE_PATH
+    model_path = model_path or COST_MODEL_PATH
+    if os.path.exists(path):
+        with open(path) as f:
+            t = json.load(f)
+        L = lib()
+        for dt, rows in t.get("variants", {}).items():
+            code = C64 if dt == "c64" else C128
+            for k, row in rows.items():
+                for cls, v in enumerate(row):
+                    _check(L.qsim_set_tune_entry(code, int(k), cls, int(v)))
+        for dt, us in t.get("cost_us", {}).items():
+            set_cost_table(C64 if dt == "c64" else C128, us, int(t["n_ref"]))
+        _tuning["table"] = t
+    if os.path.exists(model_path):
+        m = np.load(model_path, allow_pickle=False)
+        set_cost_model(m["params"], int(m["n_in"]), int(m["n_hidden"]), m["feat_mean"], m["feat_std"],
+                       float(m["y_mean"]), float(m["y_std"]))
+        _tuning["model"] = model_path
+    _tuning["loaded"] = True
+    return _tuning
+
+
+def best_opts(n: int, dtype: str = "c64") -> dict:
+    """(scheduler, kmax) the autotuner found fastest for the nearest size
+    bucket at or below n (greedy, kmax 5 without a tune table)."""
+    t = _tuning.get("table") or {}
+    best = t.get("best", {}).get(dtype, {})
+    sizes = sorted(int(x) for x in best)
+    pick = [s for s in sizes if s <= n]
+    if not pick:
+        return dict(scheduler="greedy", kmax=5)
+    b = best[str(pick[-1])]
+    return dict(scheduler=b["scheduler"], kmax=int(b["kmax"]))
 
 
 class State:
@@ -193,6 +338,8 @@ class State:
     def __init__(self, n: int, dtype: str = "c64", init: str = "zero", kmax: int = 6,
                  amps=None, stream=None, device: int = 0):
         import torch
+        if not _tuning["loaded"] and not os.environ.get("QSIM_NO_TUNING"):
+            load_tuning()
         self.n = n
         self.dt = C64 if dtype in ("c64", "complex64") else C128
         tdt = torch.complex64 if self.dt == C64 else torch.complex128
