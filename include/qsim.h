@@ -206,9 +206,21 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * (dtype, k, low_class = number of targets among qubits 0..5, capped at 3) in
  * a tune table, which qsim_set_tune_entry overwrites (the autotuner fills it
  * from measurements). QSIM_OPT_CLUSTER_VARIANT = 0 or 1 forces one variant
- * everywhere, -1 (default) uses the table. Errors: QSIM_E_INVALID for an
- * unknown option or an out-of-range value. */
-typedef enum { QSIM_OPT_CLUSTER_VARIANT = 1 } qsim_option;
+ * everywhere, -1 (default) uses the table. Batches: QSIM_OPT_BATCH_GRID is
+ * the number of work-groups of the persistent launch (0, the default: two
+ * per compute unit, the kernel's occupancy); QSIM_OPT_BATCH_PAD picks the
+ * identity qubits that pad a cluster to 5 targets (0, default: the lowest
+ * qubits outside it, which lengthens the contiguous runs of a tile; 1: the
+ * highest); QSIM_OPT_BATCH_ITEM_TILES is the number of tiles (2^11
+ * amplitudes each) of one work item, a power of two in [1, 4096] (default
+ * 128), read when a batch is planned. Errors: QSIM_E_INVALID for an unknown
+ * option or an out-of-range value. */
+typedef enum {
+    QSIM_OPT_CLUSTER_VARIANT = 1,
+    QSIM_OPT_BATCH_GRID = 2,
+    QSIM_OPT_BATCH_PAD = 3,
+    QSIM_OPT_BATCH_ITEM_TILES = 4
+} qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);
 qsim_status qsim_set_tune_entry(qsim_dtype dt, int k, int low_class, int variant);
@@ -280,6 +292,58 @@ qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates,
                           const qsim_run_opts* opts, int32_t* gate_op, int32_t* gate_role,
                           int32_t* op_kind, int32_t* op_k, int32_t* op_qubits, int op_cap,
                           int* n_ops);
+
+/* ------------------------------------------------------------------ batches
+ * Many independent circuits in one persistent launch (complex64 states).
+ * Every circuit is scheduled as by qsim_run_circuit (greedy clusters of at
+ * most opts->kmax <= 5 qubits, Sec. 3.6; diagonal gates fused or in
+ * diagonal passes); each cluster is padded with identity qubits to 5 targets
+ * and each diagonal pass becomes an identity cluster with a diagonal
+ * epilogue, so that one matrix-core kernel applies every op. Matrices are
+ * built in float64 on the GPU and rounded to float32. Work items (one op,
+ * up to 32 tiles of 2^11 amplitudes) are taken from an atomic counter in
+ * dependency order; an item waits until every earlier op of its circuit is
+ * complete. */
+typedef struct qsim_batch_s* qsim_batch;
+
+typedef struct {
+    int32_t n_qubits;        /* 11 .. 30 */
+    int32_t n_gates;
+    const qsim_gate* gates;  /* host; read by qsim_batch_plan only */
+    void* dev_amps;          /* 2^n complex64, 256-byte aligned, caller-owned, one per circuit */
+} qsim_batch_circuit;
+
+typedef struct {
+    int32_t n_circuits;
+    int32_t n_ops;           /* initialisations + cluster ops, all circuits */
+    int32_t n_clusters;      /* cluster ops (padded clusters and diagonal passes) */
+    int32_t n_items;         /* work items of the persistent launch */
+    int32_t grid;            /* work-groups of the last run */
+    int32_t n_gates_applied; /* after the skips of opts */
+    double plan_ms;          /* host time of qsim_batch_plan */
+    double run_ms;           /* host wall time of the last qsim_batch_run */
+    size_t workspace_bytes;
+} qsim_batch_stats;
+
+/* Schedule and pack n_circuits circuits (host only; no GPU work). opts:
+ * kmax in [1, 5], scheduler GREEDY, ANALYTIC or LEARNED (PER_GATE is
+ * QSIM_E_UNSUPPORTED), fuse_diag, skip_trailing_diag, skip_initial_h.
+ * *workspace_bytes receives the device workspace qsim_batch_run needs. The
+ * circuit descriptors' amplitude pointers are kept; the gate lists are not. */
+qsim_status qsim_batch_plan(const qsim_batch_circuit* circuits, int n_circuits, const qsim_run_opts* opts,
+                            qsim_batch* out, size_t* workspace_bytes);
+
+/* Run a planned batch: initialise every state, apply every op, then wait
+ * for the stream (synchronous). dev_workspace: >= the planned bytes,
+ * 256-byte aligned, caller-owned; its contents are overwritten.
+ * wait_limit_us: longest time (device wall clock, microseconds) a work-group
+ * waits for an earlier op of its circuit (0 = 10 s); a wait that gives up
+ * sets an error flag, the launch still runs to its end, and the call returns
+ * QSIM_E_DEVICE (the states are then undefined). Runs of batches sharing
+ * states or a workspace must not overlap. stats (nullable) is filled. */
+qsim_status qsim_batch_run(qsim_batch b, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                           uint32_t wait_limit_us, qsim_batch_stats* stats);
+qsim_status qsim_batch_destroy(qsim_batch b);
 
 #ifdef __cplusplus
 }

@@ -11,29 +11,27 @@
 #include <string>
 #include <vector>
 
+#include "api_common.h"
 #include "qsim_internal.h"
 #include "scheduler.h"
 
 using namespace qsim;
+using namespace qsim::api;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-qsim_status fail(qsim_status st, const std::string& msg) {
+qsim_status qsim::api::fail(qsim_status st, const std::string& msg) {
     g_err = msg;
     return st;
 }
 
-qsim_status hip_fail(hipError_t e, const char* where) {
+qsim_status qsim::api::hip_fail(hipError_t e, const char* where) {
     return fail(QSIM_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(expr, where)                          \
-    do {                                              \
-        hipError_t e_ = (expr);                       \
-        if (e_ != hipSuccess) return hip_fail(e_, where); \
-    } while (0)
+namespace {
 
 // Workspace layout (byte offsets, 256-aligned).
 constexpr size_t kPartBytes = size_t(kReduceBlocks) * 8 * sizeof(double);  // partial sums
@@ -47,8 +45,6 @@ size_t slot_bytes(bool dbl, int kmax) {
     // the largest layout for k <= kmax (real-split 2^(k+1) squared or complex 2^k squared: equal size)
     return (size_t)matrix_bytes(std::max(1, std::min(kmax, kMaxK)), LAYOUT_MFMA32F, dbl);
 }
-
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -70,6 +66,9 @@ int get_tune_entry(bool dbl, int k, int cls) { return g_tune[dbl][k][cls]; }
 // one op by k (index 0 = diagonal pass) on a state of n_ref qubits, scaled by
 // 2^(n - n_ref) (every op streams the whole state). Defaults: a k-independent
 // cost, which reduces the cost-driven scheduler to "most gates per cluster".
+int g_batch_grid = 0;
+int g_batch_pad = 0;
+int g_batch_item_tiles = 128;
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
@@ -111,10 +110,10 @@ struct qsim_state_s {
 };
 
 namespace {
-
 bool is_named_1q(int kind) { return kind >= G_H && kind <= G_PHASE && kind != G_CZ; }
+}  // namespace
 
-qsim_status check_gate(const qsim_state_s* s, const qsim_gate& g, int idx) {
+qsim_status qsim::api::check_gate(int n, const qsim_gate& g, int idx) {
     const std::string at = "gate " + std::to_string(idx) + ": ";
     int nq;
     if (g.kind == G_CZ) nq = 2;
@@ -127,14 +126,70 @@ qsim_status check_gate(const qsim_state_s* s, const qsim_gate& g, int idx) {
     uint64_t m = 0;
     for (int j = 0; j < nq; ++j) {
         const int q = g.qubits[j];
-        if (q < 0 || q >= s->n) return fail(QSIM_E_INVALID, at + "qubit " + std::to_string(q) + " out of range");
+        if (q < 0 || q >= n) return fail(QSIM_E_INVALID, at + "qubit " + std::to_string(q) + " out of range");
         if (m >> q & 1) return fail(QSIM_E_INVALID, at + "repeated qubit " + std::to_string(q));
         m |= uint64_t(1) << q;
     }
     return QSIM_OK;
 }
 
-int gate_nq(const qsim_gate& g) { return g.kind == G_CZ ? 2 : (g.kind == G_DENSE ? g.k : 1); }
+int qsim::api::gate_nq(const qsim_gate& g) { return g.kind == G_CZ ? 2 : (g.kind == G_DENSE ? g.k : 1); }
+
+BuildGate qsim::api::to_build_gate(const qsim_gate& g, const int* pos_of, std::vector<double>& dense) {
+    BuildGate b;
+    std::memset(&b, 0, sizeof(b));
+    b.kind = g.kind;
+    b.nq = gate_nq(g);
+    for (int j = 0; j < b.nq; ++j) b.pos[j] = pos_of[g.qubits[j]];
+    b.theta = g.theta;
+    b.dense_off = -1;
+    if (g.kind == G_DENSE) {
+        b.dense_off = (int)dense.size();
+        const int cnt = 2 << (2 * g.k);
+        dense.insert(dense.end(), g.mat, g.mat + cnt);
+    }
+    return b;
+}
+
+qsim_status qsim::api::split_epilogue(const int* pos_of, const qsim_gate* gates, const std::vector<int>& epi_gates,
+                                      std::vector<BuildGate>& bgates, std::vector<double>& dense, EpiDesc& e) {
+    std::memset(&e, 0, sizeof(e));
+    for (int gi : epi_gates) {
+        const qsim_gate& g = gates[gi];
+        if (g.kind == G_CZ) {
+            const int a = g.qubits[0], b = g.qubits[1];
+            const bool ta = pos_of[a] >= 0, tb = pos_of[b] >= 0;
+            if (ta && tb) {
+                bgates.push_back(to_build_gate(g, pos_of, dense));
+            } else if (ta || tb) {
+                if (e.n_mix >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "epilogue too long");
+                e.mix[e.n_mix][0] = ta ? pos_of[a] : pos_of[b];
+                e.mix[e.n_mix][1] = ta ? b : a;
+                e.n_mix++;
+            } else {
+                if (e.n_cc >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "epilogue too long");
+                e.cc[e.n_cc][0] = a;
+                e.cc[e.n_cc][1] = b;
+                e.n_cc++;
+            }
+        } else {
+            const int q = g.qubits[0];
+            if (pos_of[q] >= 0) {
+                bgates.push_back(to_build_gate(g, pos_of, dense));
+            } else {
+                if (e.n_ph >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "epilogue too long");
+                const double ang = gate_phase_angle(g.kind, g.theta);
+                e.ph_q[e.n_ph] = q;
+                e.ph[e.n_ph][0] = std::cos(ang);
+                e.ph[e.n_ph][1] = std::sin(ang);
+                e.n_ph++;
+            }
+        }
+    }
+    return QSIM_OK;
+}
+
+namespace {
 
 // One chunk of work: descriptors packed on the host, uploaded once.
 struct Chunk {
@@ -273,22 +328,6 @@ qsim_status diag_desc(int n, const std::vector<std::pair<int, int>>& pairs,
     return QSIM_OK;
 }
 
-BuildGate to_build_gate(const qsim_gate& g, const int* pos_of, std::vector<double>& dense) {
-    BuildGate b;
-    std::memset(&b, 0, sizeof(b));
-    b.kind = g.kind;
-    b.nq = gate_nq(g);
-    for (int j = 0; j < b.nq; ++j) b.pos[j] = pos_of[g.qubits[j]];
-    b.theta = g.theta;
-    b.dense_off = -1;
-    if (g.kind == G_DENSE) {
-        b.dense_off = (int)dense.size();
-        const int cnt = 2 << (2 * g.k);
-        dense.insert(dense.end(), g.mat, g.mat + cnt);
-    }
-    return b;
-}
-
 // Add a cluster op (sorted qubits, member gates, epilogue gates) to the chunk;
 // flushes first if the chunk is full.
 qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, const qsim_gate* gates,
@@ -316,34 +355,7 @@ qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, con
     for (int gi : members) c.bgates.push_back(to_build_gate(gates[gi], pos_of, c.dense));
     // epilogue: terms on target qubits only join the matrix, the rest go to the descriptor
     EpiDesc e;
-    std::memset(&e, 0, sizeof(e));
-    for (int gi : epi_gates) {
-        const qsim_gate& g = gates[gi];
-        if (g.kind == G_CZ) {
-            const int a = g.qubits[0], b = g.qubits[1];
-            const bool ta = pos_of[a] >= 0, tb = pos_of[b] >= 0;
-            if (ta && tb) {
-                c.bgates.push_back(to_build_gate(g, pos_of, c.dense));
-            } else if (ta || tb) {
-                if (e.n_mix >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "epilogue too long");
-                e.mix[e.n_mix][0] = ta ? pos_of[a] : pos_of[b];
-                e.mix[e.n_mix][1] = ta ? b : a;
-                e.n_mix++;
-            } else {
-                if (e.n_cc >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "epilogue too long");
-                e.cc[e.n_cc][0] = a; e.cc[e.n_cc][1] = b; e.n_cc++;
-            }
-        } else {
-            const int q = g.qubits[0];
-            if (pos_of[q] >= 0) {
-                c.bgates.push_back(to_build_gate(g, pos_of, c.dense));
-            } else {
-                if (e.n_ph >= kEpiMax) return fail(QSIM_E_UNSUPPORTED, "epilogue too long");
-                const double ang = gate_phase_angle(g.kind, g.theta);
-                e.ph_q[e.n_ph] = q; e.ph[e.n_ph][0] = std::cos(ang); e.ph[e.n_ph][1] = std::sin(ang); e.n_ph++;
-            }
-        }
-    }
+    if (qsim_status r = split_epilogue(pos_of, gates, epi_gates, c.bgates, c.dense, e)) return r;
     bo.n_gates = (int)c.bgates.size() - bo.gate0;
     c.bops.push_back(bo);
     Chunk::Item it;
@@ -418,7 +430,9 @@ qsim_status check_state(qsim_state s) {
     return QSIM_OK;
 }
 
-std::vector<SGate> to_sgates(const qsim_gate* gates, int n_gates) {
+}  // namespace
+
+std::vector<SGate> qsim::api::to_sgates(const qsim_gate* gates, int n_gates) {
     std::vector<SGate> sg(n_gates);
     for (int i = 0; i < n_gates; ++i) {
         sg[i].kind = gates[i].kind;
@@ -430,7 +444,7 @@ std::vector<SGate> to_sgates(const qsim_gate* gates, int n_gates) {
 }
 
 // Cost function of the cost-driven schedulers (empty for the others).
-OpCostFn cost_fn(const qsim_run_opts* o, int n, bool dbl) {
+OpCostFn qsim::api::cost_fn(const qsim_run_opts* o, int n, bool dbl) {
     if (!o || o->scheduler == QSIM_SCHED_PER_GATE || o->scheduler == QSIM_SCHED_GREEDY) return OpCostFn();
     if (o->scheduler == QSIM_SCHED_LEARNED && learned_model_loaded()) {
         return [n, dbl](int k, const int* q, int n_epi) { return learned_cost_us(n, dbl, k, q, n_epi); };
@@ -440,7 +454,7 @@ OpCostFn cost_fn(const qsim_run_opts* o, int n, bool dbl) {
     return [scale, us](int k, const int*, int) { return us[k] * scale; };
 }
 
-SchedOpts to_sched_opts(const qsim_run_opts* o) {
+SchedOpts qsim::api::to_sched_opts(const qsim_run_opts* o) {
     SchedOpts so;
     if (!o) return so;
     so.kmax = o->kmax;
@@ -451,8 +465,6 @@ SchedOpts to_sched_opts(const qsim_run_opts* o) {
     so.skip_initial_h = o->skip_initial_h != 0;
     return so;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -522,7 +534,7 @@ qsim_status qsim_apply_cluster(qsim_state s, int k, const int32_t* qubits, const
     g.k = k;
     for (int j = 0; j < k; ++j) g.qubits[j] = qubits[j];
     g.mat = mat;
-    if (qsim_status r = check_gate(s, g, 0)) return r;
+    if (qsim_status r = check_gate(s->n, g, 0)) return r;
     Chunk c;
     if (qsim_status r = add_gate(s, c, &g, 0)) return r;
     return flush(s, c);
@@ -555,7 +567,7 @@ qsim_status qsim_apply_diag(qsim_state s, int n_pairs, const int32_t* cz_pairs, 
 qsim_status qsim_apply_gate(qsim_state s, const qsim_gate* gate) {
     if (qsim_status r = check_state(s)) return r;
     if (!gate) return fail(QSIM_E_INVALID, "null gate");
-    if (qsim_status r = check_gate(s, *gate, 0)) return r;
+    if (qsim_status r = check_gate(s->n, *gate, 0)) return r;
     if (gate->kind == G_DENSE && gate->k > s->kmax_ws)
         return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
     Chunk c;
@@ -569,7 +581,7 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     if (qsim_status r = check_state(s)) return r;
     if (n_gates < 0 || (n_gates && !gates)) return fail(QSIM_E_INVALID, "bad gate list");
     for (int i = 0; i < n_gates; ++i)
-        if (qsim_status r = check_gate(s, gates[i], i)) return r;
+        if (qsim_status r = check_gate(s->n, gates[i], i)) return r;
     SchedOpts so = to_sched_opts(opts);
     if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 6]");
     if (so.mode != 0 && so.kmax > s->kmax_ws) return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
@@ -674,6 +686,22 @@ qsim_status qsim_set_option(int option, int value) {
         set_cluster_variant(value);
         return QSIM_OK;
     }
+    if (option == QSIM_OPT_BATCH_GRID) {
+        if (value < 0 || value > (1 << 20)) return fail(QSIM_E_INVALID, "batch grid must be in [0, 2^20]");
+        g_batch_grid = value;
+        return QSIM_OK;
+    }
+    if (option == QSIM_OPT_BATCH_PAD) {
+        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "batch padding must be 0 or 1");
+        g_batch_pad = value;
+        return QSIM_OK;
+    }
+    if (option == QSIM_OPT_BATCH_ITEM_TILES) {
+        if (value < 1 || value > 4096 || (value & (value - 1)))
+            return fail(QSIM_E_INVALID, "tiles per batch item must be a power of two in [1, 4096]");
+        g_batch_item_tiles = value;
+        return QSIM_OK;
+    }
     return fail(QSIM_E_INVALID, "unknown option");
 }
 
@@ -703,6 +731,9 @@ int qsim_get_tune_entry(qsim_dtype dt, int k, int low_class) {
 
 int qsim_get_option(int option) {
     if (option == QSIM_OPT_CLUSTER_VARIANT) return get_cluster_variant();
+    if (option == QSIM_OPT_BATCH_GRID) return g_batch_grid;
+    if (option == QSIM_OPT_BATCH_PAD) return g_batch_pad;
+    if (option == QSIM_OPT_BATCH_ITEM_TILES) return g_batch_item_tiles;
     return -1;
 }
 
@@ -733,10 +764,8 @@ qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates, con
                           int32_t* op_qubits, int op_cap, int* n_ops) {
     if (n_qubits < 1 || n_qubits > 64) return fail(QSIM_E_UNSUPPORTED, "n_qubits out of range");
     if (n_gates < 0 || (n_gates && !gates)) return fail(QSIM_E_INVALID, "bad gate list");
-    qsim_state_s tmp;
-    tmp.n = n_qubits;
     for (int i = 0; i < n_gates; ++i)
-        if (qsim_status r = check_gate(&tmp, gates[i], i)) return r;
+        if (qsim_status r = check_gate(n_qubits, gates[i], i)) return r;
     SchedOpts so = to_sched_opts(opts);
     if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 6]");
     const Schedule S = make_schedule(n_qubits, to_sgates(gates, n_gates), so,

@@ -129,6 +129,30 @@ struct StageGeom {
     uint64_t ioff[32];   // state offset of linear chunk i (tau = i << lane_bits ...)
 };
 
+// Batched persistent launch: every op is a 5-qubit float cluster (smaller
+// clusters padded with identity qubits) applied by the staged kernel, or the
+// initialisation of a state. Device pointers are filled in at run time.
+struct BatchOp {
+    float2* psi;           // the circuit's state
+    const float* A;        // permuted real-split matrix (clusters)
+    const EpiDesc* epi;    // diagonal epilogue or null
+    StageGeom sg;          // tile geometry (clusters)
+    uint64_t tiles;        // wave tiles of 2^11 amplitudes
+    int32_t kind;          // 0 cluster, 1 |0..0>, 2 uniform
+    int32_t circuit;
+    int32_t lowt;          // target 0 is a cluster qubit
+    int32_t n;             // qubits of the state
+    uint32_t dep;          // items of this circuit that must be complete first
+    uint32_t pad;
+};
+struct BatchItem {
+    uint32_t op;
+    uint32_t tile0;        // tiles [tile0, tile0 + item_tiles) of the op
+};
+extern int g_batch_grid;        // work-groups of the batch launch, 0 = two per CU
+extern int g_batch_pad;         // padding qubits: 0 lowest outside the cluster, 1 highest
+extern int g_batch_item_tiles;  // tiles of 2^11 amplitudes per work item
+
 // Bytes of a cluster matrix in each layout.
 inline int64_t matrix_bytes(int k, int layout, bool dbl) {
     const int64_t d = int64_t(1) << k;
@@ -165,6 +189,10 @@ void set_tune_entry(bool dbl, int k, int cls, int variant);
 int get_tune_entry(bool dbl, int k, int cls);
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout);
 hipError_t launch_diag(void* psi, bool dbl, int n, const EpiDesc* epi, hipStream_t st);
+StageGeom make_stage_geom(const ClusterGeom& g, int C, int unit);
+hipError_t launch_batch(const BatchOp* ops, const BatchItem* items, uint32_t n_items, uint32_t* counters,
+                        uint32_t n_circuits, uint32_t item_tiles, uint64_t wait_ticks, unsigned grid,
+                        hipStream_t st);
 hipError_t launch_gate1q(void* psi, bool dbl, int n, int q, const double m[8], hipStream_t st);
 hipError_t launch_phase1q(void* psi, bool dbl, int n, int q, double cs, double sn, hipStream_t st);
 hipError_t launch_cz(void* psi, bool dbl, int n, int a, int b, hipStream_t st);

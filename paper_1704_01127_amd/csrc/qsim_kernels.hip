@@ -66,8 +66,8 @@ struct ColFactor {
     T cr, ci;
 };
 
-template <typename T>
-__device__ __forceinline__ ColFactor<T> col_factor(const EpiDesc* __restrict__ e, uint64_t base) {
+template <typename T, typename E>
+__device__ __forceinline__ ColFactor<T> col_factor(E* __restrict__ e, uint64_t base) {
     ColFactor<T> f{0u, 0u, T(1), T(0)};
     const int ncc = e->n_cc;
     for (int i = 0; i < ncc; ++i)
@@ -102,6 +102,35 @@ __device__ __forceinline__ void apply_factor(T& re, T& im, const ColFactor<T>& f
     const bool neg = ((f.sgn ^ (uint32_t)__popc(y & f.w)) & 1u) != 0;
     re = neg ? -re : re;
     im = neg ? -im : im;
+}
+
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+// Explicitly global pointers for code that also runs on pointers read from a
+// descriptor (the compiler would otherwise use flat memory instructions,
+// whose outstanding loads also hold up every LDS wait).
+#define QSIM_GLOBAL __attribute__((address_space(1)))
+typedef QSIM_GLOBAL float2 g_float2;
+typedef QSIM_GLOBAL vf4 g_vf4;
+typedef const QSIM_GLOBAL EpiDesc g_epi;
+
+// Copy a cluster matrix of N elements into LDS: 16-byte loads, all in flight
+// before the first LDS store (a loop of single loads would wait for each).
+template <int N, int THREADS, typename T, typename V4>
+__device__ __forceinline__ void load_matrix(T* __restrict__ dst, const V4* __restrict__ src) {
+    typedef vf4 v4;
+    constexpr int CHUNKS = N * (int)sizeof(T) / 16;
+    static_assert(N * sizeof(T) % 16 == 0, "matrix is a whole number of 16-byte chunks");
+    constexpr int PER = CHUNKS / THREADS;
+    constexpr int REST = CHUNKS % THREADS;
+    v4 r[PER > 0 ? PER : 1];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) r[i] = src[threadIdx.x + i * THREADS];
+    v4 t{0.0f, 0.0f, 0.0f, 0.0f};
+    if (REST && threadIdx.x < REST) t = src[PER * THREADS + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) reinterpret_cast<v4*>(dst)[threadIdx.x + i * THREADS] = r[i];
+    if (REST && threadIdx.x < REST) reinterpret_cast<v4*>(dst)[PER * THREADS + threadIdx.x] = t;
 }
 
 // ------------------------------------------------------------ cluster: MFMA, float
@@ -187,7 +216,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_mfma(float2* __restrict_
     constexpr int RB = 2 * D / 32;  // 32-row blocks of the real-split matrix
     constexpr int S = D;            // MFMA steps (inner dimension 2^(K+1), 2 per step)
     __shared__ float As[RB * S * 64];
-    for (int i = threadIdx.x; i < RB * S * 64; i += 256) As[i] = Ap[i];
+    load_matrix<RB * S * 64, 256>(As, reinterpret_cast<const vf4*>(Ap));
     __syncthreads();
 
     const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
@@ -280,7 +309,7 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_mfma(dou
     constexpr int COLS = 16 * NB;
     constexpr int WAVES = THREADS / 64;
     __shared__ double As[RB * S * 64];
-    for (int i = threadIdx.x; i < RB * S * 64; i += THREADS) As[i] = Ap[i];
+    load_matrix<RB * S * 64, THREADS>(As, reinterpret_cast<const vf4*>(Ap));
     __syncthreads();
 
     const int lane = threadIdx.x & 63, p = lane & 15, q = lane >> 4;
@@ -370,8 +399,7 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_mfma(dou
 // buffer of the wave; the next tile's linear loads are in flight while the
 // current tile's MFMA chain runs.
 
-typedef float vf4 __attribute__((ext_vector_type(4)));
-typedef double vd2 __attribute__((ext_vector_type(2)));
+
 
 // LDS exchange between lanes of one wave: LDS operations of a wave execute in
 // order, so only the compiler must be kept from reordering them.
@@ -423,10 +451,10 @@ struct StageF32 {
     static constexpr int HX = (1 << K) / 2;
     static constexpr int NB = (1 << C) / 32;
     static constexpr int NL = (1 << (K + C)) / 128;
-    __device__ __forceinline__ static void load_lin(const float2* __restrict__ psi, uint64_t b0, const StageGeom& sg,
-                                                    vf4 (&R)[NL]) {
+    __device__ __forceinline__ static void load_lin(const g_float2* __restrict__ psi, uint64_t b0,
+                                                    const StageGeom& sg, vf4 (&R)[NL]) {
 #pragma unroll
-        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const vf4*>(psi + (b0 | sg.ioff[i]));
+        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const g_vf4*>(psi + (b0 | sg.ioff[i]));
     }
     __device__ __forceinline__ static void stage_in(vf4* L4, int lane, const int (&tc)[NB], int th,
                                                     const StageGeom& sg, const vf4 (&R)[NL],
@@ -458,11 +486,13 @@ struct StageF32 {
 // float: lane l covers tau = 2 (i * 64 + l) + {0, 1} in linear order. In MFMA
 // order lane (p, h) owns target indices j | h << (K-1) of columns 2p, 2p+1
 // (tau bit 0 is a column bit) or p, p+32 (tau bit 0 is target 0, LOWT).
+//
+// One wave applies the cluster whose matrix is in LDS (As) to tiles
+// tile, tile + stride, ... < tile_end, staging through its LDS buffer L4.
 template <int K, int C, bool LOWT>
-__global__ __launch_bounds__(256, 2) void k_cluster_f32_stage(float2* __restrict__ psi,
-                                                              const float* __restrict__ Ap,
-                                                              const EpiDesc* __restrict__ epi, ClusterGeom g,
-                                                              StageGeom sg) {
+__device__ __forceinline__ void staged_f32_tiles(g_float2* __restrict__ psi, const float* As, vf4* L4,
+                                                 g_epi* __restrict__ epi, const StageGeom& sg,
+                                                 uint64_t tile, uint64_t tile_end, uint64_t stride) {
     constexpr int D = 1 << K;
     constexpr int HX = D / 2;
     constexpr int RB = 2 * D / 32;
@@ -472,13 +502,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_stage(float2* __restrict
     constexpr int TILE = 1 << NT;
     constexpr int NL = TILE / 128;
     static_assert(NB == 2, "two column blocks per lane");
-    __shared__ float As[RB * S * 64];
-    __shared__ vf4 Ls[4][TILE / 2];
-    for (int i = threadIdx.x; i < RB * S * 64; i += 256) As[i] = Ap[i];
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5, w = threadIdx.x >> 6;
-    vf4* L4 = Ls[w];
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     uint64_t lane_off = 0;
 #pragma unroll
     for (int b = 0; b < 6; ++b)
@@ -498,12 +522,10 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_stage(float2* __restrict
         }
     }
     const int th = h << sg.tpos[K - 1];
-    const uint64_t ntiles = g.ncols >> C;
-    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    const uint64_t ntiles = tile_end;
     const bool has_epi = epi != nullptr;
     const bool has_ph = has_epi && epi->n_ph > 0;
 
-    uint64_t tile = (uint64_t)blockIdx.x * 4 + w;
     if (tile >= ntiles) return;
     const uint64_t last = ntiles - 1;
     vf4 R[NL];
@@ -572,13 +594,33 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_stage(float2* __restrict
 #pragma unroll
             for (int i = 0; i < NL; ++i) {
                 const vf4 v = L4[i * 64 + lane];
-                *reinterpret_cast<vf4*>(psi + (b0 | sg.ioff[i])) = v;
+                *reinterpret_cast<g_vf4*>(psi + (b0 | sg.ioff[i])) = v;
             }
         }
         wave_lds_fence();
         StageF32<K, C, LOWT>::stage_in(L4, lane, tc, th, sg, R, B);
         tile += stride;
     } while (tile < ntiles);
+}
+
+
+
+template <int K, int C, bool LOWT>
+__global__ __launch_bounds__(256, 2) void k_cluster_f32_stage(float2* __restrict__ psi,
+                                                              const float* __restrict__ Ap,
+                                                              const EpiDesc* __restrict__ epi, ClusterGeom g,
+                                                              StageGeom sg) {
+    constexpr int D = 1 << K;
+    constexpr int RB = 2 * D / 32;
+    constexpr int S = D;
+    constexpr int TILE = 1 << (K + C);
+    __shared__ float As[RB * S * 64];
+    __shared__ vf4 Ls[4][TILE / 2];
+    load_matrix<RB * S * 64, 256>(As, reinterpret_cast<const vf4*>(Ap));
+    __syncthreads();
+    const int w = threadIdx.x >> 6;
+    staged_f32_tiles<K, C, LOWT>((g_float2*)psi, As, Ls[w], (g_epi*)epi, sg, (uint64_t)blockIdx.x * 4 + w,
+                                 g.ncols >> C, (uint64_t)gridDim.x * 4);
 }
 
 template <int K, int C>
@@ -627,7 +669,7 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd
     constexpr int WAVES = THREADS / 64;
     __shared__ double As[RB * S * 64];
     __shared__ vd2 Ls[WAVES][TILE];
-    for (int i = threadIdx.x; i < RB * S * 64; i += THREADS) As[i] = Ap[i];
+    load_matrix<RB * S * 64, THREADS>(As, reinterpret_cast<const vf4*>(Ap));
     __syncthreads();
 
     const int lane = threadIdx.x & 63, p = lane & 15, q = lane >> 4, w = threadIdx.x >> 6;
@@ -705,6 +747,107 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd
         StageF64<K, C>::stage_in(L, lane, tc, tq, sg, R, B);
         tile += stride;
     } while (tile < ntiles);
+}
+
+// ------------------------------------------------------------ batched persistent launch
+// Many independent circuits in one launch. Work items (an op and a run of its
+// tiles) are handed out by an atomic ticket in dependency order -
+// the j-th op of every circuit before any (j+1)-th op - so an item only ever
+// waits for items with smaller tickets, which running work-groups hold. Before
+// starting, a work-group waits until all earlier items of its circuit are
+// complete (per-circuit counter, release / acquire at device scope); the wait
+// is bounded by the device's wall clock and sets an error flag instead of
+// hanging. counters: [0] ticket, [1] error flag, [2 + c] completed items of
+// circuit c.
+//
+// Loop shape: the loop body ends with a work-group barrier, and the single
+// thread-0 block (publish the previous item, take a ticket) opens it, so the
+// loop has one latch that every thread passes. A thread-0 block just before
+// the back edge would give the header two back edges; the compiler may then
+// split the loop into an inner loop that every other thread keeps running -
+// through the barriers, re-reading a stale ticket - while thread 0 waits
+// outside it. The ticket goes through readfirstlane so that the exit test is
+// uniform, too.
+__global__ __launch_bounds__(256, 2) void k_batch_f32(const BatchOp* __restrict__ ops,
+                                                      const BatchItem* __restrict__ items, uint32_t n_items,
+                                                      uint32_t* counters, uint32_t item_tiles, uint64_t wait_ticks) {
+    constexpr int K = 5, C = 6;
+    __shared__ float As[2 * 32 * 64];
+    __shared__ vf4 Ls[4][1 << (K + C - 1)];
+    // the ticket is broadcast through the matrix buffer (an extra LDS word
+    // would leave room for only one work-group per CU)
+    uint32_t* s_it = reinterpret_cast<uint32_t*>(As);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t* done = counters + 2;
+    int prev = -1;  // circuit of the item just finished (uniform)
+    for (;;) {
+        if (threadIdx.x == 0) {
+            // the previous item's stores are complete and released (fence + barrier below)
+            if (prev >= 0) __hip_atomic_fetch_add(done + prev, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            *s_it = atomicAdd(counters, 1u);
+        }
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(*s_it);
+        if (it >= n_items) break;
+        const BatchItem item = items[it];
+        const BatchOp* op = ops + item.op;
+        const uint32_t dep = op->dep;
+        const int circ = op->circuit;
+        if (threadIdx.x == 0 && dep > 0) {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(done + circ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < dep) {
+                if (wall_clock64() - t0 > wait_ticks) {
+                    atomicOr(counters + 1, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const uint64_t tiles = op->tiles;
+        const uint64_t t_end = item.tile0 + item_tiles < tiles ? item.tile0 + item_tiles : tiles;
+        g_float2* psi = (g_float2*)op->psi;
+        if (op->kind == 0) {
+            const g_vf4* A = (const g_vf4*)op->A;
+            g_epi* epi = (g_epi*)op->epi;
+            load_matrix<2 * 32 * 64, 256>(As, A);
+            __syncthreads();
+            if (op->lowt)
+                staged_f32_tiles<K, C, true>(psi, As, Ls[w], epi, op->sg, item.tile0 + w, t_end, 4);
+            else
+                staged_f32_tiles<K, C, false>(psi, As, Ls[w], epi, op->sg, item.tile0 + w, t_end, 4);
+        } else {
+            // initialisation: tile t is amplitudes [t 2^11, (t + 1) 2^11)
+            // 2^(-n/2): a power of two, times 1/sqrt(2) for odd n (both exact scalings of a rounded constant)
+            const float val = op->kind == 1 ? 0.0f
+                                            : __builtin_ldexpf((op->n & 1) ? 0.70710678118654752440f : 1.0f,
+                                                               -(op->n >> 1));
+            g_vf4* p4 = reinterpret_cast<g_vf4*>(psi);
+            for (uint64_t t = item.tile0 + w; t < t_end; t += 4) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const uint64_t q = (t << 10) + (uint64_t)(i * 64 + lane);  // index of an amplitude pair
+                    vf4 v = {val, 0.0f, val, 0.0f};
+                    if (op->kind == 1 && q == 0) v.x = 1.0f;
+                    p4[q] = v;
+                }
+            }
+        }
+        // every wave waits until its stores are complete in L2; after the
+        // barrier, thread 0's device-scope release (an L2 write-back, then the
+        // counter) publishes them all. A release fence in every wave would
+        // write the L2 back once per wave, which costs more than the tiles.
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        prev = circ;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ------------------------------------------------------------ cluster: vector ALU
@@ -1113,7 +1256,7 @@ hipError_t launch_build(const BuildOp* ops, int n_ops, const BuildGate* gates, c
 
 // Tile geometry of the staged kernels: the C lowest non-target bits are the
 // columns; chunk i of the linear order starts at tau = i << unit.
-static StageGeom make_stage_geom(const ClusterGeom& g, int C, int unit) {
+StageGeom make_stage_geom(const ClusterGeom& g, int C, int unit) {
     StageGeom sg;
     std::memset(&sg, 0, sizeof(sg));
     uint64_t tmask = 0;
@@ -1255,6 +1398,16 @@ hipError_t launch_diag(void* psi, bool dbl, int n, const EpiDesc* epi, hipStream
         hipLaunchKernelGGL(k_diag<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, n, epi);
     else
         hipLaunchKernelGGL(k_diag<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, n, epi);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchOp* ops, const BatchItem* items, uint32_t n_items, uint32_t* counters,
+                        uint32_t n_circuits, uint32_t item_tiles, uint64_t wait_ticks, unsigned grid,
+                        hipStream_t st) {
+    const uint32_t nc = n_circuits + 2;
+    hipLaunchKernelGGL(k_fill_u32, dim3((nc + 255) / 256), dim3(256), 0, st, counters, nc, 0u);
+    hipLaunchKernelGGL(k_batch_f32, dim3(grid), dim3(256), 0, st, ops, items, n_items, counters, item_tiles,
+                       wait_ticks);
     return hipGetLastError();
 }
 

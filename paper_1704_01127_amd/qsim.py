@@ -22,6 +22,7 @@ SCHED_PER_GATE, SCHED_GREEDY, SCHED_ANALYTIC, SCHED_LEARNED = 0, 1, 2, 3
 GATE_KIND = {"H": 0, "T": 1, "SX": 2, "SY": 3, "X": 4, "Y": 5, "Z": 6, "CZ": 7, "TDG": 8,
              "SXDG": 9, "SYDG": 10, "PHASE": 11, "U": 12}
 STATUS = {0: "QSIM_OK", -1: "QSIM_E_INVALID", -2: "QSIM_E_UNSUPPORTED", -3: "QSIM_E_DEVICE"}
+OK, E_INVALID, E_UNSUPPORTED, E_DEVICE = 0, -1, -2, -3
 SCHEDULERS = {"per_gate": 0, "greedy": 1, "analytic": 2, "learned": 3}
 
 
@@ -54,6 +55,20 @@ class RunStats(ctypes.Structure):
                     n_diag_ops=self.n_diag_ops, n_gates_applied=self.n_gates_applied,
                     n_gates_fused_epilogue=self.n_gates_fused_epilogue,
                     schedule_ms=self.schedule_ms, total_ms=self.total_ms)
+
+
+class BatchCircuit(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32), ("gates", ctypes.POINTER(Gate)),
+                ("dev_amps", ctypes.c_void_p)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("n_circuits", ctypes.c_int32), ("n_ops", ctypes.c_int32), ("n_clusters", ctypes.c_int32),
+                ("n_items", ctypes.c_int32), ("grid", ctypes.c_int32), ("n_gates_applied", ctypes.c_int32),
+                ("plan_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _lib = None
@@ -112,6 +127,13 @@ def lib():
                                              ctypes.POINTER(RunOpts), i32p, i32p, i32p, i32p, i32p,
                                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         }
+        sig.update({
+            "qsim_batch_plan": (ctypes.c_int, [ctypes.POINTER(BatchCircuit), ctypes.c_int, ctypes.POINTER(RunOpts),
+                                               ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]),
+            "qsim_batch_run": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, ctypes.c_uint32,
+                                              ctypes.POINTER(BatchStats)]),
+            "qsim_batch_destroy": (ctypes.c_int, [vp]),
+        })
         for name, (res, args) in sig.items():
             f = getattr(L, name)
             f.restype = res
@@ -190,6 +212,9 @@ def schedule(n: int, gates: Sequence, dtype: int = C64, **opts) -> dict:
 
 
 OPT_CLUSTER_VARIANT = 1
+OPT_BATCH_GRID = 2
+OPT_BATCH_PAD = 3
+OPT_BATCH_ITEM_TILES = 4
 
 
 def set_option(option: int, value: int):
@@ -444,3 +469,53 @@ class State:
 
     def sync(self):
         _check(lib().qsim_sync(self.h))
+
+
+class Batch:
+    """Many independent circuits run by one persistent launch (complex64).
+
+    circuits: objects with .n and .gates (or (n, gates) tuples). The states
+    are torch complex64 tensors (self.states[i]) owned here, as is the
+    workspace; plan at construction, run() as often as wanted."""
+
+    def __init__(self, circuits: Sequence, kmax: int = 5, scheduler: str = "greedy", fuse_diag: bool = True,
+                 skip_trailing_diag: bool = False, skip_initial_h: bool = True, stream=None, device: int = 0):
+        import torch
+        if not _tuning["loaded"] and not os.environ.get("QSIM_NO_TUNING"):
+            load_tuning()
+        dev = torch.device("cuda", device)
+        self.ns = [int(c[0] if isinstance(c, tuple) else c.n) for c in circuits]
+        gate_lists = [c[1] if isinstance(c, tuple) else c.gates for c in circuits]
+        self.states = [torch.empty(2 ** n, dtype=torch.complex64, device=dev) for n in self.ns]
+        arr = (BatchCircuit * max(1, len(circuits)))()
+        keep = []
+        for i, (n, gl) in enumerate(zip(self.ns, gate_lists)):
+            ga, kp = gate_array(gl)
+            keep.append((ga, kp))
+            arr[i].n_qubits = n
+            arr[i].n_gates = len(gl)
+            arr[i].gates = ctypes.cast(ga, ctypes.POINTER(Gate))
+            arr[i].dev_amps = self.states[i].data_ptr()
+        o = run_opts(kmax=kmax, scheduler=scheduler, fuse_diag=fuse_diag, skip_trailing_diag=skip_trailing_diag,
+                     skip_initial_h=skip_initial_h)
+        h = ctypes.c_void_p()
+        wsb = ctypes.c_size_t()
+        _check(lib().qsim_batch_plan(arr, len(circuits), ctypes.byref(o), ctypes.byref(h), ctypes.byref(wsb)))
+        self.h = h
+        self.workspace = torch.empty(max(256, wsb.value), dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.qsim_batch_destroy(h)
+            self.h = None
+
+    def run(self, wait_limit_us: int = 0) -> dict:
+        """Initialise and run every circuit; returns the launch statistics.
+        wait_limit_us bounds each dependency wait (0: the library default)."""
+        st = BatchStats()
+        _check(lib().qsim_batch_run(self.h, ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                    ctypes.c_void_p(self.stream.cuda_stream), wait_limit_us, ctypes.byref(st)))
+        return st.as_dict()
+

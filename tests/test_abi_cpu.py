@@ -52,3 +52,40 @@ def test_schedule_rejects_bad_gates():
         qsim.schedule(4, [("CZ", (1, 1))])
     with pytest.raises(qsim.QsimError, match="kmax"):
         qsim.schedule(4, [("H", (0,))], kmax=7)
+
+
+def test_batch_plan_host_checks():
+    """Batch planning is host-only: its argument checks and workspace sizing
+    run without a GPU (the amplitude pointers are never dereferenced)."""
+    import ctypes
+    from paper_1704_01127_amd import qsim
+    from supremacy_inputs import supremacy_circuit
+    L = qsim.lib()
+    circ = supremacy_circuit(3, 4, 12, 1)
+    ga, keep = qsim.gate_array(circ.gates)
+
+    def plan(n=12, ptrs=(1 << 20, 2 << 20), **opts):
+        arr = (qsim.BatchCircuit * len(ptrs))()
+        for i, p in enumerate(ptrs):
+            arr[i].n_qubits = n
+            arr[i].n_gates = len(circ.gates)
+            arr[i].gates = ctypes.cast(ga, ctypes.POINTER(qsim.Gate))
+            arr[i].dev_amps = p
+        o = qsim.run_opts(**dict(dict(kmax=5, fuse_diag=True), **opts))
+        h, ws = ctypes.c_void_p(), ctypes.c_size_t()
+        st = L.qsim_batch_plan(arr, len(ptrs), ctypes.byref(o), ctypes.byref(h), ctypes.byref(ws))
+        if st == 0:
+            L.qsim_batch_destroy(h)
+        return st, ws.value
+
+    st, ws = plan()
+    assert st == 0 and ws > 2 * 16384
+    st2, ws2 = plan(fuse_diag=False)
+    assert st2 == 0 and ws2 >= ws  # diagonal passes become extra cluster ops
+    assert plan(kmax=6)[0] == qsim.E_UNSUPPORTED
+    assert plan(scheduler="per_gate")[0] == qsim.E_UNSUPPORTED
+    assert plan(n=10)[0] == qsim.E_UNSUPPORTED      # below one tile
+    assert plan(ptrs=(1 << 20, 1 << 20))[0] == qsim.E_INVALID  # shared state
+    assert plan(ptrs=(1 << 20, (2 << 20) + 8))[0] == qsim.E_INVALID  # unaligned
+    assert plan(n=11)[0] == qsim.E_INVALID          # the circuit's qubit 11 is out of range
+    assert L.qsim_batch_run(None, None, 0, None, 0, None) == qsim.E_INVALID

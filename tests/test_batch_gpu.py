@@ -1,0 +1,163 @@
+"""Parity of the batched persistent launch (through the C ABI) with the CPU
+oracle: many circuits of uneven sizes in one launch, each compared with the
+oracle's float64 state (complex64 whole-circuit bar: fidelity >= 1 - 1e-6,
+max |d amp| <= 1e-5), plus the launch's own controls (grid, padding, repeat
+runs) and its bounded dependency wait."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1704_01127_amd import qsim
+from supremacy_inputs import batch_circuit, haar_unitary, supremacy_circuit, with_haar_layers
+from supremacy_inputs.circuits import batch_grid
+
+pytestmark = pytest.mark.gpu
+
+
+def fidelity(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return abs(np.vdot(b, a)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
+
+
+def small_batch(count, n_lo=11, n_hi=16, seed0=0):
+    """Seeded supremacy circuits with n in [n_lo, n_hi], depth in [10, 40]."""
+    circs = []
+    for i in range(count):
+        circs.append(batch_circuit(seed0 + i, n_lo=n_lo, n_hi=n_hi))
+    return circs
+
+
+def check_against_oracle(batch, circs, skip_trailing_diag=False):
+    for i, c in enumerate(circs):
+        ref = oracle.run(c)
+        got = batch.states[i].cpu().numpy()
+        if skip_trailing_diag:  # probabilities only are defined then
+            p, pr = np.abs(got) ** 2, np.abs(ref) ** 2
+            assert np.max(np.abs(p - pr)) <= 1e-6 * np.max(pr) * 10, i
+            continue
+        f = fidelity(got, ref)
+        d = np.max(np.abs(got - ref))
+        assert f >= 1 - 1e-6 and d <= 1e-5, (i, c.n, f, d)
+
+
+@pytest.fixture(autouse=True)
+def _reset_options():
+    yield
+    qsim.set_option(qsim.OPT_BATCH_GRID, 0)
+    qsim.set_option(qsim.OPT_BATCH_PAD, 0)
+
+
+@pytest.mark.parametrize("opts", [
+    dict(),
+    dict(fuse_diag=False),
+    dict(kmax=3),
+    dict(kmax=1, fuse_diag=False, skip_initial_h=False),
+    dict(kmax=4, skip_initial_h=False),
+])
+def test_batch_matches_oracle(opts):
+    circs = small_batch(12, seed0=3)
+    b = qsim.Batch(circs, **opts)
+    st = b.run()
+    assert st["n_circuits"] == 12 and st["n_items"] > 0
+    check_against_oracle(b, circs)
+
+
+@pytest.mark.parametrize("grid", [1, 3, 64])
+def test_batch_any_grid(grid):
+    """One work-group runs every item in ticket order; a few work-groups
+    wait on each other; results do not depend on the grid."""
+    qsim.set_option(qsim.OPT_BATCH_GRID, grid)
+    circs = small_batch(6, seed0=40)
+    b = qsim.Batch(circs)
+    st = b.run()
+    assert st["grid"] == min(grid, st["n_items"])
+    check_against_oracle(b, circs)
+
+
+def test_batch_high_padding():
+    qsim.set_option(qsim.OPT_BATCH_PAD, 1)
+    circs = small_batch(6, seed0=60)
+    b = qsim.Batch(circs, kmax=3)
+    b.run()
+    check_against_oracle(b, circs)
+
+
+def test_batch_dense_gates_and_skips():
+    """Haar 5- and 3-qubit gates inside the circuits; trailing diagonal gates skipped."""
+    circs = []
+    for i, n in enumerate((12, 14, 15, 11)):
+        R, C, drop = batch_grid(n)
+        c = supremacy_circuit(R, C, 20 + 3 * i, 500 + i, drop)
+        circs.append(with_haar_layers(c, 6, 5 if i % 2 == 0 else 3, 900 + i))
+    b = qsim.Batch(circs, skip_trailing_diag=True)
+    b.run()
+    check_against_oracle(b, circs, skip_trailing_diag=True)
+    b2 = qsim.Batch(circs)
+    b2.run()
+    check_against_oracle(b2, circs)
+
+
+def test_batch_repeat_runs_and_two_batches():
+    circs = small_batch(5, seed0=80)
+    b = qsim.Batch(circs)
+    b.run()
+    first = [s.cpu().numpy() for s in b.states]
+    b.run()
+    for s, f in zip(b.states, first):
+        assert np.array_equal(s.cpu().numpy(), f)
+    other = small_batch(3, n_lo=12, n_hi=13, seed0=90)
+    b2 = qsim.Batch(other)
+    b2.run()
+    check_against_oracle(b2, other)
+    check_against_oracle(b, circs)
+
+
+def test_batch_single_circuit_sizes():
+    """The smallest state (one tile), a ragged mix, and a 20-qubit state."""
+    for n, depth in ((11, 12), (20, 25)):
+        R, C, drop = batch_grid(n)
+        circ = supremacy_circuit(R, C, depth, 7 + n, drop)
+        b = qsim.Batch([circ])
+        b.run()
+        check_against_oracle(b, [circ])
+
+
+def test_batch_wait_limit_reports_error():
+    """A wait forced to give up (a 1 us limit, set by the host: the items of
+    the 20-qubit initialisation take far longer) is reported; the kernel
+    still exits and the next run with the default limit is exact."""
+    circ = supremacy_circuit(4, 5, 16, 3)
+    b = qsim.Batch([circ])
+    with pytest.raises(qsim.QsimError) as ei:
+        b.run(wait_limit_us=1)
+    assert ei.value.status == qsim.E_DEVICE
+    b.run()
+    check_against_oracle(b, [circ])
+
+
+def test_batch_full_size_sample():
+    """The 512-circuit workload (n in [14, 24], depth in [10, 40], seeds
+    1000 + i) in one launch. Every circuit is compared with the library's
+    float64 per-gate path (itself held to the oracle at 1e-12); four of them,
+    up to 20 qubits, with the oracle directly."""
+    import torch
+    circs = [batch_circuit(i) for i in range(512)]
+    b = qsim.Batch(circs)
+    st = b.run()
+    assert st["n_circuits"] == 512
+    worst = 1.0
+    by_n = {}
+    for i, c in enumerate(circs):
+        by_n.setdefault(c.n, i)
+        s = qsim.State(c.n, "c128")
+        s.run_circuit(c.gates, scheduler="per_gate")
+        f, _ = s.compare(b.states[i].to(torch.complex128))
+        worst = min(worst, f)
+        del s
+    assert worst >= 1 - 1e-6, worst
+    sample = [by_n[n] for n in sorted(by_n) if n <= 20][::2][:4]
+    for i in sample:
+        ref = oracle.run(circs[i])
+        got = b.states[i].cpu().numpy()
+        assert fidelity(got, ref) >= 1 - 1e-6 and np.max(np.abs(got - ref)) <= 1e-5, i
