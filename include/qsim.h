@@ -213,13 +213,19 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * qubits outside it, which lengthens the contiguous runs of a tile; 1: the
  * highest); QSIM_OPT_BATCH_ITEM_TILES is the number of tiles (2^11
  * amplitudes each) of one work item, a power of two in [1, 4096] (default
- * 128), read when a batch is planned. Errors: QSIM_E_INVALID for an unknown
+ * 128), read when a batch is planned. QSIM_OPT_K6_KERNEL picks the kernel
+ * of 6-qubit clusters on complex64 states: 0 the fp32 real-split product, 1
+ * the fp32 three-multiplication complex product, 2 (default) fp16 matrix
+ * cores on hi / lo halves of the operands (about 2^-21 relative error, the
+ * size of fp32 rounding),
+ * read when a cluster is enqueued. Errors: QSIM_E_INVALID for an unknown
  * option or an out-of-range value. */
 typedef enum {
     QSIM_OPT_CLUSTER_VARIANT = 1,
     QSIM_OPT_BATCH_GRID = 2,
     QSIM_OPT_BATCH_PAD = 3,
-    QSIM_OPT_BATCH_ITEM_TILES = 4
+    QSIM_OPT_BATCH_ITEM_TILES = 4,
+    QSIM_OPT_K6_KERNEL = 5
 } qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);

@@ -69,6 +69,7 @@ int get_tune_entry(bool dbl, int k, int cls) { return g_tune[dbl][k][cls]; }
 int g_batch_grid = 0;
 int g_batch_pad = 0;
 int g_batch_item_tiles = 128;
+int g_k6_kernel = 2;
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
@@ -696,6 +697,11 @@ qsim_status qsim_set_option(int option, int value) {
         g_batch_pad = value;
         return QSIM_OK;
     }
+    if (option == QSIM_OPT_K6_KERNEL) {
+        if (value < 0 || value > 2) return fail(QSIM_E_INVALID, "k = 6 kernel must be 0, 1 or 2");
+        g_k6_kernel = value;
+        return QSIM_OK;
+    }
     if (option == QSIM_OPT_BATCH_ITEM_TILES) {
         if (value < 1 || value > 4096 || (value & (value - 1)))
             return fail(QSIM_E_INVALID, "tiles per batch item must be a power of two in [1, 4096]");
@@ -734,6 +740,7 @@ int qsim_get_option(int option) {
     if (option == QSIM_OPT_BATCH_GRID) return g_batch_grid;
     if (option == QSIM_OPT_BATCH_PAD) return g_batch_pad;
     if (option == QSIM_OPT_BATCH_ITEM_TILES) return g_batch_item_tiles;
+    if (option == QSIM_OPT_K6_KERNEL) return g_k6_kernel;
     return -1;
 }
 

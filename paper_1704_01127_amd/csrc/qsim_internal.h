@@ -94,7 +94,9 @@ struct BuildGate {
 enum : int32_t {
     LAYOUT_PLAIN = 0,     // complex matrix M[y][x] (T re, T im), for the VALU kernel
     LAYOUT_MFMA32F = 1,   // real-split, permuted for v_mfma_f32_32x32x2_f32
-    LAYOUT_MFMA16D = 2    // real-split, permuted for v_mfma_f64_16x16x4_f64
+    LAYOUT_MFMA16D = 2,   // real-split, permuted for v_mfma_f64_16x16x4_f64
+    LAYOUT_GAUSS32F = 3,  // k = 6 float: Re M, Im M, Re M + Im M (three-product complex matrix)
+    LAYOUT_SPLIT16F = 4   // k = 6 float: fp16 hi / lo halves of 16 x the real-split matrix
 };
 
 struct BuildOp {
@@ -152,12 +154,15 @@ struct BatchItem {
 extern int g_batch_grid;        // work-groups of the batch launch, 0 = two per CU
 extern int g_batch_pad;         // padding qubits: 0 lowest outside the cluster, 1 highest
 extern int g_batch_item_tiles;  // tiles of 2^11 amplitudes per work item
+extern int g_k6_kernel;         // float k = 6 clusters: 0 fp32 real-split, 1 fp32 three-product, 2 fp16 halves
 
 // Bytes of a cluster matrix in each layout.
 inline int64_t matrix_bytes(int k, int layout, bool dbl) {
     const int64_t d = int64_t(1) << k;
     const int64_t es = dbl ? 8 : 4;
     if (layout == LAYOUT_PLAIN) return d * d * 2 * es;
+    if (layout == LAYOUT_GAUSS32F) return 3 * d * d * es;
+    if (layout == LAYOUT_SPLIT16F) return 2 * (2 * d) * (2 * d) * 2;
     return (2 * d) * (2 * d) * es;
 }
 

@@ -292,6 +292,234 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_mfma(float2* __restrict_
     } while (tile < ntiles);
 }
 
+// ------------------------------------------------------------ cluster: MFMA, float, k = 6
+// Three-multiplication complex product: with M = Mr + i Mi and x = xr + i xi,
+//   Re(M x) = Mr xr - Mi xi,   Im(M x) = (Mr + Mi)(xr + xi) - Mr xr - Mi xi,
+// three real 64 x 64 products instead of the four blocks of the real-split
+// matrix: 25% fewer matrix-core operations, which is what bounds k = 6.
+// v_mfma_f32_16x16x4_f32: operand lane l holds row / column l % 16 at inner
+// index l / 16; result register r of lane l holds row 4 (l / 16) + r. Wave
+// tile: 16 columns; lane (p, q) = (l % 16, l / 16) owns amplitudes j | q << 4,
+// j < 16, of column p. At step s the lane supplies inner index s | q << 4,
+// its own amplitude j = s; result register r of row block rb lands on its
+// amplitude (4 rb + r) | q << 4 (the builder permutes the matrix rows so).
+template <bool LOWT>
+__global__ __launch_bounds__(256, 2) void k_cluster_f32_gauss6(float2* __restrict__ psi,
+                                                               const float* __restrict__ Ap,
+                                                               const EpiDesc* __restrict__ epi,
+                                                               ClusterGeom g) {
+    constexpr int K = 6, HX = 16;
+    __shared__ float As[3 * 4 * 16 * 64];
+    load_matrix<3 * 4 * 16 * 64, 256>(As, reinterpret_cast<const vf4*>(Ap));
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, p = lane & 15, q = lane >> 4;
+    const uint64_t qoff = ((q & 1) ? uint64_t(1) << g.t[4] : 0) | ((q >> 1) ? uint64_t(1) << g.t[5] : 0);
+    const uint64_t ntiles = g.ncols / 16;
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+
+    uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    const uint64_t last = ntiles - 1;
+    auto load = [&](uint64_t b, float (&X)[2 * HX]) {
+        if (LOWT) {
+#pragma unroll
+            for (int j = 0; j < HX; j += 2) {
+                const float4 v = *reinterpret_cast<const float4*>(psi + (b | target_off<4>(j, g)));
+                X[2 * j] = v.x; X[2 * j + 1] = v.y; X[2 * j + 2] = v.z; X[2 * j + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                const float2 v = psi[b | target_off<4>(j, g)];
+                X[2 * j] = v.x; X[2 * j + 1] = v.y;
+            }
+        }
+    };
+    uint64_t base = deposit_cols<K>(tile * 16 + p, g);
+    float B[2 * HX];
+    load(base | qoff, B);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
+    do {
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        const uint64_t basen = deposit_cols<K>(nxt * 16 + p, g);
+        float Bn[2 * HX];
+        load(basen | qoff, Bn);
+        __builtin_amdgcn_sched_barrier(0);
+
+        ColFactor<float> f{0u, 0u, 1.0f, 0.0f};
+        if (has_epi) f = col_factor<float>(epi, base);
+        vf4 a1[4], a2[4], a3[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a1[rb][i] = a2[rb][i] = a3[rb][i] = 0.0f;
+        int aoff = lane;
+        asm volatile("" : "+v"(aoff));  // keep the matrix reads inside the loop (not in registers)
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const float xr = B[2 * st], xi = B[2 * st + 1], xs = xr + xi;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                a1[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[((0 * 4 + rb) * 16 + st) * 64 + aoff], xr, a1[rb], 0,
+                                                             0, 0);
+                a2[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[((1 * 4 + rb) * 16 + st) * 64 + aoff], xi, a2[rb], 0,
+                                                             0, 0);
+                a3[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[((2 * 4 + rb) * 16 + st) * 64 + aoff], xs, a3[rb], 0,
+                                                             0, 0);
+            }
+        }
+        // amplitude j = 4 rb + r of the lane
+        float O[2 * HX];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                O[2 * (4 * rb + r)] = a1[rb][r] - a2[rb][r];
+                O[2 * (4 * rb + r) + 1] = a3[rb][r] - a1[rb][r] - a2[rb][r];
+            }
+        if (has_epi) {
+#pragma unroll
+            for (int j = 0; j < HX; ++j)
+                apply_factor(O[2 * j], O[2 * j + 1], f, (uint32_t)(j | (q << 4)), has_ph);
+        }
+        const uint64_t b0 = base | qoff;
+        if (LOWT) {
+#pragma unroll
+            for (int j = 0; j < HX; j += 2)
+                *reinterpret_cast<float4*>(psi + (b0 | target_off<4>(j, g))) =
+                    make_float4(O[2 * j], O[2 * j + 1], O[2 * j + 2], O[2 * j + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < HX; ++j) psi[b0 | target_off<4>(j, g)] = make_float2(O[2 * j], O[2 * j + 1]);
+        }
+        base = basen;
+#pragma unroll
+        for (int j = 0; j < 2 * HX; ++j) B[j] = Bn[j];
+        tile += stride;
+    } while (tile < ntiles);
+}
+
+// ------------------------------------------------------------ cluster: float state, k = 6, fp16 matrix cores
+// The real-split product of a 6-qubit cluster needs 32 flop per byte of state,
+// beyond what the fp32 matrix cores sustain at HBM speed. The fp16 matrix
+// cores are 16 times faster, so the product runs on them with each operand
+// split into two halves, v = hi + lo (hi = fp16(v), lo = fp16(v - hi)):
+//   A x ~= A_hi x_hi + A_hi x_lo + A_lo x_hi,
+// accumulated in fp32 (the dropped A_lo x_lo and the split residuals are
+// ~2^-22 relative, the size of fp32 rounding). The matrix is stored as
+// 16 M, split by the builder. Each column of the state tile is scaled by a
+// power of two that puts its largest magnitude just below 2^14 (exact, and no
+// fp16 overflow for any input), and its results are scaled back.
+// v_mfma_f32_32x32x16_f16: operand lane l, element i holds row / column l % 32
+// at inner index 8 (l / 32) + i; result register r of lane l holds row
+// 8 (r / 4) + 4 (l / 32) + r % 4 (as for the fp32 32x32 instruction). Lane
+// (p, h) owns amplitudes j | h << 5 of column p; at step s it supplies its
+// floats 8 s .. 8 s + 7 (amplitudes 4 s .. 4 s + 3, re / im interleaved).
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
+template <bool LOWT>
+__global__ __launch_bounds__(256, 2) void k_cluster_f32_split6(float2* __restrict__ psi,
+                                                               const half8* __restrict__ Ap,
+                                                               const EpiDesc* __restrict__ epi,
+                                                               ClusterGeom g) {
+    constexpr int K = 6, HX = 32, RB = 4, S = 8;
+    using T = TileF32<K, 1, LOWT>;
+    __shared__ half8 Ah[RB * S * 64];
+    __shared__ half8 Al[RB * S * 64];
+    load_matrix<RB * S * 64 * 8, 256>(reinterpret_cast<_Float16*>(Ah), reinterpret_cast<const vf4*>(Ap));
+    load_matrix<RB * S * 64 * 8, 256>(reinterpret_cast<_Float16*>(Al),
+                                      reinterpret_cast<const vf4*>(Ap + RB * S * 64));
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const uint64_t hoff = h ? (uint64_t(1) << g.t[K - 1]) : 0;
+    const uint64_t ntiles = g.ncols / 32;
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+
+    uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    const uint64_t last = ntiles - 1;
+
+    // split the column's amplitudes (scaled) into fp16 halves; returns the
+    // factor that undoes the column and matrix scaling
+    auto split = [&](const float (&X)[2 * HX], half8 (&xh)[S], half8 (&xl)[S]) -> float {
+        uint32_t mb = 0;  // largest magnitude (as bits: monotonic for non-negative floats)
+#pragma unroll
+        for (int i = 0; i < 2 * HX; ++i) mb = max(mb, __float_as_uint(X[i]) & 0x7fffffffu);
+        mb = max(mb, (uint32_t)__shfl_xor((int)mb, 32));  // the other half of the column
+        const int e = (int)(mb >> 23) - 126;               // largest magnitude < 2^e
+        const int se = min(max(14 - e, -100), 100);
+        const float sc = __builtin_ldexpf(1.0f, se);
+#pragma unroll
+        for (int st = 0; st < S; ++st)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float v = X[8 * st + i] * sc;
+                const _Float16 hi = (_Float16)v;
+                xh[st][i] = hi;
+                xl[st][i] = (_Float16)(v - (float)hi);
+            }
+        return __builtin_ldexpf(1.0f, -se - 4);
+    };
+
+    float B[1][2 * HX];
+    uint64_t base[1];
+    T::bases(tile, p, g, base);
+    T::load(psi, base, hoff, g, B);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
+    half8 xh[S], xl[S];
+    float unscale = split(B[0], xh, xl);
+    do {
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        float Bn[1][2 * HX];
+        uint64_t basen[1];
+        T::bases(nxt, p, g, basen);
+        T::load(psi, basen, hoff, g, Bn);
+        __builtin_amdgcn_sched_barrier(0);
+
+        floatx16 acc[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[rb][i] = 0.0f;
+        int aoff = lane;
+        asm volatile("" : "+v"(aoff));  // keep the matrix reads inside the loop (not in registers)
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const half8 ah = Ah[(rb * S + st) * 64 + aoff];
+                const half8 al = Al[(rb * S + st) * 64 + aoff];
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xl[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, xh[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xh[st], acc[rb], 0, 0, 0);
+            }
+        }
+        float O[1][2 * HX];
+#pragma unroll
+        for (int j = 0; j < 2 * HX; ++j) O[0][j] = acc[j / 16][j % 16] * unscale;
+        if (has_epi) {
+            const ColFactor<float> f = col_factor<float>(epi, base[0]);
+#pragma unroll
+            for (int j = 0; j < HX; ++j)
+                apply_factor(O[0][2 * j], O[0][2 * j + 1], f, (uint32_t)(j | (h << (K - 1))), has_ph);
+        }
+        T::store(psi, base, hoff, g, O);
+        base[0] = basen[0];
+        unscale = split(Bn[0], xh, xl);
+        tile += stride;
+    } while (tile < ntiles);
+}
+
 // ------------------------------------------------------------ cluster: MFMA, double
 // v_mfma_f64_16x16x4_f64: lane l: p = l%16 (column), q = l/16 owns target
 // indices x = j | q << (K-2), j < 2^(K-2), of its column(s). Operand A/B: lane
@@ -1133,6 +1361,47 @@ __global__ __launch_bounds__(64) void k_build(const BuildOp* __restrict__ ops, c
                 A[(rb * S + s) * 64 + l] = (float)Ars(y, a, xin, b);
             }
         }
+    } else if (op.layout == LAYOUT_GAUSS32F) {
+        // k = 6: three 64 x 64 real matrices P = 0: Re M, 1: Im M, 2: Re M + Im M,
+        // for v_mfma_f32_16x16x4_f32. Entry (P, rb, s, lane l): physical row
+        // i = l % 16 of row block rb, inner index s | (l / 16) << 4. The result
+        // of physical row i lands in register i % 4 of the lanes with l / 16 =
+        // i / 4, which own amplitude (4 rb + i % 4) | (i / 4) << 4.
+        const int l = x, i = l & 15, qin = l >> 4;
+        float* A = reinterpret_cast<float*>(out);
+        for (int rb = 0; rb < 4; ++rb) {
+            const int y = (4 * rb + (i & 3)) | ((i >> 2) << 4);
+            for (int s2 = 0; s2 < 16; ++s2) {
+                const int xin = s2 | (qin << 4);
+                const double re = Mre(y, xin), im = Mim(y, xin);
+                A[((0 * 4 + rb) * 16 + s2) * 64 + l] = (float)re;
+                A[((1 * 4 + rb) * 16 + s2) * 64 + l] = (float)im;
+                A[((2 * 4 + rb) * 16 + s2) * 64 + l] = (float)(re + im);
+            }
+        }
+    } else if (op.layout == LAYOUT_SPLIT16F) {
+        // k = 6, fp16 halves of 16 x the real-split matrix for
+        // v_mfma_f32_32x32x16_f16. Entry (rb, s, lane l, i): physical row
+        // rho = l % 32 of row block rb (result rows as in LAYOUT_MFMA32F), inner
+        // index: float 8 s + i of the lanes with l / 32 = hin, i.e. component
+        // i % 2 of amplitude (4 s + i / 2) | hin << 5. hi block, then lo block.
+        const int l = x, rho = l & 31, hin = l >> 5;
+        _Float16* Ahi = reinterpret_cast<_Float16*>(out);
+        _Float16* Alo = Ahi + 4 * 8 * 64 * 8;
+        for (int rb = 0; rb < 4; ++rb) {
+            const int jout = rb * 8 + 2 * (rho >> 3) + ((rho & 3) >> 1);
+            const int hout = (rho >> 2) & 1;
+            const int y = jout | (hout << 5), a = rho & 1;
+            for (int s2 = 0; s2 < 8; ++s2)
+                for (int i = 0; i < 8; ++i) {
+                    const int xin = (4 * s2 + (i >> 1)) | (hin << 5), b = i & 1;
+                    const float v = (float)(16.0 * Ars(y, a, xin, b));
+                    const _Float16 hi = (_Float16)v;
+                    const size_t at = ((size_t)(rb * 8 + s2) * 64 + l) * 8 + i;
+                    Ahi[at] = hi;
+                    Alo[at] = (_Float16)(v - (float)hi);
+                }
+        }
     } else {  // LAYOUT_MFMA16D
         // entry (rb, s, lane l): row rho = l % 16 of row block rb, inner index 4 s + l / 16.
         // The result row rho lands in register rho / 4 of the lanes with l / 16 = rho % 4.
@@ -1286,8 +1555,11 @@ StageGeom make_stage_geom(const ClusterGeom& g, int C, int unit) {
 
 int cluster_layout(bool dbl, int k, int n) {
     if (!dbl) {
-        const int nb = (k == 6) ? 1 : 2;
-        return (k >= 4 && n - k >= 5 + (nb == 2)) ? LAYOUT_MFMA32F : LAYOUT_PLAIN;
+        if (k == 6) {
+            if (n - k < 5) return LAYOUT_PLAIN;
+            return g_k6_kernel == 2 ? LAYOUT_SPLIT16F : (g_k6_kernel == 1 ? LAYOUT_GAUSS32F : LAYOUT_MFMA32F);
+        }
+        return (k >= 4 && n - k >= 6) ? LAYOUT_MFMA32F : LAYOUT_PLAIN;
     }
     const int nb = (k == 6) ? 1 : 2;
     return (k >= 3 && n - k >= 4 + (nb == 2)) ? LAYOUT_MFMA16D : LAYOUT_PLAIN;
@@ -1370,6 +1642,28 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
             case 6: return launch_valu_k<6>(psi, dbl, g, mat, epi, st);
             default: return hipErrorInvalidValue;
         }
+    }
+    if (layout == LAYOUT_SPLIT16F && !dbl && g.k == 6) {
+        const uint64_t tiles = g.ncols / 32;
+        const unsigned grid = grid_for(tiles, 4, kPersistGrid);
+        if (g.t[0] == 0)
+            hipLaunchKernelGGL(k_cluster_f32_split6<true>, dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const half8*)mat, epi, g);
+        else
+            hipLaunchKernelGGL(k_cluster_f32_split6<false>, dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const half8*)mat, epi, g);
+        return hipGetLastError();
+    }
+    if (layout == LAYOUT_GAUSS32F && !dbl && g.k == 6) {
+        const uint64_t tiles = g.ncols / 16;
+        const unsigned grid = grid_for(tiles, 4, kPersistGrid);
+        if (g.t[0] == 0)
+            hipLaunchKernelGGL(k_cluster_f32_gauss6<true>, dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const float*)mat, epi, g);
+        else
+            hipLaunchKernelGGL(k_cluster_f32_gauss6<false>, dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const float*)mat, epi, g);
+        return hipGetLastError();
     }
     if (layout == LAYOUT_MFMA32F && !dbl) {
         switch (g.k) {

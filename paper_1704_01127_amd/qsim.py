@@ -215,6 +215,7 @@ OPT_CLUSTER_VARIANT = 1
 OPT_BATCH_GRID = 2
 OPT_BATCH_PAD = 3
 OPT_BATCH_ITEM_TILES = 4
+OPT_K6_KERNEL = 5
 
 
 def set_option(option: int, value: int):

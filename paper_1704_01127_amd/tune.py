@@ -112,9 +112,13 @@ def main(argv=None):
     ap.add_argument("--kmax", type=int, default=5)
     ap.add_argument("--fuse-diag", type=int, default=1)
     ap.add_argument("--variant", type=int, default=None, help="matrix-core cluster kernel variant (0 or 1)")
+    ap.add_argument("--k6-kernel", type=int, default=None,
+                    help="6-qubit complex64 kernel: 0 fp32 real-split, 1 fp32 three-product, 2 fp16 halves")
     args = ap.parse_args(argv)
     if args.variant is not None:
         qsim.set_option(qsim.OPT_CLUSTER_VARIANT, args.variant)
+    if args.k6_kernel is not None:
+        qsim.set_option(qsim.OPT_K6_KERNEL, args.k6_kernel)
 
     import torch  # noqa: F401
 

@@ -117,6 +117,63 @@ def test_apply_cluster_twice_large(dt, variant):
         assert np.max(np.abs(got - ref)) <= kernel_tol(dt, k, np.max(np.abs(ref)))
 
 
+# ------------------------------------------------------------------ k = 6 kernels (complex64)
+@pytest.fixture(params=[0, 1, 2], ids=["realsplit", "threeprod", "fp16halves"])
+def k6_kernel(request):
+    old = qsim.get_option(qsim.OPT_K6_KERNEL)
+    qsim.set_option(qsim.OPT_K6_KERNEL, request.param)
+    yield request.param
+    qsim.set_option(qsim.OPT_K6_KERNEL, old)
+
+
+@pytest.mark.parametrize("n", [11, 13, 21])
+@pytest.mark.parametrize("pat", ["low", "high", "mixed", "nolow"])
+def test_k6_kernels(k6_kernel, n, pat):
+    """Each 6-qubit float kernel at the one-cluster bound. The fp16-halves
+    product drops A_lo x_lo and the split residuals (each ~2^-22 relative),
+    well inside the bound's (2^(k+1) + 2) u sqrt(2^k) with u = 2^-24."""
+    qs = target_sets(n, 6, 77 * n)[pat]
+    u = haar_unitary(6, n + 5)
+    psi = random_state(n, 3 * n)
+    ref = oracle.apply_dense(psi.copy(), qs, u)
+    s = make_state(n, "c64", psi)
+    s.apply_cluster(qs, u)
+    got = s.to_numpy()
+    assert np.max(np.abs(got - ref)) <= kernel_tol("c64", 6, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("scale", [1e6, 1e-30, 0.0])
+def test_k6_kernels_any_magnitude(k6_kernel, scale):
+    """States far from unit norm, and columns that are zero: the per-column
+    power-of-two scaling of the fp16 product keeps the relative error."""
+    n = 14
+    qs = [1, 4, 6, 9, 11, 12]  # bit 13 is not a target: each column lies in one half
+    u = haar_unitary(6, 99)
+    psi = random_state(n, 5)
+    psi[: 2 ** (n - 1)] *= scale  # half the state rescaled (or zeroed)
+    ref = oracle.apply_dense(psi.copy(), qs, u)
+    s = make_state(n, "c64", psi)
+    s.apply_cluster(qs, u)
+    got = s.to_numpy()
+    assert np.all(np.isfinite(got))
+    # columns differ in scale by up to 1e30: hold each half to its own bound
+    for part in (slice(0, 2 ** (n - 1)), slice(2 ** (n - 1), 2 ** n)):
+        bound = kernel_tol("c64", 6, np.max(np.abs(ref[part])) if np.any(ref[part]) else 0.0)
+        assert np.max(np.abs(got[part] - ref[part])) <= max(bound, 0.0), (scale, part)
+
+
+def test_k6_kernels_circuit(k6_kernel):
+    """Whole circuits with 6-qubit clusters and diagonal epilogues."""
+    circ = supremacy_circuit(4, 5, 24, seed=11)
+    ref = oracle.run(circ)
+    s = make_state(circ.n, "c64")
+    st = s.run_circuit(circ.gates, scheduler="greedy", kmax=6, fuse_diag=True)
+    assert st["n_clusters_by_k"][6] > 0
+    got = s.to_numpy()
+    assert fidelity(got, ref) >= 1 - 1e-6
+    assert np.max(np.abs(got - ref)) <= 1e-5
+
+
 # ------------------------------------------------------------------ diagonal layer
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("n", [1, 2, 3, 9, 16])
