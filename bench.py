@@ -35,11 +35,13 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def kernel_name(rec) -> str:
+def kernel_name(rec, k6_kernel=2) -> str:
     """Name (as rocprofv3 reports it) of the float cluster kernel a launch used."""
     k, lowt = rec["k"], rec["qubits"][0] == 0
     if not rec.get("mfma"):
         return "k_cluster_valu<float, %d>" % k
+    if k == 6 and k6_kernel in (1, 2):
+        return "k_cluster_f32_%s<%s>" % ("split6" if k6_kernel == 2 else "gauss6", "true" if lowt else "false")
     if rec.get("staged"):
         return "k_cluster_f32_stage<%d, 6, %s>" % (k, "true" if lowt else "false")
     return "k_cluster_f32_mfma<%d, %d, %s>" % (k, 1 if k == 6 else 2, "true" if lowt else "false")
@@ -54,15 +56,59 @@ def parse():
     ap.add_argument("--cols", type=int, default=6)
     ap.add_argument("--depth", type=int, default=25)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--kmax", type=int, default=5)
-    ap.add_argument("--scheduler", default="greedy")
+    ap.add_argument("--kmax", type=int, default=6)
+    ap.add_argument("--scheduler", default="learned")
     ap.add_argument("--no-fuse-diag", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=None, help="steps of the float64 per-gate form")
-    ap.add_argument("--only", choices=["fused", "pergate"], default=None,
-                    help="run one form only (for profiling)")
+    ap.add_argument("--only", choices=["fused", "pergate", "batch"], default=None,
+                    help="run one form only (for profiling); batch: the 512-circuit launch alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-gates", type=int, default=24)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batched launch")
     return ap.parse_args()
+
+
+def batch_bench(qsim, torch, runs=3, n_check=8):
+    """512 circuits (n ~ U[14, 24], depth ~ U[10, 40], seeds 1000 + i) in one
+    persistent launch: circuits per second of qsim_batch_run (initialisation
+    and every op of every circuit, matrices built on the GPU) and of plan + run,
+    and a sample of circuits compared with the float64 per-gate path."""
+    from supremacy_inputs import batch_circuit
+    circs = [batch_circuit(i) for i in range(512)]
+    t0 = time.perf_counter()
+    b = qsim.Batch(circs)
+    plan_s = time.perf_counter() - t0
+    b.run()
+    runs_ms = [b.run()["run_ms"] for _ in range(runs)]
+    st = b.run()
+    run_s = min(runs_ms + [st["run_ms"]]) / 1e3
+    # algorithmic bytes: every cluster op reads and writes its whole state, the
+    # initialisation writes it
+    alg = 0
+    for i, c in enumerate(circs):
+        sc = qsim.schedule(c.n, c.gates, kmax=5, scheduler="greedy", fuse_diag=True, skip_initial_h=True)
+        m = len(sc["op_kind"])
+        alg += (m * 16 + 8) * 2 ** c.n
+    worst = 1.0
+    idx = [int(i) for i in range(0, 512, 512 // n_check)][:n_check]
+    for i in idx:
+        c = circs[i]
+        s = qsim.State(c.n, "c128")
+        s.run_circuit(c.gates, scheduler="per_gate")
+        f, _ = s.compare(b.states[i].to(torch.complex128))
+        worst = min(worst, f)
+        del s
+    res = {"circuits": 512, "qubits": "14-24", "depths": "10-40", "dtype": "c64",
+           "circuits_per_s": round(512 / run_s, 1), "run_ms": round(run_s * 1e3, 2),
+           "circuits_per_s_with_plan": round(512 / (run_s + st["plan_ms"] / 1e3), 1),
+           "plan_ms": round(st["plan_ms"], 2), "ops": st["n_ops"], "work_items": st["n_items"],
+           "grid": st["grid"], "algorithmic_GB": round(alg / 1e9, 1),
+           "hbm_GBs": round(alg / run_s / 1e9, 1), "hbm_frac": round(alg / run_s / 1e9 / HBM_PEAK_GBS, 4),
+           "min_fidelity_vs_fp64_per_gate": worst, "fidelity_sample": "%d circuits" % len(idx),
+           "python_plan_s": round(plan_s, 3)}
+    del b
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(circ, n_sample):
@@ -138,6 +184,9 @@ def main():
 
     out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "data": "synthetic"}
+    if args.only == "batch":
+        print(json.dumps({"batch": batch_bench(qsim, torch)}), flush=True)
+        return
 
     fused = pergate = None
     if args.only in (None, "fused"):
@@ -175,12 +224,13 @@ def main():
         out["fused_vs_fp64_per_gate"] = {"fidelity": fid, "max_abs_diff": maxd}
 
     if recs:
+        k6k = qsim.get_option(qsim.OPT_K6_KERNEL)
         amp_bytes = 8
         clusters = [r for r in recs if r["kind"] == "cluster"]
         total_ms = sum(r["ms"] for r in recs)
         groups = {}
         for r in clusters:
-            groups.setdefault(kernel_name(r), []).append(r["ms"])
+            groups.setdefault(kernel_name(r, k6k), []).append(r["ms"])
         kname, times = max(groups.items(), key=lambda kv: sum(kv[1]))
         bytes_per_launch = 2 * 2 ** n * amp_bytes
         avg_ms = sum(times) / len(times)
@@ -222,6 +272,11 @@ def main():
                 d[0] += 1
                 d[1] += r["ms"]
         out["other_kernels"] = {kk: {"launches": v[0], "total_ms": round(v[1], 3)} for kk, v in others.items()}
+
+    if not args.no_batch and args.only is None:
+        del s32, s64
+        torch.cuda.empty_cache()
+        out["batch"] = batch_bench(qsim, torch)
 
     if not args.no_cpu_baseline:
         # free the GPU states first: the oracle needs 16 GiB of host memory

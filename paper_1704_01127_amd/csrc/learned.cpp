@@ -70,8 +70,12 @@ std::mutex g_model_mu;
 size_t mlp_param_count(int n_in, int h) { return (size_t)h * n_in + h + (size_t)h * h + h + h + 1; }
 
 // Plain float32 forward pass of one sample (the same operation order as the
-// GPU forward kernel: dot products accumulated in index order).
-float mlp_forward_host(const float* p, int n_in, int h, const float* x) {
+// GPU forward kernel: each unit's dot product is a chain of fused
+// multiply-adds in index order). The loops run over the inputs outermost so
+// that the units' chains are independent of each other (and vectorise); every
+// chain keeps its order, so the result does not depend on the loop shape.
+template <bool kHwFma>
+static float mlp_forward_impl(const float* p, int n_in, int h, const float* x) {
     const float* W1 = p;
     const float* b1 = W1 + (size_t)h * n_in;
     const float* W2 = b1 + h;
@@ -79,19 +83,28 @@ float mlp_forward_host(const float* p, int n_in, int h, const float* x) {
     const float* W3 = b2 + h;
     const float* b3 = W3 + h;
     float a1[256], a2[256];
-    for (int i = 0; i < h; ++i) {
-        float s = b1[i];
-        for (int j = 0; j < n_in; ++j) s = std::fma(W1[(size_t)i * n_in + j], x[j], s);
-        a1[i] = s > 0.f ? s : 0.f;
-    }
-    for (int i = 0; i < h; ++i) {
-        float s = b2[i];
-        for (int j = 0; j < h; ++j) s = std::fma(W2[(size_t)i * h + j], a1[j], s);
-        a2[i] = s > 0.f ? s : 0.f;
-    }
+    for (int i = 0; i < h; ++i) a1[i] = b1[i];
+    for (int j = 0; j < n_in; ++j)
+        for (int i = 0; i < h; ++i) a1[i] = std::fma(W1[(size_t)i * n_in + j], x[j], a1[i]);
+    for (int i = 0; i < h; ++i) a1[i] = a1[i] > 0.f ? a1[i] : 0.f;
+    for (int i = 0; i < h; ++i) a2[i] = b2[i];
+    for (int j = 0; j < h; ++j)
+        for (int i = 0; i < h; ++i) a2[i] = std::fma(W2[(size_t)i * h + j], a1[j], a2[i]);
+    for (int i = 0; i < h; ++i) a2[i] = a2[i] > 0.f ? a2[i] : 0.f;
     float y = b3[0];
     for (int j = 0; j < h; ++j) y = std::fma(W3[j], a2[j], y);
     return y;
+}
+
+// With the FMA instructions available, std::fma compiles to them instead of a
+// library call.
+__attribute__((target("avx2,fma"))) static float mlp_forward_fma(const float* p, int n_in, int h, const float* x) {
+    return mlp_forward_impl<true>(p, n_in, h, x);
+}
+
+float mlp_forward_host(const float* p, int n_in, int h, const float* x) {
+    static const bool hw = __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma");
+    return hw ? mlp_forward_fma(p, n_in, h, x) : mlp_forward_impl<false>(p, n_in, h, x);
 }
 
 bool learned_model_loaded() {

@@ -8,11 +8,13 @@
 // search tries every ready gate as the seed and keeps the cluster with the
 // most gates, before the remaining gates are assigned to further clusters.
 //
-// Cost-driven mode (analytic or learned cost model): the complete greedy
-// schedule is built for every cap k <= kmax and the one with the smallest
-// predicted total time is kept (per-cluster "gates per microsecond" choices
-// are myopic: a wide cluster can look cheap per gate and still leave more
-// total work).
+// Cost-driven mode (analytic or learned cost model): complete candidate
+// schedules - greedy with caps kmax - 2 .. kmax, and greedy with kmax where a
+// full-width cluster may give way to the (kmax - 1)-qubit cluster of the same
+// seed when that is predicted cheaper per gate - are built, and the one with
+// the smallest predicted total time is kept. (Per-cluster choices alone are
+// myopic: a cluster can look cheap per gate and still leave more total work;
+// the final comparison is between whole schedules.)
 //
 // Extensions for the GPU kernels (both exact, as diagonal gates commute):
 //   * a cluster made only of diagonal gates becomes a diagonal pass, which
@@ -72,19 +74,38 @@ struct Grown {
     int n_gates() const { return (int)(members.size() + epi.size()); }
 };
 
-// Grow a cluster from `seed` with at most `kcap` qubits.
-Grown grow(const Dag& d, const std::vector<int>& head0, int seed, int kcap, bool fuse_diag) {
+// Take gate gi: advance the heads of its qubits and update the ready list
+// (ascending gate index): gi leaves it, and only the new heads of gi's qubits
+// can become ready.
+void take(const Dag& d, std::vector<int>& head, std::vector<int>& rl, int gi) {
+    d.pop(head, gi);
+    rl.erase(std::lower_bound(rl.begin(), rl.end(), gi));
+    const SGate& s = (*d.g)[gi];
+    for (int j = 0; j < s.nq; ++j) {
+        const auto& qq = d.queue[s.q[j]];
+        const int h = head[s.q[j]];
+        if (h >= (int)qq.size()) continue;
+        const int g2 = qq[h];
+        if (!d.ready(head, g2)) continue;
+        auto it = std::lower_bound(rl.begin(), rl.end(), g2);
+        if (it == rl.end() || *it != g2) rl.insert(it, g2);
+    }
+}
+
+// Grow a cluster from `seed` with at most `kcap` qubits; rl0 is the ready
+// list at head0.
+Grown grow(const Dag& d, const std::vector<int>& head0, const std::vector<int>& rl0, int seed, int kcap,
+           bool fuse_diag) {
     const auto& G = *d.g;
     Grown r;
     r.head = head0;
+    std::vector<int> rl = rl0;
     r.Q = d.mask[seed];
     r.members.push_back(seed);
-    d.pop(r.head, seed);
+    take(d, r.head, rl, seed);
     uint64_t sealed = 0;
     int n_epi_cz = 0, n_epi_ph = 0;
-    std::vector<int> rl;
     for (;;) {
-        d.ready_list(r.head, rl);
         // a gate that joins the matrix: fewest new qubits, then lowest index
         int best = -1, best_new = 1 << 30;
         for (int gi : rl) {
@@ -96,7 +117,7 @@ Grown grow(const Dag& d, const std::vector<int>& head0, int seed, int kcap, bool
         if (best >= 0) {
             r.members.push_back(best);
             r.Q |= d.mask[best];
-            d.pop(r.head, best);
+            take(d, r.head, rl, best);
             continue;
         }
         if (!fuse_diag) break;
@@ -112,7 +133,7 @@ Grown grow(const Dag& d, const std::vector<int>& head0, int seed, int kcap, bool
         r.epi.push_back(best);
         sealed |= d.mask[best];
         if (G[best].kind == G_CZ) ++n_epi_cz; else ++n_epi_ph;
-        d.pop(r.head, best);
+        take(d, r.head, rl, best);
     }
     return r;
 }
@@ -122,10 +143,21 @@ bool all_diag(const std::vector<SGate>& G, const Grown& c) {
     return true;
 }
 
+// Predicted time of a grown cluster (sorted qubits from its mask).
+double grown_cost(const OpCostFn& cost, const Grown& c, int n) {
+    int q[64], k = 0;
+    for (int b = 0; b < n; ++b)
+        if (c.Q >> b & 1) q[k++] = b;
+    return cost(k, q, (int)c.epi.size());
+}
+
 // Greedy clustering with at most kcap qubits per cluster (gates with more
-// qubits form a cluster of their own width).
+// qubits form a cluster of their own width). With a cost function (`trim`),
+// a cluster that reached kcap qubits is compared with the cluster the same
+// seed grows under kcap - 1, and the one with the smaller predicted time per
+// gate is taken.
 std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::vector<char>& dropped, int n_applied,
-                            int kcap_in, bool fuse_diag) {
+                            int kcap_in, bool fuse_diag, const OpCostFn* trim = nullptr) {
     const int ng = (int)gates.size();
     std::vector<SOp> out;
     Dag d;
@@ -146,12 +178,20 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
     while (remaining > 0) {
         d.ready_list(head, rl);
         Grown best;
-        int best_score = -1;
+        int best_score = -1, best_seed = -1;
         for (int seed : rl) {
             // a gate wider than kmax (a dense gate) forms a cluster of its own width
             const int khi = std::max(kmax, popc(d.mask[seed]));
-            Grown c = grow(d, head, seed, khi, fuse_diag);
-            if (c.n_gates() > best_score) { best_score = c.n_gates(); best = std::move(c); }
+            Grown c = grow(d, head, rl, seed, khi, fuse_diag);
+            if (c.n_gates() > best_score) { best_score = c.n_gates(); best = std::move(c); best_seed = seed; }
+        }
+        if (trim && kmax > 1 && popc(best.Q) == kmax && popc(d.mask[best_seed]) < kmax) {
+            Grown small = grow(d, head, rl, best_seed, kmax - 1, fuse_diag);
+            if (!all_diag(gates, small) && !all_diag(gates, best)) {
+                const double per_big = grown_cost(*trim, best, n) / best.n_gates();
+                const double per_small = grown_cost(*trim, small, n) / small.n_gates();
+                if (per_small < per_big) best = std::move(small);
+            }
         }
         SOp op;
         if (all_diag(gates, best)) {
@@ -245,22 +285,29 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
         S.ops = greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag);
         return S;
     }
-    // cost-driven: the complete greedy schedule for every cap, the one with
-    // the smallest predicted total time wins (schedules built in parallel)
+    // cost-driven: complete candidate schedules, the one with the smallest
+    // predicted total time wins (built in parallel). Candidates: the greedy
+    // schedule for each cap kmax - 2 .. kmax (smaller caps only add passes)
+    // and the cost-trimmed greedy schedule for kmax.
+    const int k_lo = std::max(1, kmax - 2);
     std::vector<std::future<std::vector<SOp>>> futs;
-    for (int kc = 1; kc <= kmax; ++kc)
+    for (int kc = k_lo; kc <= kmax; ++kc)
         futs.push_back(std::async(std::launch::async, [&, kc]() {
             return greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag);
         }));
+    if (kmax > 1)
+        futs.push_back(std::async(std::launch::async, [&]() {
+            return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost);
+        }));
     double best_cost = 0.0;
-    for (int kc = 1; kc <= kmax; ++kc) {
-        std::vector<SOp> ops = futs[kc - 1].get();
+    for (size_t c = 0; c < futs.size(); ++c) {
+        std::vector<SOp> ops = futs[c].get();
         double total = 0.0;
         for (const SOp& op : ops) {
             if (op.kind == OP_DIAG) total += cost(0, op.qubits, 0);
             else total += cost(op.k, op.qubits, (int)op.epi.size());
         }
-        if (kc == 1 || total < best_cost) {
+        if (c == 0 || total < best_cost) {
             best_cost = total;
             S.ops = std::move(ops);
         }

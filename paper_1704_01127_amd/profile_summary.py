@@ -28,8 +28,33 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def demangle(name: str) -> str:
+    """Itanium-demangled name (rocprofv3 leaves some names mangled)."""
+    if not name.startswith("_Z"):
+        return name
+    import re
+    import subprocess
+    try:
+        r = subprocess.run(["c++filt", name], capture_output=True, text=True, timeout=10)
+        out = r.stdout.strip()
+    except (OSError, subprocess.SubprocessError):
+        out = ""
+    if out and out != name:
+        return out
+    # c++filt does not know _Float16 vector parameters: read the qualified
+    # name and a single bool template argument by hand
+    m = re.match(r"_ZN4qsim(\d+)", name)
+    if not m:
+        return name
+    ln = int(m.group(1))
+    base = name[m.end():m.end() + ln]
+    rest = name[m.end() + ln:]
+    t = re.match(r"ILb([01])EE", rest)
+    return base + ("<%s>" % ("true" if t.group(1) == "1" else "false") if t else "")
+
+
 def short(name: str) -> str:
-    n = name.split("(")[0]
+    n = demangle(name).split("(")[0]
     for p in ("void ", "qsim::"):
         n = n.replace(p, "")
     return n.strip()

@@ -100,16 +100,21 @@ def test_learned_scheduler_runs_exactly():
 
 @pytest.mark.skipif(not os.path.exists(qsim.COST_MODEL_PATH), reason="no trained cost model in the tree")
 def test_learned_vs_greedy_time_to_solution():
-    """The trained model against fixed-k greedy (k = 5) on held-out 28-qubit
-    depth-40 circuits with Haar 5-qubit gates: identical results, and the
-    learned schedule is not slower (its measured gain is printed)."""
+    """What the trained model gains: held-out 28- and 30-qubit depth-40
+    circuits with Haar 5-qubit gates, timed end to end (scheduling included)
+    with the learned scheduler (k <= 6) against the fixed-k greedy scheduler
+    that is used without a model (k = 5, the default) and against fixed-k
+    greedy at k = 6. Results must agree; the learned schedule must beat k = 5
+    by at least 5% in total and be within 3% of k = 6 (the gains are printed)."""
     from paper_1704_01127_amd.costmodel import compare
     qsim.load_tuning()
     lines = []
-    rows = compare(n_list=(28,), seeds=range(110, 113), log=lines.append)
+    rows = compare(n_list=(28, 30), seeds=range(110, 113), log=lines.append)
     print("\n".join(lines))
     for r in rows:
         assert r["fidelity_learned_vs_greedy"] >= 1 - 1e-6
-    g = sum(r["greedy_ms"] for r in rows)
+    g5 = sum(r["greedy_ms"] for r in rows)
+    g6 = sum(r["greedy6_ms"] for r in rows)
     lr = sum(r["learned_ms"] for r in rows)
-    assert lr <= 1.03 * g, (lr, g)
+    assert lr <= 0.95 * g5, (lr, g5)
+    assert lr <= 1.03 * g6, (lr, g6)
