@@ -218,14 +218,18 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * the fp32 three-multiplication complex product, 2 (default) fp16 matrix
  * cores on hi / lo halves of the operands (about 2^-21 relative error, the
  * size of fp32 rounding),
- * read when a cluster is enqueued. Errors: QSIM_E_INVALID for an unknown
- * option or an out-of-range value. */
+ * read when a cluster is enqueued. QSIM_OPT_FOLD_INIT (default 1): when a
+ * run starts from the uniform state (skip_initial_h) with a cluster, that
+ * state and the cluster - a product state again - are written in one pass
+ * instead of an initialisation pass and a cluster pass. Errors:
+ * QSIM_E_INVALID for an unknown option or an out-of-range value. */
 typedef enum {
     QSIM_OPT_CLUSTER_VARIANT = 1,
     QSIM_OPT_BATCH_GRID = 2,
     QSIM_OPT_BATCH_PAD = 3,
     QSIM_OPT_BATCH_ITEM_TILES = 4,
-    QSIM_OPT_K6_KERNEL = 5
+    QSIM_OPT_K6_KERNEL = 5,
+    QSIM_OPT_FOLD_INIT = 6
 } qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);

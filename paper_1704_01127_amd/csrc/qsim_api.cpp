@@ -70,6 +70,7 @@ int g_batch_grid = 0;
 int g_batch_pad = 0;
 int g_batch_item_tiles = 128;
 int g_k6_kernel = 2;
+int g_fold_init = 1;
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
@@ -85,7 +86,8 @@ double learned_cost_us(int n, bool dbl, int k, const int* qubits, int n_epi);
 }  // namespace qsim
 
 struct OpRecord {
-    int kind;  // 0 cluster, 1 diagonal pass, 2 1-qubit gate, 3 1-qubit phase, 4 CZ, 5 matrix build
+    int kind;  // 0 cluster, 1 diagonal pass, 2 1-qubit gate, 3 1-qubit phase, 4 CZ, 5 matrix build,
+               // 6 uniform initialisation folded into a cluster
     int k;
     int qubits[6];
     int flags;  // bit 0: diagonal epilogue, bit 1: LDS-staged kernel, bit 2: matrix-core kernel
@@ -199,7 +201,7 @@ struct Chunk {
     std::vector<double> dense;
     std::vector<EpiDesc> epis;
     struct Item {
-        int kind;        // 0 cluster, 1 diag pass, 2 gate1q, 3 phase1q, 4 cz
+        int kind;        // 0 cluster, 1 diag pass, 2 gate1q, 3 phase1q, 4 cz, 6 uniform init + cluster
         ClusterGeom geom;
         int layout;
         int slot;        // matrix slot (cluster)
@@ -279,7 +281,7 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
         std::memset(&r, 0, sizeof(r));
         r.kind = it.kind;
         const int variant = it.kind == 0 ? cluster_variant_for(s->dbl, it.geom, it.layout) : 0;
-        if (it.kind == 0) {
+        if (it.kind == 0 || it.kind == 6) {
             r.k = it.geom.k;
             for (int j = 0; j < it.geom.k; ++j) r.qubits[j] = it.geom.t[j];
             r.flags = (it.epi >= 0 ? 1 : 0) | (variant == 1 ? 2 : 0) | (it.layout != LAYOUT_PLAIN ? 4 : 0);
@@ -299,6 +301,10 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
             case 2: e = launch_gate1q(s->psi, s->dbl, s->n, it.q0, it.m, s->st); break;
             case 3: e = launch_phase1q(s->psi, s->dbl, s->n, it.q0, it.m[0], it.m[1], s->st); break;
             case 4: e = launch_cz(s->psi, s->dbl, s->n, it.q0, it.q1, s->st); break;
+            case 6:
+                e = launch_init_cluster(s->psi, s->dbl, it.geom, mats + it.slot * sb,
+                                        it.epi >= 0 ? epis + it.epi : nullptr, s->st);
+                break;
         }
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         HIP_TRY(rec_end(s, r), "event record");
@@ -330,9 +336,12 @@ qsim_status diag_desc(int n, const std::vector<std::pair<int, int>>& pairs,
 }
 
 // Add a cluster op (sorted qubits, member gates, epilogue gates) to the chunk;
-// flushes first if the chunk is full.
+// flushes first if the chunk is full. fold_init: the op is the first on the
+// uniform state and is written by the folded initialisation kernel (plain
+// complex128 matrix).
 qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, const qsim_gate* gates,
-                        const std::vector<int>& members, const std::vector<int>& epi_gates) {
+                        const std::vector<int>& members, const std::vector<int>& epi_gates,
+                        bool fold_init = false) {
     size_t dense_need = 0;
     for (int gi : members) if (gates[gi].kind == G_DENSE) dense_need += size_t(2) << (2 * gates[gi].k);
     const size_t need = align256((c.bops.size() + 1) * sizeof(BuildOp)) +
@@ -350,8 +359,8 @@ qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, con
     std::memset(&bo, 0, sizeof(bo));
     bo.k = k;
     bo.gate0 = (int)c.bgates.size();
-    bo.is_double = s->dbl;
-    bo.layout = cluster_layout(s->dbl, k, s->n);
+    bo.is_double = fold_init ? 1 : s->dbl;
+    bo.layout = fold_init ? LAYOUT_PLAIN : cluster_layout(s->dbl, k, s->n);
     bo.out_off = (int64_t)c.slots_used * (int64_t)slot_bytes(s->dbl, s->kmax_ws);
     for (int gi : members) c.bgates.push_back(to_build_gate(gates[gi], pos_of, c.dense));
     // epilogue: terms on target qubits only join the matrix, the rest go to the descriptor
@@ -361,7 +370,7 @@ qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, con
     c.bops.push_back(bo);
     Chunk::Item it;
     std::memset(&it, 0, sizeof(it));
-    it.kind = 0;
+    it.kind = fold_init ? 6 : 0;
     for (int j = 0; j < k; ++j) it.geom.t[j] = qubits[j];
     it.geom.n = s->n;
     it.geom.k = k;
@@ -608,11 +617,18 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
         qsim_state_s* s;
         ~RecOff() { s->recording = false; }
     } rec_off{s};
-    if (S.uniform_init) HIP_TRY(launch_init(s->psi, s->n, s->dbl, 1, s->st), "init launch");
+    // the uniform start and a leading cluster are written in one pass
+    const bool fold = S.uniform_init && g_fold_init && !S.ops.empty() && S.ops[0].kind == OP_CLUSTER;
+    if (S.uniform_init && !fold) HIP_TRY(launch_init(s->psi, s->n, s->dbl, 1, s->st), "init launch");
     Chunk c;
-    for (const SOp& op : S.ops) {
+    for (size_t oi = 0; oi < S.ops.size(); ++oi) {
+        const SOp& op = S.ops[oi];
         qsim_status r = QSIM_OK;
-        if (op.kind == OP_GATE) {
+        if (oi == 0 && fold) {
+            r = add_cluster(s, c, op.k, op.qubits, gates, op.members, op.epi, true);
+            st.n_clusters_by_k[op.k]++;
+            st.n_gates_fused_epilogue += (int)op.epi.size();
+        } else if (op.kind == OP_GATE) {
             r = add_gate(s, c, gates, op.members[0]);
         } else if (op.kind == OP_DIAG) {
             std::vector<std::pair<int, int>> pairs;
@@ -702,6 +718,11 @@ qsim_status qsim_set_option(int option, int value) {
         g_k6_kernel = value;
         return QSIM_OK;
     }
+    if (option == QSIM_OPT_FOLD_INIT) {
+        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "fold_init must be 0 or 1");
+        g_fold_init = value;
+        return QSIM_OK;
+    }
     if (option == QSIM_OPT_BATCH_ITEM_TILES) {
         if (value < 1 || value > 4096 || (value & (value - 1)))
             return fail(QSIM_E_INVALID, "tiles per batch item must be a power of two in [1, 4096]");
@@ -741,6 +762,7 @@ int qsim_get_option(int option) {
     if (option == QSIM_OPT_BATCH_PAD) return g_batch_pad;
     if (option == QSIM_OPT_BATCH_ITEM_TILES) return g_batch_item_tiles;
     if (option == QSIM_OPT_K6_KERNEL) return g_k6_kernel;
+    if (option == QSIM_OPT_FOLD_INIT) return g_fold_init;
     return -1;
 }
 

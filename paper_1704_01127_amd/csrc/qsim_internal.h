@@ -155,6 +155,7 @@ extern int g_batch_grid;        // work-groups of the batch launch, 0 = two per 
 extern int g_batch_pad;         // padding qubits: 0 lowest outside the cluster, 1 highest
 extern int g_batch_item_tiles;  // tiles of 2^11 amplitudes per work item
 extern int g_k6_kernel;         // float k = 6 clusters: 0 fp32 real-split, 1 fp32 three-product, 2 fp16 halves
+extern int g_fold_init;         // fold the uniform initialisation into the first cluster
 
 // Bytes of a cluster matrix in each layout.
 inline int64_t matrix_bytes(int k, int layout, bool dbl) {
@@ -169,6 +170,10 @@ inline int64_t matrix_bytes(int k, int layout, bool dbl) {
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `st` and return hipSuccess or the launch error.
 hipError_t launch_init(void* psi, int n, bool dbl, int mode, hipStream_t st);
+// The uniform state followed by one cluster (matrix: plain complex128 layout)
+// and its diagonal epilogue, written in one pass.
+hipError_t launch_init_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, const EpiDesc* epi,
+                               hipStream_t st);
 hipError_t launch_build(const BuildOp* ops, int n_ops, const BuildGate* gates, const double* dense,
                         char* mat_base, hipStream_t st);
 // Variant of the cluster kernel chosen for (dtype, k, n, targets).
@@ -201,9 +206,9 @@ hipError_t launch_batch(const BatchOp* ops, const BatchItem* items, uint32_t n_i
 hipError_t launch_gate1q(void* psi, bool dbl, int n, int q, const double m[8], hipStream_t st);
 hipError_t launch_phase1q(void* psi, bool dbl, int n, int q, double cs, double sn, hipStream_t st);
 hipError_t launch_cz(void* psi, bool dbl, int n, int a, int b, hipStream_t st);
-// Reductions: partial sums go to `part` (kReduceBlocks * 4 doubles), the
+// Reductions: partial sums go to `part` (kReduceBlocks * 8 doubles), the
 // final values to `res` (4 doubles).
-constexpr int kReduceBlocks = 1024;
+constexpr int kReduceBlocks = 2048;
 hipError_t launch_stats(const void* psi, bool dbl, int n, void* probs, bool probs_dbl, double* part,
                         double* res, hipStream_t st);
 hipError_t launch_compare(const void* psi, bool dbl, int n, const void* ref, bool ref_dbl,

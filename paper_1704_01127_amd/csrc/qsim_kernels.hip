@@ -23,6 +23,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 namespace qsim {
 
@@ -1264,6 +1265,57 @@ __global__ __launch_bounds__(256) void k_init(typename Cplx<T>::type* __restrict
     }
 }
 
+// ------------------------------------------------------------ initialisation folded into the first cluster
+// The uniform state (the skipped leading H layer, Sec. 3.6) is a product state,
+// and so is the first cluster's result on it: amplitude i is
+// w[y(i)] = 2^(-n/2) sum_x M[y(i)][x], y(i) the target bits of i, times the
+// cluster's diagonal epilogue factor. One write-only pass replaces the
+// initialisation and the first cluster's read-and-write pass. M is the plain
+// complex128 matrix; w is summed in float64 and rounded once.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_init_cluster(typename Cplx<T>::type* __restrict__ psi, ClusterGeom g,
+                                                      const double2* __restrict__ M,
+                                                      const EpiDesc* __restrict__ epi, double amp) {
+    using V = typename Cplx<T>::type;
+    constexpr int D = 1 << K;
+    __shared__ double2 w[D];
+    __shared__ uint64_t toff[D];
+    if ((int)threadIdx.x < D) {
+        double re = 0.0, im = 0.0;
+        for (int x = 0; x < D; ++x) {
+            const double2 m = M[threadIdx.x * D + x];
+            re += m.x;
+            im += m.y;
+        }
+        w[threadIdx.x] = make_double2(re * amp, im * amp);
+        uint64_t o = 0;
+        for (int m = 0; m < K; ++m)
+            if ((threadIdx.x >> m) & 1) o |= uint64_t(1) << g.t[m];
+        toff[threadIdx.x] = o;
+    }
+    __syncthreads();
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    // one thread per column (assignment of the non-target bits): its diagonal
+    // factor once, then the column's 2^k amplitudes
+    for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < g.ncols; c += stride) {
+        const uint64_t base = deposit_cols<K>(c, g);
+        ColFactor<T> f{0u, 0u, T(1), T(0)};
+        if (has_epi) f = col_factor<T>(epi, base);
+#pragma unroll
+        for (int y = 0; y < D; ++y) {
+            const double2 v = w[y];
+            T re = (T)v.x, im = (T)v.y;
+            if (has_epi) apply_factor(re, im, f, (uint32_t)y, has_ph);
+            V o;
+            o.x = re;
+            o.y = im;
+            psi[base | toff[y]] = o;
+        }
+    }
+}
+
 // ------------------------------------------------------------ cluster-matrix builder
 // One work-group (64 threads) per cluster. Thread x owns column x of the
 // cluster matrix: it starts from the basis vector e_x of the 2^k space and
@@ -1447,19 +1499,34 @@ __device__ void block_reduce_store(double (&vals)[8], int nv, unsigned maxmask, 
     }
 }
 
+// The grid-stride loops below are unrolled by kRedU with all loads of a
+// round issued before any arithmetic: with one load in flight per lane the
+// reductions were bound by memory latency, not bandwidth. Every load
+// instruction stays coalesced (lane l reads element i + l, round after round).
+constexpr int kRedU = 8;
+
 template <typename T, typename P>
 __global__ __launch_bounds__(256) void k_stats(const typename Cplx<T>::type* __restrict__ psi, uint64_t count,
                                                P* __restrict__ probs, double* __restrict__ part) {
+    using V = typename Cplx<T>::type;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint64_t stride = (uint64_t)gridDim.x * 256;
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride) {
-        const auto a = psi[i];
+    auto acc = [&](const V& a, uint64_t i) {
         const double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
         v[0] += pr;
         v[1] += pr * pr;
         if (pr > 0.0) v[2] -= pr * log(pr);
         if (probs) probs[i] = (P)pr;
+    };
+    uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + (kRedU - 1) * stride < count; i += kRedU * stride) {
+        V a[kRedU];
+#pragma unroll
+        for (int u = 0; u < kRedU; ++u) a[u] = psi[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < kRedU; ++u) acc(a[u], i + u * stride);
     }
+    for (; i < count; i += stride) acc(psi[i], i);
     block_reduce_store(v, 3, 0u, part + blockIdx.x * 8);
 }
 
@@ -1467,11 +1534,11 @@ template <typename T, typename R>
 __global__ __launch_bounds__(256) void k_compare(const typename Cplx<T>::type* __restrict__ psi,
                                                  const typename Cplx<R>::type* __restrict__ ref, uint64_t count,
                                                  double* __restrict__ part) {
+    using V = typename Cplx<T>::type;
+    using W = typename Cplx<R>::type;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const uint64_t stride = (uint64_t)gridDim.x * 256;
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += stride) {
-        const auto a = psi[i];
-        const auto r = ref[i];
+    auto acc = [&](const V& a, const W& r) {
         const double ar = a.x, ai = a.y, rr = r.x, ri = r.y;
         v[0] += rr * ar + ri * ai;  // Re <ref|psi>
         v[1] += rr * ai - ri * ar;  // Im <ref|psi>
@@ -1479,7 +1546,21 @@ __global__ __launch_bounds__(256) void k_compare(const typename Cplx<T>::type* _
         v[3] += ar * ar + ai * ai;
         const double dr = ar - rr, di = ai - ri;
         v[4] = fmax(v[4], sqrt(dr * dr + di * di));
+    };
+    uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    constexpr int U = kRedU / 2;
+    for (; i + (U - 1) * stride < count; i += U * stride) {
+        V a[U];
+        W r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = psi[i + u * stride];
+            r[u] = ref[i + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc(a[u], r[u]);
     }
+    for (; i < count; i += stride) acc(psi[i], ref[i]);
     block_reduce_store(v, 5, 1u << 4, part + blockIdx.x * 8);
 }
 
@@ -1513,6 +1594,31 @@ hipError_t launch_init(void* psi, int n, bool dbl, int mode, hipStream_t st) {
         hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, cnt, mode, val);
     else
         hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, cnt, mode, (float)val);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, const EpiDesc* epi,
+                               hipStream_t st) {
+    const unsigned grid = grid_for(g.ncols, 256, kStreamGrid);
+    const double amp = std::sqrt(std::ldexp(1.0, -g.n));
+    auto go = [&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        if (dbl)
+            hipLaunchKernelGGL((k_init_cluster<double, K>), dim3(grid), dim3(256), 0, st, (double2*)psi, g,
+                               (const double2*)mat, epi, amp);
+        else
+            hipLaunchKernelGGL((k_init_cluster<float, K>), dim3(grid), dim3(256), 0, st, (float2*)psi, g,
+                               (const double2*)mat, epi, amp);
+    };
+    switch (g.k) {
+        case 1: go(std::integral_constant<int, 1>()); break;
+        case 2: go(std::integral_constant<int, 2>()); break;
+        case 3: go(std::integral_constant<int, 3>()); break;
+        case 4: go(std::integral_constant<int, 4>()); break;
+        case 5: go(std::integral_constant<int, 5>()); break;
+        case 6: go(std::integral_constant<int, 6>()); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

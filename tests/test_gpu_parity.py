@@ -174,6 +174,34 @@ def test_k6_kernels_circuit(k6_kernel):
     assert np.max(np.abs(got - ref)) <= 1e-5
 
 
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("kmax", [1, 3, 5, 6])
+def test_fold_init_matches_oracle(dt, kmax):
+    """The uniform start written together with the first cluster (and its
+    diagonal epilogue) in one pass gives the oracle's state, as does the
+    unfolded form."""
+    circ = supremacy_circuit(4, 4, 18, seed=40 + kmax)
+    ref = oracle.run(circ)
+    first_is_cluster = qsim.schedule(circ.n, circ.gates, kmax=kmax, fuse_diag=True,
+                                     skip_initial_h=True)["op_kind"][0] == 0
+    old = qsim.get_option(qsim.OPT_FOLD_INIT)
+    try:
+        for fold in (1, 0):
+            qsim.set_option(qsim.OPT_FOLD_INIT, fold)
+            s = make_state(circ.n, dt)
+            s.run_circuit(circ.gates, kmax=kmax, fuse_diag=True, skip_initial_h=True, record_timings=True)
+            kinds = [r["kind"] for r in s.op_timings()]
+            assert ("init_cluster" in kinds) == (bool(fold) and first_is_cluster), kinds
+            got = s.to_numpy()
+            if dt == "c128":
+                assert np.max(np.abs(got - ref)) <= 1e-12
+            else:
+                assert fidelity(got, ref) >= 1 - 1e-6
+                assert np.max(np.abs(got - ref)) <= 1e-5
+    finally:
+        qsim.set_option(qsim.OPT_FOLD_INIT, old)
+
+
 # ------------------------------------------------------------------ diagonal layer
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 @pytest.mark.parametrize("n", [1, 2, 3, 9, 16])
