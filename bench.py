@@ -35,9 +35,13 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def kernel_name(rec, k6_kernel=2) -> str:
+def kernel_name(rec, k6_kernel=2, pair_tile=11) -> str:
     """Name (as rocprofv3 reports it) of the float cluster kernel a launch used."""
     k, lowt = rec["k"], rec["qubits"][0] == 0
+    if rec["kind"] == "pair":
+        q = set(rec["qubits"])
+        ten = pair_tile == 10 and (0 in q or len(q) < 10)  # the 10-qubit tile holds qubit 0
+        return "k_cluster_f32_pair10<12>" if ten else "k_cluster_f32_multi<2, 8>"
     if not rec.get("mfma"):
         return "k_cluster_valu<float, %d>" % k
     if k == 6 and k6_kernel in (1, 2):
@@ -59,6 +63,10 @@ def parse():
     ap.add_argument("--kmax", type=int, default=6)
     ap.add_argument("--scheduler", default="learned")
     ap.add_argument("--no-fuse-diag", action="store_true")
+    ap.add_argument("--pair-tile", type=int, default=None, choices=[10, 11],
+                    help="qubits of the tile the pair kernel holds in LDS")
+    ap.add_argument("--pair", type=int, default=None,
+                    help="pairing of small clusters: 0 off, 1 pairs, 2 every cluster alone in the pair kernel")
     ap.add_argument("--fp64-steps", type=int, default=None, help="steps of the float64 per-gate form")
     ap.add_argument("--only", choices=["fused", "pergate", "batch"], default=None,
                     help="run one form only (for profiling); batch: the 512-circuit launch alone")
@@ -155,6 +163,10 @@ def main():
     from paper_1704_01127_amd import qsim
     from supremacy_inputs import supremacy_circuit
 
+    if args.pair is not None:
+        qsim.set_option(qsim.OPT_PAIR, args.pair)
+    if args.pair_tile is not None:
+        qsim.set_option(qsim.OPT_PAIR_TILE, args.pair_tile)
     circ = supremacy_circuit(args.rows, args.cols, args.depth, args.seed)
     n = circ.n
     gates = circ.gates
@@ -226,11 +238,12 @@ def main():
     if recs:
         k6k = qsim.get_option(qsim.OPT_K6_KERNEL)
         amp_bytes = 8
-        clusters = [r for r in recs if r["kind"] == "cluster"]
+        # passes that apply clusters: single clusters and pairs (two clusters, one pass)
+        clusters = [r for r in recs if r["kind"] in ("cluster", "pair")]
         total_ms = sum(r["ms"] for r in recs)
         groups = {}
         for r in clusters:
-            groups.setdefault(kernel_name(r, k6k), []).append(r["ms"])
+            groups.setdefault(kernel_name(r, k6k, qsim.get_option(qsim.OPT_PAIR_TILE)), []).append(r["ms"])
         kname, times = max(groups.items(), key=lambda kv: sum(kv[1]))
         bytes_per_launch = 2 * 2 ** n * amp_bytes
         avg_ms = sum(times) / len(times)
@@ -250,7 +263,7 @@ def main():
                                              for k, v in groups.items()}}
         csum = sum(r["ms"] for r in clusters)
         cbytes = len(clusters) * 2 * 2 ** n * amp_bytes
-        cflops = sum(2 ** n * (8 * 2 ** r["k"] - 2) for r in clusters)
+        cflops = sum(2 ** n * (8 * 2 ** r["k"] - 2) * (2 if r["kind"] == "pair" else 1) for r in clusters)
         out["cluster_kernels"] = {"launches_per_step": len(clusters) // max(1, args.steps),
                                   "hbm_GBs": round(cbytes / (csum * 1e-3) / 1e9, 1),
                                   "hbm_frac": round(cbytes / (csum * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -258,16 +271,16 @@ def main():
                                   "share_of_gpu_time": round(csum / total_ms, 4)}
         by_k = {}
         for r in clusters:
-            d = by_k.setdefault(r["k"], [0, 0.0])
+            d = by_k.setdefault("pair" if r["kind"] == "pair" else r["k"], [0, 0.0])
             d[0] += 1
             d[1] += r["ms"]
         out["cluster_kernels"]["by_k"] = {
             str(kk): {"launches": v[0], "avg_ms": round(v[1] / v[0], 4),
                       "GBs": round(2 * 2 ** n * amp_bytes / (v[1] / v[0] * 1e-3) / 1e9, 1)}
-            for kk, v in sorted(by_k.items())}
+            for kk, v in sorted(by_k.items(), key=lambda kv: str(kv[0]))}
         others = {}
         for r in recs:
-            if r["kind"] != "cluster":
+            if r["kind"] not in ("cluster", "pair"):
                 d = others.setdefault(r["kind"], [0, 0.0])
                 d[0] += 1
                 d[1] += r["ms"]

@@ -190,9 +190,11 @@ const char* qsim_last_error(void);
 /* Per-launch GPU times of the last qsim_run_circuit that had record_timings
  * set, measured with HIP events on the state's stream. For each launch, in
  * order: op_kind (0 cluster, 1 diagonal pass, 2 single-qubit gate, 3
- * single-qubit phase, 4 CZ, 5 cluster-matrix build), op_k (cluster size;
- * number of matrices for a build), op_qubits[6*i ..] (sorted targets of a
- * cluster, -1 padded), op_epi (flags of a cluster: bit 0 = applies diagonal
+ * single-qubit phase, 4 CZ, 5 cluster-matrix build, 6 uniform initialisation
+ * written together with the first cluster, 7 two clusters in one pass),
+ * op_k (cluster size - 5 for a pair; number of matrices for a build),
+ * op_qubits[6*i ..] (sorted targets of a cluster - of the first for a pair -
+ * or the gate's qubits, -1 padded), op_epi (flags of a cluster: bit 0 = applies diagonal
  * gates while storing, bit 1 = LDS-staged kernel variant, bit 2 = matrix-core
  * kernel) and ms (milliseconds). Arrays of cap entries (any may be NULL);
  * *n_ops receives the count. Synchronises the stream. */
@@ -221,7 +223,15 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * read when a cluster is enqueued. QSIM_OPT_FOLD_INIT (default 1): when a
  * run starts from the uniform state (skip_initial_h) with a cluster, that
  * state and the cluster - a product state again - are written in one pass
- * instead of an initialisation pass and a cluster pass. Errors:
+ * instead of an initialisation pass and a cluster pass. QSIM_OPT_PAIR
+ * (default 0): on complex64 states of >= 11 qubits, two consecutive clusters
+ * of <= 5 qubits are applied in one pass over the state (their qubits fit one
+ * tile held in LDS; fp16 matrix cores on operand halves); 2 sends every such
+ * cluster alone through that kernel. It is off by default because the paired
+ * pass is limited by per-wave ALU and LDS work and takes longer than two
+ * single passes. QSIM_OPT_PAIR_TILE is that tile's size in qubits, 11
+ * (default) or 10 (12 waves per compute unit; a pair whose ten qubits leave
+ * out qubit 0 uses the 11-qubit tile). Errors:
  * QSIM_E_INVALID for an unknown option or an out-of-range value. */
 typedef enum {
     QSIM_OPT_CLUSTER_VARIANT = 1,
@@ -229,7 +239,9 @@ typedef enum {
     QSIM_OPT_BATCH_PAD = 3,
     QSIM_OPT_BATCH_ITEM_TILES = 4,
     QSIM_OPT_K6_KERNEL = 5,
-    QSIM_OPT_FOLD_INIT = 6
+    QSIM_OPT_FOLD_INIT = 6,
+    QSIM_OPT_PAIR = 7,
+    QSIM_OPT_PAIR_TILE = 8
 } qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);

@@ -71,6 +71,8 @@ int g_batch_pad = 0;
 int g_batch_item_tiles = 128;
 int g_k6_kernel = 2;
 int g_fold_init = 1;
+int g_pair = 0;
+int g_pair_tile = 11;
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
@@ -87,7 +89,7 @@ double learned_cost_us(int n, bool dbl, int k, const int* qubits, int n_epi);
 
 struct OpRecord {
     int kind;  // 0 cluster, 1 diagonal pass, 2 1-qubit gate, 3 1-qubit phase, 4 CZ, 5 matrix build,
-               // 6 uniform initialisation folded into a cluster
+               // 6 uniform initialisation folded into a cluster, 7 two clusters in one pass
     int k;
     int qubits[6];
     int flags;  // bit 0: diagonal epilogue, bit 1: LDS-staged kernel, bit 2: matrix-core kernel
@@ -201,11 +203,14 @@ struct Chunk {
     std::vector<double> dense;
     std::vector<EpiDesc> epis;
     struct Item {
-        int kind;        // 0 cluster, 1 diag pass, 2 gate1q, 3 phase1q, 4 cz, 6 uniform init + cluster
+        int kind;        // 0 cluster, 1 diag pass, 2 gate1q, 3 phase1q, 4 cz, 6 uniform init + cluster,
+                         // 7 two 5-qubit clusters in one pass
         ClusterGeom geom;
         int layout;
         int slot;        // matrix slot (cluster)
         int epi;         // index into epis, -1 none
+        ClusterGeom geom2;  // kind 7: the second cluster
+        int slot2, epi2;
         int q0, q1;
         double m[8];
     };
@@ -281,7 +286,7 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
         std::memset(&r, 0, sizeof(r));
         r.kind = it.kind;
         const int variant = it.kind == 0 ? cluster_variant_for(s->dbl, it.geom, it.layout) : 0;
-        if (it.kind == 0 || it.kind == 6) {
+        if (it.kind == 0 || it.kind == 6 || it.kind == 7) {
             r.k = it.geom.k;
             for (int j = 0; j < it.geom.k; ++j) r.qubits[j] = it.geom.t[j];
             r.flags = (it.epi >= 0 ? 1 : 0) | (variant == 1 ? 2 : 0) | (it.layout != LAYOUT_PLAIN ? 4 : 0);
@@ -305,6 +310,17 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
                 e = launch_init_cluster(s->psi, s->dbl, it.geom, mats + it.slot * sb,
                                         it.epi >= 0 ? epis + it.epi : nullptr, s->st);
                 break;
+            case 7: {
+                int32_t t[2][5];
+                for (int j = 0; j < 5; ++j) {
+                    t[0][j] = it.geom.t[j];
+                    t[1][j] = it.geom2.t[j];
+                }
+                const void* m2[2] = {mats + it.slot * sb, mats + it.slot2 * sb};
+                const EpiDesc* e2[2] = {it.epi >= 0 ? epis + it.epi : nullptr, it.epi2 >= 0 ? epis + it.epi2 : nullptr};
+                e = launch_multi(s->psi, s->n, it.q1, t, m2, e2, s->st);
+                break;
+            }
         }
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         HIP_TRY(rec_end(s, r), "event record");
@@ -400,6 +416,87 @@ qsim_status add_diag(qsim_state_s* s, Chunk& c, const std::vector<std::pair<int,
     it.kind = 1;
     it.epi = (int)c.epis.size();
     c.epis.push_back(e);
+    c.items.push_back(it);
+    return QSIM_OK;
+}
+
+// The five targets of a cluster in a pair: its qubits, then qubits of `prefer`
+// (the pair's union), then the lowest others (identity on the added ones).
+void pad5(int n, const int* q, int k, uint64_t prefer, int* t) {
+    uint64_t m = 0;
+    for (int j = 0; j < k; ++j) {
+        t[j] = q[j];
+        m |= uint64_t(1) << q[j];
+    }
+    int cnt = k;
+    for (int b = 0; b < n && cnt < 5; ++b)
+        if ((prefer >> b & 1) && !(m >> b & 1)) { t[cnt++] = b; m |= uint64_t(1) << b; }
+    for (int b = 0; b < n && cnt < 5; ++b)
+        if (!(m >> b & 1)) { t[cnt++] = b; m |= uint64_t(1) << b; }
+    std::sort(t, t + 5);
+}
+
+// Two consecutive clusters of at most 5 qubits (complex64, n >= 11) applied
+// in one pass (fp16-halves matrices): the pair's qubits fit one 11-bit tile.
+qsim_status add_pair(qsim_state_s* s, Chunk& c, const SOp& A, const SOp* Bp, const qsim_gate* gates) {
+    const SOp& B = Bp ? *Bp : A;
+    const int m_ops = Bp ? 2 : 1;
+    size_t dense_need = 0, ng = 0;
+    for (const SOp* op : {&A, &B}) {
+        for (int gi : op->members) if (gates[gi].kind == G_DENSE) dense_need += size_t(2) << (2 * gates[gi].k);
+        ng += op->members.size() + op->epi.size();
+    }
+    const size_t need = align256((c.bops.size() + 2) * sizeof(BuildOp)) +
+                        align256((c.bgates.size() + ng) * sizeof(BuildGate)) +
+                        align256((c.dense.size() + dense_need) * sizeof(double)) +
+                        align256((c.epis.size() + 2) * sizeof(EpiDesc));
+    if (c.slots_used + 2 > kSlots || need > kDescBytes) {
+        qsim_status r = flush(s, c);
+        if (r != QSIM_OK) return r;
+    }
+    uint64_t U = 0;
+    for (const SOp* op : {&A, &B})
+        for (int j = 0; j < op->k; ++j) U |= uint64_t(1) << op->qubits[j];
+    int t[2][5];
+    pad5(s->n, A.qubits, A.k, U, t[0]);
+    for (int j = 0; j < 5; ++j) U |= uint64_t(1) << t[0][j];
+    pad5(s->n, B.qubits, B.k, U, t[1]);
+    Chunk::Item it;
+    std::memset(&it, 0, sizeof(it));
+    it.kind = 7;
+    it.layout = LAYOUT_SPLIT16F;
+    it.q1 = m_ops;  // clusters in the pass
+    const SOp* ops[2] = {&A, &B};
+    for (int m = 0; m < m_ops; ++m) {
+        int pos_of[64];
+        for (int i = 0; i < 64; ++i) pos_of[i] = -1;
+        for (int j = 0; j < 5; ++j) pos_of[t[m][j]] = j;
+        BuildOp bo;
+        std::memset(&bo, 0, sizeof(bo));
+        bo.k = 5;
+        bo.gate0 = (int)c.bgates.size();
+        bo.is_double = 0;
+        bo.layout = LAYOUT_SPLIT16F;
+        const int slot = c.slots_used++;
+        bo.out_off = (int64_t)slot * (int64_t)slot_bytes(s->dbl, s->kmax_ws);
+        for (int gi : ops[m]->members) c.bgates.push_back(to_build_gate(gates[gi], pos_of, c.dense));
+        EpiDesc e;
+        if (qsim_status r = split_epilogue(pos_of, gates, ops[m]->epi, c.bgates, c.dense, e)) return r;
+        bo.n_gates = (int)c.bgates.size() - bo.gate0;
+        c.bops.push_back(bo);
+        int epi = -1;
+        if (e.n_cc || e.n_mix || e.n_ph) {
+            epi = (int)c.epis.size();
+            c.epis.push_back(e);
+        }
+        ClusterGeom& g = m == 0 ? it.geom : it.geom2;
+        for (int j = 0; j < 5; ++j) g.t[j] = t[m][j];
+        g.n = s->n;
+        g.k = 5;
+        g.ncols = uint64_t(1) << (s->n - 5);
+        (m == 0 ? it.slot : it.slot2) = slot;
+        (m == 0 ? it.epi : it.epi2) = epi;
+    }
     c.items.push_back(it);
     return QSIM_OK;
 }
@@ -619,6 +716,9 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     } rec_off{s};
     // the uniform start and a leading cluster are written in one pass
     const bool fold = S.uniform_init && g_fold_init && !S.ops.empty() && S.ops[0].kind == OP_CLUSTER;
+    // consecutive clusters of <= 5 qubits on a complex64 state go in pairs
+    const bool pairing = g_pair && !s->dbl && s->n >= 11 && s->kmax_ws >= 5 && so.mode != 0;
+    auto small = [&](size_t i) { return S.ops[i].kind == OP_CLUSTER && S.ops[i].k <= 5; };
     if (S.uniform_init && !fold) HIP_TRY(launch_init(s->psi, s->n, s->dbl, 1, s->st), "init launch");
     Chunk c;
     for (size_t oi = 0; oi < S.ops.size(); ++oi) {
@@ -626,6 +726,17 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
         qsim_status r = QSIM_OK;
         if (oi == 0 && fold) {
             r = add_cluster(s, c, op.k, op.qubits, gates, op.members, op.epi, true);
+            st.n_clusters_by_k[op.k]++;
+            st.n_gates_fused_epilogue += (int)op.epi.size();
+        } else if (pairing && g_pair == 1 && oi + 1 < S.ops.size() && small(oi) && small(oi + 1)) {
+            const SOp& op2 = S.ops[oi + 1];
+            r = add_pair(s, c, op, &op2, gates);
+            st.n_clusters_by_k[op.k]++;
+            st.n_clusters_by_k[op2.k]++;
+            st.n_gates_fused_epilogue += (int)(op.epi.size() + op2.epi.size());
+            ++oi;
+        } else if (pairing && g_pair == 2 && small(oi)) {
+            r = add_pair(s, c, op, nullptr, gates);  // one cluster through the same kernel
             st.n_clusters_by_k[op.k]++;
             st.n_gates_fused_epilogue += (int)op.epi.size();
         } else if (op.kind == OP_GATE) {
@@ -723,6 +834,16 @@ qsim_status qsim_set_option(int option, int value) {
         g_fold_init = value;
         return QSIM_OK;
     }
+    if (option == QSIM_OPT_PAIR_TILE) {
+        if (value != 10 && value != 11) return fail(QSIM_E_INVALID, "pair tile bits must be 10 or 11");
+        g_pair_tile = value;
+        return QSIM_OK;
+    }
+    if (option == QSIM_OPT_PAIR) {
+        if (value < 0 || value > 2) return fail(QSIM_E_INVALID, "pair must be 0, 1 or 2");
+        g_pair = value;
+        return QSIM_OK;
+    }
     if (option == QSIM_OPT_BATCH_ITEM_TILES) {
         if (value < 1 || value > 4096 || (value & (value - 1)))
             return fail(QSIM_E_INVALID, "tiles per batch item must be a power of two in [1, 4096]");
@@ -763,6 +884,8 @@ int qsim_get_option(int option) {
     if (option == QSIM_OPT_BATCH_ITEM_TILES) return g_batch_item_tiles;
     if (option == QSIM_OPT_K6_KERNEL) return g_k6_kernel;
     if (option == QSIM_OPT_FOLD_INIT) return g_fold_init;
+    if (option == QSIM_OPT_PAIR) return g_pair;
+    if (option == QSIM_OPT_PAIR_TILE) return g_pair_tile;
     return -1;
 }
 
@@ -777,7 +900,8 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
         if (op_kind) op_kind[i] = r.kind;
         if (op_k) op_k[i] = r.k;
         if (op_qubits)
-            for (int j = 0; j < 6; ++j) op_qubits[6 * i + j] = (r.kind == 0 && j < r.k) ? r.qubits[j] : -1;
+            for (int j = 0; j < 6; ++j)  // diagonal passes and builds have no qubit list
+                op_qubits[6 * i + j] = (r.kind != 1 && r.kind != 5 && j < r.k) ? r.qubits[j] : -1;
         if (op_epi) op_epi[i] = r.flags;
         if (ms) {
             float t = 0.f;

@@ -156,6 +156,8 @@ extern int g_batch_pad;         // padding qubits: 0 lowest outside the cluster,
 extern int g_batch_item_tiles;  // tiles of 2^11 amplitudes per work item
 extern int g_k6_kernel;         // float k = 6 clusters: 0 fp32 real-split, 1 fp32 three-product, 2 fp16 halves
 extern int g_fold_init;         // fold the uniform initialisation into the first cluster
+extern int g_pair;              // apply consecutive clusters of <= 5 qubits (complex64) two per pass
+extern int g_pair_tile;         // tile bits of the pair kernel: 11 (8 waves) or 10 (12 waves)
 
 // Bytes of a cluster matrix in each layout.
 inline int64_t matrix_bytes(int k, int layout, bool dbl) {
@@ -170,6 +172,10 @@ inline int64_t matrix_bytes(int k, int layout, bool dbl) {
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `st` and return hipSuccess or the launch error.
 hipError_t launch_init(void* psi, int n, bool dbl, int mode, hipStream_t st);
+// m (1 or 2) five-qubit clusters on a complex64 state of n >= 11 qubits in one
+// pass, in order; targets sorted; matrices in LAYOUT_SPLIT16F (k = 5).
+hipError_t launch_multi(void* psi, int n, int m, const int32_t (*targets)[5], const void* const* mats,
+                        const EpiDesc* const* epis, hipStream_t st);
 // The uniform state followed by one cluster (matrix: plain complex128 layout)
 // and its diagonal epilogue, written in one pass.
 hipError_t launch_init_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, const EpiDesc* epi,

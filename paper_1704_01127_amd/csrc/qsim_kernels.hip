@@ -114,6 +114,11 @@ typedef double vd2 __attribute__((ext_vector_type(2)));
 typedef QSIM_GLOBAL float2 g_float2;
 typedef QSIM_GLOBAL vf4 g_vf4;
 typedef const QSIM_GLOBAL EpiDesc g_epi;
+// Diagonal descriptors read through the constant address space: uniform,
+// read-only data the compiler then loads with scalar instructions. (Vector
+// loads of them would share the vector-memory counter with a tile's prefetch,
+// and waiting for them would wait for the whole prefetch.)
+typedef const __attribute__((address_space(4))) EpiDesc c_epi;
 
 // Copy a cluster matrix of N elements into LDS: 16-byte loads, all in flight
 // before the first LDS store (a loop of single loads would wait for each).
@@ -720,7 +725,7 @@ struct StageF32 {
 // tile, tile + stride, ... < tile_end, staging through its LDS buffer L4.
 template <int K, int C, bool LOWT>
 __device__ __forceinline__ void staged_f32_tiles(g_float2* __restrict__ psi, const float* As, vf4* L4,
-                                                 g_epi* __restrict__ epi, const StageGeom& sg,
+                                                 c_epi* __restrict__ epi, const StageGeom& sg,
                                                  uint64_t tile, uint64_t tile_end, uint64_t stride) {
     constexpr int D = 1 << K;
     constexpr int HX = D / 2;
@@ -848,7 +853,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_stage(float2* __restrict
     load_matrix<RB * S * 64, 256>(As, reinterpret_cast<const vf4*>(Ap));
     __syncthreads();
     const int w = threadIdx.x >> 6;
-    staged_f32_tiles<K, C, LOWT>((g_float2*)psi, As, Ls[w], (g_epi*)epi, sg, (uint64_t)blockIdx.x * 4 + w,
+    staged_f32_tiles<K, C, LOWT>((g_float2*)psi, As, Ls[w], (c_epi*)epi, sg, (uint64_t)blockIdx.x * 4 + w,
                                  g.ncols >> C, (uint64_t)gridDim.x * 4);
 }
 
@@ -978,6 +983,359 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd
     } while (tile < ntiles);
 }
 
+// ------------------------------------------------------------ several 5-qubit clusters per pass
+// Any two 5-qubit clusters touch at most 10 qubits, so both fit in one tile of
+// 2^11 amplitudes (their qubits plus the lowest other ones): the tile is read
+// from HBM once, each cluster is applied to it in LDS, and it is written back
+// once - one pass for M clusters (the GPU form of applying several gates while
+// a block sits in fast memory, Fig. 2). Each cluster's product runs on the fp16
+// matrix cores with operand halves (as for k = 6), which keeps M = 2 within the
+// matrix-core time of one pass. The tile is kept in LDS in tile order tau; for
+// cluster m the lanes read their two columns (the tile bits that are not m's
+// targets) in MFMA order, and write the results back to the same places.
+// sg[m]: the common tile bits (tb, ioff) and cluster m's target / column
+// positions (tpos, cpos); tile bit 0 is either a column bit of m (lane (p, h)
+// owns columns 2p, 2p + 1) or m's target 0 (columns p, p + 32).
+struct MultiArgs {
+    StageGeom sg[2];
+    const half8* A[2];        // fp16-halves matrices (LAYOUT_SPLIT16F, k = 5)
+    const EpiDesc* epi[2];
+    int32_t lowt[2];
+};
+
+// LDS slot of amplitude v (tile order) in the multi-cluster kernel. With SWZ
+// the higher index bits are folded into bits 1..3 by XOR, so lanes whose
+// amplitudes differ only in high bits - a cluster's columns can sit on any
+// tile bits - use different banks. The map is linear over XOR, hence
+// slot(a | b) = slot(a) ^ slot(b) for disjoint a, b: column and target parts
+// of an address are mapped once, outside the tile loop.
+template <bool SWZ>
+__device__ __forceinline__ int lds_slot(int v) {
+    return SWZ ? v ^ ((((v >> 4) ^ (v >> 7) ^ (v >> 10)) & 7) << 1) : v;
+}
+
+template <int M, int WAVES, bool SWZ>
+__global__ __launch_bounds__(WAVES * 64, 8 / WAVES) void k_cluster_f32_multi(float2* __restrict__ psi, MultiArgs a,
+                                                                           uint64_t ntiles) {
+    constexpr int K = 5, C = 6, HX = 16, RB = 2, S = 4, NL = 16;
+    __shared__ half8 As[M][2][RB * S * 64];  // [cluster][hi, lo]
+    __shared__ float2 Ls[WAVES][1 << (K + C)];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(As[m][0]),
+                                                reinterpret_cast<const vf4*>(a.A[m]));
+        load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(As[m][1]),
+                                                reinterpret_cast<const vf4*>(a.A[m] + RB * S * 64));
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    float2* L = Ls[w];
+    g_float2* gpsi = (g_float2*)psi;
+    const StageGeom& sg0 = a.sg[0];
+    uint64_t lane_off = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if ((lane >> b) & 1) lane_off |= uint64_t(1) << sg0.tb[b + 1];
+    // Uniform state kept small (scalar registers are scarce here, and a
+    // scalar reload waits on the LDS counter too): the tile chunks' state
+    // offsets and each cluster's target offsets are linear in the index bits,
+    // so four masks each stand for the sixteen values.
+    uint64_t imask[4];  // state bit of tile bit 7 + b
+#pragma unroll
+    for (int b = 0; b < 4; ++b) imask[b] = uint64_t(1) << sg0.tb[7 + b];
+    int tmask[M][4];    // mapped LDS offset of target b (b < 4) of cluster m
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) tmask[m][b] = lds_slot<SWZ>(1 << a.sg[m].tpos[b]);
+    auto chunk_off = [&](int i) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((i >> b) & 1) o |= imask[b];
+        return o;
+    };
+    auto load_tile = [&](uint64_t b0, vf4 (&R)[NL]) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const g_vf4*>(gpsi + (b0 | chunk_off(i)));
+    };
+
+    uint64_t tile = (uint64_t)blockIdx.x * WAVES + w;
+    if (tile >= ntiles) return;
+    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+    const uint64_t last = ntiles - 1;
+    vf4 R[NL];
+    load_tile(tile_base<K + C>(tile, sg0) | lane_off, R);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
+    do {
+        // the tile to LDS (tile order: lane l holds amplitudes 2 (i 64 + l) + {0, 1}),
+        // then prefetch the next one
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int v = lds_slot<SWZ>(2 * (i * 64 + lane));  // bit 0 is 0 and not swizzled
+            L[v] = make_float2(R[i].x, R[i].y);
+            L[v | 1] = make_float2(R[i].z, R[i].w);
+        }
+        wave_lds_fence();
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        load_tile(tile_base<K + C>(nxt, sg0) | lane_off, R);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint64_t tb0 = tile_base<K + C>(tile, sg0);
+
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const StageGeom& sg = a.sg[m];
+            c_epi* epi = (c_epi*)a.epi[m];
+            const bool has_ph = epi != nullptr && epi->n_ph > 0;
+            // the lane's two columns one after the other: amplitudes j | h << 4
+#pragma unroll 1
+            for (int nb = 0; nb < 2; ++nb) {
+                const int col = a.lowt[m] ? p + 32 * nb : 2 * p + nb;
+                const int coff = lds_slot<SWZ>(tau_of_column<C>(col, sg) | (h << sg.tpos[K - 1]));
+                float X[2 * HX];
+                auto toff = [&](int j) {
+                    int o = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if ((j >> b) & 1) o ^= tmask[m][b];
+                    return o;
+                };
+#pragma unroll
+                for (int j = 0; j < HX; ++j) {
+                    const float2 v = L[coff ^ toff(j)];
+                    X[2 * j] = v.x;
+                    X[2 * j + 1] = v.y;
+                }
+                // fp16 halves, the column scaled by a power of two (shared by lanes p, p + 32)
+                uint32_t mb = 0;
+#pragma unroll
+                for (int i = 0; i < 2 * HX; ++i) mb = max(mb, __float_as_uint(X[i]) & 0x7fffffffu);
+                mb = max(mb, (uint32_t)__shfl_xor((int)mb, 32));
+                const int e = (int)(mb >> 23) - 126;
+                const int se = min(max(14 - e, -100), 100);
+                const float sc = __builtin_ldexpf(1.0f, se);
+                const float unscale = __builtin_ldexpf(1.0f, -se - 4);
+                half8 xh[S], xl[S];
+#pragma unroll
+                for (int st = 0; st < S; ++st)
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const float v = X[8 * st + i] * sc;
+                        const _Float16 hi = (_Float16)v;
+                        xh[st][i] = hi;
+                        xl[st][i] = (_Float16)(v - (float)hi);
+                    }
+                floatx16 acc[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) acc[rb][i] = 0.0f;
+                int aoff = lane;
+                asm volatile("" : "+v"(aoff));  // keep the matrix reads inside the loop (not in registers)
+#pragma unroll
+                for (int st = 0; st < S; ++st)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb) {
+                        const half8 ah = As[m][0][(rb * S + st) * 64 + aoff];
+                        const half8 al = As[m][1][(rb * S + st) * 64 + aoff];
+                        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xl[st], acc[rb], 0, 0, 0);
+                        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, xh[st], acc[rb], 0, 0, 0);
+                        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xh[st], acc[rb], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int j = 0; j < 2 * HX; ++j) X[j] = acc[j / 16][j % 16] * unscale;
+                if (epi != nullptr) {
+                    const ColFactor<float> f = col_factor<float>(epi, tb0 | state_bits_of_column<C>(col, sg));
+#pragma unroll
+                    for (int j = 0; j < HX; ++j)
+                        apply_factor(X[2 * j], X[2 * j + 1], f, (uint32_t)(j | (h << (K - 1))), has_ph);
+                }
+                // every lane reads its column before any writes it (the lanes of a
+                // column pair, p and p + 32, read disjoint amplitudes)
+#pragma unroll
+                for (int j = 0; j < HX; ++j) L[coff ^ toff(j)] = make_float2(X[2 * j], X[2 * j + 1]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            wave_lds_fence();
+        }
+        // tile order -> HBM
+        {
+            const uint64_t b0 = tb0 | lane_off;
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int v = lds_slot<SWZ>(2 * (i * 64 + lane));
+                const float2 u = L[v], x = L[v | 1];
+                *reinterpret_cast<g_vf4*>(gpsi + (b0 | chunk_off(i))) = vf4{u.x, u.y, x.x, x.y};
+            }
+        }
+        wave_lds_fence();
+        tile += stride;
+    } while (tile < ntiles);
+}
+
+// Two 5-qubit clusters per pass on a tile of 2^10 amplitudes: the 10 tile bits
+// hold both clusters' targets; each cluster's columns are the other 5 tile
+// bits, one per lane pair (lane (p, h): column p, amplitudes j | h << 4). The
+// smaller tile (8 KiB per wave) and the smaller register set let 12 waves
+// share a CU, which hides more of each wave's serial chain (LDS, split,
+// matrix cores, epilogue) under the other waves.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 1) void k_cluster_f32_pair10(float2* __restrict__ psi, MultiArgs a,
+                                                                   uint64_t ntiles) {
+    constexpr int K = 5, NT = 10, HX = 16, RB = 2, S = 4, NL = 8;
+    __shared__ half8 As[2][2][RB * S * 64];  // [cluster][hi, lo]
+    __shared__ float2 Ls[WAVES][1 << NT];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(As[m][0]),
+                                                reinterpret_cast<const vf4*>(a.A[m]));
+        load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(As[m][1]),
+                                                reinterpret_cast<const vf4*>(a.A[m] + RB * S * 64));
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    float2* L = Ls[w];
+    g_float2* gpsi = (g_float2*)psi;
+    const StageGeom& sg0 = a.sg[0];
+    uint64_t lane_off = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if ((lane >> b) & 1) lane_off |= uint64_t(1) << sg0.tb[b + 1];
+    uint64_t imask[3];  // state bit of tile bit 7 + b
+#pragma unroll
+    for (int b = 0; b < 3; ++b) imask[b] = uint64_t(1) << sg0.tb[7 + b];
+    auto chunk_off = [&](int i) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            if ((i >> b) & 1) o |= imask[b];
+        return o;
+    };
+    // per cluster: mapped target offsets (linear in j) and the lane's column
+    int tmask[2][4], coff[2];
+    uint64_t cbits[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const StageGeom& sg = a.sg[m];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) tmask[m][b] = lds_slot<true>(1 << sg.tpos[b]);
+        coff[m] = lds_slot<true>(tau_of_column<5>(p, sg) | (h << sg.tpos[K - 1]));
+        cbits[m] = state_bits_of_column<5>(p, sg);
+    }
+
+    uint64_t tile = (uint64_t)blockIdx.x * WAVES + w;
+    if (tile >= ntiles) return;
+    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+    const uint64_t last = ntiles - 1;
+    vf4 R[NL];
+    auto load_tile = [&](uint64_t b0) {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const g_vf4*>(gpsi + (b0 | chunk_off(i)));
+    };
+    load_tile(tile_base<NT>(tile, sg0) | lane_off);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
+    do {
+#pragma unroll
+        for (int i = 0; i < NL; ++i) {
+            const int v = lds_slot<true>(2 * (i * 64 + lane));
+            L[v] = make_float2(R[i].x, R[i].y);
+            L[v | 1] = make_float2(R[i].z, R[i].w);
+        }
+        wave_lds_fence();
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        load_tile(tile_base<NT>(nxt, sg0) | lane_off);
+        __builtin_amdgcn_sched_barrier(0);
+        const uint64_t tb0 = tile_base<NT>(tile, sg0);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            auto toff = [&](int j) {
+                int o = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if ((j >> b) & 1) o ^= tmask[m][b];
+                return o;
+            };
+            float X[2 * HX];
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                const float2 v = L[coff[m] ^ toff(j)];
+                X[2 * j] = v.x;
+                X[2 * j + 1] = v.y;
+            }
+            uint32_t mb = 0;
+#pragma unroll
+            for (int i = 0; i < 2 * HX; ++i) mb = max(mb, __float_as_uint(X[i]) & 0x7fffffffu);
+            mb = max(mb, (uint32_t)__shfl_xor((int)mb, 32));
+            const int e = (int)(mb >> 23) - 126;
+            const int se = min(max(14 - e, -100), 100);
+            const float sc = __builtin_ldexpf(1.0f, se);
+            half8 xh[S], xl[S];
+#pragma unroll
+            for (int st = 0; st < S; ++st)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const float v = X[8 * st + i] * sc;
+                    const _Float16 hi = (_Float16)v;
+                    xh[st][i] = hi;
+                    xl[st][i] = (_Float16)(v - (float)hi);
+                }
+            floatx16 acc[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[rb][i] = 0.0f;
+            int aoff = lane;
+            asm volatile("" : "+v"(aoff));  // keep the matrix reads inside the loop (not in registers)
+#pragma unroll
+            for (int st = 0; st < S; ++st)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const half8 ah = As[m][0][(rb * S + st) * 64 + aoff];
+                    const half8 al = As[m][1][(rb * S + st) * 64 + aoff];
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xl[st], acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, xh[st], acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xh[st], acc[rb], 0, 0, 0);
+                }
+            // undo the scaling, with the column's diagonal phase folded in
+            float ur = __builtin_ldexpf(1.0f, -se - 4), ui = 0.0f;
+            uint32_t sgn = 0, wm = 0;
+            c_epi* epi = (c_epi*)a.epi[m];
+            if (epi != nullptr) {
+                const ColFactor<float> f = col_factor<float>(epi, tb0 | cbits[m]);
+                sgn = f.sgn;
+                wm = f.w;
+                ui = ur * f.ci;
+                ur = ur * f.cr;
+            }
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                const float re = acc[j / 8][2 * (j % 8)], im = acc[j / 8][2 * (j % 8) + 1];
+                float orr = re * ur - im * ui, oi = re * ui + im * ur;
+                const bool neg = ((sgn ^ (uint32_t)__popc((uint32_t)(j | (h << (K - 1))) & wm)) & 1u) != 0;
+                orr = neg ? -orr : orr;
+                oi = neg ? -oi : oi;
+                L[coff[m] ^ toff(j)] = make_float2(orr, oi);
+            }
+            wave_lds_fence();
+        }
+        {
+            const uint64_t b0 = tb0 | lane_off;
+#pragma unroll
+            for (int i = 0; i < NL; ++i) {
+                const int v = lds_slot<true>(2 * (i * 64 + lane));
+                const float2 u = L[v], x = L[v | 1];
+                *reinterpret_cast<g_vf4*>(gpsi + (b0 | chunk_off(i))) = vf4{u.x, u.y, x.x, x.y};
+            }
+        }
+        wave_lds_fence();
+        tile += stride;
+    } while (tile < ntiles);
+}
+
 // ------------------------------------------------------------ batched persistent launch
 // Many independent circuits in one launch. Work items (an op and a run of its
 // tiles) are handed out by an atomic ticket in dependency order -
@@ -1040,7 +1398,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_f32(const BatchOp* __restrict_
         g_float2* psi = (g_float2*)op->psi;
         if (op->kind == 0) {
             const g_vf4* A = (const g_vf4*)op->A;
-            g_epi* epi = (g_epi*)op->epi;
+            c_epi* epi = (c_epi*)op->epi;
             load_matrix<2 * 32 * 64, 256>(As, A);
             __syncthreads();
             if (op->lowt)
@@ -1432,24 +1790,26 @@ __global__ __launch_bounds__(64) void k_build(const BuildOp* __restrict__ ops, c
             }
         }
     } else if (op.layout == LAYOUT_SPLIT16F) {
-        // k = 6, fp16 halves of 16 x the real-split matrix for
-        // v_mfma_f32_32x32x16_f16. Entry (rb, s, lane l, i): physical row
-        // rho = l % 32 of row block rb (result rows as in LAYOUT_MFMA32F), inner
-        // index: float 8 s + i of the lanes with l / 32 = hin, i.e. component
-        // i % 2 of amplitude (4 s + i / 2) | hin << 5. hi block, then lo block.
+        // k = 5 or 6, fp16 halves of 16 x the real-split matrix for
+        // v_mfma_f32_32x32x16_f16: RB = 2^(k-4) row blocks, S = 2^(k-3) steps
+        // of 16 inner indices. Entry (rb, s, lane l, i): physical row rho =
+        // l % 32 of row block rb (result rows as in LAYOUT_MFMA32F), inner index
+        // float 8 s + i of the lanes with l / 32 = hin, i.e. component i % 2 of
+        // amplitude (4 s + i / 2) | hin << (k - 1). hi block, then lo block.
         const int l = x, rho = l & 31, hin = l >> 5;
+        const int RB = 1 << (k - 4), S = 1 << (k - 3);
         _Float16* Ahi = reinterpret_cast<_Float16*>(out);
-        _Float16* Alo = Ahi + 4 * 8 * 64 * 8;
-        for (int rb = 0; rb < 4; ++rb) {
+        _Float16* Alo = Ahi + (size_t)RB * S * 64 * 8;
+        for (int rb = 0; rb < RB; ++rb) {
             const int jout = rb * 8 + 2 * (rho >> 3) + ((rho & 3) >> 1);
             const int hout = (rho >> 2) & 1;
-            const int y = jout | (hout << 5), a = rho & 1;
-            for (int s2 = 0; s2 < 8; ++s2)
+            const int y = jout | (hout << (k - 1)), a = rho & 1;
+            for (int s2 = 0; s2 < S; ++s2)
                 for (int i = 0; i < 8; ++i) {
-                    const int xin = (4 * s2 + (i >> 1)) | (hin << 5), b = i & 1;
+                    const int xin = (4 * s2 + (i >> 1)) | (hin << (k - 1)), b = i & 1;
                     const float v = (float)(16.0 * Ars(y, a, xin, b));
                     const _Float16 hi = (_Float16)v;
-                    const size_t at = ((size_t)(rb * 8 + s2) * 64 + l) * 8 + i;
+                    const size_t at = ((size_t)(rb * S + s2) * 64 + l) * 8 + i;
                     Ahi[at] = hi;
                     Alo[at] = (_Float16)(v - (float)hi);
                 }
@@ -1584,6 +1944,7 @@ inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap) {
 }
 constexpr unsigned kStreamGrid = 8192;  // blocks of 256 threads for grid-stride streaming kernels
 constexpr unsigned kPersistGrid = 2048; // work-groups of the persistent cluster kernels
+constexpr unsigned kPairGrid = 256;     // one 12-wave work-group per compute unit (LDS-limited)
 }  // namespace
 
 hipError_t launch_init(void* psi, int n, bool dbl, int mode, hipStream_t st) {
@@ -1594,6 +1955,75 @@ hipError_t launch_init(void* psi, int n, bool dbl, int mode, hipStream_t st) {
         hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, cnt, mode, val);
     else
         hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, cnt, mode, (float)val);
+    return hipGetLastError();
+}
+
+// Tile of 11 bits holding the targets of every cluster (their union plus the
+// lowest other bits); sg[j] gets the tile bits and cluster j's positions.
+constexpr bool kMultiSwz = true;
+
+static void make_multi_geom(int n, int m, const int32_t (*t)[5], StageGeom* sg, int nt_want = 11) {
+    uint64_t tile = 0;
+    for (int j = 0; j < m; ++j)
+        for (int q = 0; q < 5; ++q) tile |= uint64_t(1) << t[j][q];
+    for (int b = 0; b < n && __builtin_popcountll(tile) < nt_want; ++b) tile |= uint64_t(1) << b;
+    int tb[16], nt = 0;
+    for (int b = 0; b < n; ++b)
+        if (tile >> b & 1) tb[nt++] = b;
+    for (int j = 0; j < m; ++j) {
+        StageGeom& g = sg[j];
+        std::memset(&g, 0, sizeof(g));
+        g.nt = nt;
+        for (int r = 0; r < nt; ++r) g.tb[r] = tb[r];
+        int nc = 0;
+        for (int r = 0; r < nt; ++r) {
+            bool is_t = false;
+            for (int q = 0; q < 5; ++q)
+                if (tb[r] == t[j][q]) {
+                    g.tpos[q] = r;
+                    is_t = true;
+                }
+            if (!is_t) g.cpos[nc++] = r;
+        }
+        for (int i = 0; i < 16; ++i) {
+            const uint64_t tau = uint64_t(i) << 7;
+            uint64_t off = 0;
+            for (int r = 0; r < nt; ++r)
+                if (tau >> r & 1) off |= uint64_t(1) << tb[r];
+            g.ioff[i] = off;
+        }
+    }
+}
+
+hipError_t launch_multi(void* psi, int n, int m, const int32_t (*targets)[5], const void* const* mats,
+                        const EpiDesc* const* epis, hipStream_t st) {
+    if (m < 1 || m > 2 || n < 11) return hipErrorInvalidValue;
+    MultiArgs a;
+    std::memset(&a, 0, sizeof(a));
+    make_multi_geom(n, m, targets, a.sg);
+    if (a.sg[0].nt != 11) return hipErrorInvalidValue;
+    for (int j = 0; j < m; ++j) {
+        a.A[j] = reinterpret_cast<const half8*>(mats[j]);
+        a.epi[j] = epis[j];
+        a.lowt[j] = a.sg[j].tpos[0] == 0;
+    }
+    const uint64_t ntiles = uint64_t(1) << (n - 11);
+    MultiArgs a10 = a;
+    if (m == 2 && g_pair_tile == 10) make_multi_geom(n, m, targets, a10.sg, 10);
+    // the 10-bit tile needs state bit 0 (16-byte accesses of amplitude pairs)
+    if (m == 2 && g_pair_tile == 10 && a10.sg[0].nt == 10 && a10.sg[0].tb[0] == 0) {
+        const uint64_t nt10 = uint64_t(1) << (n - 10);
+        const unsigned grid = grid_for(nt10, 12, kPairGrid);
+        hipLaunchKernelGGL((k_cluster_f32_pair10<12>), dim3(grid), dim3(768), 0, st, (float2*)psi, a10, nt10);
+    } else if (m == 2) {
+        const unsigned grid = grid_for(ntiles, 8, kPersistGrid / 2);
+        hipLaunchKernelGGL((k_cluster_f32_multi<2, 8, kMultiSwz>), dim3(grid), dim3(512), 0, st, (float2*)psi, a,
+                           ntiles);
+    } else {
+        const unsigned grid = grid_for(ntiles, 4, kPersistGrid);
+        hipLaunchKernelGGL((k_cluster_f32_multi<1, 4, kMultiSwz>), dim3(grid), dim3(256), 0, st, (float2*)psi, a,
+                           ntiles);
+    }
     return hipGetLastError();
 }
 

@@ -217,6 +217,8 @@ OPT_BATCH_PAD = 3
 OPT_BATCH_ITEM_TILES = 4
 OPT_K6_KERNEL = 5
 OPT_FOLD_INIT = 6
+OPT_PAIR = 7
+OPT_PAIR_TILE = 8
 
 
 def set_option(option: int, value: int):
@@ -464,7 +466,8 @@ class State:
         kind, k, epi = (ctypes.c_int32 * m)(), (ctypes.c_int32 * m)(), (ctypes.c_int32 * m)()
         qs, ms = (ctypes.c_int32 * (6 * m))(), (ctypes.c_float * m)()
         _check(L.qsim_op_timings(self.h, kind, k, qs, epi, ms, m, ctypes.byref(n)))
-        kinds = {0: "cluster", 1: "diag", 2: "gate1q", 3: "phase1q", 4: "cz", 5: "build", 6: "init_cluster"}
+        kinds = {0: "cluster", 1: "diag", 2: "gate1q", 3: "phase1q", 4: "cz", 5: "build", 6: "init_cluster",
+                 7: "pair"}
         return [dict(kind=kinds[kind[i]], k=k[i], qubits=[q for q in qs[6 * i:6 * i + 6] if q >= 0],
                      epi=bool(epi[i] & 1), staged=bool(epi[i] & 2), mfma=bool(epi[i] & 4), ms=float(ms[i]))
                 for i in range(m)]

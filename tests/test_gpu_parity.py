@@ -22,7 +22,7 @@ import torch
 import oracle
 from paper_1704_01127_amd import qsim
 from supremacy_inputs import (Circuit, Gate, blocked_circuit, drop_trailing_cz_layer, haar_unitary,
-                              mirror_circuit, random_state, supremacy_circuit)
+                              mirror_circuit, random_state, supremacy_circuit, with_haar_layers)
 
 pytestmark = pytest.mark.gpu
 
@@ -200,6 +200,62 @@ def test_fold_init_matches_oracle(dt, kmax):
                 assert np.max(np.abs(got - ref)) <= 1e-5
     finally:
         qsim.set_option(qsim.OPT_FOLD_INIT, old)
+
+
+# ------------------------------------------------------------------ two clusters per pass (complex64)
+@pytest.fixture(params=[(1, 10), (1, 11), (0, 10)], ids=["paired10", "paired11", "single"])
+def pairing(request):
+    """Pairing on (a tile of 10 or 11 qubits held in LDS) or off."""
+    old = qsim.get_option(qsim.OPT_PAIR), qsim.get_option(qsim.OPT_PAIR_TILE)
+    qsim.set_option(qsim.OPT_PAIR, request.param[0])
+    qsim.set_option(qsim.OPT_PAIR_TILE, request.param[1])
+    yield request.param[0]
+    qsim.set_option(qsim.OPT_PAIR, old[0])
+    qsim.set_option(qsim.OPT_PAIR_TILE, old[1])
+
+
+PAIR_SETS = [
+    ([0, 1, 2, 3, 4], [5, 6, 7, 8, 9]),        # disjoint, low
+    ([0, 3, 7, 9, 12], [1, 3, 8, 12, 13]),     # overlapping, target 0 in the first
+    ([9, 10, 11, 12, 13], [2, 4, 10, 12, 13]),  # high, then mixed
+    ([1, 2, 6], [0, 5, 7, 8]),                  # padded (3 and 4 qubits), target 0 in the second
+    ([4, 5, 6, 7, 8], [4, 5, 6, 7, 8]),        # the same qubits twice
+    ([1, 2, 3, 4, 5], [6, 7, 8, 9, 10]),       # ten targets above bit 0 (the 11-qubit tile)
+]
+
+
+@pytest.mark.parametrize("n", [11, 14, 21])
+@pytest.mark.parametrize("case", range(len(PAIR_SETS)))
+def test_pair_of_dense_clusters(pairing, n, case):
+    """Two dense clusters in a row: one pass (pairing) or two; the bound is
+    twice the one-cluster bound (two products, each ~2^-22 relative)."""
+    qa, qb = PAIR_SETS[case]
+    qa = [q for q in qa if q < n]
+    qb = [q for q in qb if q < n]
+    ua, ub = haar_unitary(len(qa), 7 * n + case), haar_unitary(len(qb), 11 * n + case)
+    psi = random_state(n, 13 * n + case)
+    ref = oracle.apply_dense(oracle.apply_dense(psi.copy(), qa, ua), qb, ub)
+    gates = [("U", tuple(qa), ua), ("U", tuple(qb), ub)]
+    two_ops = len(qsim.schedule(n, gates, kmax=5)["op_kind"]) == 2  # else one cluster holds both
+    s = make_state(n, "c64", psi)
+    s.run_circuit(gates, kmax=5, record_timings=True)
+    kinds = [r["kind"] for r in s.op_timings()]
+    assert ("pair" in kinds) == (bool(pairing) and two_ops), kinds
+    got = s.to_numpy()
+    assert np.max(np.abs(got - ref)) <= 2 * kernel_tol("c64", 5, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("kmax", [3, 4, 5])
+@pytest.mark.parametrize("fuse", [False, True])
+def test_pair_circuits_match_oracle(pairing, kmax, fuse):
+    """Whole circuits with clusters paired (diagonal epilogues on both)."""
+    circ = with_haar_layers(supremacy_circuit(4, 4, 22, seed=60 + kmax), 7, 3, 5)
+    ref = oracle.run(circ)
+    s = make_state(circ.n, "c64")
+    s.run_circuit(circ.gates, kmax=kmax, fuse_diag=fuse, skip_initial_h=True)
+    got = s.to_numpy()
+    assert fidelity(got, ref) >= 1 - 1e-6
+    assert np.max(np.abs(got - ref)) <= 1e-5
 
 
 # ------------------------------------------------------------------ diagonal layer
