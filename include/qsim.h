@@ -105,8 +105,10 @@ typedef struct {
                                    their qubits: they change phases, not probabilities (Sec. 3.6) */
     int32_t fuse_diag;          /* let a cluster carry diagonal gates outside its qubits and apply
                                    them while storing (no extra pass over the state) */
-    int32_t skip_initial_h;     /* caller promises the state is |0...0>: the leading H on every
-                                   qubit is replaced by the uniform initialisation (Sec. 3.6) */
+    int32_t skip_initial_h;     /* the run starts from |0...0>. If every qubit's first gate is an
+                                   H, that layer is replaced by writing the uniform state over
+                                   the whole vector (its contents are not read; Sec. 3.6);
+                                   otherwise the caller promises the state holds |0...0> */
     int32_t record_timings;     /* time every launched op with HIP events (slows the run) */
     int32_t reserved[2];        /* reserved[0]: qsim_dtype the cost models assume in
                                    qsim_schedule (qsim_run_circuit uses the state's); 0 = C64 */

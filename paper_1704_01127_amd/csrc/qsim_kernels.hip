@@ -1655,6 +1655,50 @@ __global__ __launch_bounds__(256) void k_init_cluster(typename Cplx<T>::type* __
     const bool has_epi = epi != nullptr;
     const bool has_ph = has_epi && epi->n_ph > 0;
     const uint64_t stride = (uint64_t)gridDim.x * 256;
+    if constexpr (sizeof(T) == 4) {
+        // float: 16-byte stores. With qubit 0 a target, amplitudes y, y + 1 of a
+        // column are neighbours; otherwise columns 2c, 2c + 1 differ in bit 0 only
+        // and a thread writes both, side by side.
+        if (g.t[0] == 0) {
+            for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < g.ncols; c += stride) {
+                const uint64_t base = deposit_cols<K>(c, g);
+                ColFactor<T> f{0u, 0u, T(1), T(0)};
+                if (has_epi) f = col_factor<T>(epi, base);
+#pragma unroll 8
+                for (int y = 0; y < D; y += 2) {
+                    const double2 v0 = w[y], v1 = w[y + 1];
+                    T r0 = (T)v0.x, i0 = (T)v0.y, r1 = (T)v1.x, i1 = (T)v1.y;
+                    if (has_epi) {
+                        apply_factor(r0, i0, f, (uint32_t)y, has_ph);
+                        apply_factor(r1, i1, f, (uint32_t)(y + 1), has_ph);
+                    }
+                    *reinterpret_cast<vf4*>(psi + (base | toff[y])) = vf4{r0, i0, r1, i1};
+                }
+            }
+            return;
+        }
+        if (g.ncols >= 2) {
+            for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < g.ncols / 2; c += stride) {
+                const uint64_t base = deposit_cols<K>(2 * c, g);  // bit 0 clear; column 2c + 1 is base | 1
+                ColFactor<T> f0{0u, 0u, T(1), T(0)}, f1 = f0;
+                if (has_epi) {
+                    f0 = col_factor<T>(epi, base);
+                    f1 = col_factor<T>(epi, base | 1);
+                }
+#pragma unroll 8
+                for (int y = 0; y < D; ++y) {
+                    const double2 v = w[y];
+                    T r0 = (T)v.x, i0 = (T)v.y, r1 = r0, i1 = i0;
+                    if (has_epi) {
+                        apply_factor(r0, i0, f0, (uint32_t)y, has_ph);
+                        apply_factor(r1, i1, f1, (uint32_t)y, has_ph);
+                    }
+                    *reinterpret_cast<vf4*>(psi + (base | toff[y])) = vf4{r0, i0, r1, i1};
+                }
+            }
+            return;
+        }
+    }
     // one thread per column (assignment of the non-target bits): its diagonal
     // factor once, then the column's 2^k amplitudes
     for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < g.ncols; c += stride) {
@@ -1875,7 +1919,19 @@ __global__ __launch_bounds__(256) void k_stats(const typename Cplx<T>::type* __r
         const double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
         v[0] += pr;
         v[1] += pr * pr;
-        if (pr > 0.0) v[2] -= pr * log(pr);
+        if (pr > 0.0) {
+            if constexpr (sizeof(T) == 4) {
+                // float amplitudes: ln p = e ln 2 + ln m with p = m 2^e split exactly
+                // and ln m (m in [1/2, 1)) in float, within ~1.4e-7 absolute - far
+                // below what a float state resolves; a double log costs as much ALU
+                // time as reading the state
+                int e;
+                const double m = frexp(pr, &e);
+                v[2] -= pr * ((double)e * 0.6931471805599453 + (double)logf((float)m));
+            } else {
+                v[2] -= pr * log(pr);
+            }
+        }
         if (probs) probs[i] = (P)pr;
     };
     uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;

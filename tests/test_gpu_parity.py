@@ -202,6 +202,48 @@ def test_fold_init_matches_oracle(dt, kmax):
         qsim.set_option(qsim.OPT_FOLD_INIT, old)
 
 
+FOLD_CASES = [
+    (6, (0, 1, 2, 3, 4, 5)),     # one column
+    (7, (1, 2, 3, 4, 5, 6)),     # one column pair (float: columns side by side)
+    (7, (0, 2, 3, 4, 5, 6)),     # qubit 0 a target (float: amplitude pairs)
+    (12, (2, 5, 7, 9, 10, 11)),
+    (12, (0, 5, 7, 9, 10, 11)),
+    (13, (3, 8)),
+    (13, (0, 12)),
+    (11, (4,)),
+]
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("case", range(len(FOLD_CASES)))
+def test_fold_init_first_cluster(dt, case):
+    """A first cluster on chosen qubits (with and without qubit 0, down to one
+    column) written together with the uniform start, with diagonal gates outside
+    it applied while storing."""
+    n, qs = FOLD_CASES[case]
+    rest = [q for q in range(n) if q not in qs]
+    gates = [Gate("H", (q,)) for q in range(n)]
+    gates.append(Gate("U", qs, haar_unitary(len(qs), 100 + case)))
+    if len(rest) >= 2:
+        gates += [Gate("CZ", (rest[0], rest[-1])), Gate("T", (rest[1],)), Gate("CZ", (qs[0], rest[0]))]
+    gates += [Gate("SX", (q,)) for q in range(n)]
+    circ = Circuit(n, gates)
+    ref = oracle.run(circ)
+    kmax = len(qs)
+    sc = qsim.schedule(n, gates, kmax=kmax, fuse_diag=True, skip_initial_h=True)
+    assert sc["op_kind"][0] == 0 and sorted(sc["op_qubits"][0][:sc["op_k"][0]]) == sorted(qs), sc
+    s = make_state(n, dt)
+    s.run_circuit(gates, kmax=kmax, fuse_diag=True, skip_initial_h=True, record_timings=True)
+    kinds = [r["kind"] for r in s.op_timings() if r["kind"] != "build"]
+    assert kinds[0] == "init_cluster", kinds
+    got = s.to_numpy()
+    if dt == "c128":
+        assert np.max(np.abs(got - ref)) <= 1e-12
+    else:
+        assert fidelity(got, ref) >= 1 - 1e-6
+        assert np.max(np.abs(got - ref)) <= 1e-5
+
+
 # ------------------------------------------------------------------ two clusters per pass (complex64)
 @pytest.fixture(params=[(1, 10), (1, 11), (0, 10)], ids=["paired10", "paired11", "single"])
 def pairing(request):
@@ -414,6 +456,13 @@ def test_probs_and_compare(dt):
     norm, s2, ent = s.probs(out)
     tol = 1e-12 if dt == "c128" else 1e-5
     assert abs(norm - norm_o) <= tol and abs(ent - ent_o) <= tol * 20 and abs(s2 - s2_o) <= tol * s2_o
+    # the reduction alone: against the exact statistics of the state's own amplitudes
+    # (float states take ln of the mantissa in float: <= ~1.4e-7 absolute per unit of
+    # probability)
+    pg = np.abs(s.to_numpy().astype(np.complex128)) ** 2
+    ent_g = float(-np.sum(pg[pg > 0] * np.log(pg[pg > 0])))
+    assert abs(ent - ent_g) <= (1e-12 if dt == "c128" else 3e-7)
+    assert abs(norm - float(np.sum(pg))) <= (1e-12 if dt == "c128" else 1e-9)
     p = out.cpu().numpy()
     assert np.max(np.abs(p - np.abs(ref) ** 2)) <= (1e-15 if dt == "c128" else 1e-6 * np.max(np.abs(ref) ** 2))
     refd = torch.from_numpy(ref).cuda()
