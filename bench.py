@@ -45,7 +45,8 @@ def kernel_name(rec, k6_kernel=2, pair_tile=11) -> str:
     if not rec.get("mfma"):
         return "k_cluster_valu<float, %d>" % k
     if k == 6 and k6_kernel in (1, 2):
-        return "k_cluster_f32_%s<%s>" % ("split6" if k6_kernel == 2 else "gauss6", "true" if lowt else "false")
+        name = "split6s" if k6_kernel == 2 and rec.get("staged") else ("split6" if k6_kernel == 2 else "gauss6")
+        return "k_cluster_f32_%s<%s>" % (name, "true" if lowt else "false")
     if rec.get("staged"):
         return "k_cluster_f32_stage<%d, 6, %s>" % (k, "true" if lowt else "false")
     return "k_cluster_f32_mfma<%d, %d, %s>" % (k, 1 if k == 6 else 2, "true" if lowt else "false")

@@ -204,9 +204,10 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
                             int32_t* op_epi, float* ms, int cap, int* n_ops);
 
 /* Process-wide tuning (the autotuner's controls).
- * The matrix-core cluster kernels exist in two variants: 0 gathers each
- * lane's amplitudes straight from HBM into registers, 1 moves the wave's tile
- * as linear runs and re-orders it through LDS. The variant is looked up per
+ * The matrix-core cluster kernels (k <= 5; k = 6 on complex64 states) exist
+ * in two variants: 0 gathers each lane's amplitudes straight from HBM into
+ * registers, 1 moves the wave's tile as linear runs and re-orders it through
+ * LDS. The variant is looked up per
  * (dtype, k, low_class = number of targets among qubits 0..5, capped at 3) in
  * a tune table, which qsim_set_tune_entry overwrites (the autotuner fills it
  * from measurements). QSIM_OPT_CLUSTER_VARIANT = 0 or 1 forces one variant

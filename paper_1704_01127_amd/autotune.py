@@ -53,8 +53,8 @@ def tune_variants(n, dt, reps, seed, log):
     rng = np.random.default_rng(seed)
     state = qsim.State(n, dt, init="uniform", kmax=6)
     table = {}
-    kmin = 4 if dt == "c64" else 3
-    for k in range(kmin, 6):
+    kmin, kmax = (4, 6) if dt == "c64" else (3, 5)  # complex64 k = 6: the fp16-halves kernel's variants
+    for k in range(kmin, kmax + 1):
         mat = haar(k, k)
         row = []
         for cls in range(4):

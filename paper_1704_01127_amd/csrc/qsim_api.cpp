@@ -53,9 +53,10 @@ namespace qsim {
 namespace {
 int g_cluster_variant = -1;
 // [dtype][k][low_class]: a direct gather when no target is on the low bits,
-// the LDS-staged variant otherwise
+// the LDS-staged variant otherwise (k = 6, complex64: from two low targets on;
+// with one the direct kernel's loads still use whole cache lines)
 int g_tune[2][kMaxK + 1][kLowClasses] = {
-    {{0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}},
+    {{0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 0, 1, 1}},
     {{0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}}};
 }  // namespace
 void set_cluster_variant(int v) { g_cluster_variant = v; }
@@ -76,7 +77,8 @@ int g_pair_tile = 11;
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
-    if (layout == LAYOUT_PLAIN || g.k > 5) return 0;
+    if (layout == LAYOUT_PLAIN) return 0;
+    if (g.k > 5 && (dbl || layout != LAYOUT_SPLIT16F)) return 0;  // k = 6: float, fp16-halves kernel only
     if (g_cluster_variant >= 0) return g_cluster_variant;
     return g_tune[dbl][g.k][low_class(g.t, g.k)];
 }

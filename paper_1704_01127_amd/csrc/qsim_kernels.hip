@@ -1336,6 +1336,199 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_cluster_f32_pair10(float2* __
     } while (tile < ntiles);
 }
 
+// ------------------------------------------------------------ cluster: float state, k = 6, LDS-staged
+// The direct kernel above reads lane p's column with one load per amplitude;
+// when several targets sit on the lowest state bits the 32 columns of a load
+// are spread over up to 64 cache lines (8 - 16 bytes used of each), and the
+// vector L1 becomes the bottleneck. This variant reads a tile of 2^11
+// amplitudes (the 6 targets and the 5 lowest other bits) with linear 16-byte
+// loads - 1 KiB runs - and re-orders it through LDS. Per wave the LDS holds
+// half a tile (8 KiB): tile bit 10 is either target 5 (h) or column bit 4,
+// so each lane's whole column lies in one half and the halves are staged one
+// after the other. Eight waves and the matrix halves (64 KiB) fill 128 KiB.
+// Core (fp16 halves on matrix cores, column scaling, epilogue) as above.
+// Addresses: slot(tau) = lds_slot<true>(tau) & 1023, linear over XOR, so the
+// lane's column part and the row part are mapped separately.
+template <bool LOWT>
+__global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restrict__ psi,
+                                                                const half8* __restrict__ Ap,
+                                                                const EpiDesc* __restrict__ epi_p, StageGeom sg,
+                                                                uint64_t ntiles) {
+    constexpr int K = 6, C = 5, NT = K + C, HX = 32, RB = 4, S = 8, NL = 16, WAVES = 8;
+    __shared__ half8 Ah[RB * S * 64];
+    __shared__ half8 Al[RB * S * 64];
+    __shared__ float2 Ls[WAVES][1024];
+    load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Ah), reinterpret_cast<const vf4*>(Ap));
+    load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Al),
+                                            reinterpret_cast<const vf4*>(Ap + RB * S * 64));
+    __syncthreads();
+
+    // the wave index is uniform in the wave: tile numbers and bases are scalar
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, p = lane & 31,
+              h = lane >> 5;
+    float2* L = Ls[w];
+    vf4* L4 = reinterpret_cast<vf4*>(L);
+    g_float2* gpsi = (g_float2*)psi;
+    c_epi* epi = (c_epi*)epi_p;
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+    uint64_t lane_off = 0;  // state offset of tile bits 1..6 (the lane of a linear load)
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if ((lane >> b) & 1) lane_off |= uint64_t(1) << sg.tb[b + 1];
+    // the lane's column (tile order, then LDS slot), its half of the targets
+    const int ctau = tau_of_column<C>(p, sg) | (h << sg.tpos[K - 1]);
+    int lslot = lds_slot<true>(ctau);
+    uint32_t h5 = (uint32_t)h << (K - 1);
+    const uint64_t cbits = state_bits_of_column<C>(p, sg);
+    const int lph = (ctau >> 10) & 1;  // the half of the tile holding the column
+    int lin = lds_slot<true>(2 * lane);  // slot of linear chunk 0; chunk i adds slot(128 i) by XOR
+    // row j's slot and linear chunk i's state offset, rebuilt from 5 and 4
+    // uniform masks at each use (cheap scalar work) rather than 32 + 16 values
+    // held across the loop
+    int rmask[K - 1];
+#pragma unroll
+    for (int m = 0; m < K - 1; ++m) rmask[m] = lds_slot<true>(1 << sg.tpos[m]);
+    uint64_t imask[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) imask[b] = uint64_t(1) << sg.tb[7 + b];
+    auto rslot = [&](int j) {
+        int o = 0;
+#pragma unroll
+        for (int m = 0; m < K - 1; ++m)
+            if ((j >> m) & 1) o ^= rmask[m];
+        return o;
+    };
+    auto ioff = [&](int i) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((i >> b) & 1) o |= imask[b];
+        return o;
+    };
+
+    uint64_t tile = (uint64_t)blockIdx.x * WAVES + w;
+    if (tile >= ntiles) return;
+    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
+    const uint64_t last = ntiles - 1;
+    vf4 R[NL];
+    auto load_tile = [&](uint64_t t0) {  // t0: the tile's base (uniform)
+#pragma unroll
+        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const g_vf4*>(gpsi + ((t0 | ioff(i)) | lane_off));
+    };
+    load_tile(tile_base<NT>(tile, sg));
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_sched_barrier(0);
+    do {
+        // per-lane bases stay in place: the 16 chunk addresses derived from them
+        // are recomputed (one OR / XOR each) instead of held across the loop
+        asm volatile("" : "+v"(lane_off), "+v"(lin), "+v"(lslot), "+v"(h5));
+        asm volatile("" : "+s"(rmask[0]), "+s"(rmask[1]), "+s"(rmask[2]), "+s"(rmask[3]), "+s"(rmask[4]));
+        asm volatile("" : "+s"(imask[0]), "+s"(imask[1]), "+s"(imask[2]), "+s"(imask[3]));
+        // tile -> LDS, half by half; each lane reads its column in its half
+        float X[2 * HX];
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+#pragma unroll
+            for (int ii = 0; ii < NL / 2; ++ii) {
+                const int i = ph * (NL / 2) + ii;
+                L4[((lin ^ lds_slot<true>(128 * i)) & 1023) >> 1] = R[i];
+            }
+            wave_lds_fence();
+            if (lph == ph) {
+                if (LOWT) {
+#pragma unroll
+                    for (int j = 0; j < HX; j += 2) {
+                        const vf4 v = L4[((lslot ^ rslot(j)) & 1023) >> 1];
+                        X[2 * j] = v.x; X[2 * j + 1] = v.y; X[2 * j + 2] = v.z; X[2 * j + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < HX; ++j) {
+                        const float2 v = L[(lslot ^ rslot(j)) & 1023];
+                        X[2 * j] = v.x; X[2 * j + 1] = v.y;
+                    }
+                }
+            }
+            wave_lds_fence();
+        }
+        // fp16 halves of the scaled column (shared scale with lane p + 32)
+        uint32_t mb = 0;
+#pragma unroll
+        for (int i = 0; i < 2 * HX; ++i) mb = max(mb, __float_as_uint(X[i]) & 0x7fffffffu);
+        mb = max(mb, (uint32_t)__shfl_xor((int)mb, 32));
+        const int e = (int)(mb >> 23) - 126;
+        const int se = min(max(14 - e, -100), 100);
+        const float sc = __builtin_ldexpf(1.0f, se);
+        half8 xh[S], xl[S];
+#pragma unroll
+        for (int st = 0; st < S; ++st)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float v = X[8 * st + i] * sc;
+                const _Float16 hi = (_Float16)v;
+                xh[st][i] = hi;
+                xl[st][i] = (_Float16)(v - (float)hi);
+            }
+        // the column is in registers: prefetch the next tile
+        const uint64_t tb0 = tile_base<NT>(tile, sg);
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        __builtin_amdgcn_sched_barrier(0);
+        load_tile(tile_base<NT>(nxt, sg));
+        __builtin_amdgcn_sched_barrier(0);
+        floatx16 acc[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[rb][i] = 0.0f;
+        int aoff = lane;
+        asm volatile("" : "+v"(aoff));  // keep the matrix reads inside the loop (not in registers)
+#pragma unroll
+        for (int st = 0; st < S; ++st)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const half8 ah = Ah[(rb * S + st) * 64 + aoff];
+                const half8 al = Al[(rb * S + st) * 64 + aoff];
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xl[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, xh[st], acc[rb], 0, 0, 0);
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xh[st], acc[rb], 0, 0, 0);
+            }
+        const float unscale = __builtin_ldexpf(1.0f, -se - 4);
+#pragma unroll
+        for (int j = 0; j < 2 * HX; ++j) X[j] = acc[j / 16][j % 16] * unscale;
+        if (has_epi) {
+            const ColFactor<float> f = col_factor<float>(epi, tb0 | cbits);
+#pragma unroll
+            for (int j = 0; j < HX; ++j)
+                apply_factor(X[2 * j], X[2 * j + 1], f, (uint32_t)j | h5, has_ph);
+        }
+        // results -> LDS -> HBM, half by half
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+            if (lph == ph) {
+                if (LOWT) {
+#pragma unroll
+                    for (int j = 0; j < HX; j += 2)
+                        L4[((lslot ^ rslot(j)) & 1023) >> 1] = vf4{X[2 * j], X[2 * j + 1], X[2 * j + 2], X[2 * j + 3]};
+                } else {
+#pragma unroll
+                    for (int j = 0; j < HX; ++j) L[(lslot ^ rslot(j)) & 1023] = make_float2(X[2 * j], X[2 * j + 1]);
+                }
+            }
+            wave_lds_fence();
+#pragma unroll
+            for (int ii = 0; ii < NL / 2; ++ii) {
+                const int i = ph * (NL / 2) + ii;
+                *reinterpret_cast<g_vf4*>(gpsi + ((tb0 | ioff(i)) | lane_off)) =
+                    L4[((lin ^ lds_slot<true>(128 * i)) & 1023) >> 1];
+            }
+            wave_lds_fence();
+        }
+        tile += stride;
+    } while (tile < ntiles);
+}
+
 // ------------------------------------------------------------ batched persistent launch
 // Many independent circuits in one launch. Work items (an op and a run of its
 // tiles) are handed out by an atomic ticket in dependency order -
@@ -2001,6 +2194,7 @@ inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap) {
 constexpr unsigned kStreamGrid = 8192;  // blocks of 256 threads for grid-stride streaming kernels
 constexpr unsigned kPersistGrid = 2048; // work-groups of the persistent cluster kernels
 constexpr unsigned kPairGrid = 256;     // one 12-wave work-group per compute unit (LDS-limited)
+constexpr unsigned kStagedGrid = 256;   // one 8-wave work-group per compute unit (LDS-limited)
 }  // namespace
 
 hipError_t launch_init(void* psi, int n, bool dbl, int mode, hipStream_t st) {
@@ -2234,6 +2428,18 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
             case 6: return launch_valu_k<6>(psi, dbl, g, mat, epi, st);
             default: return hipErrorInvalidValue;
         }
+    }
+    if (layout == LAYOUT_SPLIT16F && !dbl && g.k == 6 && variant == 1) {
+        const StageGeom sg = make_stage_geom(g, 5, 7);  // 11 tile bits; chunks of 2^7 amplitudes
+        const uint64_t tiles = g.ncols >> 5;
+        const unsigned grid = grid_for(tiles, 8, kStagedGrid);
+        if (g.t[0] == 0)
+            hipLaunchKernelGGL(k_cluster_f32_split6s<true>, dim3(grid), dim3(512), 0, st, (float2*)psi,
+                               (const half8*)mat, epi, sg, tiles);
+        else
+            hipLaunchKernelGGL(k_cluster_f32_split6s<false>, dim3(grid), dim3(512), 0, st, (float2*)psi,
+                               (const half8*)mat, epi, sg, tiles);
+        return hipGetLastError();
     }
     if (layout == LAYOUT_SPLIT16F && !dbl && g.k == 6) {
         const uint64_t tiles = g.ncols / 32;

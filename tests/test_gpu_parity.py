@@ -142,8 +142,56 @@ def test_k6_kernels(k6_kernel, n, pat):
     assert np.max(np.abs(got - ref)) <= kernel_tol("c64", 6, np.max(np.abs(ref)))
 
 
+# (n, targets): the tile's top bit (bit 10 of 11) is target 5 or the highest
+# column bit, with qubit 0 a target or not; the last ones are the target sets
+# that are slow for the direct gather
+K6_STAGED_SETS = [
+    (11, [0, 1, 2, 3, 4, 5]), (11, [5, 6, 7, 8, 9, 10]), (11, [0, 2, 4, 6, 8, 10]),
+    (14, [1, 2, 3, 4, 7, 13]), (14, [1, 2, 3, 4, 7, 9]), (16, [0, 1, 2, 3, 12, 15]),
+    (16, [0, 1, 2, 3, 4, 6]), (21, [2, 3, 4, 10, 15, 20]), (23, [0, 1, 2, 3, 21, 22]),
+    (23, [1, 2, 3, 4, 7, 14]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(K6_STAGED_SETS)))
+def test_k6_staged(case):
+    """The LDS-staged fp16-halves kernel against the oracle at the one-cluster
+    bound (forced variant 1), and against the direct kernel on the same input."""
+    n, qs = K6_STAGED_SETS[case]
+    u = haar_unitary(6, 500 + case)
+    psi = random_state(n, 600 + case)
+    ref = oracle.apply_dense(psi.copy(), qs, u)
+    old = qsim.get_option(qsim.OPT_CLUSTER_VARIANT), qsim.get_option(qsim.OPT_K6_KERNEL)
+    try:
+        qsim.set_option(qsim.OPT_K6_KERNEL, 2)
+        outs = {}
+        for v in (1, 0):
+            qsim.set_option(qsim.OPT_CLUSTER_VARIANT, v)
+            s = make_state(n, "c64", psi)
+            s.run_circuit([Gate("U", tuple(qs), u)], kmax=6, record_timings=True)
+            recs = [r for r in s.op_timings() if r["kind"] == "cluster"]
+            assert len(recs) == 1 and recs[0]["k"] == 6 and recs[0]["staged"] == (v == 1), recs
+            outs[v] = s.to_numpy()
+            del s
+    finally:
+        qsim.set_option(qsim.OPT_CLUSTER_VARIANT, old[0])
+        qsim.set_option(qsim.OPT_K6_KERNEL, old[1])
+    tol = kernel_tol("c64", 6, np.max(np.abs(ref)))
+    assert np.max(np.abs(outs[1] - ref)) <= tol
+    # same arithmetic in the same order per column: the two variants agree exactly
+    assert np.array_equal(outs[1], outs[0])
+
+
+@pytest.fixture(params=[0, 1], ids=["direct", "staged"])
+def k6_variant(request):
+    old = qsim.get_option(qsim.OPT_CLUSTER_VARIANT)
+    qsim.set_option(qsim.OPT_CLUSTER_VARIANT, request.param)
+    yield request.param
+    qsim.set_option(qsim.OPT_CLUSTER_VARIANT, old)
+
+
 @pytest.mark.parametrize("scale", [1e6, 1e-30, 0.0])
-def test_k6_kernels_any_magnitude(k6_kernel, scale):
+def test_k6_kernels_any_magnitude(k6_kernel, k6_variant, scale):
     """States far from unit norm, and columns that are zero: the per-column
     power-of-two scaling of the fp16 product keeps the relative error."""
     n = 14
@@ -162,7 +210,7 @@ def test_k6_kernels_any_magnitude(k6_kernel, scale):
         assert np.max(np.abs(got[part] - ref[part])) <= max(bound, 0.0), (scale, part)
 
 
-def test_k6_kernels_circuit(k6_kernel):
+def test_k6_kernels_circuit(k6_kernel, k6_variant):
     """Whole circuits with 6-qubit clusters and diagonal epilogues."""
     circ = supremacy_circuit(4, 5, 24, seed=11)
     ref = oracle.run(circ)
