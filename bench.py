@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--cols", type=int, default=6)
     ap.add_argument("--depth", type=int, default=25)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--drop-corner", action="store_true",
+                    help="leave out the grid's last site (34 qubits: 5x7 minus site (4, 6))")
     ap.add_argument("--kmax", type=int, default=6)
     ap.add_argument("--scheduler", default="learned")
     ap.add_argument("--no-fuse-diag", action="store_true")
@@ -168,7 +170,8 @@ def main():
         qsim.set_option(qsim.OPT_PAIR, args.pair)
     if args.pair_tile is not None:
         qsim.set_option(qsim.OPT_PAIR_TILE, args.pair_tile)
-    circ = supremacy_circuit(args.rows, args.cols, args.depth, args.seed)
+    drop = ((args.rows - 1, args.cols - 1),) if args.drop_corner else ()
+    circ = supremacy_circuit(args.rows, args.cols, args.depth, args.seed, drop=drop)
     n = circ.n
     gates = circ.gates
     fused_opts = dict(kmax=args.kmax, scheduler=args.scheduler, fuse_diag=not args.no_fuse_diag,
@@ -230,8 +233,9 @@ def main():
     out["unit"] = "s"
     out["ms_per_step"] = round(tts * 1e3, 3)
     out["dtype"] = "f32" if fused is not None else "f64"
-    out["config"] = {"workload": "%d-qubit %dx%d-grid depth-%d random supremacy circuit (%d gates, seed %d)"
-                                 % (n, args.rows, args.cols, args.depth, len(gates), args.seed),
+    out["config"] = {"workload": "%d-qubit %dx%d-grid%s depth-%d random supremacy circuit (%d gates, seed %d)"
+                                 % (n, args.rows, args.cols, " minus corner site" if args.drop_corner else "",
+                                    args.depth, len(gates), args.seed),
                      "form": "float32 state, fused clusters k<=%d, scheduler %s, diagonal fusion %s"
                              % (args.kmax, args.scheduler, "on" if not args.no_fuse_diag else "off")
                              if fused is not None else "float64 state, one launch per gate",
@@ -266,7 +270,7 @@ def main():
         ach = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         traffic = None
         tpath = os.path.join(ROOT, "profiles", "traffic_cluster_f32_30q.json")
-        if os.path.exists(tpath):
+        if n == 30 and os.path.exists(tpath):  # the counters were taken on the 30-qubit workload
             with open(tpath) as f:
                 t = json.load(f)
             if t.get("kernel_source_sha") == kernel_source_hash() and kname in t.get("kernels", {}):

@@ -1435,6 +1435,13 @@ __global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restri
                 const int i = ph * (NL / 2) + ii;
                 L4[((lin ^ lds_slot<true>(128 * i)) & 1023) >> 1] = R[i];
             }
+            if (ph == 1) {
+                // the tile is in LDS: prefetch the next one
+                const uint64_t nxt = tile + stride < last ? tile + stride : last;
+                __builtin_amdgcn_sched_barrier(0);
+                load_tile(tile_base<NT>(nxt, sg));
+                __builtin_amdgcn_sched_barrier(0);
+            }
             wave_lds_fence();
             if (lph == ph) {
                 if (LOWT) {
@@ -1471,12 +1478,7 @@ __global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restri
                 xh[st][i] = hi;
                 xl[st][i] = (_Float16)(v - (float)hi);
             }
-        // the column is in registers: prefetch the next tile
         const uint64_t tb0 = tile_base<NT>(tile, sg);
-        const uint64_t nxt = tile + stride < last ? tile + stride : last;
-        __builtin_amdgcn_sched_barrier(0);
-        load_tile(tile_base<NT>(nxt, sg));
-        __builtin_amdgcn_sched_barrier(0);
         floatx16 acc[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)

@@ -75,6 +75,35 @@ __global__ __launch_bounds__(256) void k_write(f4* __restrict__ a, size_t n4) {
         a[i] = f4{1.f, 2.f, 3.f, 4.f};
 }
 
+// The access pattern of the 6-qubit cluster kernel without its arithmetic:
+// a wave owns 32 neighbouring columns x 64 rows (rows 2^tshift amplitudes
+// apart, 8-byte amplitudes), lane (p, h) column p, rows j | h << 5, with the
+// next tile's rows loaded into registers before the current tile is stored.
+__global__ __launch_bounds__(256, 2) void k_rows(float* __restrict__ p, size_t ntiles, int tshift, float s) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2* q = reinterpret_cast<f2*>(p);
+    const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
+    const size_t stride = (size_t)gridDim.x * 4;
+    size_t tile = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    const size_t last = ntiles - 1;
+    auto addr = [&](size_t t, int j) { return t * 32 + col + ((size_t)(j | (h << 5)) << tshift); };
+    f2 B[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) B[j] = q[addr(tile, j)];
+    do {
+        const size_t nxt = tile + stride < last ? tile + stride : last;
+        f2 Bn[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) Bn[j] = q[addr(nxt, j)];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) q[addr(tile, j)] = B[j] * s;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) B[j] = Bn[j];
+        tile += stride;
+    } while (tile < ntiles);
+}
+
 template <typename F>
 static float time_ms(F f, int reps) {
     hipEvent_t e0, e1;
@@ -111,6 +140,21 @@ int main(int argc, char** argv) {
     CHECK(hipMemset(b, 0, bytes));
     const double gb = bytes / 1e9;
     std::printf("buffer %.2f GB\n", gb);
+    // the cluster kernel's pattern: 2^(lg-3) amplitudes, rows on the top 6 bits
+    {
+        const int na = lg - 3;
+        const size_t ntiles = (size_t(1) << (na - 6)) / 32;
+        for (unsigned grid : {512u, 1024u, 2048u, 8192u}) {
+            const float t = time_ms([&] { hipLaunchKernelGGL(k_rows, dim3(grid), dim3(256), 0, 0, (float*)a, ntiles,
+                                                             na - 6, 1.0f); }, reps);
+            std::printf("rows     k=6 top grid %6u  %7.3f ms  %7.0f GB/s\n", grid, t, 2 * gb / t * 1e3);
+        }
+    }
+    for (unsigned grid : {8192u, 32768u, 65536u}) {
+        const float t = time_ms([&] { hipLaunchKernelGGL((k_inplace<8, false>), dim3(grid), dim3(256), 0, 0, a, n4,
+                                                         1.0f); }, reps);
+        std::printf("inplace  U8      grid %6u  %7.3f ms  %7.0f GB/s\n", grid, t, 2 * gb / t * 1e3);
+    }
     for (unsigned grid : {1024u, 2048u, 4096u, 8192u, 32768u}) {
         float t;
         t = time_ms([&] { hipLaunchKernelGGL((k_inplace<1, false>), dim3(grid), dim3(256), 0, 0, a, n4, 1.0f); }, reps);

@@ -67,6 +67,38 @@ def counters(path):
     return d
 
 
+PEAK_TFLOPS = {"F16": 2500.0, "F32": 157.3, "F64": 78.6}  # MI355X dense matrix-core peaks
+
+
+def mfma_table(path):
+    """Per kernel: matrix-core FLOP rate from SQ_INSTS_VALU_MFMA_MOPS_* (units
+    of 512 FLOP) over the dispatches' own durations."""
+    disp = collections.defaultdict(dict)
+    for r in csv.DictReader(open(path)):
+        d = disp[(short(r["Kernel_Name"]), r["Dispatch_Id"])]
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+        d["ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    for (k, _), d in disp.items():
+        a = agg[k]
+        a["n"] += 1
+        for c, v in d.items():
+            a[c] += v
+    lines = ["| kernel | dispatches | avg ms | MFMA TFLOP/s (f16 / f32 / f64) | % of that dtype's peak |",
+             "|---|---:|---:|---|---:|"]
+    for k, a in sorted(agg.items(), key=lambda kv: -kv[1]["ns"]):
+        sec = a["ns"] * 1e-9
+        rates = {t: a.get("SQ_INSTS_VALU_MFMA_MOPS_" + t, 0.0) * 512 / sec / 1e12 if sec > 0 else 0.0
+                 for t in ("F16", "F32", "F64")}
+        if sum(rates.values()) == 0:
+            continue
+        top = max(rates, key=rates.get)
+        lines.append("| `%s` | %d | %.3f | %.1f / %.1f / %.1f | %.1f %% (%s) |" % (
+            k, a["n"], a["ns"] / a["n"] / 1e6, rates["F16"], rates["F32"], rates["F64"],
+            100 * rates[top] / PEAK_TFLOPS[top], top.lower()))
+    return lines
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--stats", required=True)
@@ -81,6 +113,8 @@ def main(argv=None):
     ap.add_argument("--title", default="rocprofv3 summary")
     ap.add_argument("--algorithmic", default="",
                     help="kernel=bytes,... algorithmic bytes per launch to compare with")
+    ap.add_argument("--mfma", help="counter CSV of SQ_INSTS_VALU_MFMA_MOPS_F16 / F32 / F64")
+    ap.add_argument("--mfma-command", default="")
     ap.add_argument("--out-md", required=True)
     ap.add_argument("--out-json")
     args = ap.parse_args(argv)
@@ -118,6 +152,10 @@ def main(argv=None):
             lines.append("| `%s` | %d | %.3f | %.3f | %.3f | %s |" % (k, len(fe[k]), f / 1e9, w / 1e9, (f + w) / 1e9,
                                                                    "%.3f" % (a / 1e9) if a else ""))
         rec["fetch_factor"], rec["write_factor"] = f_fac, w_fac
+    if args.mfma:
+        lines += ["", "Matrix-core use per kernel (rocprofv3 --pmc, its own run; rate = MOPS x 512 FLOP over the "
+                  "dispatch durations of that run, peaks: f16 2.5 PFLOP/s, f32 157.3, f64 78.6 TFLOP/s dense):", "",
+                  "    " + args.mfma_command, ""] + mfma_table(args.mfma)
     lines += ["", "Kernel source sha256[:16] of qsim_kernels.hip: `%s`" % rec["kernel_source_sha"], ""]
     with open(args.out_md, "w") as f:
         f.write("\n".join(lines))
