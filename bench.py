@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--pair", type=int, default=None,
                     help="pairing of small clusters: 0 off, 1 pairs, 2 every cluster alone in the pair kernel")
     ap.add_argument("--fp64-steps", type=int, default=None, help="steps of the float64 per-gate form")
+    ap.add_argument("--fp64-kmax", type=int, default=5, help="largest cluster of the float64 fused form")
+    ap.add_argument("--no-fp64-fused", action="store_true", help="skip the float64 fused form")
     ap.add_argument("--only", choices=["fused", "pergate", "batch"], default=None,
                     help="run one form only (for profiling); batch: the 512-circuit launch alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -254,6 +256,18 @@ def main():
         out["speedup_vs_fp64_per_gate"] = round(pergate[0] / fused[0], 2)
         fid, maxd = s32.compare(s64.amps)
         out["fused_vs_fp64_per_gate"] = {"fidelity": fid, "max_abs_diff": maxd}
+        if not args.no_fp64_fused:
+            # float64 state, fused clusters: the float64 path's accuracy at full size
+            f64_opts = dict(fused_opts, kmax=args.fp64_kmax)
+            s64f = qsim.State(n, "c128", kmax=max(args.fp64_kmax, 5))
+            f64 = timed(s64f, f64_opts, args.steps, min(args.warmup, 1), record=False)
+            fid64, maxd64 = s64f.compare(s64.amps)
+            out["fp64_fused"] = {"tts_s": round(f64[0], 5), "steps": len(f64[1]), "kmax": args.fp64_kmax,
+                                 "scheduler": args.scheduler, "ops": f64[2]["n_ops"],
+                                 "vs_fp64_per_gate": {"fidelity": fid64, "max_abs_diff": maxd64},
+                                 "speedup_vs_fp64_per_gate": round(pergate[0] / f64[0], 2)}
+            del s64f
+            torch.cuda.empty_cache()
 
     if recs:
         k6k = qsim.get_option(qsim.OPT_K6_KERNEL)
