@@ -9,8 +9,11 @@ to use, and write them to a tune table the library loads.
 3. Best (scheduler, k_max) per (dtype, size bucket): the supremacy circuit of
    that size is timed with every k_max and both the greedy and the analytic
    scheduler.
+4. Launch shape of the batched persistent kernel (tiles per work item,
+   work-groups, padding qubits), timed on the 512-circuit batch workload.
 
     python -m paper_1704_01127_amd.autotune --out paper_1704_01127_amd/tune_table.json
+    python -m paper_1704_01127_amd.autotune --only-batch --out paper_1704_01127_amd/tune_table.json
 """
 from __future__ import annotations
 
@@ -127,6 +130,47 @@ def tune_kmax(dt, buckets, seed, log):
     return res
 
 
+BATCH_OPTIONS = ("item_tiles", "grid", "pad")
+
+
+def tune_batch(n_circuits, reps, log):
+    """Launch shape of the batched persistent kernel, timed on the batch
+    workload (n_circuits circuits of 14-24 qubits, depth 10-40): tiles per work
+    item, work-groups (0: two per compute unit, its occupancy; 256: one), and
+    the identity qubits that pad clusters to 5 targets (0 lowest, 1 highest)."""
+    import torch
+    from supremacy_inputs import batch_circuit
+    circs = [batch_circuit(i) for i in range(n_circuits)]
+    opt = {"item_tiles": qsim.OPT_BATCH_ITEM_TILES, "grid": qsim.OPT_BATCH_GRID, "pad": qsim.OPT_BATCH_PAD}
+    old = {k: qsim.get_option(v) for k, v in opt.items()}
+    best = None
+    try:
+        for pad in (0, 1):
+            for tiles in (32, 64, 128, 256, 512):
+                for grid in (0, 256):
+                    cfg = {"item_tiles": tiles, "grid": grid, "pad": pad}
+                    for k, v in cfg.items():
+                        qsim.set_option(opt[k], v)
+                    b = qsim.Batch(circs)
+                    b.run()
+                    t = min(b.run()["run_ms"] for _ in range(reps))
+                    log("batch pad=%d item_tiles=%d grid=%d: %.2f ms" % (pad, tiles, grid, t))
+                    if best is None or t < best[0]:
+                        best = (t, cfg)
+                    del b
+                    torch.cuda.empty_cache()
+    finally:
+        for k, v in old.items():
+            qsim.set_option(opt[k], v)
+    return dict(best[1], ms=best[0], circuits=n_circuits)
+
+
+def apply_batch(cfg):
+    qsim.set_option(qsim.OPT_BATCH_ITEM_TILES, int(cfg["item_tiles"]))
+    qsim.set_option(qsim.OPT_BATCH_GRID, int(cfg["grid"]))
+    qsim.set_option(qsim.OPT_BATCH_PAD, int(cfg["pad"]))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--n", type=int, default=28, help="state size of the cost-table measurements")
@@ -135,6 +179,9 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--dtypes", default="c64,c128")
     ap.add_argument("--no-kmax", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-circuits", type=int, default=512)
+    ap.add_argument("--only-batch", action="store_true", help="re-tune the batch launch shape in an existing table")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
 
@@ -143,6 +190,15 @@ def main(argv=None):
     def log(msg):
         print(msg, flush=True)
 
+    if args.only_batch:
+        qsim.load_tuning(args.out)
+        with open(args.out) as f:
+            out = json.load(f)
+        out["batch"] = tune_batch(args.batch_circuits, args.reps, log)
+        log("batch best: %s" % json.dumps(out["batch"]))
+        with open(args.out, "w") as f:
+            json.dump(out, f, indent=1)
+        return out
     out = {"device": torch.cuda.get_device_name(0), "n_ref": args.n, "variants": {}, "cost_us": {},
            "best": {}, "created": time.strftime("%Y-%m-%d %H:%M:%S")}
     dts = args.dtypes.split(",")
@@ -158,6 +214,9 @@ def main(argv=None):
         for dt in dts:
             out["best"][dt] = tune_kmax(dt, buckets if dt == "c64" else {k: v for k, v in buckets.items() if k <= 28},
                                         args.seed, log)
+    if not args.no_batch:
+        out["batch"] = tune_batch(args.batch_circuits, args.reps, log)
+        log("batch best: %s" % json.dumps(out["batch"]))
     if args.out:
         with open(args.out, "w") as f:
             json.dump(out, f, indent=1)

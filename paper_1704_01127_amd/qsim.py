@@ -338,6 +338,10 @@ def load_tuning(path: Optional[str] = None, model_path: Optional[str] = None) ->
                     _check(L.qsim_set_tune_entry(code, int(k), cls, int(v)))
         for dt, us in t.get("cost_us", {}).items():
             set_cost_table(C64 if dt == "c64" else C128, us, int(t["n_ref"]))
+        if "batch" in t:  # launch shape of the batched kernel
+            set_option(OPT_BATCH_ITEM_TILES, int(t["batch"]["item_tiles"]))
+            set_option(OPT_BATCH_GRID, int(t["batch"]["grid"]))
+            set_option(OPT_BATCH_PAD, int(t["batch"]["pad"]))
         _tuning["table"] = t
     if os.path.exists(model_path):
         m = np.load(model_path, allow_pickle=False)
