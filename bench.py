@@ -78,10 +78,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-gates", type=int, default=24)
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batched launch")
+    ap.add_argument("--batch-kmax", type=int, default=None,
+                    help="largest cluster of the batched circuits (default: the binding's, from the tune table)")
     return ap.parse_args()
 
 
-def batch_bench(qsim, torch, runs=3, n_check=8):
+def batch_bench(qsim, torch, kmax, runs=3, n_check=8):
     """512 circuits (n ~ U[14, 24], depth ~ U[10, 40], seeds 1000 + i) in one
     persistent launch: circuits per second of qsim_batch_run (initialisation
     and every op of every circuit, matrices built on the GPU) and of plan + run,
@@ -89,8 +91,9 @@ def batch_bench(qsim, torch, runs=3, n_check=8):
     from supremacy_inputs import batch_circuit
     circs = [batch_circuit(i) for i in range(512)]
     t0 = time.perf_counter()
-    b = qsim.Batch(circs)
+    b = qsim.Batch(circs, kmax=kmax)
     plan_s = time.perf_counter() - t0
+    kmax = b.kmax
     b.run()
     runs_ms = [b.run()["run_ms"] for _ in range(runs)]
     st = b.run()
@@ -99,7 +102,7 @@ def batch_bench(qsim, torch, runs=3, n_check=8):
     # initialisation writes it
     alg = 0
     for i, c in enumerate(circs):
-        sc = qsim.schedule(c.n, c.gates, kmax=5, scheduler="greedy", fuse_diag=True, skip_initial_h=True)
+        sc = qsim.schedule(c.n, c.gates, kmax=kmax, scheduler="greedy", fuse_diag=True, skip_initial_h=True)
         m = len(sc["op_kind"])
         alg += (m * 16 + 8) * 2 ** c.n
     worst = 1.0
@@ -111,7 +114,7 @@ def batch_bench(qsim, torch, runs=3, n_check=8):
         f, _ = s.compare(b.states[i].to(torch.complex128))
         worst = min(worst, f)
         del s
-    res = {"circuits": 512, "qubits": "14-24", "depths": "10-40", "dtype": "c64",
+    res = {"circuits": 512, "qubits": "14-24", "depths": "10-40", "dtype": "c64", "kmax": kmax,
            "circuits_per_s": round(512 / run_s, 1), "run_ms": round(run_s * 1e3, 2),
            "circuits_per_s_with_plan": round(512 / (run_s + st["plan_ms"] / 1e3), 1),
            "plan_ms": round(st["plan_ms"], 2), "ops": st["n_ops"], "work_items": st["n_items"],
@@ -217,7 +220,7 @@ def main():
     out = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "data": "synthetic"}
     if args.only == "batch":
-        print(json.dumps({"batch": batch_bench(qsim, torch)}), flush=True)
+        print(json.dumps({"batch": batch_bench(qsim, torch, args.batch_kmax)}), flush=True)
         return
 
     fused = pergate = None
@@ -323,7 +326,7 @@ def main():
     if not args.no_batch and args.only is None:
         del s32, s64
         torch.cuda.empty_cache()
-        out["batch"] = batch_bench(qsim, torch)
+        out["batch"] = batch_bench(qsim, torch, args.batch_kmax)
 
     if not args.no_cpu_baseline:
         # free the GPU states first: the oracle needs 16 GiB of host memory

@@ -212,8 +212,8 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * a tune table, which qsim_set_tune_entry overwrites (the autotuner fills it
  * from measurements). QSIM_OPT_CLUSTER_VARIANT = 0 or 1 forces one variant
  * everywhere, -1 (default) uses the table. Batches: QSIM_OPT_BATCH_GRID is
- * the number of work-groups of the persistent launch (0, the default: two
- * per compute unit, the kernel's occupancy); QSIM_OPT_BATCH_PAD picks the
+ * the number of work-groups of the persistent launch (0, the default: one
+ * 8-wave work-group per compute unit, the kernel's occupancy); QSIM_OPT_BATCH_PAD picks the
  * identity qubits that pad a cluster to 5 targets (0, default: the lowest
  * qubits outside it, which lengthens the contiguous runs of a tile; 1: the
  * highest); QSIM_OPT_BATCH_ITEM_TILES is the number of tiles (2^11
@@ -321,14 +321,15 @@ qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates,
 /* ------------------------------------------------------------------ batches
  * Many independent circuits in one persistent launch (complex64 states).
  * Every circuit is scheduled as by qsim_run_circuit (greedy clusters of at
- * most opts->kmax <= 5 qubits, Sec. 3.6; diagonal gates fused or in
- * diagonal passes); each cluster is padded with identity qubits to 5 targets
- * and each diagonal pass becomes an identity cluster with a diagonal
- * epilogue, so that one matrix-core kernel applies every op. Matrices are
- * built in float64 on the GPU and rounded to float32. Work items (one op,
- * up to 32 tiles of 2^11 amplitudes) are taken from an atomic counter in
- * dependency order; an item waits until every earlier op of its circuit is
- * complete. */
+ * most opts->kmax <= 6 qubits, Sec. 3.6; diagonal gates fused or in
+ * diagonal passes). A 6-qubit cluster is applied on fp16 matrix cores with
+ * operand halves; smaller clusters are padded with identity qubits to 5
+ * targets (fp32 real-split product), and each diagonal pass becomes an
+ * identity 5-qubit cluster with a diagonal epilogue, so that one persistent
+ * kernel applies every op. Matrices are built in float64 on the GPU. Work
+ * items (one op, QSIM_OPT_BATCH_ITEM_TILES tiles of 2^11 amplitudes) are
+ * taken from an atomic counter in dependency order; an item waits until
+ * every earlier op of its circuit is complete. */
 typedef struct qsim_batch_s* qsim_batch;
 
 typedef struct {
@@ -351,7 +352,7 @@ typedef struct {
 } qsim_batch_stats;
 
 /* Schedule and pack n_circuits circuits (host only; no GPU work). opts:
- * kmax in [1, 5], scheduler GREEDY, ANALYTIC or LEARNED (PER_GATE is
+ * kmax in [1, 6], scheduler GREEDY, ANALYTIC or LEARNED (PER_GATE is
  * QSIM_E_UNSUPPORTED), fuse_diag, skip_trailing_diag, skip_initial_h.
  * *workspace_bytes receives the device workspace qsim_batch_run needs. The
  * circuit descriptors' amplitude pointers are kept; the gate lists are not. */

@@ -9,8 +9,8 @@ to use, and write them to a tune table the library loads.
 3. Best (scheduler, k_max) per (dtype, size bucket): the supremacy circuit of
    that size is timed with every k_max and both the greedy and the analytic
    scheduler.
-4. Launch shape of the batched persistent kernel (tiles per work item,
-   work-groups, padding qubits), timed on the 512-circuit batch workload.
+4. Cluster size and launch shape of the batched persistent kernel (k_max,
+   tiles per work item, padding qubits), timed on the 512-circuit workload.
 
     python -m paper_1704_01127_amd.autotune --out paper_1704_01127_amd/tune_table.json
     python -m paper_1704_01127_amd.autotune --only-batch --out paper_1704_01127_amd/tune_table.json
@@ -134,10 +134,12 @@ BATCH_OPTIONS = ("item_tiles", "grid", "pad")
 
 
 def tune_batch(n_circuits, reps, log):
-    """Launch shape of the batched persistent kernel, timed on the batch
-    workload (n_circuits circuits of 14-24 qubits, depth 10-40): tiles per work
-    item, work-groups (0: two per compute unit, its occupancy; 256: one), and
-    the identity qubits that pad clusters to 5 targets (0 lowest, 1 highest)."""
+    """Cluster size and launch shape of the batched persistent kernel, timed
+    on the batch workload (n_circuits circuits of 14-24 qubits, depth 10-40):
+    k_max (5: every cluster padded to 5 qubits; 6: 6-qubit clusters on the
+    fp16 kernel), tiles per work item, and the identity qubits that pad
+    clusters to 5 targets (0 lowest, 1 highest). The grid is the kernel's
+    occupancy (one work-group per compute unit)."""
     import torch
     from supremacy_inputs import batch_circuit
     circs = [batch_circuit(i) for i in range(n_circuits)]
@@ -145,18 +147,18 @@ def tune_batch(n_circuits, reps, log):
     old = {k: qsim.get_option(v) for k, v in opt.items()}
     best = None
     try:
-        for pad in (0, 1):
-            for tiles in (32, 64, 128, 256, 512):
-                for grid in (0, 256):
-                    cfg = {"item_tiles": tiles, "grid": grid, "pad": pad}
+        for kmax in (5, 6):
+            for pad in (0, 1):
+                for tiles in (32, 64, 128, 256, 512):
+                    cfg = {"item_tiles": tiles, "grid": 0, "pad": pad}
                     for k, v in cfg.items():
                         qsim.set_option(opt[k], v)
-                    b = qsim.Batch(circs)
+                    b = qsim.Batch(circs, kmax=kmax)
                     b.run()
                     t = min(b.run()["run_ms"] for _ in range(reps))
-                    log("batch pad=%d item_tiles=%d grid=%d: %.2f ms" % (pad, tiles, grid, t))
+                    log("batch kmax=%d pad=%d item_tiles=%d: %.2f ms" % (kmax, pad, tiles, t))
                     if best is None or t < best[0]:
-                        best = (t, cfg)
+                        best = (t, dict(cfg, kmax=kmax))
                     del b
                     torch.cuda.empty_cache()
     finally:

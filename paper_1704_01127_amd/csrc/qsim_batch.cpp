@@ -21,18 +21,18 @@ using namespace qsim::api;
 
 namespace {
 
-constexpr int kBatchK = 5;                           // every cluster op has 5 targets
-constexpr int kBatchC = 6;                           // column bits of a tile
-constexpr int kTileBits = kBatchK + kBatchC;         // 2^11 amplitudes per tile
+constexpr int kBatchK = 5;                           // smaller clusters are padded to 5 targets
+constexpr int kBatchC = 6;                           // column bits of a 5-qubit tile
+constexpr int kTileBits = kBatchK + kBatchC;         // 2^11 amplitudes per tile (6 + 5 for 6-qubit ops)
 constexpr int kBatchMinQ = kTileBits;                // smallest state: one tile
 constexpr int kBatchMaxQ = 30;
 constexpr uint32_t kDefaultWaitUs = 10u * 1000 * 1000;  // longest dependency wait: 10 s
-constexpr size_t kMatBytes = size_t(2 * 32) * (2 * 32) * sizeof(float);  // real-split 64 x 64
 
 // One circuit's packed ops, built independently of the others.
 struct Packed {
     std::vector<BatchOp> ops;      // psi / A / epi filled at run time
     std::vector<int> op_mat;       // per op: index into bops (-1: initialisation)
+    std::vector<int64_t> mat_bytes;  // per bop: size of its matrix
     std::vector<int> op_epi;       // per op: index into epis (-1: none)
     std::vector<BuildOp> bops;     // gate0 relative to bgates, out_off unset
     std::vector<BuildGate> bgates; // dense_off relative to dense
@@ -84,7 +84,7 @@ Packed pack_circuit(const qsim_batch_circuit& c, const qsim_run_opts* opts, int 
             P.err = "per-gate ops are not batched";
             return P;
         }
-        int q[kMaxK], t[kBatchK];
+        int q[kMaxK], t[kMaxK];
         int k = 0;
         std::vector<int> members, epi;
         if (op.kind == OP_CLUSTER) {
@@ -96,21 +96,29 @@ Packed pack_circuit(const qsim_batch_circuit& c, const qsim_run_opts* opts, int 
             // a diagonal pass: identity cluster whose store applies every gate
             epi = op.members;
         }
-        if (k > kBatchK) {
+        if (k > 6) {
             P.st = QSIM_E_UNSUPPORTED;
-            P.err = "batched clusters have at most 5 qubits";
+            P.err = "batched clusters have at most 6 qubits";
             return P;
         }
-        pad_targets(n, q, k, pad_policy, t);
+        // 6-qubit clusters keep their targets (fp16-halves kernel); smaller
+        // ones are padded to 5 (fp32 real-split kernel)
+        const int kk = k == 6 ? 6 : kBatchK;
+        if (k == 6) {
+            for (int j = 0; j < 6; ++j) t[j] = q[j];
+            std::sort(t, t + 6);
+        } else {
+            pad_targets(n, q, k, pad_policy, t);
+        }
         int pos_of[64];
         for (int i = 0; i < 64; ++i) pos_of[i] = -1;
-        for (int j = 0; j < kBatchK; ++j) pos_of[t[j]] = j;
+        for (int j = 0; j < kk; ++j) pos_of[t[j]] = j;
 
         BuildOp bo;
         std::memset(&bo, 0, sizeof(bo));
-        bo.k = kBatchK;
+        bo.k = kk;
         bo.gate0 = (int)P.bgates.size();
-        bo.layout = LAYOUT_MFMA32F;
+        bo.layout = kk == 6 ? LAYOUT_SPLIT16F : LAYOUT_MFMA32F;
         bo.is_double = 0;
         for (int gi : members) P.bgates.push_back(to_build_gate(c.gates[gi], pos_of, P.dense));
         EpiDesc e;
@@ -123,20 +131,21 @@ Packed pack_circuit(const qsim_batch_circuit& c, const qsim_run_opts* opts, int 
 
         ClusterGeom g;
         std::memset(&g, 0, sizeof(g));
-        for (int j = 0; j < kBatchK; ++j) g.t[j] = t[j];
+        for (int j = 0; j < kk; ++j) g.t[j] = t[j];
         g.n = n;
-        g.k = kBatchK;
-        g.ncols = uint64_t(1) << (n - kBatchK);
+        g.k = kk;
+        g.ncols = uint64_t(1) << (n - kk);
         BatchOp b;
         std::memset(&b, 0, sizeof(b));
-        b.sg = make_stage_geom(g, kBatchC, 7);
+        b.sg = make_stage_geom(g, kTileBits - kk, 7);  // 11 tile bits either way
         b.tiles = tiles;
-        b.kind = 0;
+        b.kind = kk == 6 ? 3 : 0;
         b.circuit = circuit;
         b.lowt = t[0] == 0;
         b.n = n;
         P.op_mat.push_back((int)P.bops.size());
         P.bops.push_back(bo);
+        P.mat_bytes.push_back(matrix_bytes(kk, bo.layout, false));
         if (e.n_cc || e.n_mix || e.n_ph) {
             P.op_epi.push_back((int)P.epis.size());
             P.epis.push_back(e);
@@ -155,6 +164,8 @@ struct qsim_batch_s {
     std::vector<void*> amps;
     std::vector<BatchOp> ops;
     std::vector<int> op_mat, op_epi;
+    std::vector<int64_t> mat_off;  // per bop: byte offset of its matrix in the matrix region
+    int64_t mat_total = 0;
     std::vector<BatchItem> items;
     std::vector<BuildOp> bops;
     std::vector<BuildGate> bgates;
@@ -180,7 +191,7 @@ qsim_status qsim_batch_plan(const qsim_batch_circuit* circuits, int n_circuits, 
     if (opts->scheduler == QSIM_SCHED_PER_GATE) return fail(QSIM_E_UNSUPPORTED, "per-gate runs are not batched");
     if (opts->scheduler < QSIM_SCHED_PER_GATE || opts->scheduler > QSIM_SCHED_LEARNED)
         return fail(QSIM_E_INVALID, "unknown scheduler");
-    if (opts->kmax < 1 || opts->kmax > kBatchK) return fail(QSIM_E_UNSUPPORTED, "batch kmax must be in [1, 5]");
+    if (opts->kmax < 1 || opts->kmax > 6) return fail(QSIM_E_UNSUPPORTED, "batch kmax must be in [1, 6]");
     for (int i = 0; i < n_circuits; ++i) {
         const qsim_batch_circuit& c = circuits[i];
         const std::string at = "circuit " + std::to_string(i) + ": ";
@@ -224,8 +235,12 @@ qsim_status qsim_batch_plan(const qsim_batch_circuit* circuits, int n_circuits, 
             b->op_mat.push_back(P.op_mat[j] < 0 ? -1 : P.op_mat[j] + bop0);
             b->op_epi.push_back(P.op_epi[j] < 0 ? -1 : P.op_epi[j] + epi0);
         }
-        for (BuildOp bo : P.bops) {
+        for (size_t j = 0; j < P.bops.size(); ++j) {
+            BuildOp bo = P.bops[j];
             bo.gate0 += bg0;
+            bo.out_off = b->mat_total;
+            b->mat_off.push_back(b->mat_total);
+            b->mat_total += (int64_t)align256((size_t)P.mat_bytes[j]);
             b->bops.push_back(bo);
         }
         for (BuildGate bg : P.bgates) {
@@ -236,7 +251,6 @@ qsim_status qsim_batch_plan(const qsim_batch_circuit* circuits, int n_circuits, 
         b->epis.insert(b->epis.end(), P.epis.begin(), P.epis.end());
         b->n_applied += P.n_applied;
     }
-    for (size_t j = 0; j < b->bops.size(); ++j) b->bops[j].out_off = (int64_t)(j * kMatBytes);
 
     // work items in level order (the j-th op of every circuit before any
     // (j+1)-th), larger states first within a level; dep = items of the
@@ -282,7 +296,7 @@ qsim_status qsim_batch_plan(const qsim_batch_circuit* circuits, int n_circuits, 
     b->off_dense = off;
     off += align256(b->dense.size() * sizeof(double));
     b->off_mats = off;
-    off += b->bops.size() * kMatBytes;
+    off += (size_t)b->mat_total;
     b->ws_bytes = off;
     b->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (workspace_bytes) *workspace_bytes = b->ws_bytes;
@@ -307,7 +321,7 @@ qsim_status qsim_batch_run(qsim_batch b, void* dev_workspace, size_t ws_bytes, v
         ops[j] = b->ops[j];
         ops[j].psi = static_cast<float2*>(b->amps[b->ops[j].circuit]);
         ops[j].A = b->op_mat[j] < 0 ? nullptr
-                                     : reinterpret_cast<const float*>(ws + b->off_mats + b->op_mat[j] * kMatBytes);
+                                     : reinterpret_cast<const float*>(ws + b->off_mats + b->mat_off[b->op_mat[j]]);
         ops[j].epi = b->op_epi[j] < 0 ? nullptr
                                        : reinterpret_cast<const EpiDesc*>(ws + b->off_epis) + b->op_epi[j];
     }
@@ -334,7 +348,7 @@ qsim_status qsim_batch_run(qsim_batch b, void* dev_workspace, size_t ws_bytes, v
         std::max<uint64_t>(1, uint64_t(wait_limit_us ? wait_limit_us : kDefaultWaitUs) *
                                   uint64_t(std::max(clock_khz, 1)) / 1000);
     const uint32_t n_items = (uint32_t)b->items.size();
-    uint32_t grid = g_batch_grid > 0 ? (uint32_t)g_batch_grid : (uint32_t)(2 * std::max(cus, 1));
+    uint32_t grid = g_batch_grid > 0 ? (uint32_t)g_batch_grid : (uint32_t)std::max(cus, 1);  // one per CU (LDS)
     grid = std::max(1u, std::min(grid, n_items));
     uint32_t* counters = reinterpret_cast<uint32_t*>(ws);
     HIP_TRY(launch_batch(reinterpret_cast<const BatchOp*>(ws + b->off_ops),

@@ -131,16 +131,17 @@ struct StageGeom {
     uint64_t ioff[32];   // state offset of linear chunk i (tau = i << lane_bits ...)
 };
 
-// Batched persistent launch: every op is a 5-qubit float cluster (smaller
-// clusters padded with identity qubits) applied by the staged kernel, or the
-// initialisation of a state. Device pointers are filled in at run time.
+// Batched persistent launch: every op is a 6-qubit float cluster (fp16 matrix
+// halves, staged half tiles), a 5-qubit one (smaller clusters padded with
+// identity qubits; fp32 real-split, staged tiles), or the initialisation of a
+// state. Device pointers are filled in at run time.
 struct BatchOp {
     float2* psi;           // the circuit's state
     const float* A;        // permuted real-split matrix (clusters)
     const EpiDesc* epi;    // diagonal epilogue or null
     StageGeom sg;          // tile geometry (clusters)
     uint64_t tiles;        // wave tiles of 2^11 amplitudes
-    int32_t kind;          // 0 cluster, 1 |0..0>, 2 uniform
+    int32_t kind;          // 0 5-qubit cluster, 1 |0..0>, 2 uniform, 3 6-qubit cluster
     int32_t circuit;
     int32_t lowt;          // target 0 is a cluster qubit
     int32_t n;             // qubits of the state

@@ -1349,27 +1349,17 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_cluster_f32_pair10(float2* __
 // Core (fp16 halves on matrix cores, column scaling, epilogue) as above.
 // Addresses: slot(tau) = lds_slot<true>(tau) & 1023, linear over XOR, so the
 // lane's column part and the row part are mapped separately.
+//
+// One wave applies the cluster whose fp16 matrix halves are in LDS (Ah, Al)
+// to tiles tile, tile + stride, ... < tile_end (tile numbers uniform in the
+// wave), staging through its 8 KiB LDS buffer L.
 template <bool LOWT>
-__global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restrict__ psi,
-                                                                const half8* __restrict__ Ap,
-                                                                const EpiDesc* __restrict__ epi_p, StageGeom sg,
-                                                                uint64_t ntiles) {
-    constexpr int K = 6, C = 5, NT = K + C, HX = 32, RB = 4, S = 8, NL = 16, WAVES = 8;
-    __shared__ half8 Ah[RB * S * 64];
-    __shared__ half8 Al[RB * S * 64];
-    __shared__ float2 Ls[WAVES][1024];
-    load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Ah), reinterpret_cast<const vf4*>(Ap));
-    load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Al),
-                                            reinterpret_cast<const vf4*>(Ap + RB * S * 64));
-    __syncthreads();
-
-    // the wave index is uniform in the wave: tile numbers and bases are scalar
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63, p = lane & 31,
-              h = lane >> 5;
-    float2* L = Ls[w];
+__device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const half8* Ah, const half8* Al, float2* L,
+                                              c_epi* __restrict__ epi, const StageGeom& sg, uint64_t tile,
+                                              uint64_t tile_end, uint64_t stride) {
+    constexpr int K = 6, C = 5, NT = K + C, HX = 32, RB = 4, S = 8, NL = 16;
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     vf4* L4 = reinterpret_cast<vf4*>(L);
-    g_float2* gpsi = (g_float2*)psi;
-    c_epi* epi = (c_epi*)epi_p;
     const bool has_epi = epi != nullptr;
     const bool has_ph = has_epi && epi->n_ph > 0;
     uint64_t lane_off = 0;  // state offset of tile bits 1..6 (the lane of a linear load)
@@ -1407,10 +1397,8 @@ __global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restri
         return o;
     };
 
-    uint64_t tile = (uint64_t)blockIdx.x * WAVES + w;
-    if (tile >= ntiles) return;
-    const uint64_t stride = (uint64_t)gridDim.x * WAVES;
-    const uint64_t last = ntiles - 1;
+    if (tile >= tile_end) return;
+    const uint64_t last = tile_end - 1;
     vf4 R[NL];
     auto load_tile = [&](uint64_t t0) {  // t0: the tile's base (uniform)
 #pragma unroll
@@ -1528,7 +1516,26 @@ __global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restri
             wave_lds_fence();
         }
         tile += stride;
-    } while (tile < ntiles);
+    } while (tile < tile_end);
+}
+
+template <bool LOWT>
+__global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restrict__ psi,
+                                                                const half8* __restrict__ Ap,
+                                                                const EpiDesc* __restrict__ epi, StageGeom sg,
+                                                                uint64_t ntiles) {
+    constexpr int RB = 4, S = 8, WAVES = 8;
+    __shared__ half8 Ah[RB * S * 64];
+    __shared__ half8 Al[RB * S * 64];
+    __shared__ float2 Ls[WAVES][1024];
+    load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Ah), reinterpret_cast<const vf4*>(Ap));
+    load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Al),
+                                            reinterpret_cast<const vf4*>(Ap + RB * S * 64));
+    __syncthreads();
+    // the wave index is uniform in the wave: tile numbers and bases are scalar
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    split6s_tiles<LOWT>((g_float2*)psi, Ah, Al, Ls[w], (c_epi*)epi, sg, (uint64_t)blockIdx.x * WAVES + w, ntiles,
+                        (uint64_t)gridDim.x * WAVES);
 }
 
 // ------------------------------------------------------------ batched persistent launch
@@ -1550,16 +1557,18 @@ __global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restri
 // through the barriers, re-reading a stale ticket - while thread 0 waits
 // outside it. The ticket goes through readfirstlane so that the exit test is
 // uniform, too.
-__global__ __launch_bounds__(256, 2) void k_batch_f32(const BatchOp* __restrict__ ops,
+__global__ __launch_bounds__(512, 1) void k_batch_f32(const BatchOp* __restrict__ ops,
                                                       const BatchItem* __restrict__ items, uint32_t n_items,
                                                       uint32_t* counters, uint32_t item_tiles, uint64_t wait_ticks) {
-    constexpr int K = 5, C = 6;
-    __shared__ float As[2 * 32 * 64];
-    __shared__ vf4 Ls[4][1 << (K + C - 1)];
-    // the ticket is broadcast through the matrix buffer (an extra LDS word
-    // would leave room for only one work-group per CU)
-    uint32_t* s_it = reinterpret_cast<uint32_t*>(As);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int K = 5, C = 6, WAVES = 8;
+    // One LDS buffer, two layouts. 5-qubit ops: the real-split matrix (16 KiB)
+    // and a 16 KiB tile per wave; 6-qubit ops: the fp16 matrix halves (64 KiB)
+    // and an 8 KiB half tile per wave. 144 KiB: one work-group per CU.
+    __shared__ vf4 Lraw[1024 + WAVES * 1024];
+    // the ticket is broadcast through the matrix region (read before the
+    // barrier that precedes every matrix load)
+    uint32_t* s_it = reinterpret_cast<uint32_t*>(Lraw);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     uint32_t* done = counters + 2;
     int prev = -1;  // circuit of the item just finished (uniform)
     for (;;) {
@@ -1594,12 +1603,28 @@ __global__ __launch_bounds__(256, 2) void k_batch_f32(const BatchOp* __restrict_
         if (op->kind == 0) {
             const g_vf4* A = (const g_vf4*)op->A;
             c_epi* epi = (c_epi*)op->epi;
-            load_matrix<2 * 32 * 64, 256>(As, A);
+            float* As = reinterpret_cast<float*>(Lraw);
+            load_matrix<2 * 32 * 64, WAVES * 64>(As, A);
             __syncthreads();
+            vf4* L4 = Lraw + 1024 + w * 1024;
             if (op->lowt)
-                staged_f32_tiles<K, C, true>(psi, As, Ls[w], epi, op->sg, item.tile0 + w, t_end, 4);
+                staged_f32_tiles<K, C, true>(psi, As, L4, epi, op->sg, item.tile0 + w, t_end, WAVES);
             else
-                staged_f32_tiles<K, C, false>(psi, As, Ls[w], epi, op->sg, item.tile0 + w, t_end, 4);
+                staged_f32_tiles<K, C, false>(psi, As, L4, epi, op->sg, item.tile0 + w, t_end, WAVES);
+        } else if (op->kind == 3) {
+            // a 6-qubit cluster: fp16 matrix halves, staged half tiles
+            const g_vf4* A = (const g_vf4*)op->A;
+            c_epi* epi = (c_epi*)op->epi;
+            half8* Ah = reinterpret_cast<half8*>(Lraw);
+            half8* Al = Ah + 2048;
+            load_matrix<2048 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Ah), A);
+            load_matrix<2048 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Al), A + 2048);
+            __syncthreads();
+            float2* L = reinterpret_cast<float2*>(Lraw + 4096 + w * 512);
+            if (op->lowt)
+                split6s_tiles<true>(psi, Ah, Al, L, epi, op->sg, item.tile0 + w, t_end, WAVES);
+            else
+                split6s_tiles<false>(psi, Ah, Al, L, epi, op->sg, item.tile0 + w, t_end, WAVES);
         } else {
             // initialisation: tile t is amplitudes [t 2^11, (t + 1) 2^11)
             // 2^(-n/2): a power of two, times 1/sqrt(2) for odd n (both exact scalings of a rounded constant)
@@ -1607,7 +1632,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_f32(const BatchOp* __restrict_
                                             : __builtin_ldexpf((op->n & 1) ? 0.70710678118654752440f : 1.0f,
                                                                -(op->n >> 1));
             g_vf4* p4 = reinterpret_cast<g_vf4*>(psi);
-            for (uint64_t t = item.tile0 + w; t < t_end; t += 4) {
+            for (uint64_t t = item.tile0 + w; t < t_end; t += WAVES) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const uint64_t q = (t << 10) + (uint64_t)(i * 64 + lane);  // index of an amplitude pair
@@ -2500,7 +2525,7 @@ hipError_t launch_batch(const BatchOp* ops, const BatchItem* items, uint32_t n_i
                         hipStream_t st) {
     const uint32_t nc = n_circuits + 2;
     hipLaunchKernelGGL(k_fill_u32, dim3((nc + 255) / 256), dim3(256), 0, st, counters, nc, 0u);
-    hipLaunchKernelGGL(k_batch_f32, dim3(grid), dim3(256), 0, st, ops, items, n_items, counters, item_tiles,
+    hipLaunchKernelGGL(k_batch_f32, dim3(grid), dim3(512), 0, st, ops, items, n_items, counters, item_tiles,
                        wait_ticks);
     return hipGetLastError();
 }

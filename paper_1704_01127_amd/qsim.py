@@ -485,13 +485,19 @@ class Batch:
 
     circuits: objects with .n and .gates (or (n, gates) tuples). The states
     are torch complex64 tensors (self.states[i]) owned here, as is the
-    workspace; plan at construction, run() as often as wanted."""
+    workspace; plan at construction, run() as often as wanted. kmax: largest
+    cluster (1..6); None takes the tune table's batch choice (else 5)."""
 
-    def __init__(self, circuits: Sequence, kmax: int = 5, scheduler: str = "greedy", fuse_diag: bool = True,
-                 skip_trailing_diag: bool = False, skip_initial_h: bool = True, stream=None, device: int = 0):
+    def __init__(self, circuits: Sequence, kmax: Optional[int] = None, scheduler: str = "greedy",
+                 fuse_diag: bool = True, skip_trailing_diag: bool = False, skip_initial_h: bool = True, stream=None,
+                 device: int = 0):
         import torch
         if not _tuning["loaded"] and not os.environ.get("QSIM_NO_TUNING"):
             load_tuning()
+        if kmax is None:
+            t = _tuning["table"] or {}
+            kmax = int(t.get("batch", {}).get("kmax", 5))
+        self.kmax = kmax
         dev = torch.device("cuda", device)
         self.ns = [int(c[0] if isinstance(c, tuple) else c.n) for c in circuits]
         gate_lists = [c[1] if isinstance(c, tuple) else c.gates for c in circuits]

@@ -82,7 +82,9 @@ def test_batch_plan_host_checks():
     assert st == 0 and ws > 2 * 16384
     st2, ws2 = plan(fuse_diag=False)
     assert st2 == 0 and ws2 >= ws  # diagonal passes become extra cluster ops
-    assert plan(kmax=6)[0] == qsim.E_UNSUPPORTED
+    st6, ws6 = plan(kmax=6)
+    assert st6 == 0 and ws6 > 0                     # 6-qubit clusters: fp16 matrix halves (64 KiB each)
+    assert plan(kmax=7)[0] == qsim.E_UNSUPPORTED
     assert plan(scheduler="per_gate")[0] == qsim.E_UNSUPPORTED
     assert plan(n=10)[0] == qsim.E_UNSUPPORTED      # below one tile
     assert plan(ptrs=(1 << 20, 1 << 20))[0] == qsim.E_INVALID  # shared state

@@ -54,6 +54,9 @@ def _reset_options():
     dict(kmax=3),
     dict(kmax=1, fuse_diag=False, skip_initial_h=False),
     dict(kmax=4, skip_initial_h=False),
+    dict(kmax=6),
+    dict(kmax=6, fuse_diag=False),
+    dict(kmax=6, skip_initial_h=False),
 ])
 def test_batch_matches_oracle(opts):
     circs = small_batch(12, seed0=3)
@@ -96,6 +99,24 @@ def test_batch_dense_gates_and_skips():
     b2 = qsim.Batch(circs)
     b2.run()
     check_against_oracle(b2, circs)
+
+
+@pytest.mark.parametrize("pad", [0, 1])
+def test_batch_six_qubit_clusters(pad):
+    """6-qubit clusters (fp16 matrix halves, staged half tiles) next to padded
+    smaller ones in one launch: Haar 6-qubit gates, targets on the lowest
+    qubits and elsewhere, qubit 0 a target or not."""
+    qsim.set_option(qsim.OPT_BATCH_PAD, pad)
+    circs = []
+    for i, n in enumerate((11, 12, 14, 16, 13)):
+        R, C, drop = batch_grid(n)
+        c = supremacy_circuit(R, C, 14 + 4 * i, 700 + i, drop)
+        circs.append(with_haar_layers(c, 5, 6, 950 + i))
+    scheds = [qsim.schedule(c.n, c.gates, kmax=6, fuse_diag=True, skip_initial_h=True) for c in circs]
+    assert any(6 in s["op_k"] for s in scheds) and any(k < 6 for s in scheds for k in s["op_k"])
+    b = qsim.Batch(circs, kmax=6)
+    b.run()
+    check_against_oracle(b, circs)
 
 
 def test_batch_repeat_runs_and_two_batches():
