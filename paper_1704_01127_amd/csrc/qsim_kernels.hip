@@ -105,6 +105,16 @@ __device__ __forceinline__ void apply_factor(T& re, T& im, const ColFactor<T>& f
     im = neg ? -im : im;
 }
 
+// Work-groups of a launch are dealt to the 8 XCDs round-robin (work-group b
+// runs on XCD b % 8). Renumbered so that the work-groups of one XCD are
+// consecutive, the tiles a persistent grid has in flight form one contiguous
+// stretch per XCD (each XCD has its own L2). A bijection of the work-group
+// numbers when the grid is a multiple of 8, else the identity.
+__device__ __forceinline__ uint32_t xcd_block() {
+    const uint32_t b = blockIdx.x, g = gridDim.x;
+    return (g & 7) == 0 ? (b & 7) * (g >> 3) + (b >> 3) : b;
+}
+
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef double vd2 __attribute__((ext_vector_type(2)));
 // Explicitly global pointers for code that also runs on pointers read from a
@@ -235,7 +245,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_mfma(float2* __restrict_
     // The prefetch is unconditional (the last tile is re-read instead of
     // reading past the end) so the load count per iteration is fixed and the
     // waits the compiler places for the amplitudes cover only their own loads.
-    uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    uint64_t tile = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
     const uint64_t last = ntiles - 1;
     float B[NB][2 * HX];
@@ -326,7 +336,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_gauss6(float2* __restric
     const bool has_epi = epi != nullptr;
     const bool has_ph = has_epi && epi->n_ph > 0;
 
-    uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    uint64_t tile = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
     const uint64_t last = ntiles - 1;
     auto load = [&](uint64_t b, float (&X)[2 * HX]) {
@@ -449,7 +459,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_split6(float2* __restric
     const bool has_epi = epi != nullptr;
     const bool has_ph = has_epi && epi->n_ph > 0;
 
-    uint64_t tile = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    uint64_t tile = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
     const uint64_t last = ntiles - 1;
 
@@ -566,7 +576,7 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_mfma(dou
             }
     };
 
-    uint64_t tile = (uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    uint64_t tile = (uint64_t)xcd_block() * WAVES + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
     const uint64_t last = ntiles - 1;
     double B[NB][2 * HX];
@@ -853,7 +863,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_stage(float2* __restrict
     load_matrix<RB * S * 64, 256>(As, reinterpret_cast<const vf4*>(Ap));
     __syncthreads();
     const int w = threadIdx.x >> 6;
-    staged_f32_tiles<K, C, LOWT>((g_float2*)psi, As, Ls[w], (c_epi*)epi, sg, (uint64_t)blockIdx.x * 4 + w,
+    staged_f32_tiles<K, C, LOWT>((g_float2*)psi, As, Ls[w], (c_epi*)epi, sg, (uint64_t)xcd_block() * 4 + w,
                                  g.ncols >> C, (uint64_t)gridDim.x * 4);
 }
 
@@ -925,7 +935,7 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd
     const bool has_epi = epi != nullptr;
     const bool has_ph = has_epi && epi->n_ph > 0;
 
-    uint64_t tile = (uint64_t)blockIdx.x * WAVES + w;
+    uint64_t tile = (uint64_t)xcd_block() * WAVES + w;
     if (tile >= ntiles) return;
     const uint64_t last = ntiles - 1;
     vd2 R[NL];
@@ -1060,7 +1070,7 @@ __global__ __launch_bounds__(WAVES * 64, 8 / WAVES) void k_cluster_f32_multi(flo
         for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const g_vf4*>(gpsi + (b0 | chunk_off(i)));
     };
 
-    uint64_t tile = (uint64_t)blockIdx.x * WAVES + w;
+    uint64_t tile = (uint64_t)xcd_block() * WAVES + w;
     if (tile >= ntiles) return;
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
     const uint64_t last = ntiles - 1;
@@ -1225,7 +1235,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_cluster_f32_pair10(float2* __
         cbits[m] = state_bits_of_column<5>(p, sg);
     }
 
-    uint64_t tile = (uint64_t)blockIdx.x * WAVES + w;
+    uint64_t tile = (uint64_t)xcd_block() * WAVES + w;
     if (tile >= ntiles) return;
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
     const uint64_t last = ntiles - 1;
@@ -1534,7 +1544,7 @@ __global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restri
     __syncthreads();
     // the wave index is uniform in the wave: tile numbers and bases are scalar
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    split6s_tiles<LOWT>((g_float2*)psi, Ah, Al, Ls[w], (c_epi*)epi, sg, (uint64_t)blockIdx.x * WAVES + w, ntiles,
+    split6s_tiles<LOWT>((g_float2*)psi, Ah, Al, Ls[w], (c_epi*)epi, sg, (uint64_t)xcd_block() * WAVES + w, ntiles,
                         (uint64_t)gridDim.x * WAVES);
 }
 

@@ -104,6 +104,44 @@ __global__ __launch_bounds__(256, 2) void k_rows(float* __restrict__ p, size_t n
     } while (tile < ntiles);
 }
 
+// Variants of the same pattern: MODE 1 gives each XCD (work-groups are
+// dealt round-robin to 8 of them) a contiguous share of the tiles; MODE 2
+// rotates each wave's row order by its tile number; WAVES 8 makes 2 KiB row
+// runs per work-group.
+template <int MODE, int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_rows_v(float* __restrict__ p, size_t ntiles, int tshift, float s) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    f2* q = reinterpret_cast<f2*>(p);
+    const int lane = threadIdx.x & 63, col = lane & 31, h = lane >> 5;
+    const size_t waves = (size_t)gridDim.x * WAVES;
+    size_t wid = (size_t)blockIdx.x * WAVES + (threadIdx.x >> 6);
+    if (MODE == 1) {  // work-group b runs on XCD b % 8: renumber so that each XCD's waves are consecutive
+        const size_t per = gridDim.x / 8;
+        wid = ((blockIdx.x % 8) * per + blockIdx.x / 8) * WAVES + (threadIdx.x >> 6);
+    }
+    size_t tile = wid;
+    if (tile >= ntiles) return;
+    const size_t last = ntiles - 1;
+    auto addr = [&](size_t t, int j) {
+        const int r = MODE == 2 ? ((j + (int)(t & 31)) & 31) : j;
+        return t * 32 + col + ((size_t)(r | (h << 5)) << tshift);
+    };
+    f2 B[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) B[j] = q[addr(tile, j)];
+    do {
+        const size_t nxt = tile + waves < last ? tile + waves : last;
+        f2 Bn[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) Bn[j] = q[addr(nxt, j)];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) q[addr(tile, j)] = B[j] * s;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) B[j] = Bn[j];
+        tile += waves;
+    } while (tile < ntiles);
+}
+
 template <typename F>
 static float time_ms(F f, int reps) {
     hipEvent_t e0, e1;
@@ -148,6 +186,17 @@ int main(int argc, char** argv) {
             const float t = time_ms([&] { hipLaunchKernelGGL(k_rows, dim3(grid), dim3(256), 0, 0, (float*)a, ntiles,
                                                              na - 6, 1.0f); }, reps);
             std::printf("rows     k=6 top grid %6u  %7.3f ms  %7.0f GB/s\n", grid, t, 2 * gb / t * 1e3);
+        }
+        for (unsigned grid : {512u, 1024u, 2048u}) {
+            float t = time_ms([&] { hipLaunchKernelGGL((k_rows_v<1, 4>), dim3(grid), dim3(256), 0, 0, (float*)a,
+                                                       ntiles, na - 6, 1.0f); }, reps);
+            std::printf("rows xcd k=6 top grid %6u  %7.3f ms  %7.0f GB/s\n", grid, t, 2 * gb / t * 1e3);
+            t = time_ms([&] { hipLaunchKernelGGL((k_rows_v<2, 4>), dim3(grid), dim3(256), 0, 0, (float*)a, ntiles,
+                                                 na - 6, 1.0f); }, reps);
+            std::printf("rows rot k=6 top grid %6u  %7.3f ms  %7.0f GB/s\n", grid, t, 2 * gb / t * 1e3);
+            t = time_ms([&] { hipLaunchKernelGGL((k_rows_v<0, 8>), dim3(grid / 2), dim3(512), 0, 0, (float*)a,
+                                                 ntiles, na - 6, 1.0f); }, reps);
+            std::printf("rows 8w  k=6 top grid %6u  %7.3f ms  %7.0f GB/s\n", grid / 2, t, 2 * gb / t * 1e3);
         }
     }
     for (unsigned grid : {8192u, 32768u, 65536u}) {
