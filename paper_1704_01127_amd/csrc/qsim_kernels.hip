@@ -1890,7 +1890,7 @@ __global__ __launch_bounds__(256) void k_init_cluster(typename Cplx<T>::type* __
         // column are neighbours; otherwise columns 2c, 2c + 1 differ in bit 0 only
         // and a thread writes both, side by side.
         if (g.t[0] == 0) {
-            for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < g.ncols; c += stride) {
+            for (uint64_t c = (uint64_t)xcd_block() * 256 + threadIdx.x; c < g.ncols; c += stride) {
                 const uint64_t base = deposit_cols<K>(c, g);
                 ColFactor<T> f{0u, 0u, T(1), T(0)};
                 if (has_epi) f = col_factor<T>(epi, base);
@@ -1908,7 +1908,7 @@ __global__ __launch_bounds__(256) void k_init_cluster(typename Cplx<T>::type* __
             return;
         }
         if (g.ncols >= 2) {
-            for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < g.ncols / 2; c += stride) {
+            for (uint64_t c = (uint64_t)xcd_block() * 256 + threadIdx.x; c < g.ncols / 2; c += stride) {
                 const uint64_t base = deposit_cols<K>(2 * c, g);  // bit 0 clear; column 2c + 1 is base | 1
                 ColFactor<T> f0{0u, 0u, T(1), T(0)}, f1 = f0;
                 if (has_epi) {
@@ -1931,7 +1931,7 @@ __global__ __launch_bounds__(256) void k_init_cluster(typename Cplx<T>::type* __
     }
     // one thread per column (assignment of the non-target bits): its diagonal
     // factor once, then the column's 2^k amplitudes
-    for (uint64_t c = (uint64_t)blockIdx.x * 256 + threadIdx.x; c < g.ncols; c += stride) {
+    for (uint64_t c = (uint64_t)xcd_block() * 256 + threadIdx.x; c < g.ncols; c += stride) {
         const uint64_t base = deposit_cols<K>(c, g);
         ColFactor<T> f{0u, 0u, T(1), T(0)};
         if (has_epi) f = col_factor<T>(epi, base);
@@ -2164,7 +2164,7 @@ __global__ __launch_bounds__(256) void k_stats(const typename Cplx<T>::type* __r
         }
         if (probs) probs[i] = (P)pr;
     };
-    uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    uint64_t i = (uint64_t)xcd_block() * 256 + threadIdx.x;  // any bijection: partials stay per work-group
     for (; i + (kRedU - 1) * stride < count; i += kRedU * stride) {
         V a[kRedU];
 #pragma unroll
