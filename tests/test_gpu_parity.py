@@ -577,6 +577,30 @@ def test_30q_product_state_sampled(dt, opts):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("opts", [dict(kmax=6, scheduler="learned", fuse_diag=True, skip_initial_h=True),
+                                  dict(kmax=5, fuse_diag=True)])
+def test_34q_product_state_sampled(opts):
+    """34 qubits (the largest complex64 state: 128 GiB) in six independent
+    groups interleaved across all bit positions (qubit q in group q mod 6),
+    run in the benchmark's form and at k <= 5; 65536 sampled amplitudes
+    against the oracle's exact products."""
+    groups = [[q for q in range(34) if q % 6 == r] for r in range(6)]
+    circ = blocked_circuit(34, groups, 18, seed=5)
+    s = make_state(34, "c64")
+    s.run_circuit(circ.gates, **opts)
+    s.sync()
+    rng = np.random.default_rng(1)
+    idx = np.concatenate([rng.integers(0, 2 ** 34, 65536 - 2), [0, 2 ** 34 - 1]]).astype(np.int64)
+    ref = _product_amplitudes(circ, groups, idx)
+    got = s.amps[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.complex128)
+    err = np.max(np.abs(got - ref))
+    assert err <= 2e-5 * np.max(np.abs(ref)), err
+    norm, _, _ = s.probs()
+    assert abs(norm - 1) <= 1e-5
+    del s
+    torch.cuda.empty_cache()
+
+
 def test_30q_depth25_mirror_float32():
     """5x6 grid, depth 25, followed by its inverse: the float32 fused run must
     return to |0...0> (the workload the benchmark times)."""
