@@ -695,10 +695,11 @@ struct StageF32 {
     static constexpr int HX = (1 << K) / 2;
     static constexpr int NB = (1 << C) / 32;
     static constexpr int NL = (1 << (K + C)) / 128;
-    __device__ __forceinline__ static void load_lin(const g_float2* __restrict__ psi, uint64_t b0,
-                                                    const StageGeom& sg, vf4 (&R)[NL]) {
+    // t0: the tile's base (uniform in the wave); lane_off: the lane's bits
+    __device__ __forceinline__ static void load_lin(const g_float2* __restrict__ psi, uint64_t t0,
+                                                    uint64_t lane_off, const StageGeom& sg, vf4 (&R)[NL]) {
 #pragma unroll
-        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const g_vf4*>(psi + (b0 | sg.ioff[i]));
+        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const g_vf4*>(psi + ((t0 | sg.ioff[i]) | lane_off));
     }
     __device__ __forceinline__ static void stage_in(vf4* L4, int lane, const int (&tc)[NB], int th,
                                                     const StageGeom& sg, const vf4 (&R)[NL],
@@ -773,15 +774,18 @@ __device__ __forceinline__ void staged_f32_tiles(g_float2* __restrict__ psi, con
     if (tile >= ntiles) return;
     const uint64_t last = ntiles - 1;
     vf4 R[NL];
-    StageF32<K, C, LOWT>::load_lin(psi, tile_base<NT>(tile, sg) | lane_off, sg, R);
+    StageF32<K, C, LOWT>::load_lin(psi, tile_base<NT>(tile, sg), lane_off, sg, R);
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_sched_barrier(0);
     float B[NB][2 * HX];
     StageF32<K, C, LOWT>::stage_in(L4, lane, tc, th, sg, R, B);
     do {
+        // the lane offset stays one value: the 16 chunk addresses built from it
+        // are recomputed (an OR each) instead of held across the loop
+        asm volatile("" : "+v"(lane_off));
         const uint64_t nxt = tile + stride < last ? tile + stride : last;
-        StageF32<K, C, LOWT>::load_lin(psi, tile_base<NT>(nxt, sg) | lane_off, sg, R);
+        StageF32<K, C, LOWT>::load_lin(psi, tile_base<NT>(nxt, sg), lane_off, sg, R);
         __builtin_amdgcn_sched_barrier(0);
 
         floatx16 acc[NB][RB];
@@ -833,13 +837,10 @@ __device__ __forceinline__ void staged_f32_tiles(g_float2* __restrict__ psi, con
                         vf4{O[nb][2 * j], O[nb][2 * j + 1], O[nb][2 * j + 2], O[nb][2 * j + 3]};
         }
         wave_lds_fence();
-        {
-            const uint64_t b0 = tb0 | lane_off;
 #pragma unroll
-            for (int i = 0; i < NL; ++i) {
-                const vf4 v = L4[i * 64 + lane];
-                *reinterpret_cast<g_vf4*>(psi + (b0 | sg.ioff[i])) = v;
-            }
+        for (int i = 0; i < NL; ++i) {
+            const vf4 v = L4[i * 64 + lane];
+            *reinterpret_cast<g_vf4*>(psi + ((tb0 | sg.ioff[i]) | lane_off)) = v;
         }
         wave_lds_fence();
         StageF32<K, C, LOWT>::stage_in(L4, lane, tc, th, sg, R, B);
@@ -862,7 +863,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_stage(float2* __restrict
     __shared__ vf4 Ls[4][TILE / 2];
     load_matrix<RB * S * 64, 256>(As, reinterpret_cast<const vf4*>(Ap));
     __syncthreads();
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile bases are scalar
     staged_f32_tiles<K, C, LOWT>((g_float2*)psi, As, Ls[w], (c_epi*)epi, sg, (uint64_t)xcd_block() * 4 + w,
                                  g.ncols >> C, (uint64_t)gridDim.x * 4);
 }
@@ -872,10 +873,11 @@ struct StageF64 {
     static constexpr int HX = (1 << K) / 4;
     static constexpr int NB = (1 << C) / 16;
     static constexpr int NL = (1 << (K + C)) / 64;
-    __device__ __forceinline__ static void load_lin(const vd2* __restrict__ psi, uint64_t b0,
+    // t0: the tile's base (uniform in the wave); lane_off: the lane's bits
+    __device__ __forceinline__ static void load_lin(const vd2* __restrict__ psi, uint64_t t0, uint64_t lane_off,
                                                     const StageGeom& sg, vd2 (&R)[NL]) {
 #pragma unroll
-        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const vd2*>(psi + (b0 | sg.ioff[i]));
+        for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const vd2*>(psi + ((t0 | sg.ioff[i]) | lane_off));
     }
     __device__ __forceinline__ static void stage_in(vd2* L, int lane, const int (&tc)[NB], int tq,
                                                     const StageGeom& sg, const vd2 (&R)[NL],
@@ -916,7 +918,8 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd
     load_matrix<RB * S * 64, THREADS>(As, reinterpret_cast<const vf4*>(Ap));
     __syncthreads();
 
-    const int lane = threadIdx.x & 63, p = lane & 15, q = lane >> 4, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, p = lane & 15, q = lane >> 4,
+              w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile bases are scalar
     vd2* L = Ls[w];
     uint64_t lane_off = 0;
 #pragma unroll
@@ -939,15 +942,16 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd
     if (tile >= ntiles) return;
     const uint64_t last = ntiles - 1;
     vd2 R[NL];
-    StageF64<K, C>::load_lin(psi, tile_base<NT>(tile, sg) | lane_off, sg, R);
+    StageF64<K, C>::load_lin(psi, tile_base<NT>(tile, sg), lane_off, sg, R);
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_sched_barrier(0);
     double B[NB][2 * HX];
     StageF64<K, C>::stage_in(L, lane, tc, tq, sg, R, B);
     do {
+        asm volatile("" : "+v"(lane_off));  // chunk addresses recomputed, not held across the loop
         const uint64_t nxt = tile + stride < last ? tile + stride : last;
-        StageF64<K, C>::load_lin(psi, tile_base<NT>(nxt, sg) | lane_off, sg, R);
+        StageF64<K, C>::load_lin(psi, tile_base<NT>(nxt, sg), lane_off, sg, R);
         __builtin_amdgcn_sched_barrier(0);
 
         doublex4 acc[NB][RB];
@@ -983,9 +987,8 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd
         }
         wave_lds_fence();
         {
-            const uint64_t b0 = tb0 | lane_off;
 #pragma unroll
-            for (int i = 0; i < NL; ++i) *reinterpret_cast<vd2*>(psi + (b0 | sg.ioff[i])) = L[i * 64 + lane];
+            for (int i = 0; i < NL; ++i) *reinterpret_cast<vd2*>(psi + ((tb0 | sg.ioff[i]) | lane_off)) = L[i * 64 + lane];
         }
         wave_lds_fence();
         StageF64<K, C>::stage_in(L, lane, tc, tq, sg, R, B);
@@ -1433,13 +1436,6 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
                 const int i = ph * (NL / 2) + ii;
                 L4[((lin ^ lds_slot<true>(128 * i)) & 1023) >> 1] = R[i];
             }
-            if (ph == 1) {
-                // the tile is in LDS: prefetch the next one
-                const uint64_t nxt = tile + stride < last ? tile + stride : last;
-                __builtin_amdgcn_sched_barrier(0);
-                load_tile(tile_base<NT>(nxt, sg));
-                __builtin_amdgcn_sched_barrier(0);
-            }
             wave_lds_fence();
             if (lph == ph) {
                 if (LOWT) {
@@ -1476,6 +1472,12 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
                 xh[st][i] = hi;
                 xl[st][i] = (_Float16)(v - (float)hi);
             }
+        // the column is in registers: prefetch the next tile (issued here, the
+        // peak register use is the halves + accumulators + the tile in flight)
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        __builtin_amdgcn_sched_barrier(0);
+        load_tile(tile_base<NT>(nxt, sg));
+        __builtin_amdgcn_sched_barrier(0);
         const uint64_t tb0 = tile_base<NT>(tile, sg);
         floatx16 acc[RB];
 #pragma unroll
