@@ -926,12 +926,8 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd
     for (int b = 0; b < 6; ++b)
         if ((lane >> b) & 1) lane_off |= uint64_t(1) << sg.tb[b];
     int tc[NB];
-    uint64_t cbits[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        tc[nb] = tau_of_column<C>(p + 16 * nb, sg);
-        cbits[nb] = state_bits_of_column<C>(p + 16 * nb, sg);
-    }
+    for (int nb = 0; nb < NB; ++nb) tc[nb] = tau_of_column<C>(p + 16 * nb, sg);
     const int tq = ((q & 1) << sg.tpos[K - 2]) | ((q >> 1) << sg.tpos[K - 1]);
     const uint64_t ntiles = g.ncols >> C;
     const uint64_t stride = (uint64_t)gridDim.x * WAVES;
@@ -977,7 +973,9 @@ __global__ __launch_bounds__(THREADS, 512 / THREADS) void k_cluster_f64_stage(vd
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             ColFactor<double> f{0u, 0u, 1.0, 0.0};
-            if (has_epi) f = col_factor<double>(epi, tb0 | cbits[nb]);
+            // the column's state bits are rebuilt here (a few scalar-indexed
+            // ORs) rather than held across the loop, where they were spilled
+            if (has_epi) f = col_factor<double>(epi, tb0 | state_bits_of_column<C>(p + 16 * nb, sg));
 #pragma unroll
             for (int j = 0; j < HX; ++j) {
                 double re = acc[nb][j / 2][2 * (j % 2)], im = acc[nb][j / 2][2 * (j % 2) + 1];
