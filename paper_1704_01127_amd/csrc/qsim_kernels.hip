@@ -1793,7 +1793,7 @@ __global__ __launch_bounds__(256) void k_gate1q(typename Cplx<T>::type* __restri
     using V = typename Cplx<T>::type;
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     const uint64_t bit = uint64_t(1) << q;
-    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < npairs; p += stride) {
+    for (uint64_t p = (uint64_t)xcd_block() * 256 + threadIdx.x; p < npairs; p += stride) {
         const uint64_t i = insert_zero(p, q);
         const V a = psi[i], b = psi[i | bit];
         V o0, o1;
@@ -1813,7 +1813,7 @@ __global__ __launch_bounds__(256) void k_phase1q(typename Cplx<T>::type* __restr
     using V = typename Cplx<T>::type;
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     const uint64_t bit = uint64_t(1) << q;
-    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < nhalf; p += stride) {
+    for (uint64_t p = (uint64_t)xcd_block() * 256 + threadIdx.x; p < nhalf; p += stride) {
         const uint64_t i = insert_zero(p, q) | bit;
         const V a = psi[i];
         V o;
@@ -1830,7 +1830,7 @@ __global__ __launch_bounds__(256) void k_cz(typename Cplx<T>::type* __restrict__
     using V = typename Cplx<T>::type;
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     const uint64_t m = (uint64_t(1) << a) | (uint64_t(1) << b);
-    for (uint64_t p = (uint64_t)blockIdx.x * 256 + threadIdx.x; p < nquarter; p += stride) {
+    for (uint64_t p = (uint64_t)xcd_block() * 256 + threadIdx.x; p < nquarter; p += stride) {
         const uint64_t i = insert_zero(insert_zero(p, a), b) | m;
         V v = psi[i];
         v.x = -v.x;

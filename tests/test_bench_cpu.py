@@ -1,0 +1,39 @@
+"""Host-side checks of the benchmark script: it refuses more than one GPU
+before touching the GPU, and it names the kernel each recorded launch used
+(the roofline's dominant kernel is matched to the profiled one by name)."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_module", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_kernel_names_of_launch_records():
+    b = _bench()
+    rec = lambda k, q, **f: dict(kind=f.pop("kind", "cluster"), k=k, qubits=q, **f)
+    assert b.kernel_name(rec(6, [1, 3, 9, 12, 20, 25], mfma=True)) == "k_cluster_f32_split6<false>"
+    assert b.kernel_name(rec(6, [0, 3, 9, 12, 20, 25], mfma=True)) == "k_cluster_f32_split6<true>"
+    assert b.kernel_name(rec(6, [1, 2, 3, 4, 7, 14], mfma=True, staged=True)) == "k_cluster_f32_split6s<false>"
+    assert b.kernel_name(rec(6, [0, 1, 2, 3, 21, 22], mfma=True, staged=True)) == "k_cluster_f32_split6s<true>"
+    assert b.kernel_name(rec(4, [18, 20, 24, 26], mfma=True, staged=True)) == "k_cluster_f32_stage<4, 6, false>"
+    assert b.kernel_name(rec(5, [0, 9, 14, 16, 26], mfma=True)) == "k_cluster_f32_mfma<5, 2, true>"
+    assert b.kernel_name(rec(3, [2, 5, 9])) == "k_cluster_valu<float, 3>"
+    assert b.kernel_name(rec(6, [1, 3, 9, 12, 20, 25], mfma=True), k6_kernel=1) == "k_cluster_f32_gauss6<false>"
+    pair = rec(5, [0, 1, 2, 3, 4, 5, 6, 7, 8, 9], kind="pair")
+    assert b.kernel_name(pair) == "k_cluster_f32_multi<2, 8>"
+    assert b.kernel_name(pair, pair_tile=10) == "k_cluster_f32_pair10<12>"
