@@ -152,7 +152,7 @@ struct BatchItem {
     uint32_t op;
     uint32_t tile0;        // tiles [tile0, tile0 + item_tiles) of the op
 };
-extern int g_batch_grid;        // work-groups of the batch launch, 0 = two per CU
+extern int g_batch_grid;        // work-groups of the batch launch, 0 = one per CU (its occupancy)
 extern int g_batch_pad;         // padding qubits: 0 lowest outside the cluster, 1 highest
 extern int g_batch_item_tiles;  // tiles of 2^11 amplitudes per work item
 extern int g_k6_kernel;         // float k = 6 clusters: 0 fp32 real-split, 1 fp32 three-product, 2 fp16 halves
