@@ -193,9 +193,11 @@ const char* qsim_last_error(void);
  * set, measured with HIP events on the state's stream. For each launch, in
  * order: op_kind (0 cluster, 1 diagonal pass, 2 single-qubit gate, 3
  * single-qubit phase, 4 CZ, 5 cluster-matrix build, 6 uniform initialisation
- * written together with the first cluster, 7 two clusters in one pass),
- * op_k (cluster size - 5 for a pair; number of matrices for a build),
- * op_qubits[6*i ..] (sorted targets of a cluster - of the first for a pair -
+ * written together with the first cluster, 7 two clusters in one pass, 8 the
+ * uniform initialisation and the first two clusters in one pass),
+ * op_k (cluster size - 5 for a pair, 6 for kind 8; number of matrices for a build),
+ * op_qubits[6*i ..] (sorted targets of a cluster - of the first for a pair,
+ * of the second for kind 8 -
  * or the gate's qubits, -1 padded), op_epi (flags of a cluster: bit 0 = applies diagonal
  * gates while storing, bit 1 = LDS-staged kernel variant, bit 2 = matrix-core
  * kernel) and ms (milliseconds). Arrays of cap entries (any may be NULL);
@@ -223,10 +225,13 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * the fp32 three-multiplication complex product, 2 (default) fp16 matrix
  * cores on hi / lo halves of the operands (about 2^-21 relative error, the
  * size of fp32 rounding),
- * read when a cluster is enqueued. QSIM_OPT_FOLD_INIT (default 1): when a
- * run starts from the uniform state (skip_initial_h) with a cluster, that
- * state and the cluster - a product state again - are written in one pass
- * instead of an initialisation pass and a cluster pass. QSIM_OPT_PAIR
+ * read when a cluster is enqueued. QSIM_OPT_FOLD_INIT (default 2): when a
+ * run starts from the uniform state (skip_initial_h) with a cluster, 1
+ * writes that state and the cluster - a product state again - in one pass
+ * instead of an initialisation pass and a cluster pass; 2 also takes in the
+ * second op when it is a 6-qubit cluster on a complex64 state: its inputs are
+ * computed from that closed form instead of read, so one write-only pass
+ * stands for three; 0 keeps them apart. QSIM_OPT_PAIR
  * (default 0): on complex64 states of >= 11 qubits, two consecutive clusters
  * of <= 5 qubits are applied in one pass over the state (their qubits fit one
  * tile held in LDS; fp16 matrix cores on operand halves); 2 sends every such

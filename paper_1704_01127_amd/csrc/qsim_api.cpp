@@ -71,7 +71,7 @@ int g_batch_grid = 0;
 int g_batch_pad = 0;
 int g_batch_item_tiles = 128;
 int g_k6_kernel = 2;
-int g_fold_init = 1;
+int g_fold_init = 2;
 int g_pair = 0;
 int g_pair_tile = 11;
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
@@ -206,7 +206,8 @@ struct Chunk {
     std::vector<EpiDesc> epis;
     struct Item {
         int kind;        // 0 cluster, 1 diag pass, 2 gate1q, 3 phase1q, 4 cz, 6 uniform init + cluster,
-                         // 7 two 5-qubit clusters in one pass
+                         // 7 two 5-qubit clusters in one pass, 8 uniform init + two clusters
+                         // (geom2 / slot2 / epi2: the first one)
         ClusterGeom geom;
         int layout;
         int slot;        // matrix slot (cluster)
@@ -288,7 +289,7 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
         std::memset(&r, 0, sizeof(r));
         r.kind = it.kind;
         const int variant = it.kind == 0 ? cluster_variant_for(s->dbl, it.geom, it.layout) : 0;
-        if (it.kind == 0 || it.kind == 6 || it.kind == 7) {
+        if (it.kind == 0 || it.kind == 6 || it.kind == 7 || it.kind == 8) {
             r.k = it.geom.k;
             for (int j = 0; j < it.geom.k; ++j) r.qubits[j] = it.geom.t[j];
             r.flags = (it.epi >= 0 ? 1 : 0) | (variant == 1 ? 2 : 0) | (it.layout != LAYOUT_PLAIN ? 4 : 0);
@@ -311,6 +312,10 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
             case 6:
                 e = launch_init_cluster(s->psi, s->dbl, it.geom, mats + it.slot * sb,
                                         it.epi >= 0 ? epis + it.epi : nullptr, s->st);
+                break;
+            case 8:
+                e = launch_fold2(s->psi, it.geom, mats + it.slot * sb, it.epi >= 0 ? epis + it.epi : nullptr,
+                                 it.epi2 >= 0 ? epis + it.epi2 : nullptr, it.geom2, mats + it.slot2 * sb, s->st);
                 break;
             case 7: {
                 int32_t t[2][5];
@@ -399,6 +404,84 @@ qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, con
     if (e.n_cc || e.n_mix || e.n_ph) {
         it.epi = (int)c.epis.size();
         c.epis.push_back(e);
+    }
+    c.items.push_back(it);
+    return QSIM_OK;
+}
+
+// The uniform start and the first two clusters A and B (B: 6 qubits, complex64,
+// fp16-halves layout) in one write-only pass. A's matrix is built plain in
+// complex128 without its epilogue; the epilogue is split relative to B's
+// targets: terms on B's targets join B's matrix ahead of B's gates, the rest
+// becomes a descriptor read per column of B.
+qsim_status add_fold2(qsim_state_s* s, Chunk& c, const SOp& A, const SOp& B, const qsim_gate* gates) {
+    size_t dense_need = 0, ng = 0;
+    for (const SOp* op : {&A, &B}) {
+        for (int gi : op->members) if (gates[gi].kind == G_DENSE) dense_need += size_t(2) << (2 * gates[gi].k);
+        ng += op->members.size() + op->epi.size();
+    }
+    const size_t need = align256((c.bops.size() + 2) * sizeof(BuildOp)) +
+                        align256((c.bgates.size() + ng) * sizeof(BuildGate)) +
+                        align256((c.dense.size() + dense_need) * sizeof(double)) +
+                        align256((c.epis.size() + 2) * sizeof(EpiDesc));
+    if (c.slots_used + 2 > kSlots || need > kDescBytes) {
+        qsim_status r = flush(s, c);
+        if (r != QSIM_OK) return r;
+    }
+    const int64_t sb = (int64_t)slot_bytes(s->dbl, s->kmax_ws);
+    // A: plain complex128, its member gates only
+    int posA[64], posB[64];
+    for (int i = 0; i < 64; ++i) posA[i] = posB[i] = -1;
+    for (int j = 0; j < A.k; ++j) posA[A.qubits[j]] = j;
+    for (int j = 0; j < B.k; ++j) posB[B.qubits[j]] = j;
+    BuildOp ba;
+    std::memset(&ba, 0, sizeof(ba));
+    ba.k = A.k;
+    ba.gate0 = (int)c.bgates.size();
+    ba.is_double = 1;
+    ba.layout = LAYOUT_PLAIN;
+    const int slotA = c.slots_used++;
+    ba.out_off = slotA * sb;
+    for (int gi : A.members) c.bgates.push_back(to_build_gate(gates[gi], posA, c.dense));
+    ba.n_gates = (int)c.bgates.size() - ba.gate0;
+    c.bops.push_back(ba);
+    // B: A's epilogue terms on B's targets, B's gates, B's own epilogue terms on its targets
+    BuildOp bb;
+    std::memset(&bb, 0, sizeof(bb));
+    bb.k = B.k;
+    bb.gate0 = (int)c.bgates.size();
+    bb.is_double = 0;
+    bb.layout = LAYOUT_SPLIT16F;
+    const int slotB = c.slots_used++;
+    bb.out_off = slotB * sb;
+    EpiDesc e1, e2;
+    if (qsim_status r = split_epilogue(posB, gates, A.epi, c.bgates, c.dense, e1)) return r;
+    for (int gi : B.members) c.bgates.push_back(to_build_gate(gates[gi], posB, c.dense));
+    if (qsim_status r = split_epilogue(posB, gates, B.epi, c.bgates, c.dense, e2)) return r;
+    bb.n_gates = (int)c.bgates.size() - bb.gate0;
+    c.bops.push_back(bb);
+    Chunk::Item it;
+    std::memset(&it, 0, sizeof(it));
+    it.kind = 8;
+    it.layout = LAYOUT_SPLIT16F;
+    for (int j = 0; j < B.k; ++j) it.geom.t[j] = B.qubits[j];
+    it.geom.n = s->n;
+    it.geom.k = B.k;
+    it.geom.ncols = uint64_t(1) << (s->n - B.k);
+    for (int j = 0; j < A.k; ++j) it.geom2.t[j] = A.qubits[j];
+    it.geom2.n = s->n;
+    it.geom2.k = A.k;
+    it.geom2.ncols = uint64_t(1) << (s->n - A.k);
+    it.slot = slotB;
+    it.slot2 = slotA;
+    it.epi = it.epi2 = -1;
+    if (e2.n_cc || e2.n_mix || e2.n_ph) {
+        it.epi = (int)c.epis.size();
+        c.epis.push_back(e2);
+    }
+    if (e1.n_cc || e1.n_mix || e1.n_ph) {
+        it.epi2 = (int)c.epis.size();
+        c.epis.push_back(e1);
     }
     c.items.push_back(it);
     return QSIM_OK;
@@ -716,8 +799,11 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
         qsim_state_s* s;
         ~RecOff() { s->recording = false; }
     } rec_off{s};
-    // the uniform start and a leading cluster are written in one pass
+    // the uniform start and a leading cluster are written in one pass; with a
+    // second cluster of 6 qubits (complex64, fp16-halves kernel) that one too
     const bool fold = S.uniform_init && g_fold_init && !S.ops.empty() && S.ops[0].kind == OP_CLUSTER;
+    const bool fold2 = fold && g_fold_init == 2 && !s->dbl && S.ops.size() >= 2 && S.ops[1].kind == OP_CLUSTER &&
+                       S.ops[1].k == 6 && cluster_layout(false, 6, s->n) == LAYOUT_SPLIT16F;
     // consecutive clusters of <= 5 qubits on a complex64 state go in pairs
     const bool pairing = g_pair && !s->dbl && s->n >= 11 && s->kmax_ws >= 5 && so.mode != 0;
     auto small = [&](size_t i) { return S.ops[i].kind == OP_CLUSTER && S.ops[i].k <= 5; };
@@ -726,7 +812,14 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     for (size_t oi = 0; oi < S.ops.size(); ++oi) {
         const SOp& op = S.ops[oi];
         qsim_status r = QSIM_OK;
-        if (oi == 0 && fold) {
+        if (oi == 0 && fold2) {
+            const SOp& op2 = S.ops[1];
+            r = add_fold2(s, c, op, op2, gates);
+            st.n_clusters_by_k[op.k]++;
+            st.n_clusters_by_k[op2.k]++;
+            st.n_gates_fused_epilogue += (int)(op.epi.size() + op2.epi.size());
+            ++oi;
+        } else if (oi == 0 && fold) {
             r = add_cluster(s, c, op.k, op.qubits, gates, op.members, op.epi, true);
             st.n_clusters_by_k[op.k]++;
             st.n_gates_fused_epilogue += (int)op.epi.size();
@@ -832,7 +925,7 @@ qsim_status qsim_set_option(int option, int value) {
         return QSIM_OK;
     }
     if (option == QSIM_OPT_FOLD_INIT) {
-        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "fold_init must be 0 or 1");
+        if (value < 0 || value > 2) return fail(QSIM_E_INVALID, "fold_init must be 0, 1 or 2");
         g_fold_init = value;
         return QSIM_OK;
     }

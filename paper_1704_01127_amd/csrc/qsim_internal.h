@@ -179,6 +179,12 @@ hipError_t launch_multi(void* psi, int n, int m, const int32_t (*targets)[5], co
                         const EpiDesc* const* epis, hipStream_t st);
 // The uniform state followed by one cluster (matrix: plain complex128 layout)
 // and its diagonal epilogue, written in one pass.
+// The uniform start, a first cluster (g1: plain complex128 matrix mat1) with
+// its epilogue expressed relative to the second cluster's targets (epi1), and
+// a second 6-qubit cluster (g2, LAYOUT_SPLIT16F, its own epilogue epi2), in one
+// write-only pass over a complex64 state of n >= 11 qubits.
+hipError_t launch_fold2(void* psi, const ClusterGeom& g2, const void* mat2, const EpiDesc* epi2, const EpiDesc* epi1,
+                        const ClusterGeom& g1, const void* mat1, hipStream_t st);
 hipError_t launch_init_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, const EpiDesc* epi,
                                hipStream_t st);
 hipError_t launch_build(const BuildOp* ops, int n_ops, const BuildGate* gates, const double* dense,

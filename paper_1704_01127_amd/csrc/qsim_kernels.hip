@@ -1364,15 +1364,30 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_cluster_f32_pair10(float2* __
 // One wave applies the cluster whose fp16 matrix halves are in LDS (Ah, Al)
 // to tiles tile, tile + stride, ... < tile_end (tile numbers uniform in the
 // wave), staging through its 8 KiB LDS buffer L.
-template <bool LOWT>
+//
+// FOLD: the input is not loaded but computed - the state after the uniform
+// start, a first cluster and its diagonal epilogue (see k_fold2_f32).
+struct FoldIn {
+    const float2* W;  // LDS: w over the first cluster's qubits (bit m of the index: its qubit m)
+    int ymask[6];     // per row bit (this cluster's target m): the w-index bit it sets, 0 if none
+    int t1[6];        // the first cluster's qubits
+    int k1;
+    c_epi* epi1;      // the first epilogue relative to this cluster's targets, or null
+};
+
+template <bool LOWT, bool FOLD = false>
 __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const half8* Ah, const half8* Al, float2* L,
                                               c_epi* __restrict__ epi, const StageGeom& sg, uint64_t tile,
-                                              uint64_t tile_end, uint64_t stride) {
+                                              uint64_t tile_end, uint64_t stride, const FoldIn* fin = nullptr) {
     constexpr int K = 6, C = 5, NT = K + C, HX = 32, RB = 4, S = 8, NL = 16;
     const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     vf4* L4 = reinterpret_cast<vf4*>(L);
-    const bool has_epi = epi != nullptr;
-    const bool has_ph = has_epi && epi->n_ph > 0;
+    bool has_epi = epi != nullptr;
+    bool has_ph = has_epi && epi->n_ph > 0;
+    if constexpr (FOLD) {
+        has_epi = has_epi || fin->epi1 != nullptr;
+        has_ph = has_ph || (fin->epi1 != nullptr && fin->epi1->n_ph > 0);
+    }
     uint64_t lane_off = 0;  // state offset of tile bits 1..6 (the lane of a linear load)
 #pragma unroll
     for (int b = 0; b < 6; ++b)
@@ -1415,18 +1430,46 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
 #pragma unroll
         for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const g_vf4*>(gpsi + ((t0 | ioff(i)) | lane_off));
     };
-    load_tile(tile_base<NT>(tile, sg));
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (!FOLD) {
+        load_tile(tile_base<NT>(tile, sg));
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_sched_barrier(0);
+    }
     do {
         // per-lane bases stay in place: the 16 chunk addresses derived from them
         // are recomputed (one OR / XOR each) instead of held across the loop
         asm volatile("" : "+v"(lane_off), "+v"(lin), "+v"(lslot), "+v"(h5));
         asm volatile("" : "+s"(rmask[0]), "+s"(rmask[1]), "+s"(rmask[2]), "+s"(rmask[3]), "+s"(rmask[4]));
         asm volatile("" : "+s"(imask[0]), "+s"(imask[1]), "+s"(imask[2]), "+s"(imask[3]));
-        // tile -> LDS, half by half; each lane reads its column in its half
         float X[2 * HX];
+        ColFactor<float> f1{0u, 0u, 1.0f, 0.0f};
+        if constexpr (FOLD) {
+            // the column's inputs from the closed form: w at the first cluster's
+            // index (its qubits among the column bits, then among the row bits),
+            // negated where a gate of the first epilogue couples a row bit with
+            // a column bit; the column-only factor of that epilogue joins the
+            // output factor
+            const uint64_t base = tile_base<NT>(tile, sg) | cbits;
+            int ic = 0;
+#pragma unroll
+            for (int m = 0; m < 6; ++m)
+                if (m < fin->k1) ic |= (int)((base >> fin->t1[m]) & 1) << m;
+            if (fin->epi1 != nullptr) f1 = col_factor<float>(fin->epi1, base);
+            const int yh = h ? fin->ymask[K - 1] : 0;
+#pragma unroll
+            for (int j = 0; j < HX; ++j) {
+                int iy = yh;
+#pragma unroll
+                for (int b = 0; b < K - 1; ++b)
+                    if ((j >> b) & 1) iy |= fin->ymask[b];
+                const float2 v = fin->W[ic | iy];
+                const bool neg = (__popc(((uint32_t)j | h5) & f1.w) & 1u) != 0;
+                X[2 * j] = neg ? -v.x : v.x;
+                X[2 * j + 1] = neg ? -v.y : v.y;
+            }
+        } else {
+        // tile -> LDS, half by half; each lane reads its column in its half
 #pragma unroll
         for (int ph = 0; ph < 2; ++ph) {
 #pragma unroll
@@ -1452,6 +1495,7 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
             }
             wave_lds_fence();
         }
+        }
         // fp16 halves of the scaled column (shared scale with lane p + 32)
         uint32_t mb = 0;
 #pragma unroll
@@ -1472,10 +1516,12 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
             }
         // the column is in registers: prefetch the next tile (issued here, the
         // peak register use is the halves + accumulators + the tile in flight)
-        const uint64_t nxt = tile + stride < last ? tile + stride : last;
-        __builtin_amdgcn_sched_barrier(0);
-        load_tile(tile_base<NT>(nxt, sg));
-        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (!FOLD) {
+            const uint64_t nxt = tile + stride < last ? tile + stride : last;
+            __builtin_amdgcn_sched_barrier(0);
+            load_tile(tile_base<NT>(nxt, sg));
+            __builtin_amdgcn_sched_barrier(0);
+        }
         const uint64_t tb0 = tile_base<NT>(tile, sg);
         floatx16 acc[RB];
 #pragma unroll
@@ -1498,7 +1544,14 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
 #pragma unroll
         for (int j = 0; j < 2 * HX; ++j) X[j] = acc[j / 16][j % 16] * unscale;
         if (has_epi) {
-            const ColFactor<float> f = col_factor<float>(epi, tb0 | cbits);
+            ColFactor<float> f{0u, 0u, 1.0f, 0.0f};
+            if (epi != nullptr) f = col_factor<float>(epi, tb0 | cbits);
+            if constexpr (FOLD) {  // the first epilogue's column-only sign and phase
+                f.sgn ^= f1.sgn;
+                const float r = f.cr * f1.cr - f.ci * f1.ci;
+                f.ci = f.cr * f1.ci + f.ci * f1.cr;
+                f.cr = r;
+            }
 #pragma unroll
             for (int j = 0; j < HX; ++j)
                 apply_factor(X[2 * j], X[2 * j + 1], f, (uint32_t)j | h5, has_ph);
@@ -1546,6 +1599,69 @@ __global__ __launch_bounds__(512, 1) void k_cluster_f32_split6s(float2* __restri
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     split6s_tiles<LOWT>((g_float2*)psi, Ah, Al, Ls[w], (c_epi*)epi, sg, (uint64_t)xcd_block() * WAVES + w, ntiles,
                         (uint64_t)gridDim.x * WAVES);
+}
+
+// ------------------------------------------------------------ uniform start + two clusters, one write-only pass
+// From the uniform start, after a first cluster (qubits T1, matrix M1) and its
+// diagonal epilogue E1 the state is a closed form: psi(x) = w[x on T1] E1(x),
+// w = 2^(-n/2) times the row sums of M1. Relative to the second cluster's
+// targets T2, E1 splits into terms on T2 alone (folded into the second matrix,
+// before its gates, when it is built), terms coupling one T2 qubit with one
+// column bit (a sign mask over the row index, per column) and terms on column
+// bits alone (a sign and a phase per column, which commute with the product
+// and join the second epilogue). The second cluster is then applied to inputs
+// computed from w instead of loaded: one write-only pass stands for the
+// initialisation and two cluster passes. The second cluster has 6 qubits; its
+// core and write-back are those of the staged 6-qubit kernel.
+struct Fold2Args {
+    const double2* M1;  // first cluster: plain complex128 2^k1 x 2^k1, row-major
+    double amp;         // 2^(-n/2)
+    int32_t k1;
+    int32_t t1[6];      // its qubits (sorted)
+};
+
+template <bool LOWT>
+__global__ __launch_bounds__(512, 1) void k_fold2_f32(float2* __restrict__ psi, const half8* __restrict__ Ap,
+                                                      const EpiDesc* __restrict__ epi2, const EpiDesc* __restrict__ epi1,
+                                                      StageGeom sg, Fold2Args f, uint64_t ntiles) {
+    constexpr int RB = 4, S = 8, WAVES = 8;
+    __shared__ half8 Ah[RB * S * 64];
+    __shared__ half8 Al[RB * S * 64];
+    __shared__ float2 Ls[WAVES][1024];
+    __shared__ float2 W[64];
+    load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Ah), reinterpret_cast<const vf4*>(Ap));
+    load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Al),
+                                            reinterpret_cast<const vf4*>(Ap + RB * S * 64));
+    const int d1 = 1 << f.k1;
+    if ((int)threadIdx.x < 64) {  // w: the first cluster applied to the uniform vector
+        double re = 0.0, im = 0.0;
+        if ((int)threadIdx.x < d1)
+            for (int x = 0; x < d1; ++x) {
+                const double2 m = f.M1[threadIdx.x * d1 + x];
+                re += m.x;
+                im += m.y;
+            }
+        W[threadIdx.x] = make_float2((float)(re * f.amp), (float)(im * f.amp));
+    }
+    __syncthreads();
+    FoldIn fin;
+    fin.W = W;
+    fin.k1 = f.k1;
+    fin.epi1 = (c_epi*)epi1;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) fin.t1[m] = f.t1[m];
+#pragma unroll
+    for (int m2 = 0; m2 < 6; ++m2) {
+        const int q = sg.tb[sg.tpos[m2]];
+        int b = 0;
+#pragma unroll
+        for (int m1 = 0; m1 < 6; ++m1)
+            if (m1 < f.k1 && f.t1[m1] == q) b = 1 << m1;
+        fin.ymask[m2] = b;
+    }
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    split6s_tiles<LOWT, true>((g_float2*)psi, Ah, Al, Ls[w], (c_epi*)epi2, sg, (uint64_t)xcd_block() * WAVES + w,
+                              ntiles, (uint64_t)gridDim.x * WAVES, &fin);
 }
 
 // ------------------------------------------------------------ batched persistent launch
@@ -2311,6 +2427,27 @@ hipError_t launch_multi(void* psi, int n, int m, const int32_t (*targets)[5], co
         hipLaunchKernelGGL((k_cluster_f32_multi<1, 4, kMultiSwz>), dim3(grid), dim3(256), 0, st, (float2*)psi, a,
                            ntiles);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fold2(void* psi, const ClusterGeom& g2, const void* mat2, const EpiDesc* epi2, const EpiDesc* epi1,
+                        const ClusterGeom& g1, const void* mat1, hipStream_t st) {
+    if (g2.k != 6 || g2.n < 11 || g1.k < 1 || g1.k > 6) return hipErrorInvalidValue;
+    Fold2Args f;
+    std::memset(&f, 0, sizeof(f));
+    f.M1 = reinterpret_cast<const double2*>(mat1);
+    f.amp = std::sqrt(std::ldexp(1.0, -g2.n));
+    f.k1 = g1.k;
+    for (int m = 0; m < g1.k; ++m) f.t1[m] = g1.t[m];
+    const StageGeom sg = make_stage_geom(g2, 5, 7);
+    const uint64_t tiles = g2.ncols >> 5;
+    const unsigned grid = grid_for(tiles, 8, kStagedGrid);
+    if (g2.t[0] == 0)
+        hipLaunchKernelGGL(k_fold2_f32<true>, dim3(grid), dim3(512), 0, st, (float2*)psi, (const half8*)mat2, epi2,
+                           epi1, sg, f, tiles);
+    else
+        hipLaunchKernelGGL(k_fold2_f32<false>, dim3(grid), dim3(512), 0, st, (float2*)psi, (const half8*)mat2, epi2,
+                           epi1, sg, f, tiles);
     return hipGetLastError();
 }
 

@@ -471,6 +471,7 @@ class State:
         qs, ms = (ctypes.c_int32 * (6 * m))(), (ctypes.c_float * m)()
         _check(L.qsim_op_timings(self.h, kind, k, qs, epi, ms, m, ctypes.byref(n)))
         kinds = {0: "cluster", 1: "diag", 2: "gate1q", 3: "phase1q", 4: "cz", 5: "build", 6: "init_cluster",
+                 8: "init_cluster2",
                  7: "pair"}
         return [dict(kind=kinds[kind[i]], k=k[i], qubits=[q for q in qs[6 * i:6 * i + 6] if q >= 0],
                      epi=bool(epi[i] & 1), staged=bool(epi[i] & 2), mfma=bool(epi[i] & 4), ms=float(ms[i]))

@@ -230,16 +230,19 @@ def test_fold_init_matches_oracle(dt, kmax):
     unfolded form."""
     circ = supremacy_circuit(4, 4, 18, seed=40 + kmax)
     ref = oracle.run(circ)
-    first_is_cluster = qsim.schedule(circ.n, circ.gates, kmax=kmax, fuse_diag=True,
-                                     skip_initial_h=True)["op_kind"][0] == 0
+    sc = qsim.schedule(circ.n, circ.gates, kmax=kmax, fuse_diag=True, skip_initial_h=True)
+    first_is_cluster = sc["op_kind"][0] == 0
+    two = (dt == "c64" and first_is_cluster and len(sc["op_kind"]) > 1 and sc["op_kind"][1] == 0
+           and sc["op_k"][1] == 6)
     old = qsim.get_option(qsim.OPT_FOLD_INIT)
     try:
-        for fold in (1, 0):
+        for fold in (2, 1, 0):
             qsim.set_option(qsim.OPT_FOLD_INIT, fold)
             s = make_state(circ.n, dt)
             s.run_circuit(circ.gates, kmax=kmax, fuse_diag=True, skip_initial_h=True, record_timings=True)
             kinds = [r["kind"] for r in s.op_timings()]
-            assert ("init_cluster" in kinds) == (bool(fold) and first_is_cluster), kinds
+            want = ("init_cluster2" if fold == 2 and two else "init_cluster" if fold and first_is_cluster else None)
+            assert (want in kinds if want else not any(k.startswith("init_cluster") for k in kinds)), kinds
             got = s.to_numpy()
             if dt == "c128":
                 assert np.max(np.abs(got - ref)) <= 1e-12
@@ -280,8 +283,13 @@ def test_fold_init_first_cluster(dt, case):
     kmax = len(qs)
     sc = qsim.schedule(n, gates, kmax=kmax, fuse_diag=True, skip_initial_h=True)
     assert sc["op_kind"][0] == 0 and sorted(sc["op_qubits"][0][:sc["op_k"][0]]) == sorted(qs), sc
-    s = make_state(n, dt)
-    s.run_circuit(gates, kmax=kmax, fuse_diag=True, skip_initial_h=True, record_timings=True)
+    old = qsim.get_option(qsim.OPT_FOLD_INIT)
+    qsim.set_option(qsim.OPT_FOLD_INIT, 1)  # the first cluster alone (two: test_fold2_matches_oracle)
+    try:
+        s = make_state(n, dt)
+        s.run_circuit(gates, kmax=kmax, fuse_diag=True, skip_initial_h=True, record_timings=True)
+    finally:
+        qsim.set_option(qsim.OPT_FOLD_INIT, old)
     kinds = [r["kind"] for r in s.op_timings() if r["kind"] != "build"]
     assert kinds[0] == "init_cluster", kinds
     got = s.to_numpy()
@@ -290,6 +298,40 @@ def test_fold_init_first_cluster(dt, case):
     else:
         assert fidelity(got, ref) >= 1 - 1e-6
         assert np.max(np.abs(got - ref)) <= 1e-5
+
+
+# (n, seed, Haar gate size): the second cluster's targets with qubit 0 or not,
+# the first cluster of 6 qubits or fewer, the two overlapping or not
+FOLD2_CASES = [(16, 19, 6), (11, 1, 2), (13, 7, 6), (11, 0, 6), (11, 2, 3), (11, 4, 6)]
+
+
+@pytest.mark.parametrize("case", range(len(FOLD2_CASES)))
+def test_fold2_matches_oracle(case):
+    """The uniform start, a first cluster and a second 6-qubit cluster in one
+    write-only pass (the second's inputs computed from the closed form, the
+    first epilogue split by the second's targets) against the oracle, and
+    against the same run with the three passes apart."""
+    from supremacy_inputs.circuits import batch_grid
+    n, seed, hk = FOLD2_CASES[case]
+    R, C, drop = batch_grid(n)
+    circ = with_haar_layers(supremacy_circuit(R, C, 16, 300 + seed, drop), 4, hk, 400 + seed)
+    ref = oracle.run(circ)
+    opts = dict(kmax=6, fuse_diag=True, skip_initial_h=True, record_timings=True)
+    old = qsim.get_option(qsim.OPT_FOLD_INIT)
+    try:
+        got = {}
+        for fold in (2, 0):
+            qsim.set_option(qsim.OPT_FOLD_INIT, fold)
+            s = make_state(n, "c64")
+            s.run_circuit(circ.gates, **opts)
+            kinds = [r["kind"] for r in s.op_timings() if r["kind"] != "build"]
+            assert (kinds[0] == "init_cluster2") == (fold == 2), kinds
+            got[fold] = s.to_numpy()
+    finally:
+        qsim.set_option(qsim.OPT_FOLD_INIT, old)
+    assert fidelity(got[2], ref) >= 1 - 1e-6
+    assert np.max(np.abs(got[2] - ref)) <= 1e-5
+    assert np.max(np.abs(got[2] - got[0])) <= 1e-5
 
 
 # ------------------------------------------------------------------ two clusters per pass (complex64)
