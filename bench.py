@@ -99,12 +99,17 @@ def batch_bench(qsim, torch, kmax, runs=3, n_check=8):
     st = b.run()
     run_s = min(runs_ms + [st["run_ms"]]) / 1e3
     # algorithmic bytes: every cluster op reads and writes its whole state, the
-    # initialisation writes it
+    # initialisation writes it; with the folded start the first cluster starts
+    # from the uniform state in registers and only writes
+    fold = qsim.get_option(qsim.OPT_FOLD_INIT) != 0
     alg = 0
     for i, c in enumerate(circs):
         sc = qsim.schedule(c.n, c.gates, kmax=kmax, scheduler="greedy", fuse_diag=True, skip_initial_h=True)
         m = len(sc["op_kind"])
-        alg += (m * 16 + 8) * 2 ** c.n
+        if fold and m and sc["op_kind"][0] == 0:
+            alg += ((m - 1) * 16 + 8) * 2 ** c.n
+        else:
+            alg += (m * 16 + 8) * 2 ** c.n
     worst = 1.0
     idx = [int(i) for i in range(0, 512, 512 // n_check)][:n_check]
     for i in idx:

@@ -68,17 +68,24 @@ Packed pack_circuit(const qsim_batch_circuit& c, const qsim_run_opts* opts, int 
     P.n_applied = S.n_applied;
     const uint64_t tiles = uint64_t(1) << (n - kTileBits);
 
-    BatchOp init;
-    std::memset(&init, 0, sizeof(init));
-    init.kind = S.uniform_init ? 2 : 1;
-    init.circuit = circuit;
-    init.n = n;
-    init.tiles = tiles;
-    P.ops.push_back(init);
-    P.op_mat.push_back(-1);
-    P.op_epi.push_back(-1);
+    // from the uniform start with a cluster first, the start and that cluster
+    // are one write-only op
+    const bool fold = S.uniform_init && g_fold_init && !S.ops.empty() && S.ops[0].kind == OP_CLUSTER;
+    if (!fold) {
+        BatchOp init;
+        std::memset(&init, 0, sizeof(init));
+        init.kind = S.uniform_init ? 2 : 1;
+        init.circuit = circuit;
+        init.n = n;
+        init.tiles = tiles;
+        P.ops.push_back(init);
+        P.op_mat.push_back(-1);
+        P.op_epi.push_back(-1);
+    }
 
-    for (const SOp& op : S.ops) {
+    for (size_t oi = 0; oi < S.ops.size(); ++oi) {
+        const SOp& op = S.ops[oi];
+        const bool first_folded = fold && oi == 0;
         if (op.kind == OP_GATE) {
             P.st = QSIM_E_UNSUPPORTED;
             P.err = "per-gate ops are not batched";
@@ -118,8 +125,8 @@ Packed pack_circuit(const qsim_batch_circuit& c, const qsim_run_opts* opts, int 
         std::memset(&bo, 0, sizeof(bo));
         bo.k = kk;
         bo.gate0 = (int)P.bgates.size();
-        bo.layout = kk == 6 ? LAYOUT_SPLIT16F : LAYOUT_MFMA32F;
-        bo.is_double = 0;
+        bo.layout = first_folded ? LAYOUT_PLAIN : kk == 6 ? LAYOUT_SPLIT16F : LAYOUT_MFMA32F;
+        bo.is_double = first_folded ? 1 : 0;
         for (int gi : members) P.bgates.push_back(to_build_gate(c.gates[gi], pos_of, P.dense));
         EpiDesc e;
         if (qsim_status r = split_epilogue(pos_of, c.gates, epi, P.bgates, P.dense, e)) {
@@ -139,13 +146,14 @@ Packed pack_circuit(const qsim_batch_circuit& c, const qsim_run_opts* opts, int 
         std::memset(&b, 0, sizeof(b));
         b.sg = make_stage_geom(g, kTileBits - kk, 7);  // 11 tile bits either way
         b.tiles = tiles;
-        b.kind = kk == 6 ? 3 : 0;
+        b.kind = first_folded ? 4 : kk == 6 ? 3 : 0;
+        b.k = (uint32_t)kk;
         b.circuit = circuit;
         b.lowt = t[0] == 0;
         b.n = n;
         P.op_mat.push_back((int)P.bops.size());
         P.bops.push_back(bo);
-        P.mat_bytes.push_back(matrix_bytes(kk, bo.layout, false));
+        P.mat_bytes.push_back(matrix_bytes(kk, bo.layout, bo.is_double != 0));
         if (e.n_cc || e.n_mix || e.n_ph) {
             P.op_epi.push_back((int)P.epis.size());
             P.epis.push_back(e);

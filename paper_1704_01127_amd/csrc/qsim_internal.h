@@ -141,12 +141,13 @@ struct BatchOp {
     const EpiDesc* epi;    // diagonal epilogue or null
     StageGeom sg;          // tile geometry (clusters)
     uint64_t tiles;        // wave tiles of 2^11 amplitudes
-    int32_t kind;          // 0 5-qubit cluster, 1 |0..0>, 2 uniform, 3 6-qubit cluster
+    int32_t kind;          // 0 5-qubit cluster, 1 |0..0>, 2 uniform, 3 6-qubit cluster,
+                           // 4 uniform start with the first cluster (write-only; A: plain complex128)
     int32_t circuit;
     int32_t lowt;          // target 0 is a cluster qubit
     int32_t n;             // qubits of the state
     uint32_t dep;          // items of this circuit that must be complete first
-    uint32_t pad;
+    uint32_t k;            // kind 4: the cluster's targets (5 or 6)
 };
 struct BatchItem {
     uint32_t op;

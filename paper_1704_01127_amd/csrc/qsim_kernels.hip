@@ -115,6 +115,34 @@ __device__ __forceinline__ uint32_t xcd_block() {
     return (g & 7) == 0 ? (b & 7) * (g >> 3) + (b >> 3) : b;
 }
 
+// Row sums of a plain complex128 d x d matrix, times amp, into LDS: eight
+// threads per row, each summing every eighth entry (so all loads are in
+// flight at once), combined by shuffles within the eight. Every thread of the
+// block takes part (the shuffles); the caller synchronises afterwards.
+template <typename V2>
+__device__ __forceinline__ void row_sums(const double2* __restrict__ M, int d, double amp, V2* out) {
+    const int sub = (int)threadIdx.x & 7;
+    for (int r0 = 0; r0 < d; r0 += (int)blockDim.x / 8) {
+        const int r = r0 + (int)threadIdx.x / 8;
+        double re = 0.0, im = 0.0;
+        if (r < d)
+            for (int x = sub; x < d; x += 8) {
+                const double2 m = M[r * d + x];
+                re += m.x;
+                im += m.y;
+            }
+#pragma unroll
+        for (int o = 4; o > 0; o >>= 1) {
+            re += __shfl_xor(re, o);
+            im += __shfl_xor(im, o);
+        }
+        if (r < d && sub == 0) {
+            out[r].x = (decltype(out[r].x))(re * amp);
+            out[r].y = (decltype(out[r].y))(im * amp);
+        }
+    }
+}
+
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef double vd2 __attribute__((ext_vector_type(2)));
 // Explicitly global pointers for code that also runs on pointers read from a
@@ -747,7 +775,11 @@ __device__ __forceinline__ void staged_f32_tiles(g_float2* __restrict__ psi, con
     constexpr int TILE = 1 << NT;
     constexpr int NL = TILE / 128;
     static_assert(NB == 2, "two column blocks per lane");
-    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    // an opaque lane: what is derived from it is computed per call, not hoisted
+    // into a caller's loop (the batch kernel's item loop) and kept live there
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const int p = lane & 31, h = lane >> 5;
     uint64_t lane_off = 0;
 #pragma unroll
     for (int b = 0; b < 6; ++b)
@@ -1380,7 +1412,11 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
                                               c_epi* __restrict__ epi, const StageGeom& sg, uint64_t tile,
                                               uint64_t tile_end, uint64_t stride, const FoldIn* fin = nullptr) {
     constexpr int K = 6, C = 5, NT = K + C, HX = 32, RB = 4, S = 8, NL = 16;
-    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    // an opaque lane: what is derived from it is computed per call, not hoisted
+    // into a caller's loop (the batch kernel's item loop) and kept live there
+    int lane = threadIdx.x & 63;
+    asm volatile("" : "+v"(lane));
+    const int p = lane & 31, h = lane >> 5;
     vf4* L4 = reinterpret_cast<vf4*>(L);
     bool has_epi = epi != nullptr;
     bool has_ph = has_epi && epi->n_ph > 0;
@@ -1633,16 +1669,9 @@ __global__ __launch_bounds__(512, 1) void k_fold2_f32(float2* __restrict__ psi, 
     load_matrix<RB * S * 64 * 8, WAVES * 64>(reinterpret_cast<_Float16*>(Al),
                                             reinterpret_cast<const vf4*>(Ap + RB * S * 64));
     const int d1 = 1 << f.k1;
-    if ((int)threadIdx.x < 64) {  // w: the first cluster applied to the uniform vector
-        double re = 0.0, im = 0.0;
-        if ((int)threadIdx.x < d1)
-            for (int x = 0; x < d1; ++x) {
-                const double2 m = f.M1[threadIdx.x * d1 + x];
-                re += m.x;
-                im += m.y;
-            }
-        W[threadIdx.x] = make_float2((float)(re * f.amp), (float)(im * f.amp));
-    }
+    if ((int)threadIdx.x < 64) W[threadIdx.x] = make_float2(0.0f, 0.0f);
+    __syncthreads();
+    row_sums(f.M1, d1, f.amp, W);  // w: the first cluster applied to the uniform vector
     __syncthreads();
     FoldIn fin;
     fin.W = W;
@@ -1751,6 +1780,87 @@ __global__ __launch_bounds__(512, 1) void k_batch_f32(const BatchOp* __restrict_
                 split6s_tiles<true>(psi, Ah, Al, L, epi, op->sg, item.tile0 + w, t_end, WAVES);
             else
                 split6s_tiles<false>(psi, Ah, Al, L, epi, op->sg, item.tile0 + w, t_end, WAVES);
+        } else if (op->kind == 4) {
+            // the uniform start with the circuit's first cluster, written in one
+            // pass: amplitude (column, target index y) = w[y] times the column's
+            // epilogue factor, w = 2^(-n/2) times the row sums of the cluster
+            // an opaque copy of the lane: what this branch derives from it is not
+            // hoisted out of the item loop, where it would be live in every branch
+            int ln = lane;
+            asm volatile("" : "+v"(ln));
+            const int k = (int)op->k, d = 1 << k, cb = 11 - k;
+            const double2* M = reinterpret_cast<const double2*>(op->A);
+            c_epi* epi = (c_epi*)op->epi;
+            const bool has_ph = epi != nullptr && epi->n_ph > 0;
+            float2* Wl = reinterpret_cast<float2*>(Lraw);  // 64 entries
+            ColFactor<float>* Fl = reinterpret_cast<ColFactor<float>*>(Lraw + 32 + w * 64);  // per wave, 64
+            row_sums(M, d, std::sqrt(__builtin_ldexp(1.0, -op->n)), Wl);
+            __syncthreads();
+            const StageGeom& sg = op->sg;
+            // tile index tau -> (y over the targets, column index): linear over
+            // OR, so the lane's, the chunk's and bit 0's parts are taken apart
+            auto y_of = [&](int tau) {
+                int y = 0;
+                for (int m = 0; m < k; ++m) y |= ((tau >> sg.tpos[m]) & 1) << m;
+                return y;
+            };
+            auto c_of = [&](int tau) {
+                int c = 0;
+                for (int b = 0; b < cb; ++b) c |= ((tau >> sg.cpos[b]) & 1) << b;
+                return c;
+            };
+            const int yl = y_of(ln << 1), cl = c_of(ln << 1), y1 = y_of(1), c1 = c_of(1);
+            // per chunk bit (tile bits 7..10): its row / column index bit and state offset
+            int ych[4], cch[4];
+            uint64_t och[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                ych[b] = y_of(128 << b);
+                cch[b] = c_of(128 << b);
+                och[b] = uint64_t(1) << sg.tb[7 + b];
+            }
+            uint64_t lane_off = 0;
+#pragma unroll
+            for (int b = 0; b < 6; ++b)
+                if ((ln >> b) & 1) lane_off |= uint64_t(1) << sg.tb[b + 1];
+            uint64_t cstate = 0;  // state bits of column `lane` (its factor is this lane's to compute)
+            for (int b = 0; b < cb; ++b)
+                if ((ln >> b) & 1) cstate |= uint64_t(1) << sg.tb[sg.cpos[b]];
+            g_vf4* p4 = reinterpret_cast<g_vf4*>(psi);
+            for (uint64_t t = item.tile0 + w; t < t_end; t += WAVES) {
+                const uint64_t tb0 = tile_base<11>(t, sg);
+                if (ln < (1 << cb)) {
+                    ColFactor<float> f{0u, 0u, 1.0f, 0.0f};
+                    if (epi != nullptr) f = col_factor<float>(epi, tb0 | cstate);
+                    Fl[ln] = f;
+                }
+                wave_lds_fence();
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    int yi = 0, ci = 0;  // uniform
+                    uint64_t o = tb0 | lane_off;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if ((i >> b) & 1) {
+                            yi |= ych[b];
+                            ci |= cch[b];
+                            o |= och[b];
+                        }
+                    vf4 v;
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const int y = yl | yi | (b ? y1 : 0), c = cl | ci | (b ? c1 : 0);
+                        const float2 a = Wl[y];
+                        const ColFactor<float> f = Fl[c];
+                        float re = a.x, im = a.y;
+                        apply_factor(re, im, f, (uint32_t)y, has_ph);
+                        v[2 * b] = re;
+                        v[2 * b + 1] = im;
+                    }
+                    p4[o >> 1] = v;  // linear chunk i of the tile
+                }
+                wave_lds_fence();
+            }
         } else {
             // initialisation: tile t is amplitudes [t 2^11, (t + 1) 2^11)
             // 2^(-n/2): a power of two, times 1/sqrt(2) for odd n (both exact scalings of a rounded constant)
@@ -1984,14 +2094,8 @@ __global__ __launch_bounds__(256) void k_init_cluster(typename Cplx<T>::type* __
     constexpr int D = 1 << K;
     __shared__ double2 w[D];
     __shared__ uint64_t toff[D];
+    row_sums(M, D, amp, w);
     if ((int)threadIdx.x < D) {
-        double re = 0.0, im = 0.0;
-        for (int x = 0; x < D; ++x) {
-            const double2 m = M[threadIdx.x * D + x];
-            re += m.x;
-            im += m.y;
-        }
-        w[threadIdx.x] = make_double2(re * amp, im * amp);
         uint64_t o = 0;
         for (int m = 0; m < K; ++m)
             if ((threadIdx.x >> m) & 1) o |= uint64_t(1) << g.t[m];

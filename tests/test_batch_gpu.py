@@ -43,9 +43,28 @@ def check_against_oracle(batch, circs, skip_trailing_diag=False):
 
 @pytest.fixture(autouse=True)
 def _reset_options():
+    fold = qsim.get_option(qsim.OPT_FOLD_INIT)
     yield
     qsim.set_option(qsim.OPT_BATCH_GRID, 0)
     qsim.set_option(qsim.OPT_BATCH_PAD, 0)
+    qsim.set_option(qsim.OPT_FOLD_INIT, fold)
+
+
+@pytest.mark.parametrize("kmax", [5, 6])
+@pytest.mark.parametrize("fold", [1, 0])
+def test_batch_folded_start(fold, kmax):
+    """The uniform start written together with each circuit's first cluster
+    (one write-only op: w over the cluster's targets times the column's
+    epilogue factor) or as a separate initialisation; both against the oracle."""
+    qsim.set_option(qsim.OPT_FOLD_INIT, fold)
+    circs = small_batch(10, seed0=120 + kmax)
+    b = qsim.Batch(circs, kmax=kmax)
+    st = b.run()
+    # ops: one initialisation per circuit unless folded
+    n_sched = sum(len(qsim.schedule(c.n, c.gates, kmax=kmax, fuse_diag=True, skip_initial_h=True)["op_kind"])
+                  for c in circs)
+    assert st["n_ops"] == n_sched + (0 if fold else len(circs))
+    check_against_oracle(b, circs)
 
 
 @pytest.mark.parametrize("opts", [
