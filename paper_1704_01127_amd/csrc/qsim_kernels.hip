@@ -1933,19 +1933,134 @@ __global__ __launch_bounds__(256) void k_cluster_valu(typename Cplx<T>::type* __
     }
 }
 
+// Two- and three-qubit clusters. With one column per thread, targets among
+// the lowest state bits put lanes 2^k amplitudes apart, so each load
+// instruction spreads over 2^k times the cache lines it uses, and a thread
+// that holds its column and the matrix limits occupancy. Here a wave tile is
+// 64 columns: the k targets and the 6 lowest non-target bits, whose lowest 6
+// positions are always state bits 0..5. Chunk x of the tile (tau = 64 x +
+// lane) is one contiguous run of 64 amplitudes; LDS hands each thread its
+// column, then takes the results back for contiguous stores.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void k_cluster_valu_staged(typename Cplx<T>::type* __restrict__ psi,
+                                                             const typename Cplx<T>::type* __restrict__ M,
+                                                             const EpiDesc* __restrict__ epi, StageGeom sg,
+                                                             uint64_t tiles) {
+    using V = typename Cplx<T>::type;
+    constexpr int D = 1 << K, RS = D + 1;  // LDS row of a column, padded
+    __shared__ V Ms[D * D];
+    __shared__ V Ls[4][64 * RS];
+    for (int i = threadIdx.x; i < D * D; i += 256) Ms[i] = M[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    V* L = Ls[threadIdx.x >> 6];
+    // element tau = 64 x + lane: its column (bits cpos) and target index (bits tpos)
+    int yl = 0, cl = 0, yx[D], cx[D];
+#pragma unroll
+    for (int m = 0; m < K; ++m)
+        if (sg.tpos[m] < 6) yl |= ((lane >> sg.tpos[m]) & 1) << m;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if (sg.cpos[b] < 6) cl |= ((lane >> sg.cpos[b]) & 1) << b;
+#pragma unroll
+    for (int x = 0; x < D; ++x) {
+        yx[x] = 0;
+        cx[x] = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            if (sg.tpos[m] >= 6) yx[x] |= ((x >> (sg.tpos[m] - 6)) & 1) << m;
+#pragma unroll
+        for (int b = 0; b < 6; ++b)
+            if (sg.cpos[b] >= 6) cx[x] |= ((x >> (sg.cpos[b] - 6)) & 1) << b;
+    }
+    // state offset of this thread's column (lane = column inside the tile)
+    uint64_t coff = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if ((lane >> b) & 1) coff |= uint64_t(1) << sg.tb[sg.cpos[b]];
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+    for (uint64_t tile = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6); tile < tiles;
+         tile += (uint64_t)gridDim.x * 4) {
+        const uint64_t tb0 = tile_base<K + 6>(tile, sg);
+        V v[D];
+#pragma unroll
+        for (int x = 0; x < D; ++x) v[x] = psi[tb0 | sg.ioff[x] | (uint64_t)lane];
+#pragma unroll
+        for (int x = 0; x < D; ++x) L[(cl | cx[x]) * RS + (yl | yx[x])] = v[x];
+        wave_lds_fence();
+#pragma unroll
+        for (int x = 0; x < D; ++x) v[x] = L[lane * RS + x];
+        ColFactor<T> f{0u, 0u, T(1), T(0)};
+        if (has_epi) f = col_factor<T>(epi, tb0 | coff);
+#pragma unroll
+        for (int y = 0; y < D; ++y) {
+            T ar = 0, ai = 0;
+#pragma unroll
+            for (int x = 0; x < D; ++x) {
+                const V m = Ms[y * D + x];
+                ar += m.x * v[x].x - m.y * v[x].y;
+                ai += m.x * v[x].y + m.y * v[x].x;
+            }
+            if (has_epi) apply_factor(ar, ai, f, (uint32_t)y, has_ph);
+            V o;
+            o.x = ar;
+            o.y = ai;
+            L[lane * RS + y] = o;  // a thread reads and writes only its own row here
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int x = 0; x < D; ++x) psi[tb0 | sg.ioff[x] | (uint64_t)lane] = L[(cl | cx[x]) * RS + (yl | yx[x])];
+        wave_lds_fence();  // the next tile's writes come after these reads
+    }
+}
+
 // ------------------------------------------------------------ diagonal pass
 // Every amplitude times the diagonal factor of its index (Sec. 3.5: diagonal
-// gates need no gather). A wave covers one window of 128 consecutive
-// amplitudes per step (2 per lane, 16-byte accesses). The index splits into
-// lo (bits 0..6, fixed per lane) and hi (the window, uniform per wave): terms
-// of lo bits only are per-lane constants, terms of hi bits only are computed
-// once per window, and CZ pairs with one bit in each half give a sign mask
-// over lo. The descriptor lists the pairs in `cc` and the phases in `ph`.
+// gates need no gather). A wave covers windows of 128 consecutive amplitudes
+// (2 per lane, 16-byte accesses), U neighbouring windows per step, all loaded
+// before any factor is applied. The index splits into lo (bits 0..6, fixed per
+// lane) and hi (the window, uniform per wave): terms of lo bits only are
+// per-lane constants; CZ pairs with one bit in each half give a sign mask over
+// lo. The hi part (sign, mask and phase) costs a loop over every gate of the
+// pass, too much per window, so a wave takes runs of 64 windows: each lane
+// forms the hi part of one window of the run and the window reads it from that
+// lane. The descriptor lists the pairs in `cc` and the phases in `ph`.
 template <typename T>
+__device__ __forceinline__ void load_pair(const typename Cplx<T>::type* p, typename Cplx<T>::type (&v)[2]) {
+    v[0] = p[0];
+    v[1] = p[1];
+}
+template <>
+__device__ __forceinline__ void load_pair<float>(const float2* p, float2 (&v)[2]) {
+    const float4 w = *reinterpret_cast<const float4*>(p);  // p is 16-byte aligned (even index)
+    v[0] = make_float2(w.x, w.y);
+    v[1] = make_float2(w.z, w.w);
+}
+template <typename T>
+__device__ __forceinline__ void store_pair(typename Cplx<T>::type* p, const typename Cplx<T>::type (&v)[2]) {
+    p[0] = v[0];
+    p[1] = v[1];
+}
+template <>
+__device__ __forceinline__ void store_pair<float>(float2* p, const float2 (&v)[2]) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <typename T, int U>
 __global__ __launch_bounds__(256) void k_diag(typename Cplx<T>::type* __restrict__ psi, int n,
                                               const EpiDesc* __restrict__ e) {
     using V = typename Cplx<T>::type;
-    constexpr int LO = 7;
+    constexpr int LO = 7;         // amplitude index bits inside a window
+    constexpr int RB = 6;         // a wave takes runs of 2^RB windows, one per lane
+    constexpr int R = 1 << RB;
     const int lane = threadIdx.x & 63;
     const int np = e->n_cc, nph = e->n_ph;
     // per-lane constants: the factor of the two lo indices of this lane
@@ -1968,10 +2083,15 @@ __global__ __launch_bounds__(256) void k_diag(typename Cplx<T>::type* __restrict
             }
         }
     }
+    const uint64_t N = uint64_t(1) << n;
     const uint64_t nwin = (n >= LO) ? (uint64_t(1) << (n - LO)) : 1;
-    const uint64_t wstride = (uint64_t)gridDim.x * 4;
-    for (uint64_t win = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); win < nwin; win += wstride) {
-        const uint64_t hi = win << LO;
+    const uint64_t nrun = (nwin + R - 1) >> RB;
+    const uint64_t rstride = (uint64_t)gridDim.x * 4;
+    for (uint64_t run = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6); run < nrun; run += rstride) {
+        // lane j forms the hi part of the factor of window j of the run: the
+        // sign of CZ pairs on hi bits, the sign mask over lo of pairs with
+        // one bit in each half, and the phases of hi bits
+        const uint64_t hi = ((run << RB) | (uint64_t)lane) << LO;
         uint32_t sgn_hi = 0u, wmask = 0u;
         double phr = 1.0, phi = 0.0;
         for (int i = 0; i < np; ++i) {
@@ -1989,24 +2109,37 @@ __global__ __launch_bounds__(256) void k_diag(typename Cplx<T>::type* __restrict
                 phr = r;
             }
         }
-        const uint64_t i0 = hi | (uint64_t)(2 * lane);
-        if (i0 >= (uint64_t(1) << n)) continue;  // states of fewer than 7 qubits: lanes past the end
-        V v[2];
-        v[0] = psi[i0];
-        v[1] = psi[i0 + 1];
+        const int sw = (int)(wmask | (sgn_hi << LO));  // wmask has bits 0..6 only
+        const uint64_t left = nwin - (run << RB);
+        const int wend = left < (uint64_t)R ? (int)left : R;  // uniform
+        for (int w0 = 0; w0 < wend; w0 += U) {
+            V v[U][2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const uint32_t lo = 2 * lane + h;
-            const bool neg = ((sgn_lo[h] ^ sgn_hi ^ (uint32_t)__popc(lo & wmask)) & 1u) != 0;
-            const T fr = (T)(phr * plr[h] - phi * pli[h]);
-            const T fi = (T)(phr * pli[h] + phi * plr[h]);
-            const T re = v[h].x * fr - v[h].y * fi;
-            const T im = v[h].x * fi + v[h].y * fr;
-            v[h].x = neg ? -re : re;
-            v[h].y = neg ? -im : im;
+            for (int u = 0; u < U; ++u) {
+                const uint64_t i0 = (((run << RB) | (uint64_t)(w0 + u)) << LO) | (uint64_t)(2 * lane);
+                // windows past the end, and lanes past the end of states of fewer than 7 qubits
+                if (w0 + u < wend && i0 < N) load_pair<T>(psi + i0, v[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t i0 = (((run << RB) | (uint64_t)(w0 + u)) << LO) | (uint64_t)(2 * lane);
+                if (w0 + u >= wend || i0 >= N) continue;
+                const uint32_t swu = (uint32_t)__builtin_amdgcn_readlane(sw, w0 + u);
+                const double hr = readlane_f64(phr, w0 + u), hq = readlane_f64(phi, w0 + u);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t lo = 2 * lane + h;
+                    const bool neg = ((sgn_lo[h] ^ (swu >> LO) ^ (uint32_t)__popc(lo & swu & 0x7fu)) & 1u) != 0;
+                    const T fr = (T)(hr * plr[h] - hq * pli[h]);
+                    const T fi = (T)(hr * pli[h] + hq * plr[h]);
+                    const T re = v[u][h].x * fr - v[u][h].y * fi;
+                    const T im = v[u][h].x * fi + v[u][h].y * fr;
+                    v[u][h].x = neg ? -re : re;
+                    v[u][h].y = neg ? -im : im;
+                }
+                store_pair<T>(psi + i0, v[u]);
+            }
         }
-        psi[i0] = v[0];
-        psi[i0 + 1] = v[1];
     }
 }
 
@@ -2633,6 +2766,21 @@ namespace {
 template <int K>
 hipError_t launch_valu_k(void* psi, bool dbl, const ClusterGeom& g, const void* mat, const EpiDesc* epi,
                          hipStream_t st) {
+    if (K >= 2 && K <= 3 && g.n - K >= 6) {
+        constexpr int KS = K >= 2 && K <= 3 ? K : 2;
+        const StageGeom sg = make_stage_geom(g, 6, 6);  // tile: the targets and 6 column bits
+        for (int i = 0; i < 6; ++i)
+            if (sg.tb[i] != i) return hipErrorInvalidValue;  // cannot happen: bits 0..5 are tile bits
+        const uint64_t tiles = g.ncols >> 6;
+        const unsigned grid = grid_for(tiles, 4, kStreamGrid);
+        if (dbl)
+            hipLaunchKernelGGL((k_cluster_valu_staged<double, KS>), dim3(grid), dim3(256), 0, st, (double2*)psi,
+                               (const double2*)mat, epi, sg, tiles);
+        else
+            hipLaunchKernelGGL((k_cluster_valu_staged<float, KS>), dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const float2*)mat, epi, sg, tiles);
+        return hipGetLastError();
+    }
     const unsigned grid = grid_for(g.ncols, 256, kStreamGrid);
     if (dbl)
         hipLaunchKernelGGL((k_cluster_valu<double, K>), dim3(grid), dim3(256), 0, st, (double2*)psi,
@@ -2762,12 +2910,15 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
 }
 
 hipError_t launch_diag(void* psi, bool dbl, int n, const EpiDesc* epi, hipStream_t st) {
+    // windows per wave step: 4 KiB of loads in flight per wave for either dtype
+    constexpr int UF = 4, UD = 2;
     const uint64_t nwin = n >= 7 ? (uint64_t(1) << (n - 7)) : 1;
-    const unsigned grid = grid_for(nwin, 4, kStreamGrid);
+    const uint64_t nrun = (nwin + 63) >> 6;  // runs of 64 windows, one per wave at a time
+    const unsigned grid = grid_for(nrun, 4, kStreamGrid);
     if (dbl)
-        hipLaunchKernelGGL(k_diag<double>, dim3(grid), dim3(256), 0, st, (double2*)psi, n, epi);
+        hipLaunchKernelGGL((k_diag<double, UD>), dim3(grid), dim3(256), 0, st, (double2*)psi, n, epi);
     else
-        hipLaunchKernelGGL(k_diag<float>, dim3(grid), dim3(256), 0, st, (float2*)psi, n, epi);
+        hipLaunchKernelGGL((k_diag<float, UF>), dim3(grid), dim3(256), 0, st, (float2*)psi, n, epi);
     return hipGetLastError();
 }
 

@@ -117,6 +117,40 @@ def test_apply_cluster_twice_large(dt, variant):
         assert np.max(np.abs(got - ref)) <= kernel_tol(dt, k, np.max(np.abs(ref)))
 
 
+# Two- and three-qubit clusters go through the LDS-staged vector kernel
+# (64-column tiles) once n - k >= 6; targets among state bits 0..5 are the
+# cases where its element-to-column mapping is least trivial.
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("k,qs", [(2, [0, 1]), (2, [5, 9]), (2, [3, 0]), (3, [0, 1, 2]), (3, [2, 5, 6]),
+                                  (3, [4, 1, 11])])
+@pytest.mark.parametrize("n", [8, 9, 14])
+def test_small_cluster_staged(dt, k, qs, n):
+    if max(qs) >= n:
+        pytest.skip("targets outside the state")
+    u = haar_unitary(k, 5 * k + n)
+    psi = random_state(n, 3 * n + k)
+    ref = oracle.apply_dense(psi.copy(), qs, u)
+    s = make_state(n, dt, psi)
+    s.apply_cluster(qs, u)
+    got = s.to_numpy()
+    assert np.max(np.abs(got - ref)) <= kernel_tol(dt, k, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+def test_small_cluster_staged_many_tiles(dt):
+    """More 64-column tiles than one sweep of the grid (2^19 at n = 27, k = 2)."""
+    n = 27
+    for k, qs in ((2, [1, 0]), (3, [0, 2, 26])):
+        u = haar_unitary(k, 77 + k)
+        psi = random_state(n, 40 + k)
+        ref = oracle.apply_dense(psi.copy(), qs, u)
+        s = make_state(n, dt, psi)
+        s.apply_cluster(qs, u)
+        got = s.to_numpy()
+        assert np.max(np.abs(got - ref)) <= kernel_tol(dt, k, np.max(np.abs(ref)))
+        del s, got, ref, psi
+
+
 # ------------------------------------------------------------------ k = 6 kernels (complex64)
 @pytest.fixture(params=[0, 1, 2], ids=["realsplit", "threeprod", "fp16halves"])
 def k6_kernel(request):
@@ -392,7 +426,8 @@ def test_pair_circuits_match_oracle(pairing, kmax, fuse):
 
 # ------------------------------------------------------------------ diagonal layer
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("n", [1, 2, 3, 9, 16])
+# 8: fewer windows than one wave's step; 25: more windows than one sweep of the grid
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 9, 16, 25])
 def test_apply_diag(dt, n):
     rng = np.random.default_rng(n)
     pairs = []
