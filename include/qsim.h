@@ -239,7 +239,13 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * pass is limited by per-wave ALU and LDS work and takes longer than two
  * single passes. QSIM_OPT_PAIR_TILE is that tile's size in qubits, 11
  * (default) or 10 (12 waves per compute unit; a pair whose ten qubits leave
- * out qubit 0 uses the 11-qubit tile). Errors:
+ * out qubit 0 uses the 11-qubit tile). QSIM_OPT_CLUSTER_SETS (default 1):
+ * the clustering schedulers (greedy and cost-driven) also offer, at every
+ * step, the closure of each dense connected qubit set of the circuit's
+ * interaction graph (all ready gates inside the set) besides the clusters
+ * grown gate by gate from a seed, and keep the schedule with fewer ops
+ * (greedy) or the smaller predicted time (cost-driven); 0 grows from seeds
+ * only (Sec. 3.6.1's greedy), read when a schedule is built. Errors:
  * QSIM_E_INVALID for an unknown option or an out-of-range value. */
 typedef enum {
     QSIM_OPT_CLUSTER_VARIANT = 1,
@@ -249,7 +255,8 @@ typedef enum {
     QSIM_OPT_K6_KERNEL = 5,
     QSIM_OPT_FOLD_INIT = 6,
     QSIM_OPT_PAIR = 7,
-    QSIM_OPT_PAIR_TILE = 8
+    QSIM_OPT_PAIR_TILE = 8,
+    QSIM_OPT_CLUSTER_SETS = 9
 } qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);

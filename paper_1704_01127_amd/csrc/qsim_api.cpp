@@ -74,6 +74,7 @@ int g_k6_kernel = 2;
 int g_fold_init = 2;
 int g_pair = 0;
 int g_pair_tile = 11;
+int g_cluster_sets = 1;
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
@@ -648,6 +649,7 @@ OpCostFn qsim::api::cost_fn(const qsim_run_opts* o, int n, bool dbl) {
 
 SchedOpts qsim::api::to_sched_opts(const qsim_run_opts* o) {
     SchedOpts so;
+    so.cluster_sets = g_cluster_sets != 0;
     if (!o) return so;
     so.kmax = o->kmax;
     so.mode = o->scheduler == QSIM_SCHED_PER_GATE ? 0 : (o->scheduler == QSIM_SCHED_GREEDY ? 1 : 2);
@@ -939,6 +941,11 @@ qsim_status qsim_set_option(int option, int value) {
         g_pair = value;
         return QSIM_OK;
     }
+    if (option == QSIM_OPT_CLUSTER_SETS) {
+        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "cluster_sets must be 0 or 1");
+        g_cluster_sets = value;
+        return QSIM_OK;
+    }
     if (option == QSIM_OPT_BATCH_ITEM_TILES) {
         if (value < 1 || value > 4096 || (value & (value - 1)))
             return fail(QSIM_E_INVALID, "tiles per batch item must be a power of two in [1, 4096]");
@@ -981,6 +988,7 @@ int qsim_get_option(int option) {
     if (option == QSIM_OPT_FOLD_INIT) return g_fold_init;
     if (option == QSIM_OPT_PAIR) return g_pair;
     if (option == QSIM_OPT_PAIR_TILE) return g_pair_tile;
+    if (option == QSIM_OPT_CLUSTER_SETS) return g_cluster_sets;
     return -1;
 }
 

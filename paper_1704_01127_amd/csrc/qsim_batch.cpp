@@ -63,7 +63,8 @@ Packed pack_circuit(const qsim_batch_circuit& c, const qsim_run_opts* opts, int 
     Packed P;
     const int n = c.n_qubits;
     const std::vector<SGate> sg = to_sgates(c.gates, c.n_gates);
-    const SchedOpts so = to_sched_opts(opts);
+    SchedOpts so = to_sched_opts(opts);
+    so.parallel = false;  // circuits are already planned on parallel threads
     const Schedule S = make_schedule(n, sg, so, cost_fn(opts, n, false));
     P.n_applied = S.n_applied;
     const uint64_t tiles = uint64_t(1) << (n - kTileBits);

@@ -160,6 +160,7 @@ extern int g_k6_kernel;         // float k = 6 clusters: 0 fp32 real-split, 1 fp
 extern int g_fold_init;         // fold the uniform initialisation into the first cluster
 extern int g_pair;              // apply consecutive clusters of <= 5 qubits (complex64) two per pass
 extern int g_pair_tile;         // tile bits of the pair kernel: 11 (8 waves) or 10 (12 waves)
+extern int g_cluster_sets;  // scheduler: candidate qubit sets on (1) or off (0)
 
 // Bytes of a cluster matrix in each layout.
 inline int64_t matrix_bytes(int k, int layout, bool dbl) {

@@ -16,6 +16,13 @@
 // myopic: a cluster can look cheap per gate and still leave more total work;
 // the final comparison is between whole schedules.)
 //
+// Candidate clusters besides the seeded ones: the closure of a dense qubit
+// set of the interaction graph (every ready gate inside the set joins, until
+// none is left). Growing gate by gate from a seed tends to give chains of
+// qubits; a compact set (a 2 x 3 block of a grid) holds more gates per pass.
+// Greedy mode builds the schedule with and without these candidates and keeps
+// the one with fewer ops; cost-driven mode adds them to its candidates.
+//
 // Extensions for the GPU kernels (both exact, as diagonal gates commute):
 //   * a cluster made only of diagonal gates becomes a diagonal pass, which
 //     then absorbs every ready diagonal gate;
@@ -74,68 +81,135 @@ struct Grown {
     int n_gates() const { return (int)(members.size() + epi.size()); }
 };
 
-// Take gate gi: advance the heads of its qubits and update the ready list
-// (ascending gate index): gi leaves it, and only the new heads of gi's qubits
-// can become ready.
-void take(const Dag& d, std::vector<int>& head, std::vector<int>& rl, int gi) {
-    d.pop(head, gi);
-    rl.erase(std::lower_bound(rl.begin(), rl.end(), gi));
+// Queue heads and ready list (ascending gate index) of one growth, on fixed
+// arrays: a state has at most 64 qubits, so at most 64 gates are ready, and
+// the many trial growths of a step need no heap memory.
+struct Frontier {
+    int head[64];
+    int rl[64];
+    int nrl = 0;
+};
+
+bool ready_at(const Dag& d, const int* head, int gi) {
     const SGate& s = (*d.g)[gi];
     for (int j = 0; j < s.nq; ++j) {
         const auto& qq = d.queue[s.q[j]];
         const int h = head[s.q[j]];
+        if (h >= (int)qq.size() || qq[h] != gi) return false;
+    }
+    return true;
+}
+
+// Take gate gi: advance the heads of its qubits and update the ready list:
+// gi leaves it, and only the new heads of gi's qubits can become ready.
+void take(const Dag& d, Frontier& f, int gi) {
+    const SGate& s = (*d.g)[gi];
+    for (int j = 0; j < s.nq; ++j) f.head[s.q[j]]++;
+    int* end = f.rl + f.nrl;
+    int* p = std::lower_bound(f.rl, end, gi);
+    std::memmove(p, p + 1, (end - p - 1) * sizeof(int));
+    --f.nrl;
+    for (int j = 0; j < s.nq; ++j) {
+        const auto& qq = d.queue[s.q[j]];
+        const int h = f.head[s.q[j]];
         if (h >= (int)qq.size()) continue;
         const int g2 = qq[h];
-        if (!d.ready(head, g2)) continue;
-        auto it = std::lower_bound(rl.begin(), rl.end(), g2);
-        if (it == rl.end() || *it != g2) rl.insert(it, g2);
+        if (!ready_at(d, f.head, g2)) continue;
+        end = f.rl + f.nrl;
+        p = std::lower_bound(f.rl, end, g2);
+        if (p != end && *p == g2) continue;
+        std::memmove(p + 1, p, (end - p) * sizeof(int));
+        *p = g2;
+        ++f.nrl;
     }
 }
 
-// Grow a cluster from `seed` with at most `kcap` qubits; rl0 is the ready
-// list at head0.
-Grown grow(const Dag& d, const std::vector<int>& head0, const std::vector<int>& rl0, int seed, int kcap,
-           bool fuse_diag) {
+// Grow a cluster from `seed` with at most `kcap` qubits, starting at f0. With
+// `within` != 0 there is no seed (seed = -1) and the cluster is the closure
+// of that qubit set: every gate that becomes ready and lies inside it joins
+// the matrix. Returns the number of gates taken (matrix and diagonal
+// epilogue); `out`, when given, receives the cluster.
+int grow(const Dag& d, const Frontier& f0, int seed, int kcap, bool fuse_diag, uint64_t within, Grown* out) {
     const auto& G = *d.g;
-    Grown r;
-    r.head = head0;
-    std::vector<int> rl = rl0;
-    r.Q = d.mask[seed];
-    r.members.push_back(seed);
-    take(d, r.head, rl, seed);
-    uint64_t sealed = 0;
-    int n_epi_cz = 0, n_epi_ph = 0;
+    Frontier f = f0;
+    uint64_t Q = 0;
+    int n_mat = 0, n_epi_cz = 0, n_epi_ph = 0;
+    if (seed >= 0) {
+        Q = d.mask[seed];
+        ++n_mat;
+        if (out) out->members.push_back(seed);
+        take(d, f, seed);
+    }
     for (;;) {
         // a gate that joins the matrix: fewest new qubits, then lowest index
         int best = -1, best_new = 1 << 30;
-        for (int gi : rl) {
+        for (int i = 0; i < f.nrl; ++i) {
+            const int gi = f.rl[i];
             const uint64_t m = d.mask[gi];
-            if ((m & sealed) || popc(r.Q | m) > kcap) continue;
-            const int nw = popc(m & ~r.Q);
+            if (within ? (m & ~within) != 0 : popc(Q | m) > kcap) continue;
+            const int nw = popc(m & ~Q);
             if (nw < best_new) { best = gi; best_new = nw; }
         }
-        if (best >= 0) {
-            r.members.push_back(best);
-            r.Q |= d.mask[best];
-            take(d, r.head, rl, best);
-            continue;
-        }
-        if (!fuse_diag) break;
-        // nothing fits: attach the lowest-index ready diagonal gate
-        for (int gi : rl) {
-            if (!G[gi].diag) continue;
-            const bool cz = G[gi].kind == G_CZ;
-            if ((cz && n_epi_cz >= kEpiMax) || (!cz && n_epi_ph >= kEpiMax)) continue;
-            best = gi;
-            break;
-        }
         if (best < 0) break;
-        r.epi.push_back(best);
-        sealed |= d.mask[best];
-        if (G[best].kind == G_CZ) ++n_epi_cz; else ++n_epi_ph;
-        take(d, r.head, rl, best);
+        ++n_mat;
+        if (out) out->members.push_back(best);
+        Q |= d.mask[best];
+        take(d, f, best);
     }
-    return r;
+    // nothing fits: attach ready diagonal gates, lowest index first. Their
+    // qubits are sealed, and every gate they make ready touches one, so no
+    // further matrix gate can join; a gate made ready has a higher index than
+    // the one taken, so one forward pass over the ready list finds them all.
+    if (fuse_diag && n_mat > 0) {
+        for (int i = 0; i < f.nrl;) {
+            const int gi = f.rl[i];
+            const bool cz = G[gi].kind == G_CZ;
+            if (!G[gi].diag || (cz && n_epi_cz >= kEpiMax) || (!cz && n_epi_ph >= kEpiMax)) {
+                ++i;
+                continue;
+            }
+            if (out) out->epi.push_back(gi);
+            if (cz) ++n_epi_cz; else ++n_epi_ph;
+            take(d, f, gi);  // removes rl[i]; gates it makes ready sort after it
+        }
+    }
+    if (out) {
+        out->Q = Q;
+        out->head.assign(f.head, f.head + d.n);
+    }
+    return n_mat + n_epi_cz + n_epi_ph;
+}
+
+// Gates the closure of qubit set S takes into its matrix from `head`: every
+// gate inside S that reaches the head of all its qubits. Only the queues of
+// S's qubits matter (the diagonal gates a cluster carries afterwards never add
+// matrix gates), so this count ranks the candidate sets cheaply.
+int closure_size(const Dag& d, const std::vector<int>& head, uint64_t S) {
+    const auto& G = *d.g;
+    int h[64];
+    for (uint64_t m = S; m; m &= m - 1) h[__builtin_ctzll(m)] = head[__builtin_ctzll(m)];
+    int cnt = 0;
+    for (bool prog = true; prog;) {
+        prog = false;
+        for (uint64_t m = S; m; m &= m - 1) {
+            const int q = __builtin_ctzll(m);
+            const auto& qq = d.queue[q];
+            while (h[q] < (int)qq.size()) {
+                const int gi = qq[h[q]];
+                if (d.mask[gi] & ~S) break;
+                bool at_head = true;
+                for (int j = 0; j < G[gi].nq && at_head; ++j) {
+                    const int p = G[gi].q[j];
+                    at_head = h[p] < (int)d.queue[p].size() && d.queue[p][h[p]] == gi;
+                }
+                if (!at_head) break;
+                for (int j = 0; j < G[gi].nq; ++j) h[G[gi].q[j]]++;
+                ++cnt;
+                prog = true;
+            }
+        }
+    }
+    return cnt;
 }
 
 bool all_diag(const std::vector<SGate>& G, const Grown& c) {
@@ -157,7 +231,8 @@ double grown_cost(const OpCostFn& cost, const Grown& c, int n) {
 // seed grows under kcap - 1, and the one with the smaller predicted time per
 // gate is taken.
 std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::vector<char>& dropped, int n_applied,
-                            int kcap_in, bool fuse_diag, const OpCostFn* trim = nullptr) {
+                            int kcap_in, bool fuse_diag, const OpCostFn* trim = nullptr,
+                            const std::vector<uint64_t>* sets = nullptr) {
     const int ng = (int)gates.size();
     std::vector<SOp> out;
     Dag d;
@@ -174,25 +249,66 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
     int remaining = n_applied;
     std::vector<int> rl;
     const int kmax = kcap_in;
+    // closure sizes of the candidate sets, recomputed only for sets with a
+    // qubit whose queue head moved since (the size depends on those heads only)
+    std::vector<int> csize(sets ? sets->size() : 0, 0);
+    uint64_t moved = ~uint64_t(0);
+    std::vector<int> head_before;
 
     while (remaining > 0) {
         d.ready_list(head, rl);
-        Grown best;
-        int best_score = -1, best_seed = -1;
+        Frontier f0;
+        for (int q = 0; q < n; ++q) f0.head[q] = head[q];
+        f0.nrl = (int)rl.size();
+        std::copy(rl.begin(), rl.end(), f0.rl);
+        int best_score = -1, best_seed = -1, best_cap = kmax;
+        uint64_t best_within = 0;
         for (int seed : rl) {
             // a gate wider than kmax (a dense gate) forms a cluster of its own width
             const int khi = std::max(kmax, popc(d.mask[seed]));
-            Grown c = grow(d, head, rl, seed, khi, fuse_diag);
-            if (c.n_gates() > best_score) { best_score = c.n_gates(); best = std::move(c); best_seed = seed; }
+            const int c = grow(d, f0, seed, khi, fuse_diag, 0, nullptr);
+            if (c > best_score) {
+                best_score = c;
+                best_seed = seed;
+                best_cap = khi;
+            }
         }
-        if (trim && kmax > 1 && popc(best.Q) == kmax && popc(d.mask[best_seed]) < kmax) {
-            Grown small = grow(d, head, rl, best_seed, kmax - 1, fuse_diag);
+        // closures of the candidate qubit sets compete with the seeded
+        // clusters: ranked by their matrix gates, the top kTopSets are grown
+        // in full (with the diagonal gates they carry)
+        if (sets) {
+            constexpr size_t kTopSets = 8;
+            std::vector<std::pair<int, uint64_t>> ranked;
+            ranked.reserve(sets->size());
+            for (size_t i = 0; i < sets->size(); ++i) {
+                const uint64_t S = (*sets)[i];
+                if (S & moved) csize[i] = closure_size(d, head, S);
+                if (csize[i] > 0) ranked.emplace_back(-csize[i], S);
+            }
+            const size_t top = std::min(kTopSets, ranked.size());
+            std::partial_sort(ranked.begin(), ranked.begin() + top, ranked.end());
+            for (size_t i = 0; i < top; ++i) {
+                const int c = grow(d, f0, -1, kmax, fuse_diag, ranked[i].second, nullptr);
+                if (c > best_score) {  // c > 0: the closure took a matrix gate
+                    best_score = c;
+                    best_seed = -1;
+                    best_cap = kmax;
+                    best_within = ranked[i].second;
+                }
+            }
+        }
+        Grown best;
+        grow(d, f0, best_seed, best_cap, fuse_diag, best_within, &best);
+        if (trim && best_seed >= 0 && kmax > 1 && popc(best.Q) == kmax && popc(d.mask[best_seed]) < kmax) {
+            Grown small;
+            grow(d, f0, best_seed, kmax - 1, fuse_diag, 0, &small);
             if (!all_diag(gates, small) && !all_diag(gates, best)) {
                 const double per_big = grown_cost(*trim, best, n) / best.n_gates();
                 const double per_small = grown_cost(*trim, small, n) / small.n_gates();
                 if (per_small < per_big) best = std::move(small);
             }
         }
+        head_before = head;
         SOp op;
         if (all_diag(gates, best)) {
             // a diagonal pass: take every ready diagonal gate, repeatedly
@@ -226,8 +342,70 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
             remaining -= best.n_gates();
         }
         out.push_back(std::move(op));
+        moved = 0;
+        for (int q = 0; q < n; ++q)
+            if (head[q] != head_before[q]) moved |= uint64_t(1) << q;
     }
     return out;
+}
+
+// Candidate qubit sets for clusters: dense connected k-qubit sets of the
+// interaction graph (two qubits are joined when a gate acts on both). From
+// every edge, a set grows by the outside neighbour with the most edges into
+// it; all neighbours that tie are followed. Sets whose internal edge count is
+// within `slack` (0 and 1) of the largest are kept. On a grid circuit, k = 6 and slack
+// 0 give the 2 x 3 and 3 x 2 blocks: a cluster there takes more gates per
+// qubit than one grown gate by gate. Each level is capped at kSetCap sets.
+void dense_sets(int n, const std::vector<SGate>& gates, const std::vector<char>& dropped, int k,
+                std::vector<uint64_t>& slack0, std::vector<uint64_t>& slack1) {
+    constexpr size_t kSetCap = 4096;
+    slack0.clear();
+    slack1.clear();
+    std::vector<uint64_t> level;
+    if (k < 2 || n > 64) return;
+    std::vector<uint64_t> adj(n, 0);
+    for (size_t i = 0; i < gates.size(); ++i) {
+        if (dropped[i]) continue;
+        for (int a = 0; a < gates[i].nq; ++a)
+            for (int b = 0; b < gates[i].nq; ++b)
+                if (a != b) adj[gates[i].q[a]] |= uint64_t(1) << gates[i].q[b];
+    }
+    for (int a = 0; a < n; ++a)
+        for (int b = a + 1; b < n; ++b)
+            if (adj[a] >> b & 1) level.push_back((uint64_t(1) << a) | (uint64_t(1) << b));
+    for (int size = 2; size < k && !level.empty(); ++size) {
+        std::vector<uint64_t> next;
+        for (uint64_t S : level) {
+            uint64_t nb = 0;
+            for (int q = 0; q < n; ++q)
+                if (S >> q & 1) nb |= adj[q];
+            nb &= ~S;
+            int top = -1;
+            for (int q = 0; q < n; ++q)
+                if (nb >> q & 1) top = std::max(top, popc(adj[q] & S));
+            for (int q = 0; q < n; ++q)
+                if ((nb >> q & 1) && popc(adj[q] & S) == top) next.push_back(S | (uint64_t(1) << q));
+        }
+        std::sort(next.begin(), next.end());
+        next.erase(std::unique(next.begin(), next.end()), next.end());
+        if (next.size() > kSetCap) next.resize(kSetCap);
+        level = std::move(next);
+    }
+    auto edges = [&](uint64_t S) {
+        int e = 0;
+        for (int q = 0; q < n; ++q)
+            if (S >> q & 1) e += popc(adj[q] & S);
+        return e / 2;
+    };
+    int top = 0;
+    for (uint64_t S : level)
+        if (popc(S) == k) top = std::max(top, edges(S));
+    for (uint64_t S : level) {
+        if (popc(S) != k) continue;
+        const int e = edges(S);
+        if (e >= top) slack0.push_back(S);
+        if (e >= top - 1) slack1.push_back(S);
+    }
 }
 
 }  // namespace
@@ -281,24 +459,49 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     }
 
     const int kmax = std::max(1, std::min(o.kmax, kMaxK));
+    // candidate qubit sets (dense sets of the interaction graph, two slacks)
+    std::vector<uint64_t> sets0, sets1;
+    if (o.cluster_sets && kmax >= 2) dense_sets(n, gates, S.dropped, kmax, sets0, sets1);
     if (o.mode == 1 || !cost) {
-        S.ops = greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag);
+        if (sets0.empty()) {
+            S.ops = greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag);
+            return S;
+        }
+        // the greedy schedules with and without the candidate sets; the one
+        // with the fewest ops wins (ties: the earlier)
+        const auto policy = o.parallel ? std::launch::async : std::launch::deferred;
+        auto f0 = std::async(policy, [&]() { return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag); });
+        auto f1 = std::async(policy, [&]() {
+            return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, &sets0);
+        });
+        std::vector<SOp> c2 = greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, &sets1);
+        S.ops = f0.get();
+        std::vector<SOp> c1 = f1.get();
+        if (c1.size() < S.ops.size()) S.ops = std::move(c1);
+        if (c2.size() < S.ops.size()) S.ops = std::move(c2);
         return S;
     }
     // cost-driven: complete candidate schedules, the one with the smallest
     // predicted total time wins (built in parallel). Candidates: the greedy
-    // schedule for each cap kmax - 2 .. kmax (smaller caps only add passes)
-    // and the cost-trimmed greedy schedule for kmax.
+    // schedule for each cap kmax - 2 .. kmax (smaller caps only add passes),
+    // the cost-trimmed greedy schedule for kmax, and the greedy schedules for
+    // kmax with each family of candidate qubit sets.
     const int k_lo = std::max(1, kmax - 2);
+    const auto policy = o.parallel ? std::launch::async : std::launch::deferred;
     std::vector<std::future<std::vector<SOp>>> futs;
     for (int kc = k_lo; kc <= kmax; ++kc)
-        futs.push_back(std::async(std::launch::async, [&, kc]() {
+        futs.push_back(std::async(policy, [&, kc]() {
             return greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag);
         }));
     if (kmax > 1)
-        futs.push_back(std::async(std::launch::async, [&]() {
+        futs.push_back(std::async(policy, [&]() {
             return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost);
         }));
+    for (const std::vector<uint64_t>* sets : {&sets0, &sets1})
+        if (!sets->empty())
+            futs.push_back(std::async(policy, [&, sets]() {
+                return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, sets);
+            }));
     double best_cost = 0.0;
     for (size_t c = 0; c < futs.size(); ++c) {
         std::vector<SOp> ops = futs[c].get();

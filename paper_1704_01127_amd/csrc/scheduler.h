@@ -35,6 +35,8 @@ struct SchedOpts {
     bool fuse_diag = false;
     bool skip_trailing_diag = false;
     bool skip_initial_h = false;
+    bool cluster_sets = true;  // also offer closures of dense qubit sets (greedy and cost-driven)
+    bool parallel = true;      // build candidate schedules on threads of their own
 };
 
 struct Schedule {

@@ -219,6 +219,7 @@ OPT_K6_KERNEL = 5
 OPT_FOLD_INIT = 6
 OPT_PAIR = 7
 OPT_PAIR_TILE = 8
+OPT_CLUSTER_SETS = 9
 
 
 def set_option(option: int, value: int):

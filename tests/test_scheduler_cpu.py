@@ -58,16 +58,25 @@ def check_schedule(circ, sch, kmax, skip_trailing=False, skip_initial_h=False):
             last[q] = (key, g.name in DIAG)
 
 
+@pytest.fixture(params=[1, 0], ids=["sets", "seeds"])
+def cluster_sets(request):
+    """Schedule with and without the dense qubit-set candidates, then restore the default."""
+    old = qsim.get_option(qsim.OPT_CLUSTER_SETS)
+    qsim.set_option(qsim.OPT_CLUSTER_SETS, request.param)
+    yield request.param
+    qsim.set_option(qsim.OPT_CLUSTER_SETS, old)
+
+
 @pytest.mark.parametrize("kmax", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("fuse", [False, True])
-def test_supremacy_schedule_valid(kmax, fuse):
+def test_supremacy_schedule_valid(kmax, fuse, cluster_sets):
     circ = supremacy_circuit(5, 6, 25, seed=kmax)
     sch = qsim.schedule(circ.n, circ.gates, kmax=kmax, fuse_diag=fuse)
     check_schedule(circ, sch, kmax)
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_random_circuit_schedule_valid(seed):
+def test_random_circuit_schedule_valid(seed, cluster_sets):
     rng = np.random.default_rng(seed)
     n = 9
     names = ["H", "T", "SX", "SY", "X", "Z", "TDG"]
@@ -141,3 +150,38 @@ def test_dense_gate_wider_than_kmax():
     sch = qsim.schedule(circ.n, circ.gates, kmax=3)
     check_schedule(circ, sch, 3)
     assert 5 in sch["op_k"]
+
+
+def test_candidate_sets_reduce_passes():
+    """Closures of dense qubit sets (2 x 3 blocks on a grid) as extra cluster
+    candidates: never more ops than growing from seeds alone, and fewer in
+    total over grid circuits and k_max 5, 6 (greedy and cost-driven)."""
+    old = qsim.get_option(qsim.OPT_CLUSTER_SETS)
+    try:
+        tot = {0: 0, 1: 0}
+        for R, C in ((5, 6), (4, 5)):
+            for seed in range(3):
+                circ = supremacy_circuit(R, C, 25, seed)
+                for kmax in (5, 6):
+                    for sched in ("greedy", "analytic"):
+                        cnt = {}
+                        for cs in (0, 1):
+                            qsim.set_option(qsim.OPT_CLUSTER_SETS, cs)
+                            sch = qsim.schedule(circ.n, circ.gates, kmax=kmax, scheduler=sched, fuse_diag=True,
+                                                skip_initial_h=True, skip_trailing_diag=True)
+                            check_schedule(circ, sch, kmax, skip_trailing=True, skip_initial_h=True)
+                            cnt[cs] = len(sch["op_kind"])
+                            tot[cs] += cnt[cs]
+                        if sched == "greedy":
+                            assert cnt[1] <= cnt[0], (R, C, seed, kmax, cnt)
+        assert tot[1] < 0.9 * tot[0], tot
+    finally:
+        qsim.set_option(qsim.OPT_CLUSTER_SETS, old)
+
+
+def test_cluster_sets_option_range():
+    old = qsim.get_option(qsim.OPT_CLUSTER_SETS)
+    assert old in (0, 1)
+    with pytest.raises(qsim.QsimError):
+        qsim.set_option(qsim.OPT_CLUSTER_SETS, 2)
+    assert qsim.get_option(qsim.OPT_CLUSTER_SETS) == old
