@@ -115,6 +115,14 @@ __device__ __forceinline__ uint32_t xcd_block() {
     return (g & 7) == 0 ? (b & 7) * (g >> 3) + (b >> 3) : b;
 }
 
+// Lane l's value of x, in every lane (l uniform).
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Row sums of a plain complex128 d x d matrix, times amp, into LDS: eight
 // threads per row, each summing every eighth entry (so all loads are in
 // flight at once), combined by shuffles within the eight. Every thread of the
@@ -1407,6 +1415,88 @@ struct FoldIn {
     c_epi* epi1;      // the first epilogue relative to this cluster's targets, or null
 };
 
+// A column's diagonal-epilogue factor (col_factor), split for a wave that
+// walks many tiles: terms on the state bits above the tile (uniform in the
+// wave, new each tile) and terms on the column bits (fixed per lane) are
+// separate, and a CZ pair with one qubit of each kind is a mask over the
+// column index, set per tile. Target bits take no part (the host moved such
+// terms into the matrix or the mask over rows).
+// Tile part of base (tile bits zero): bit 0 the sign, bits 1-6 the mask over
+// rows, bits 7-11 the mask over the column index; the phase in (cr, ci).
+__device__ __forceinline__ uint32_t epi_tile_part(c_epi* __restrict__ e, uint64_t base, uint64_t colmask,
+                                                  double& cr, double& ci) {
+    uint32_t sgn = 0, w = 0, cross = 0;
+    const int ncc = e->n_cc;
+    for (int i = 0; i < ncc; ++i) {
+        const int a = e->cc[i][0], b = e->cc[i][1];
+        const bool ca = (colmask >> a) & 1, cb = (colmask >> b) & 1;
+        if (!ca && !cb)
+            sgn ^= (uint32_t)((base >> a) & (base >> b) & 1);
+        else if (ca && !cb)
+            cross ^= (uint32_t)((base >> b) & 1) << __popcll(colmask & ((uint64_t(1) << a) - 1));
+        else if (!ca && cb)
+            cross ^= (uint32_t)((base >> a) & 1) << __popcll(colmask & ((uint64_t(1) << b) - 1));
+    }
+    const int nm = e->n_mix;
+    for (int i = 0; i < nm; ++i) {
+        const int b = e->mix[i][1];
+        if (!((colmask >> b) & 1)) w ^= (uint32_t)((base >> b) & 1) << e->mix[i][0];
+    }
+    cr = 1.0;
+    ci = 0.0;
+    const int np = e->n_ph;
+    for (int i = 0; i < np; ++i) {
+        const int q = e->ph_q[i];
+        if (!((colmask >> q) & 1) && ((base >> q) & 1)) {
+            const double a = e->ph[i][0], b = e->ph[i][1];
+            const double t = cr * a - ci * b;
+            ci = cr * b + ci * a;
+            cr = t;
+        }
+    }
+    return sgn | (w << 1) | (cross << 7);
+}
+
+// Column part of the same factor (cbits: the column's state bits).
+__device__ __forceinline__ void epi_lane_part(c_epi* __restrict__ e, uint64_t cbits, uint64_t colmask, uint32_t& sgn,
+                                              uint32_t& w, double& cr, double& ci) {
+    sgn = 0;
+    w = 0;
+    const int ncc = e->n_cc;
+    for (int i = 0; i < ncc; ++i) {
+        const int a = e->cc[i][0], b = e->cc[i][1];
+        if (((colmask >> a) & 1) && ((colmask >> b) & 1)) sgn ^= (uint32_t)((cbits >> a) & (cbits >> b) & 1);
+    }
+    const int nm = e->n_mix;
+    for (int i = 0; i < nm; ++i) {
+        const int b = e->mix[i][1];
+        if ((colmask >> b) & 1) w ^= (uint32_t)((cbits >> b) & 1) << e->mix[i][0];
+    }
+    cr = 1.0;
+    ci = 0.0;
+    const int np = e->n_ph;
+    for (int i = 0; i < np; ++i) {
+        const int q = e->ph_q[i];
+        if (((colmask >> q) & 1) && ((cbits >> q) & 1)) {
+            const double a = e->ph[i][0], b = e->ph[i][1];
+            const double t = cr * a - ci * b;
+            ci = cr * b + ci * a;
+            cr = t;
+        }
+    }
+}
+
+// Combine the two parts for column index p (tile part read from its lane).
+__device__ __forceinline__ ColFactor<float> epi_combine(uint32_t tb, double tr, double ti, uint32_t ls, uint32_t lw,
+                                                        double lr, double li, int p) {
+    ColFactor<float> f;
+    f.sgn = ls ^ (tb & 1u) ^ ((uint32_t)__popc((uint32_t)p & (tb >> 7) & 31u) & 1u);
+    f.w = lw ^ ((tb >> 1) & 63u);
+    f.cr = (float)(tr * lr - ti * li);
+    f.ci = (float)(tr * li + ti * lr);
+    return f;
+}
+
 template <bool LOWT, bool FOLD = false>
 __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const half8* Ah, const half8* Al, float2* L,
                                               c_epi* __restrict__ epi, const StageGeom& sg, uint64_t tile,
@@ -1461,6 +1551,22 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
 
     if (tile >= tile_end) return;
     const uint64_t last = tile_end - 1;
+    // FOLD: the epilogue factors of both clusters and the w index, split into
+    // column parts (here, once) and tile parts (lane j forms those of the
+    // wave's tile it + j once per 64 tiles; each tile reads them from its lane)
+    uint64_t colmask = 0;
+    uint32_t l1s = 0, l1w = 0, l2s = 0, l2w = 0, t1b = 0, t2b = 0;
+    double l1r = 1.0, l1i = 0.0, l2r = 1.0, l2i = 0.0, t1r = 1.0, t1i = 0.0, t2r = 1.0, t2i = 0.0;
+    int icl = 0, it = 0;
+    if constexpr (FOLD) {
+#pragma unroll
+        for (int b = 0; b < C; ++b) colmask |= uint64_t(1) << sg.tb[sg.cpos[b]];
+        if (fin->epi1 != nullptr) epi_lane_part(fin->epi1, cbits, colmask, l1s, l1w, l1r, l1i);
+        if (epi != nullptr) epi_lane_part(epi, cbits, colmask, l2s, l2w, l2r, l2i);
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            if (m < fin->k1) icl |= (int)((cbits >> fin->t1[m]) & 1) << m;
+    }
     vf4 R[NL];
     auto load_tile = [&](uint64_t t0) {  // t0: the tile's base (uniform)
 #pragma unroll
@@ -1479,19 +1585,34 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
         asm volatile("" : "+s"(rmask[0]), "+s"(rmask[1]), "+s"(rmask[2]), "+s"(rmask[3]), "+s"(rmask[4]));
         asm volatile("" : "+s"(imask[0]), "+s"(imask[1]), "+s"(imask[2]), "+s"(imask[3]));
         float X[2 * HX];
-        ColFactor<float> f1{0u, 0u, 1.0f, 0.0f};
+        ColFactor<float> f1{0u, 0u, 1.0f, 0.0f}, f2{0u, 0u, 1.0f, 0.0f};
         if constexpr (FOLD) {
             // the column's inputs from the closed form: w at the first cluster's
             // index (its qubits among the column bits, then among the row bits),
             // negated where a gate of the first epilogue couples a row bit with
             // a column bit; the column-only factor of that epilogue joins the
             // output factor
-            const uint64_t base = tile_base<NT>(tile, sg) | cbits;
-            int ic = 0;
+            if ((it & 63) == 0) {
+                const uint64_t bj = tile_base<NT>(tile + (uint64_t)lane * stride, sg);  // past the end: unused
+                t1b = 0;
+                t2b = 0;
+                if (fin->epi1 != nullptr) t1b = epi_tile_part(fin->epi1, bj, colmask, t1r, t1i);
+                if (epi != nullptr) t2b = epi_tile_part(epi, bj, colmask, t2r, t2i);
+                int ict = 0;
 #pragma unroll
-            for (int m = 0; m < 6; ++m)
-                if (m < fin->k1) ic |= (int)((base >> fin->t1[m]) & 1) << m;
-            if (fin->epi1 != nullptr) f1 = col_factor<float>(fin->epi1, base);
+                for (int m = 0; m < 6; ++m)
+                    if (m < fin->k1) ict |= (int)((bj >> fin->t1[m]) & 1) << m;
+                t1b |= (uint32_t)ict << 12;
+            }
+            const int sl = it & 63;
+            const uint32_t b1 = (uint32_t)__builtin_amdgcn_readlane((int)t1b, sl);
+            const int ic = icl | (int)((b1 >> 12) & 63u);
+            if (fin->epi1 != nullptr)
+                f1 = epi_combine(b1, readlane_f64(t1r, sl), readlane_f64(t1i, sl), l1s, l1w, l1r, l1i, p);
+            if (epi != nullptr)
+                f2 = epi_combine((uint32_t)__builtin_amdgcn_readlane((int)t2b, sl), readlane_f64(t2r, sl),
+                                 readlane_f64(t2i, sl), l2s, l2w, l2r, l2i, p);
+            ++it;
             const int yh = h ? fin->ymask[K - 1] : 0;
 #pragma unroll
             for (int j = 0; j < HX; ++j) {
@@ -1581,7 +1702,11 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
         for (int j = 0; j < 2 * HX; ++j) X[j] = acc[j / 16][j % 16] * unscale;
         if (has_epi) {
             ColFactor<float> f{0u, 0u, 1.0f, 0.0f};
-            if (epi != nullptr) f = col_factor<float>(epi, tb0 | cbits);
+            if constexpr (FOLD) {
+                f = f2;
+            } else {
+                if (epi != nullptr) f = col_factor<float>(epi, tb0 | cbits);
+            }
             if constexpr (FOLD) {  // the first epilogue's column-only sign and phase
                 f.sgn ^= f1.sgn;
                 const float r = f.cr * f1.cr - f.ci * f1.ci;
@@ -2045,13 +2170,6 @@ __device__ __forceinline__ void store_pair(typename Cplx<T>::type* p, const type
 template <>
 __device__ __forceinline__ void store_pair<float>(float2* p, const float2 (&v)[2]) {
     *reinterpret_cast<float4*>(p) = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
-}
-
-__device__ __forceinline__ double readlane_f64(double x, int l) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 template <typename T, int U>
