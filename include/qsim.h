@@ -245,7 +245,15 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * interaction graph (all ready gates inside the set) besides the clusters
  * grown gate by gate from a seed, and keep the schedule with fewer ops
  * (greedy) or the smaller predicted time (cost-driven); 0 grows from seeds
- * only (Sec. 3.6.1's greedy), read when a schedule is built. Errors:
+ * only (Sec. 3.6.1's greedy), read when a schedule is built.
+ * QSIM_OPT_BATCH_ORDER: the order in which a batch's work items are handed
+ * out, read when a batch is planned: 0 (default) level order (the j-th op
+ * of every circuit before any (j+1)-th), 1 critical path first (a list
+ * schedule simulated on the host: an op's items become available when the
+ * circuit's previous op is done, circuits with the longest remaining chain
+ * go first; it shortens the end of the launch, where only the deepest
+ * circuits are left, but costs more planning than it saves on the
+ * 512-circuit workload). Either order is free of deadlock. Errors:
  * QSIM_E_INVALID for an unknown option or an out-of-range value. */
 typedef enum {
     QSIM_OPT_CLUSTER_VARIANT = 1,
@@ -256,7 +264,8 @@ typedef enum {
     QSIM_OPT_FOLD_INIT = 6,
     QSIM_OPT_PAIR = 7,
     QSIM_OPT_PAIR_TILE = 8,
-    QSIM_OPT_CLUSTER_SETS = 9
+    QSIM_OPT_CLUSTER_SETS = 9,
+    QSIM_OPT_BATCH_ORDER = 10
 } qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);

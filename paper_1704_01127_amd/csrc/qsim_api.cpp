@@ -75,6 +75,7 @@ int g_fold_init = 2;
 int g_pair = 0;
 int g_pair_tile = 11;
 int g_cluster_sets = 1;
+int g_batch_order = 0;
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
@@ -946,6 +947,11 @@ qsim_status qsim_set_option(int option, int value) {
         g_cluster_sets = value;
         return QSIM_OK;
     }
+    if (option == QSIM_OPT_BATCH_ORDER) {
+        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "batch order must be 0 or 1");
+        g_batch_order = value;
+        return QSIM_OK;
+    }
     if (option == QSIM_OPT_BATCH_ITEM_TILES) {
         if (value < 1 || value > 4096 || (value & (value - 1)))
             return fail(QSIM_E_INVALID, "tiles per batch item must be a power of two in [1, 4096]");
@@ -989,6 +995,7 @@ int qsim_get_option(int option) {
     if (option == QSIM_OPT_PAIR) return g_pair;
     if (option == QSIM_OPT_PAIR_TILE) return g_pair_tile;
     if (option == QSIM_OPT_CLUSTER_SETS) return g_cluster_sets;
+    if (option == QSIM_OPT_BATCH_ORDER) return g_batch_order;
     return -1;
 }
 

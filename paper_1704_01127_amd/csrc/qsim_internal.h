@@ -161,6 +161,7 @@ extern int g_fold_init;         // fold the uniform initialisation into the firs
 extern int g_pair;              // apply consecutive clusters of <= 5 qubits (complex64) two per pass
 extern int g_pair_tile;         // tile bits of the pair kernel: 11 (8 waves) or 10 (12 waves)
 extern int g_cluster_sets;  // scheduler: candidate qubit sets on (1) or off (0)
+extern int g_batch_order;   // batch ticket order: 0 level order (default), 1 critical path first
 
 // Bytes of a cluster matrix in each layout.
 inline int64_t matrix_bytes(int k, int layout, bool dbl) {

@@ -220,6 +220,7 @@ OPT_FOLD_INIT = 6
 OPT_PAIR = 7
 OPT_PAIR_TILE = 8
 OPT_CLUSTER_SETS = 9
+OPT_BATCH_ORDER = 10
 
 
 def set_option(option: int, value: int):

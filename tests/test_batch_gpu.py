@@ -44,10 +44,19 @@ def check_against_oracle(batch, circs, skip_trailing_diag=False):
 @pytest.fixture(autouse=True)
 def _reset_options():
     fold = qsim.get_option(qsim.OPT_FOLD_INIT)
+    order = qsim.get_option(qsim.OPT_BATCH_ORDER)
     yield
     qsim.set_option(qsim.OPT_BATCH_GRID, 0)
     qsim.set_option(qsim.OPT_BATCH_PAD, 0)
     qsim.set_option(qsim.OPT_FOLD_INIT, fold)
+    qsim.set_option(qsim.OPT_BATCH_ORDER, order)
+
+
+@pytest.fixture(params=[1, 0], ids=["critical_path", "level"])
+def batch_order(request):
+    """Plan with each work-item order (restored by _reset_options)."""
+    qsim.set_option(qsim.OPT_BATCH_ORDER, request.param)
+    return request.param
 
 
 @pytest.mark.parametrize("kmax", [5, 6])
@@ -77,7 +86,7 @@ def test_batch_folded_start(fold, kmax):
     dict(kmax=6, fuse_diag=False),
     dict(kmax=6, skip_initial_h=False),
 ])
-def test_batch_matches_oracle(opts):
+def test_batch_matches_oracle(opts, batch_order):
     circs = small_batch(12, seed0=3)
     b = qsim.Batch(circs, **opts)
     st = b.run()
@@ -86,7 +95,7 @@ def test_batch_matches_oracle(opts):
 
 
 @pytest.mark.parametrize("grid", [1, 3, 64])
-def test_batch_any_grid(grid):
+def test_batch_any_grid(grid, batch_order):
     """One work-group runs every item in ticket order; a few work-groups
     wait on each other; results do not depend on the grid."""
     qsim.set_option(qsim.OPT_BATCH_GRID, grid)

@@ -179,9 +179,11 @@ def test_candidate_sets_reduce_passes():
         qsim.set_option(qsim.OPT_CLUSTER_SETS, old)
 
 
-def test_cluster_sets_option_range():
-    old = qsim.get_option(qsim.OPT_CLUSTER_SETS)
+@pytest.mark.parametrize("option", [qsim.OPT_CLUSTER_SETS, qsim.OPT_BATCH_ORDER])
+def test_planning_option_range(option):
+    old = qsim.get_option(option)
     assert old in (0, 1)
-    with pytest.raises(qsim.QsimError):
-        qsim.set_option(qsim.OPT_CLUSTER_SETS, 2)
-    assert qsim.get_option(qsim.OPT_CLUSTER_SETS) == old
+    for bad in (-1, 2):
+        with pytest.raises(qsim.QsimError):
+            qsim.set_option(option, bad)
+    assert qsim.get_option(option) == old
