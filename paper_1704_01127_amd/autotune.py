@@ -52,7 +52,7 @@ def diag_ms(state, n, reps):
     return statistics.median(ts)
 
 
-def tune_variants(n, dt, reps, seed, log):
+def tune_variants(n, dt, reps, seed, log, trials=8):
     rng = np.random.default_rng(seed)
     state = qsim.State(n, dt, init="uniform", kmax=6)
     table = {}
@@ -62,7 +62,7 @@ def tune_variants(n, dt, reps, seed, log):
         row = []
         for cls in range(4):
             t = {0: [], 1: []}
-            for trial in range(2):
+            for trial in range(trials):
                 qs = targets_for(n, k, cls, rng)
                 for v in (0, 1):
                     qsim.set_option(qsim.OPT_CLUSTER_VARIANT, v)
@@ -184,6 +184,10 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-circuits", type=int, default=512)
     ap.add_argument("--only-batch", action="store_true", help="re-tune the batch launch shape in an existing table")
+    ap.add_argument("--only-variants", action="store_true",
+                    help="re-tune the cluster kernel variants in an existing table")
+    ap.add_argument("--variant-trials", type=int, default=8,
+                    help="random target sets per (k, low class) in the variant search")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
 
@@ -201,12 +205,22 @@ def main(argv=None):
         with open(args.out, "w") as f:
             json.dump(out, f, indent=1)
         return out
+    if args.only_variants:
+        qsim.load_tuning(args.out)
+        with open(args.out) as f:
+            out = json.load(f)
+        for dt in args.dtypes.split(","):
+            out["variants"][dt] = tune_variants(args.n_variant if dt == "c64" else args.n_variant - 1, dt,
+                                                args.reps, args.seed, log, args.variant_trials)
+        with open(args.out, "w") as f:
+            json.dump(out, f, indent=1)
+        return out
     out = {"device": torch.cuda.get_device_name(0), "n_ref": args.n, "variants": {}, "cost_us": {},
            "best": {}, "created": time.strftime("%Y-%m-%d %H:%M:%S")}
     dts = args.dtypes.split(",")
     for dt in dts:
         out["variants"][dt] = tune_variants(args.n_variant if dt == "c64" else args.n_variant - 1, dt, args.reps,
-                                            args.seed, log)
+                                            args.seed, log, args.variant_trials)
     apply_variants(out["variants"])
     for dt in dts:
         out["cost_us"][dt] = tune_costs(args.n, dt, args.reps, args.seed, log)
