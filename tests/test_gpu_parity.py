@@ -692,6 +692,32 @@ def test_30q_depth25_mirror_float32():
     torch.cuda.empty_cache()
 
 
+BENCH_FORM = dict(scheduler="learned", fuse_diag=True, skip_initial_h=True)
+
+
+@pytest.mark.parametrize("R,C,drop,dt,kmax,bar", [
+    (5, 6, (), "c64", 6, 1e-6),
+    (5, 6, (), "c128", 5, 1e-12),
+    (5, 7, ((4, 6),), "c64", 6, 1e-6),
+], ids=["30q-f32", "30q-f64", "34q-f32"])
+def test_mirror_bench_form(R, C, drop, dt, kmax, bar):
+    """The depth-25 grid circuits followed by their inverse, run the way the
+    benchmark runs them (learned schedule, diagonal epilogues, the leading H
+    layer as the uniform start folded into the first clusters): the state
+    must return to |0...0> (float32 >= 1 - 1e-6, float64 >= 1 - 1e-12) with
+    unit norm; at 34 qubits no host oracle fits, this is its whole-circuit pin."""
+    circ = mirror_circuit(supremacy_circuit(R, C, 25, 0, list(drop)))
+    s = make_state(circ.n, dt)
+    st = s.run_circuit(circ.gates, kmax=kmax, **BENCH_FORM)
+    assert st["n_ops"] > 0
+    a0 = s.amps[0].item()
+    assert abs(a0) ** 2 >= 1 - bar, abs(a0) ** 2
+    norm, _, _ = s.probs()
+    assert abs(norm - 1) <= (1e-12 if dt == "c128" else 1e-5)
+    del s
+    torch.cuda.empty_cache()
+
+
 # ------------------------------------------------------------------ errors
 def test_argument_errors():
     s = make_state(6, "c64")
