@@ -2425,35 +2425,43 @@ __global__ __launch_bounds__(256) void k_init_cluster(typename Cplx<T>::type* __
 // applies the cluster's gates in order, in float64 (the matrix is reused for
 // all 2^(n-k) columns of the state, Sec. 3.2, so building it is cheap). The
 // result is then written in the layout of the kernel that will apply it.
+// The columns are interleaved in LDS (real / imaginary part c of entry i of
+// column x at (2 i + c) * kBuildThreads + x): the threads touch consecutive
+// words at every step (a column per contiguous block put them a multiple of
+// 256 words apart, all in one bank).
+constexpr int kBuildThreads = 64;
+// entry i (2 per amplitude: real, imaginary) of the column at v
+__device__ __forceinline__ double& BV(double* v, int i) { return v[i * kBuildThreads]; }
 __device__ void build_apply_1q(double* v, int D, int a, const double m[8]) {
     for (int i = 0; i < D; ++i) {
         if ((i >> a) & 1) continue;
         const int j = i | (1 << a);
-        const double ar = v[2 * i], ai = v[2 * i + 1], br = v[2 * j], bi = v[2 * j + 1];
-        v[2 * i] = (m[0] * ar - m[1] * ai) + (m[2] * br - m[3] * bi);
-        v[2 * i + 1] = (m[0] * ai + m[1] * ar) + (m[2] * bi + m[3] * br);
-        v[2 * j] = (m[4] * ar - m[5] * ai) + (m[6] * br - m[7] * bi);
-        v[2 * j + 1] = (m[4] * ai + m[5] * ar) + (m[6] * bi + m[7] * br);
+        const double ar = BV(v, 2 * i), ai = BV(v, 2 * i + 1), br = BV(v, 2 * j), bi = BV(v, 2 * j + 1);
+        BV(v, 2 * i) = (m[0] * ar - m[1] * ai) + (m[2] * br - m[3] * bi);
+        BV(v, 2 * i + 1) = (m[0] * ai + m[1] * ar) + (m[2] * bi + m[3] * br);
+        BV(v, 2 * j) = (m[4] * ar - m[5] * ai) + (m[6] * br - m[7] * bi);
+        BV(v, 2 * j + 1) = (m[4] * ai + m[5] * ar) + (m[6] * bi + m[7] * br);
     }
 }
 
-__global__ __launch_bounds__(64) void k_build(const BuildOp* __restrict__ ops, const BuildGate* __restrict__ gates,
-                                              const double* __restrict__ dense, char* __restrict__ mat_base) {
-    __shared__ double Vs[64 * 64 * 2];
-    __shared__ double Ws[64 * 64 * 2];
+__global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restrict__ ops,
+                                                         const BuildGate* __restrict__ gates,
+                                                         const double* __restrict__ dense, char* __restrict__ mat_base) {
+    __shared__ double Vs[64 * 2 * kBuildThreads];
+    __shared__ double Ws[64 * 2 * kBuildThreads];
     const BuildOp op = ops[blockIdx.x];
     const int k = op.k, D = 1 << k, x = threadIdx.x;
     if (x < D) {
-        double* v = Vs + x * D * 2;
-        double* w = Ws + x * D * 2;
-        for (int i = 0; i < 2 * D; ++i) v[i] = 0.0;
-        v[2 * x] = 1.0;
+        double* v = Vs + x;
+        double* w = Ws + x;
+        for (int i = 0; i < 2 * D; ++i) BV(v, i) = 0.0;
+        BV(v, 2 * x) = 1.0;
         for (int gi = 0; gi < op.n_gates; ++gi) {
             const BuildGate bg = gates[op.gate0 + gi];
             if (bg.kind == G_CZ) {
                 const int m = (1 << bg.pos[0]) | (1 << bg.pos[1]);
                 for (int i = 0; i < D; ++i)
-                    if ((i & m) == m) { v[2 * i] = -v[2 * i]; v[2 * i + 1] = -v[2 * i + 1]; }
+                    if ((i & m) == m) { BV(v, 2 * i) = -BV(v, 2 * i); BV(v, 2 * i + 1) = -BV(v, 2 * i + 1); }
             } else if (bg.kind == G_DENSE) {
                 const int dq = bg.nq, dd = 1 << dq;
                 const double* u = dense + bg.dense_off;
@@ -2468,13 +2476,13 @@ __global__ __launch_bounds__(64) void k_build(const BuildOp* __restrict__ ops, c
                         int src = rest;
                         for (int j = 0; j < dq; ++j) src |= ((xl >> j) & 1) << bg.pos[j];
                         const double mr = u[2 * (yl * dd + xl)], mi = u[2 * (yl * dd + xl) + 1];
-                        sr += mr * v[2 * src] - mi * v[2 * src + 1];
-                        si += mr * v[2 * src + 1] + mi * v[2 * src];
+                        sr += mr * BV(v, 2 * src) - mi * BV(v, 2 * src + 1);
+                        si += mr * BV(v, 2 * src + 1) + mi * BV(v, 2 * src);
                     }
-                    w[2 * y] = sr;
-                    w[2 * y + 1] = si;
+                    BV(w, 2 * y) = sr;
+                    BV(w, 2 * y + 1) = si;
                 }
-                for (int i = 0; i < 2 * D; ++i) v[i] = w[i];
+                for (int i = 0; i < 2 * D; ++i) BV(v, i) = BV(w, i);
             } else {
                 double m[8];
                 gate2x2(bg.kind, bg.theta, m);
@@ -2483,9 +2491,9 @@ __global__ __launch_bounds__(64) void k_build(const BuildOp* __restrict__ ops, c
         }
     }
     __syncthreads();
-    // M[y][x] = Vs[x][y]
-    auto Mre = [&](int y, int xx) { return Vs[xx * D * 2 + 2 * y]; };
-    auto Mim = [&](int y, int xx) { return Vs[xx * D * 2 + 2 * y + 1]; };
+    // M[y][x] = entry y of column x
+    auto Mre = [&](int y, int xx) { return Vs[(2 * y) * kBuildThreads + xx]; };
+    auto Mim = [&](int y, int xx) { return Vs[(2 * y + 1) * kBuildThreads + xx]; };
     // entry (R, Kc) of the real-split matrix [[Re, -Im], [Im, Re]]
     auto Ars = [&](int y, int a, int xx, int b) {
         const double re = Mre(y, xx), im = Mim(y, xx);
@@ -2834,7 +2842,7 @@ hipError_t launch_init_cluster(void* psi, bool dbl, const ClusterGeom& g, const 
 hipError_t launch_build(const BuildOp* ops, int n_ops, const BuildGate* gates, const double* dense,
                         char* mat_base, hipStream_t st) {
     if (n_ops <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build, dim3(n_ops), dim3(64), 0, st, ops, gates, dense, mat_base);
+    hipLaunchKernelGGL(k_build, dim3(n_ops), dim3(kBuildThreads), 0, st, ops, gates, dense, mat_base);
     return hipGetLastError();
 }
 
