@@ -44,12 +44,16 @@ def kernel_name(rec, k6_kernel=2, pair_tile=11) -> str:
         return "k_cluster_f32_pair10<12>" if ten else "k_cluster_f32_multi<2, 8>"
     if not rec.get("mfma"):
         return "k_cluster_valu<float, %d>" % k
+    b = lambda x: "true" if x else "false"  # noqa: E731
     if k == 6 and k6_kernel in (1, 2):
-        name = "split6s" if k6_kernel == 2 and rec.get("staged") else ("split6" if k6_kernel == 2 else "gauss6")
-        return "k_cluster_f32_%s<%s>" % (name, "true" if lowt else "false")
+        if k6_kernel == 2 and rec.get("staged"):
+            return "k_cluster_f32_split6s<%s>" % b(lowt)
+        if k6_kernel == 2:  # the direct kernel: its second flag sums the reductions (a run's last op)
+            return "k_cluster_f32_split6<%s, %s>" % (b(lowt), b(rec.get("stats")))
+        return "k_cluster_f32_gauss6<%s>" % b(lowt)
     if rec.get("staged"):
-        return "k_cluster_f32_stage<%d, 6, %s>" % (k, "true" if lowt else "false")
-    return "k_cluster_f32_mfma<%d, %d, %s>" % (k, 1 if k == 6 else 2, "true" if lowt else "false")
+        return "k_cluster_f32_stage<%d, 6, %s>" % (k, b(lowt))
+    return "k_cluster_f32_mfma<%d, %d, %s, %s>" % (k, 1 if k == 6 else 2, b(lowt), b(rec.get("stats")))
 
 
 def parse():
@@ -184,8 +188,9 @@ def main():
     circ = supremacy_circuit(args.rows, args.cols, args.depth, args.seed, drop=drop)
     n = circ.n
     gates = circ.gates
+    # fused_stats: the last cluster pass also sums the reductions the step reports
     fused_opts = dict(kmax=args.kmax, scheduler=args.scheduler, fuse_diag=not args.no_fuse_diag,
-                      skip_trailing_diag=True, skip_initial_h=True)
+                      skip_trailing_diag=True, skip_initial_h=True, fused_stats=True)
     pergate_opts = dict(scheduler="per_gate", skip_trailing_diag=True, skip_initial_h=True)
 
     def writes_whole_state(opts):

@@ -110,8 +110,15 @@ typedef struct {
                                    the whole vector (its contents are not read; Sec. 3.6);
                                    otherwise the caller promises the state holds |0...0> */
     int32_t record_timings;     /* time every launched op with HIP events (slows the run) */
-    int32_t reserved[2];        /* reserved[0]: qsim_dtype the cost models assume in
-                                   qsim_schedule (qsim_run_circuit uses the state's); 0 = C64 */
+    int32_t schedule_dtype;     /* qsim_dtype the cost models assume in qsim_schedule
+                                   (qsim_run_circuit uses the state's); 0 = C64 */
+    int32_t fused_stats;        /* when the run's last op is a cluster on a complex64 state applied
+                                   by a direct matrix-core kernel (k = 4..6), that kernel also sums
+                                   the float64 norm, sum of p^2 and entropy of the amplitudes it
+                                   stores, and the next qsim_probs with dev_out = NULL returns them
+                                   without reading the state again. Any library call that changes
+                                   the state or computes other reductions discards them; a caller
+                                   that writes the amplitudes itself must not set this flag. */
 } qsim_run_opts;
 
 typedef struct {

@@ -108,6 +108,10 @@ struct qsim_state_s {
     size_t ws_bytes = 0;
     hipStream_t st = nullptr;
     int kmax_ws = 6;  // largest k the workspace slots can hold
+    // the last run's final cluster launch left the sums of p, p^2, -p ln p of
+    // the current state in the workspace's partial area (stats_blocks of them)
+    bool stats_ready = false;
+    unsigned stats_blocks = 0;
     // op timing (record_timings): HIP events around every launch
     bool recording = false;
     std::vector<OpRecord> recs;
@@ -218,6 +222,7 @@ struct Chunk {
         int slot2, epi2;
         int q0, q1;
         double m[8];
+        bool stats;      // kind 0: also sum p, p^2, -p ln p of the stored state (the run's last op)
     };
     std::vector<Item> items;
     int slots_used = 0;
@@ -294,7 +299,8 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
         if (it.kind == 0 || it.kind == 6 || it.kind == 7 || it.kind == 8) {
             r.k = it.geom.k;
             for (int j = 0; j < it.geom.k; ++j) r.qubits[j] = it.geom.t[j];
-            r.flags = (it.epi >= 0 ? 1 : 0) | (variant == 1 ? 2 : 0) | (it.layout != LAYOUT_PLAIN ? 4 : 0);
+            r.flags = (it.epi >= 0 ? 1 : 0) | (variant == 1 ? 2 : 0) | (it.layout != LAYOUT_PLAIN ? 4 : 0) |
+                      (it.stats ? 8 : 0);
         } else if (it.kind >= 2) {
             r.k = it.kind == 4 ? 2 : 1;
             r.qubits[0] = it.q0;
@@ -303,10 +309,17 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
         HIP_TRY(rec_begin(s, r), "event record");
         hipError_t e = hipSuccess;
         switch (it.kind) {
-            case 0:
+            case 0: {
+                double* sp = it.stats ? reinterpret_cast<double*>(s->ws) : nullptr;
+                unsigned nb = 0;
                 e = launch_cluster(s->psi, s->dbl, it.geom, mats + it.slot * sb, it.layout,
-                                   it.epi >= 0 ? epis + it.epi : nullptr, variant, s->st);
+                                   it.epi >= 0 ? epis + it.epi : nullptr, variant, s->st, sp, sp ? &nb : nullptr);
+                if (e == hipSuccess && sp) {
+                    s->stats_ready = true;
+                    s->stats_blocks = nb;
+                }
                 break;
+            }
             case 1: e = launch_diag(s->psi, s->dbl, s->n, epis + it.epi, s->st); break;
             case 2: e = launch_gate1q(s->psi, s->dbl, s->n, it.q0, it.m, s->st); break;
             case 3: e = launch_phase1q(s->psi, s->dbl, s->n, it.q0, it.m[0], it.m[1], s->st); break;
@@ -711,6 +724,7 @@ qsim_status qsim_destroy(qsim_state s) {
 
 qsim_status qsim_init_state(qsim_state s, qsim_init init) {
     if (qsim_status r = check_state(s)) return r;
+    s->stats_ready = false;
     if (init == QSIM_INIT_KEEP) return QSIM_OK;
     if (init != QSIM_INIT_ZERO && init != QSIM_INIT_UNIFORM) return fail(QSIM_E_INVALID, "unknown init");
     HIP_TRY(launch_init(s->psi, s->n, s->dbl, init == QSIM_INIT_ZERO ? 0 : 1, s->st), "init launch");
@@ -719,6 +733,7 @@ qsim_status qsim_init_state(qsim_state s, qsim_init init) {
 
 qsim_status qsim_apply_cluster(qsim_state s, int k, const int32_t* qubits, const double* mat) {
     if (qsim_status r = check_state(s)) return r;
+    s->stats_ready = false;
     if (!qubits || !mat) return fail(QSIM_E_INVALID, "null argument");
     if (k < 1 || k > kMaxK) return fail(QSIM_E_UNSUPPORTED, "k must be in [1, 6]");
     if (k > s->kmax_ws) return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
@@ -738,6 +753,7 @@ qsim_status qsim_apply_cluster(qsim_state s, int k, const int32_t* qubits, const
 qsim_status qsim_apply_diag(qsim_state s, int n_pairs, const int32_t* cz_pairs, int n_phase,
                             const int32_t* phase_qubits, const double* phase_theta) {
     if (qsim_status r = check_state(s)) return r;
+    s->stats_ready = false;
     if (n_pairs < 0 || n_phase < 0) return fail(QSIM_E_INVALID, "negative count");
     if ((n_pairs && !cz_pairs) || (n_phase && (!phase_qubits || !phase_theta)))
         return fail(QSIM_E_INVALID, "null argument");
@@ -761,6 +777,7 @@ qsim_status qsim_apply_diag(qsim_state s, int n_pairs, const int32_t* cz_pairs, 
 
 qsim_status qsim_apply_gate(qsim_state s, const qsim_gate* gate) {
     if (qsim_status r = check_state(s)) return r;
+    s->stats_ready = false;
     if (!gate) return fail(QSIM_E_INVALID, "null gate");
     if (qsim_status r = check_gate(s->n, *gate, 0)) return r;
     if (gate->kind == G_DENSE && gate->k > s->kmax_ws)
@@ -780,6 +797,7 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     SchedOpts so = to_sched_opts(opts);
     if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 6]");
     if (so.mode != 0 && so.kmax > s->kmax_ws) return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
+    s->stats_ready = false;
     for (int i = 0; i < n_gates; ++i)
         if (gates[i].kind == G_DENSE && gates[i].k > s->kmax_ws)
             return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
@@ -856,6 +874,14 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
         if (r != QSIM_OK) return r;
         st.n_ops++;
     }
+    // fused_stats: the last op, when it is a cluster of a kernel that can, also
+    // sums the quantities qsim_probs reports, so they need no further pass
+    if (opts && opts->fused_stats && !c.items.empty()) {
+        Chunk::Item& last = c.items.back();
+        if (last.kind == 0 &&
+            cluster_stats_supported(s->dbl, last.geom.k, last.layout, cluster_variant_for(s->dbl, last.geom, last.layout)))
+            last.stats = true;
+    }
     if (qsim_status r = flush(s, c)) return r;
     const auto t2 = std::chrono::steady_clock::now();
     st.schedule_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -870,7 +896,12 @@ qsim_status qsim_probs(qsim_state s, void* dev_out, qsim_dtype out_dt, double* n
     if (dev_out && out_dt != QSIM_C64 && out_dt != QSIM_C128) return fail(QSIM_E_INVALID, "unknown out dtype");
     double* part = reinterpret_cast<double*>(s->ws);
     double* res = reinterpret_cast<double*>(s->ws + kResOff);
-    HIP_TRY(launch_stats(s->psi, s->dbl, s->n, dev_out, out_dt == QSIM_C128, part, res, s->st), "stats launch");
+    if (!dev_out && s->stats_ready) {  // the sums of the last run's final pass
+        HIP_TRY(launch_reduce_stats(part, s->stats_blocks, res, s->st), "stats reduce launch");
+    } else {
+        s->stats_ready = false;  // the partial area is rewritten
+        HIP_TRY(launch_stats(s->psi, s->dbl, s->n, dev_out, out_dt == QSIM_C128, part, res, s->st), "stats launch");
+    }
     double h[8];
     HIP_TRY(hipMemcpyAsync(h, res, 8 * sizeof(double), hipMemcpyDeviceToHost, s->st), "stats copy");
     HIP_TRY(hipStreamSynchronize(s->st), "stats sync");
@@ -887,6 +918,7 @@ qsim_status qsim_compare(qsim_state s, const void* dev_ref, qsim_dtype ref_dt, d
     if (ref_dt != QSIM_C64 && ref_dt != QSIM_C128) return fail(QSIM_E_INVALID, "unknown reference dtype");
     double* part = reinterpret_cast<double*>(s->ws);
     double* res = reinterpret_cast<double*>(s->ws + kResOff);
+    s->stats_ready = false;  // the partial area is rewritten
     HIP_TRY(launch_compare(s->psi, s->dbl, s->n, dev_ref, ref_dt == QSIM_C128, part, res, s->st), "compare launch");
     double h[8];
     HIP_TRY(hipMemcpyAsync(h, res, 8 * sizeof(double), hipMemcpyDeviceToHost, s->st), "compare copy");
@@ -1032,7 +1064,7 @@ qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates, con
     SchedOpts so = to_sched_opts(opts);
     if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 6]");
     const Schedule S = make_schedule(n_qubits, to_sgates(gates, n_gates), so,
-                                     cost_fn(opts, n_qubits, opts && opts->reserved[0] == QSIM_C128));
+                                     cost_fn(opts, n_qubits, opts && opts->schedule_dtype == QSIM_C128));
     if (n_ops) *n_ops = (int)S.ops.size();
     if ((int)S.ops.size() > op_cap) return fail(QSIM_E_INVALID, "op_cap too small");
     if (gate_op)

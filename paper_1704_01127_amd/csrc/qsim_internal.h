@@ -195,8 +195,17 @@ hipError_t launch_build(const BuildOp* ops, int n_ops, const BuildGate* gates, c
 // Variant of the cluster kernel chosen for (dtype, k, n, targets).
 int cluster_layout(bool dbl, int k, int n);
 // variant (matrix-core layouts, k <= 5): 0 = direct register gather, 1 = LDS-staged.
+// stats_part: also sum p, p^2 and -p ln p of the stored amplitudes into
+// stats_part (per work-group, 8 doubles each; *stats_blocks receives their
+// number); only the direct float matrix-core kernels (k = 4..6) do this,
+// other cases return hipErrorInvalidValue.
 hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, int layout,
-                          const EpiDesc* epi, int variant, hipStream_t st);
+                          const EpiDesc* epi, int variant, hipStream_t st, double* stats_part = nullptr,
+                          unsigned* stats_blocks = nullptr);
+// Can a cluster launch also produce the sums (see launch_cluster)?
+inline bool cluster_stats_supported(bool dbl, int k, int layout, int variant) {
+    return !dbl && variant == 0 && ((layout == LAYOUT_SPLIT16F && k == 6) || (layout == LAYOUT_MFMA32F && k >= 4));
+}
 // Kernel variant of the matrix-core cluster path: 0 = direct register
 // gather, 1 = LDS-staged linear loads. Chosen per (dtype, k, low_class) from a
 // process-wide tune table; a forced variant (>= 0) overrides the table.
@@ -227,6 +236,8 @@ hipError_t launch_cz(void* psi, bool dbl, int n, int a, int b, hipStream_t st);
 constexpr int kReduceBlocks = 2048;
 hipError_t launch_stats(const void* psi, bool dbl, int n, void* probs, bool probs_dbl, double* part,
                         double* res, hipStream_t st);
+// Final reduction of per-work-group sums written by a cluster launch (stats_part).
+hipError_t launch_reduce_stats(const double* part, unsigned nblocks, double* res, hipStream_t st);
 hipError_t launch_compare(const void* psi, bool dbl, int n, const void* ref, bool ref_dbl,
                           double* part, double* res, hipStream_t st);
 

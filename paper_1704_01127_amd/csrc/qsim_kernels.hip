@@ -115,6 +115,25 @@ __device__ __forceinline__ uint32_t xcd_block() {
     return (g & 7) == 0 ? (b & 7) * (g >> 3) + (b >> 3) : b;
 }
 
+// Float64 sums of p = |a|^2 (slot 0), p^2 (slot 1) and -p ln p (slot 2) over
+// float amplitudes. ln p = e ln 2 + ln m with p = m 2^e split exactly and
+// ln m (m in [1/2, 1)) in float, within ~1.4e-7 absolute - far below what a
+// float state resolves; a double log costs as much ALU time as reading the
+// state.
+__device__ __forceinline__ void stats_acc_f(double (&v)[8], float x, float y) {
+    const double pr = (double)x * (double)x + (double)y * (double)y;
+    v[0] += pr;
+    v[1] += pr * pr;
+    if (pr > 0.0) {
+        int e;
+        const double m = frexp(pr, &e);
+        v[2] -= pr * ((double)e * 0.6931471805599453 + (double)logf((float)m));
+    }
+}
+
+// Block reduction of up to 8 values into out (defined with the reductions).
+__device__ void block_reduce_store(double (&vals)[8], int nv, unsigned maxmask, double* out);
+
 // Lane l's value of x, in every lane (l uniform).
 __device__ __forceinline__ double readlane_f64(double x, int l) {
     const long long b = __double_as_longlong(x);
@@ -257,11 +276,15 @@ struct TileF32 {
 // Persistent: each wave walks tiles with a stride of the whole grid and
 // prefetches the next tile's amplitudes into registers before it runs the
 // current tile's MFMA chain, so loads stay in flight under the matrix work.
-template <int K, int NB, bool LOWT>
+//
+// STATS: the launch is the last op of a run; the kernel also sums p = |a|^2,
+// p^2 and -p ln p of the amplitudes it stores (float64, per work-group into
+// part[blockIdx.x * 8 + 0..2]), so the state need not be read again for them.
+template <int K, int NB, bool LOWT, bool STATS = false>
 __global__ __launch_bounds__(256, 2) void k_cluster_f32_mfma(float2* __restrict__ psi,
                                                              const float* __restrict__ Ap,
                                                              const EpiDesc* __restrict__ epi,
-                                                             ClusterGeom g) {
+                                                             ClusterGeom g, double* __restrict__ part) {
     using T = TileF32<K, NB, LOWT>;
     constexpr int D = 1 << K;
     constexpr int HX = D / 2;       // amplitudes per lane and column
@@ -282,7 +305,11 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_mfma(float2* __restrict_
     // reading past the end) so the load count per iteration is fixed and the
     // waits the compiler places for the amplitudes cover only their own loads.
     uint64_t tile = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;
+    double sv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (tile >= ntiles) {  // uniform in the wave: every wave reaches one reduction
+        if constexpr (STATS) block_reduce_store(sv, 3, 0u, part + blockIdx.x * 8);
+        return;
+    }
     const uint64_t last = ntiles - 1;
     float B[NB][2 * HX];
     uint64_t base[NB];
@@ -333,6 +360,12 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_mfma(float2* __restrict_
                     apply_factor(O[nb][2 * j], O[nb][2 * j + 1], f, (uint32_t)(j | (h << (K - 1))), has_ph);
             }
         }
+        if constexpr (STATS) {
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int j = 0; j < HX; ++j) stats_acc_f(sv, O[nb][2 * j], O[nb][2 * j + 1]);
+        }
         T::store(psi, base, hoff, g, O);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
@@ -342,6 +375,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_mfma(float2* __restrict_
         }
         tile += stride;
     } while (tile < ntiles);
+    if constexpr (STATS) block_reduce_store(sv, 3, 0u, part + blockIdx.x * 8);
 }
 
 // ------------------------------------------------------------ cluster: MFMA, float, k = 6
@@ -474,11 +508,13 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_gauss6(float2* __restric
 // floats 8 s .. 8 s + 7 (amplitudes 4 s .. 4 s + 3, re / im interleaved).
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
-template <bool LOWT>
+// STATS: as in k_cluster_f32_mfma (sums of the stored amplitudes' p, p^2,
+// -p ln p into part, per work-group).
+template <bool LOWT, bool STATS = false>
 __global__ __launch_bounds__(256, 2) void k_cluster_f32_split6(float2* __restrict__ psi,
                                                                const half8* __restrict__ Ap,
                                                                const EpiDesc* __restrict__ epi,
-                                                               ClusterGeom g) {
+                                                               ClusterGeom g, double* __restrict__ part) {
     constexpr int K = 6, HX = 32, RB = 4, S = 8;
     using T = TileF32<K, 1, LOWT>;
     __shared__ half8 Ah[RB * S * 64];
@@ -496,7 +532,11 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_split6(float2* __restric
     const bool has_ph = has_epi && epi->n_ph > 0;
 
     uint64_t tile = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;
+    double sv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (tile >= ntiles) {  // uniform in the wave: every wave reaches one reduction
+        if constexpr (STATS) block_reduce_store(sv, 3, 0u, part + blockIdx.x * 8);
+        return;
+    }
     const uint64_t last = ntiles - 1;
 
     // split the column's amplitudes (scaled) into fp16 halves; returns the
@@ -565,11 +605,16 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_split6(float2* __restric
             for (int j = 0; j < HX; ++j)
                 apply_factor(O[0][2 * j], O[0][2 * j + 1], f, (uint32_t)(j | (h << (K - 1))), has_ph);
         }
+        if constexpr (STATS) {
+#pragma unroll
+            for (int j = 0; j < HX; ++j) stats_acc_f(sv, O[0][2 * j], O[0][2 * j + 1]);
+        }
         T::store(psi, base, hoff, g, O);
         base[0] = basen[0];
         unscale = split(Bn[0], xh, xl);
         tile += stride;
     } while (tile < ntiles);
+    if constexpr (STATS) block_reduce_store(sv, 3, 0u, part + blockIdx.x * 8);
 }
 
 // ------------------------------------------------------------ cluster: MFMA, double
@@ -2626,20 +2671,12 @@ __global__ __launch_bounds__(256) void k_stats(const typename Cplx<T>::type* __r
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     auto acc = [&](const V& a, uint64_t i) {
         const double pr = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-        v[0] += pr;
-        v[1] += pr * pr;
-        if (pr > 0.0) {
-            if constexpr (sizeof(T) == 4) {
-                // float amplitudes: ln p = e ln 2 + ln m with p = m 2^e split exactly
-                // and ln m (m in [1/2, 1)) in float, within ~1.4e-7 absolute - far
-                // below what a float state resolves; a double log costs as much ALU
-                // time as reading the state
-                int e;
-                const double m = frexp(pr, &e);
-                v[2] -= pr * ((double)e * 0.6931471805599453 + (double)logf((float)m));
-            } else {
-                v[2] -= pr * log(pr);
-            }
+        if constexpr (sizeof(T) == 4) {
+            stats_acc_f(v, a.x, a.y);
+        } else {
+            v[0] += pr;
+            v[1] += pr * pr;
+            if (pr > 0.0) v[2] -= pr * log(pr);
         }
         if (probs) probs[i] = (P)pr;
     };
@@ -2919,7 +2956,8 @@ hipError_t launch_valu_k(void* psi, bool dbl, const ClusterGeom& g, const void* 
 
 template <int K>
 hipError_t launch_mfma32_k(void* psi, const ClusterGeom& g, const void* mat, const EpiDesc* epi, int variant,
-                           hipStream_t st) {
+                           hipStream_t st, double* stats_part, unsigned* stats_blocks) {
+    if (stats_part && variant == 1) return hipErrorInvalidValue;  // sums come from the direct kernel only
     if (K <= 5 && variant == 1) {
         constexpr int KS = K <= 5 ? K : 5;
         const StageGeom sg = make_stage_geom(g, 6, 7);
@@ -2936,12 +2974,22 @@ hipError_t launch_mfma32_k(void* psi, const ClusterGeom& g, const void* mat, con
     constexpr int NB = (K == 6) ? 1 : 2;
     const uint64_t tiles = g.ncols / (32 * NB);
     const unsigned grid = grid_for(tiles, 4, kPersistGrid);
+    if (stats_part) {
+        *stats_blocks = grid;
+        if (g.t[0] == 0)
+            hipLaunchKernelGGL((k_cluster_f32_mfma<K, NB, true, true>), dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const float*)mat, epi, g, stats_part);
+        else
+            hipLaunchKernelGGL((k_cluster_f32_mfma<K, NB, false, true>), dim3(grid), dim3(256), 0, st,
+                               (float2*)psi, (const float*)mat, epi, g, stats_part);
+        return hipGetLastError();
+    }
     if (g.t[0] == 0)
         hipLaunchKernelGGL((k_cluster_f32_mfma<K, NB, true>), dim3(grid), dim3(256), 0, st, (float2*)psi,
-                           (const float*)mat, epi, g);
+                           (const float*)mat, epi, g, nullptr);
     else
         hipLaunchKernelGGL((k_cluster_f32_mfma<K, NB, false>), dim3(grid), dim3(256), 0, st, (float2*)psi,
-                           (const float*)mat, epi, g);
+                           (const float*)mat, epi, g, nullptr);
     return hipGetLastError();
 }
 
@@ -2969,7 +3017,11 @@ hipError_t launch_mfma64_k(void* psi, const ClusterGeom& g, const void* mat, con
 }  // namespace
 
 hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, int layout,
-                          const EpiDesc* epi, int variant, hipStream_t st) {
+                          const EpiDesc* epi, int variant, hipStream_t st, double* stats_part,
+                          unsigned* stats_blocks) {
+    // the sums of the stored amplitudes come from the direct float matrix-core kernels only
+    if (stats_part && (!cluster_stats_supported(dbl, g.k, layout, variant) || !stats_blocks))
+        return hipErrorInvalidValue;
     if (layout == LAYOUT_PLAIN) {
         switch (g.k) {
             case 1: return launch_valu_k<1>(psi, dbl, g, mat, epi, st);
@@ -2996,12 +3048,22 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
     if (layout == LAYOUT_SPLIT16F && !dbl && g.k == 6) {
         const uint64_t tiles = g.ncols / 32;
         const unsigned grid = grid_for(tiles, 4, kPersistGrid);
+        if (stats_part) {
+            *stats_blocks = grid;
+            if (g.t[0] == 0)
+                hipLaunchKernelGGL((k_cluster_f32_split6<true, true>), dim3(grid), dim3(256), 0, st, (float2*)psi,
+                                   (const half8*)mat, epi, g, stats_part);
+            else
+                hipLaunchKernelGGL((k_cluster_f32_split6<false, true>), dim3(grid), dim3(256), 0, st,
+                                   (float2*)psi, (const half8*)mat, epi, g, stats_part);
+            return hipGetLastError();
+        }
         if (g.t[0] == 0)
             hipLaunchKernelGGL(k_cluster_f32_split6<true>, dim3(grid), dim3(256), 0, st, (float2*)psi,
-                               (const half8*)mat, epi, g);
+                               (const half8*)mat, epi, g, nullptr);
         else
             hipLaunchKernelGGL(k_cluster_f32_split6<false>, dim3(grid), dim3(256), 0, st, (float2*)psi,
-                               (const half8*)mat, epi, g);
+                               (const half8*)mat, epi, g, nullptr);
         return hipGetLastError();
     }
     if (layout == LAYOUT_GAUSS32F && !dbl && g.k == 6) {
@@ -3017,9 +3079,9 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
     }
     if (layout == LAYOUT_MFMA32F && !dbl) {
         switch (g.k) {
-            case 4: return launch_mfma32_k<4>(psi, g, mat, epi, variant, st);
-            case 5: return launch_mfma32_k<5>(psi, g, mat, epi, variant, st);
-            case 6: return launch_mfma32_k<6>(psi, g, mat, epi, variant, st);
+            case 4: return launch_mfma32_k<4>(psi, g, mat, epi, variant, st, stats_part, stats_blocks);
+            case 5: return launch_mfma32_k<5>(psi, g, mat, epi, variant, st, stats_part, stats_blocks);
+            case 6: return launch_mfma32_k<6>(psi, g, mat, epi, variant, st, stats_part, stats_blocks);
             default: return hipErrorInvalidValue;
         }
     }
@@ -3113,6 +3175,11 @@ hipError_t launch_stats(const void* psi, bool dbl, int n, void* probs, bool prob
                                (float*)probs, part);
     }
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, part, (int)grid, 3, 0u, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_stats(const double* part, unsigned nblocks, double* res, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, part, (int)nblocks, 3, 0u, res);
     return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ class RunOpts(ctypes.Structure):
     _fields_ = [("kmax", ctypes.c_int32), ("scheduler", ctypes.c_int32),
                 ("skip_trailing_diag", ctypes.c_int32), ("fuse_diag", ctypes.c_int32),
                 ("skip_initial_h", ctypes.c_int32), ("record_timings", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("schedule_dtype", ctypes.c_int32), ("fused_stats", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):
@@ -180,7 +180,7 @@ def gate_array(gates: Sequence) -> tuple:
 
 
 def run_opts(kmax=5, scheduler="greedy", fuse_diag=False, skip_trailing_diag=False,
-             skip_initial_h=False, record_timings=False) -> RunOpts:
+             skip_initial_h=False, record_timings=False, fused_stats=False) -> RunOpts:
     o = RunOpts()
     o.kmax = kmax
     o.scheduler = SCHEDULERS[scheduler] if isinstance(scheduler, str) else int(scheduler)
@@ -188,6 +188,7 @@ def run_opts(kmax=5, scheduler="greedy", fuse_diag=False, skip_trailing_diag=Fal
     o.skip_trailing_diag = int(skip_trailing_diag)
     o.skip_initial_h = int(skip_initial_h)
     o.record_timings = int(record_timings)
+    o.fused_stats = int(fused_stats)
     return o
 
 
@@ -195,7 +196,7 @@ def schedule(n: int, gates: Sequence, dtype: int = C64, **opts) -> dict:
     """Host-only: the schedule the library would run (no GPU needed)."""
     arr, keep = gate_array(gates)
     o = run_opts(**opts)
-    o.reserved[0] = dtype
+    o.schedule_dtype = dtype
     ng = len(gates)
     cap = max(1, ng)
     gate_op = (ctypes.c_int32 * max(1, ng))()
@@ -476,7 +477,8 @@ class State:
                  8: "init_cluster2",
                  7: "pair"}
         return [dict(kind=kinds[kind[i]], k=k[i], qubits=[q for q in qs[6 * i:6 * i + 6] if q >= 0],
-                     epi=bool(epi[i] & 1), staged=bool(epi[i] & 2), mfma=bool(epi[i] & 4), ms=float(ms[i]))
+                     epi=bool(epi[i] & 1), staged=bool(epi[i] & 2), mfma=bool(epi[i] & 4),
+                     stats=bool(epi[i] & 8), ms=float(ms[i]))
                 for i in range(m)]
 
     def sync(self):

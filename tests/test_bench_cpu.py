@@ -26,12 +26,14 @@ def test_more_than_one_gpu_is_refused():
 def test_kernel_names_of_launch_records():
     b = _bench()
     rec = lambda k, q, **f: dict(kind=f.pop("kind", "cluster"), k=k, qubits=q, **f)
-    assert b.kernel_name(rec(6, [1, 3, 9, 12, 20, 25], mfma=True)) == "k_cluster_f32_split6<false>"
-    assert b.kernel_name(rec(6, [0, 3, 9, 12, 20, 25], mfma=True)) == "k_cluster_f32_split6<true>"
+    assert b.kernel_name(rec(6, [1, 3, 9, 12, 20, 25], mfma=True)) == "k_cluster_f32_split6<false, false>"
+    assert b.kernel_name(rec(6, [0, 3, 9, 12, 20, 25], mfma=True)) == "k_cluster_f32_split6<true, false>"
+    assert b.kernel_name(rec(6, [0, 3, 9, 12, 20, 25], mfma=True, stats=True)) == "k_cluster_f32_split6<true, true>"
     assert b.kernel_name(rec(6, [1, 2, 3, 4, 7, 14], mfma=True, staged=True)) == "k_cluster_f32_split6s<false>"
     assert b.kernel_name(rec(6, [0, 1, 2, 3, 21, 22], mfma=True, staged=True)) == "k_cluster_f32_split6s<true>"
     assert b.kernel_name(rec(4, [18, 20, 24, 26], mfma=True, staged=True)) == "k_cluster_f32_stage<4, 6, false>"
-    assert b.kernel_name(rec(5, [0, 9, 14, 16, 26], mfma=True)) == "k_cluster_f32_mfma<5, 2, true>"
+    assert b.kernel_name(rec(5, [0, 9, 14, 16, 26], mfma=True)) == "k_cluster_f32_mfma<5, 2, true, false>"
+    assert b.kernel_name(rec(5, [1, 9, 14, 16, 26], mfma=True, stats=True)) == "k_cluster_f32_mfma<5, 2, false, true>"
     assert b.kernel_name(rec(3, [2, 5, 9])) == "k_cluster_valu<float, 3>"
     assert b.kernel_name(rec(6, [1, 3, 9, 12, 20, 25], mfma=True), k6_kernel=1) == "k_cluster_f32_gauss6<false>"
     pair = rec(5, [0, 1, 2, 3, 4, 5, 6, 7, 8, 9], kind="pair")

@@ -692,6 +692,65 @@ def test_30q_depth25_mirror_float32():
     torch.cuda.empty_cache()
 
 
+# ------------------------------------------------------------------ reductions fused into the last pass
+FUSED_CASES = [
+    (6, [10, 11, 12, 13, 14, 15], 0), (6, [0, 3, 7, 9, 12, 14], 0),  # direct k = 6, without / with qubit 0
+    (5, [9, 10, 11, 12, 13], 0), (5, [0, 4, 8, 12, 14], 0),          # direct k = 5
+    (4, [3, 8, 11, 15], 0), (4, [0, 5, 9, 13], 0),                   # direct k = 4 (forced)
+    (4, [3, 8, 11, 15], 1),                                          # staged: not fused, recomputed
+]
+
+
+@pytest.mark.parametrize("n", [12, 16, 22])
+@pytest.mark.parametrize("k,qs,variant", FUSED_CASES)
+def test_fused_stats(n, k, qs, variant):
+    """A run whose last op is a cluster applied by a direct matrix-core kernel
+    with fused_stats: the norm, sum p^2 and entropy of the stored state come
+    from that kernel and equal the separate reduction's. The probe: the state
+    is then overwritten directly; the fused path still reports the run's sums
+    (they describe the state the run left), the staged kernel's run reads the
+    overwritten state. At n = 12 some waves of the launch own no tile."""
+    if max(qs) >= n:
+        pytest.skip("targets outside the state")
+    old = qsim.get_option(qsim.OPT_CLUSTER_VARIANT)
+    qsim.set_option(qsim.OPT_CLUSTER_VARIANT, variant)
+    try:
+        u = haar_unitary(k, 3 * k + n)
+        psi = random_state(n, 7 * n + k)
+        gates = [("CZ", (1, 2)), ("U", tuple(qs), u)]
+        ref = make_state(n, "c64", psi)
+        ref.run_circuit(gates, kmax=k, fuse_diag=True)
+        want = ref.probs()
+        s = make_state(n, "c64", psi)
+        s.run_circuit(gates, kmax=k, fuse_diag=True, fused_stats=True)
+        s.amps.zero_()
+        torch.cuda.synchronize()
+        got = s.probs()
+        if variant == 0:
+            for a, b in zip(got, want):
+                assert abs(a - b) <= 1e-12 * max(1.0, abs(b)), (got, want)
+            assert abs(got[0] - 1) <= 1e-5
+            # a call that rewrites the partial sums ends the fused result
+            s.probs(torch.empty(2 ** n, dtype=torch.float32, device="cuda"))
+            assert s.probs()[0] == 0.0
+        else:
+            assert got == (0.0, 0.0, 0.0)
+    finally:
+        qsim.set_option(qsim.OPT_CLUSTER_VARIANT, old)
+
+
+def test_fused_stats_cleared_by_state_changes():
+    """After a fused run, any call that changes the state recomputes."""
+    n = 14
+    u = haar_unitary(6, 1)
+    s = make_state(n, "c64", random_state(n, 2))
+    s.run_circuit([("U", (8, 9, 10, 11, 12, 13), u)], kmax=6, fused_stats=True)
+    s.apply_cluster([0], np.array([[0, 1], [1, 0]], np.complex128))
+    s.amps.zero_()
+    torch.cuda.synchronize()
+    assert s.probs()[0] == 0.0
+
+
 BENCH_FORM = dict(scheduler="learned", fuse_diag=True, skip_initial_h=True)
 
 
