@@ -42,15 +42,18 @@ def demangle(name: str) -> str:
     if out and out != name:
         return out
     # c++filt does not know _Float16 vector parameters: read the qualified
-    # name and a single bool template argument by hand
+    # name and its bool template arguments by hand
     m = re.match(r"_ZN4qsim(\d+)", name)
     if not m:
         return name
     ln = int(m.group(1))
     base = name[m.end():m.end() + ln]
     rest = name[m.end() + ln:]
-    t = re.match(r"ILb([01])EE", rest)
-    return base + ("<%s>" % ("true" if t.group(1) == "1" else "false") if t else "")
+    t = re.match(r"I((?:Lb[01]E)+)E", rest)
+    if not t:
+        return base
+    args = ["true" if b == "1" else "false" for b in re.findall(r"Lb([01])E", t.group(1))]
+    return base + "<%s>" % ", ".join(args)
 
 
 def short(name: str) -> str:
