@@ -187,3 +187,32 @@ def test_planning_option_range(option):
         with pytest.raises(qsim.QsimError):
             qsim.set_option(option, bad)
     assert qsim.get_option(option) == old
+
+
+def test_candidate_sets_are_grid_blocks():
+    """On a 5 x 6 grid circuit at k_max 6 the dense-set candidates are the
+    2 x 3 and 3 x 2 blocks of the grid (qubit q = row * 6 + column): several
+    clusters of the schedule are exactly such blocks, none when clusters only
+    grow gate by gate from a seed."""
+    R, C = 5, 6
+    circ = supremacy_circuit(R, C, 25, 0)
+
+    def is_block(qs):
+        rows = sorted({q // C for q in qs})
+        cols = sorted({q % C for q in qs})
+        return (len(qs) == 6 and len(qs) == len(rows) * len(cols)
+                and rows == list(range(rows[0], rows[0] + len(rows)))
+                and cols == list(range(cols[0], cols[0] + len(cols))))
+
+    old = qsim.get_option(qsim.OPT_CLUSTER_SETS)
+    blocks = {}
+    try:
+        for cs in (0, 1):
+            qsim.set_option(qsim.OPT_CLUSTER_SETS, cs)
+            sch = qsim.schedule(circ.n, circ.gates, kmax=6, fuse_diag=True, skip_initial_h=True,
+                                skip_trailing_diag=True)
+            qs = [o[:k] for o, k in zip(sch["op_qubits"], sch["op_k"])]
+            blocks[cs] = sum(is_block(q) for q in qs)
+    finally:
+        qsim.set_option(qsim.OPT_CLUSTER_SETS, old)
+    assert blocks[0] == 0 and blocks[1] >= 3, blocks
