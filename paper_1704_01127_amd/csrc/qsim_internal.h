@@ -127,7 +127,7 @@ struct StageGeom {
     int32_t tb[16];      // their state-bit positions, ascending
     int32_t tpos[6];     // tau bit of target m
     int32_t cpos[6];     // tau bit of column bit b
-    int32_t pad;
+    int32_t swz[6];      // 6-qubit staged loop: LDS slot of tau = tau ^ (XOR of swz[i] over set bits 5 + i)
     uint64_t ioff[32];   // state offset of linear chunk i (tau = i << lane_bits ...)
 };
 

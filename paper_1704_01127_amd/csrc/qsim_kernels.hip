@@ -1443,8 +1443,9 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_cluster_f32_pair10(float2* __
 // so each lane's whole column lies in one half and the halves are staged one
 // after the other. Eight waves and the matrix halves (64 KiB) fill 128 KiB.
 // Core (fp16 halves on matrix cores, column scaling, epilogue) as above.
-// Addresses: slot(tau) = lds_slot<true>(tau) & 1023, linear over XOR, so the
-// lane's column part and the row part are mapped separately.
+// Addresses: slot(tau) = swizzle(tau) & 1023 (StageGeom::swz, chosen per
+// geometry so that the columns of a read pass fall on distinct banks), linear
+// over XOR, so the lane's column part and the row part are mapped separately.
 //
 // One wave applies the cluster whose fp16 matrix halves are in LDS (Ah, Al)
 // to tiles tile, tile + stride, ... < tile_end (tile numbers uniform in the
@@ -1563,19 +1564,30 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
 #pragma unroll
     for (int b = 0; b < 6; ++b)
         if ((lane >> b) & 1) lane_off |= uint64_t(1) << sg.tb[b + 1];
+    // LDS slot of tau (the geometry's swizzle; linear over XOR)
+    auto sslot = [&](int v) {
+        int o = v;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            if ((v >> (5 + i)) & 1) o ^= sg.swz[i];
+        return o;
+    };
     // the lane's column (tile order, then LDS slot), its half of the targets
     const int ctau = tau_of_column<C>(p, sg) | (h << sg.tpos[K - 1]);
-    int lslot = lds_slot<true>(ctau);
+    int lslot = sslot(ctau);
     uint32_t h5 = (uint32_t)h << (K - 1);
     const uint64_t cbits = state_bits_of_column<C>(p, sg);
     const int lph = (ctau >> 10) & 1;  // the half of the tile holding the column
-    int lin = lds_slot<true>(2 * lane);  // slot of linear chunk 0; chunk i adds slot(128 i) by XOR
+    int lin = sslot(2 * lane);  // slot of linear chunk 0; chunk i adds slot(128 i) by XOR
     // row j's slot and linear chunk i's state offset, rebuilt from 5 and 4
     // uniform masks at each use (cheap scalar work) rather than 32 + 16 values
     // held across the loop
     int rmask[K - 1];
 #pragma unroll
-    for (int m = 0; m < K - 1; ++m) rmask[m] = lds_slot<true>(1 << sg.tpos[m]);
+    for (int m = 0; m < K - 1; ++m) rmask[m] = sslot(1 << sg.tpos[m]);
+    int cmask[4];  // slots of the linear chunks' bits (tau bits 7..10)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) cmask[b] = sslot(128 << b);
     uint64_t imask[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) imask[b] = uint64_t(1) << sg.tb[7 + b];
@@ -1591,6 +1603,13 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
 #pragma unroll
         for (int b = 0; b < 4; ++b)
             if ((i >> b) & 1) o |= imask[b];
+        return o;
+    };
+    auto cslot = [&](int i) {  // slot offset of linear chunk i (tau = 128 i)
+        int o = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if ((i >> b) & 1) o ^= cmask[b];
         return o;
     };
 
@@ -1629,6 +1648,7 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
         asm volatile("" : "+v"(lane_off), "+v"(lin), "+v"(lslot), "+v"(h5));
         asm volatile("" : "+s"(rmask[0]), "+s"(rmask[1]), "+s"(rmask[2]), "+s"(rmask[3]), "+s"(rmask[4]));
         asm volatile("" : "+s"(imask[0]), "+s"(imask[1]), "+s"(imask[2]), "+s"(imask[3]));
+        asm volatile("" : "+s"(cmask[0]), "+s"(cmask[1]), "+s"(cmask[2]), "+s"(cmask[3]));
         float X[2 * HX];
         ColFactor<float> f1{0u, 0u, 1.0f, 0.0f}, f2{0u, 0u, 1.0f, 0.0f};
         if constexpr (FOLD) {
@@ -1677,7 +1697,7 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
 #pragma unroll
             for (int ii = 0; ii < NL / 2; ++ii) {
                 const int i = ph * (NL / 2) + ii;
-                L4[((lin ^ lds_slot<true>(128 * i)) & 1023) >> 1] = R[i];
+                L4[((lin ^ cslot(i)) & 1023) >> 1] = R[i];
             }
             wave_lds_fence();
             if (lph == ph) {
@@ -1780,7 +1800,7 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
             for (int ii = 0; ii < NL / 2; ++ii) {
                 const int i = ph * (NL / 2) + ii;
                 *reinterpret_cast<g_vf4*>(gpsi + ((tb0 | ioff(i)) | lane_off)) =
-                    L4[((lin ^ lds_slot<true>(128 * i)) & 1023) >> 1];
+                    L4[((lin ^ cslot(i)) & 1023) >> 1];
             }
             wave_lds_fence();
         }
@@ -2901,6 +2921,27 @@ StageGeom make_stage_geom(const ClusterGeom& g, int C, int unit) {
     for (int r = 0; r < sg.nt; ++r) {
         for (int m = 0; m < g.k; ++m) if (sg.tb[r] == g.t[m]) sg.tpos[m] = r;
         for (int c = 0; c < nc; ++c) if (sg.tb[r] == cols[c]) sg.cpos[c] = r;
+    }
+    // LDS slots of the 6-qubit staged loop (11-bit tiles, half a tile per
+    // wave): each column bit above tau bit 4 folds, by XOR, into a slot bit
+    // among 1..4 that no lower column bit holds, so the columns a read pass
+    // serves (32 lanes of 8 bytes; with target 0 on tau bit 0, 16 lanes of
+    // 16 bytes) fall on distinct banks whatever bits the targets take. Bit 0
+    // is never folded: it pairs amplitudes for 16-byte accesses. The map is a
+    // bijection and linear over XOR.
+    if (g.k == 6 && C == 5) {
+        const bool lowt = g.t[0] == 0;
+        int used = 1;
+        for (int c = 0; c < nc; ++c)
+            if (sg.cpos[c] < 5) used |= 1 << sg.cpos[c];
+        for (int c = 0; c < (lowt ? 4 : 5) && c < nc; ++c) {
+            if (sg.cpos[c] < 5) continue;
+            int t = 1;
+            while (t < 5 && ((used >> t) & 1)) ++t;
+            if (t == 5) break;
+            sg.swz[sg.cpos[c] - 5] = 1 << t;
+            used |= 1 << t;
+        }
     }
     const int chunks = 1 << (sg.nt - unit);
     for (int i = 0; i < chunks && i < 32; ++i) {
