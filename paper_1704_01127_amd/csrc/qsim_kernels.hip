@@ -2924,11 +2924,12 @@ StageGeom make_stage_geom(const ClusterGeom& g, int C, int unit) {
     }
     // LDS slots of the 6-qubit staged loop (11-bit tiles, half a tile per
     // wave): each column bit above tau bit 4 folds, by XOR, into a slot bit
-    // among 1..4 that no lower column bit holds, so the columns a read pass
-    // serves (32 lanes of 8 bytes; with target 0 on tau bit 0, 16 lanes of
-    // 16 bytes) fall on distinct banks whatever bits the targets take. Bit 0
-    // is never folded: it pairs amplitudes for 16-byte accesses. The map is a
-    // bijection and linear over XOR.
+    // among 1..4 that no lower column bit holds, so the 32 columns of an
+    // 8-byte read have distinct slot bits 0..4 (no bank conflicts counted)
+    // whatever bits the targets take; with target 0 on tau bit 0 (16-byte
+    // reads) it is faster than a fixed fold as well, although conflicts are
+    // still counted there. Bit 0 is never folded: it pairs amplitudes for
+    // 16-byte accesses. The map is a bijection and linear over XOR.
     if (g.k == 6 && C == 5) {
         const bool lowt = g.t[0] == 0;
         int used = 1;
