@@ -143,3 +143,30 @@ def stats(psi: np.ndarray):
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+# Gates whose matrix is diagonal in the computational basis (Sec. 2: T and CZ
+# as printed; Z, T^dagger and the phase gate diag(1, e^{i theta})).
+DIAGONAL_GATES = frozenset({"T", "TDG", "Z", "CZ", "PHASE"})
+
+
+def drop_trailing_diagonal(circ):
+    """The circuit without its trailing diagonal gates (Sec. 3.6: the final CZ
+    gates are not simulated, as they change phases and not the output
+    probabilities). A diagonal gate is trailing when no non-diagonal gate
+    comes after it on any of its qubits; diagonal gates commute with one
+    another, so removing all of them multiplies every amplitude by a phase.
+    Returns (circuit, indices of the removed gates)."""
+    from supremacy_inputs import Circuit
+    later_dense = set()
+    drop = []
+    for i in range(len(circ.gates) - 1, -1, -1):
+        g = circ.gates[i]
+        if g.name in DIAGONAL_GATES:
+            if not any(q in later_dense for q in g.qubits):
+                drop.append(i)
+        else:
+            later_dense.update(g.qubits)
+    gone = set(drop)
+    kept = [g for i, g in enumerate(circ.gates) if i not in gone]
+    return Circuit(circ.n, kept, dict(circ.meta, trailing_diagonal_dropped=len(drop))), sorted(drop)

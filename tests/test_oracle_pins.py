@@ -182,6 +182,33 @@ def test_final_cz_layer_leaves_probabilities():
     assert np.max(np.abs(a - b)) > 1e-3  # the phases did change
 
 
+def test_drop_trailing_diagonal():
+    """Sec. 3.6 generalised: diagonal gates that only meet diagonal gates
+    afterwards commute to the end and change phases only. A hand-worked case
+    (T on qubit 0 commutes past the CZ; the CZ is followed by H on qubit 1),
+    then a supremacy circuit: the whole final CZ layer goes, and the
+    probabilities (brute force and oracle) do not change."""
+    small = Circuit(2, [Gate("H", (0,)), Gate("T", (0,)), Gate("CZ", (0, 1)), Gate("H", (1,)),
+                        Gate("T", (1,))])
+    kept, dropped = oracle.drop_trailing_diagonal(small)
+    assert dropped == [1, 4]
+    assert [g.name for g in kept.gates] == ["H", "CZ", "H"]
+    psi0 = random_state(2, 4)
+    a, b = bf.run(small, psi0.copy()), bf.run(kept, psi0.copy())
+    assert np.max(np.abs(np.abs(a) ** 2 - np.abs(b) ** 2)) <= 1e-15
+    circ = supremacy_circuit(3, 3, 17, seed=6)
+    kept, dropped = oracle.drop_trailing_diagonal(circ)
+    last = max(g.cycle for g in circ.gates)
+    final_cz = {i for i, g in enumerate(circ.gates) if g.cycle == last and g.name == "CZ"}
+    assert final_cz and final_cz <= set(dropped)
+    assert all(circ.gates[i].name in ("CZ", "T") for i in dropped)
+    full, cut = oracle.run(circ), oracle.run(kept)
+    assert np.max(np.abs(np.abs(full) ** 2 - np.abs(cut) ** 2)) <= 1e-15
+    bfull, bcut = bf.run(circ), bf.run(kept)
+    assert np.max(np.abs(np.abs(bfull) ** 2 - np.abs(bcut) ** 2)) <= 1e-15
+    assert np.max(np.abs(full - cut)) > 1e-3  # phases changed: the gates really went
+
+
 def test_uniform_start_equals_hadamard_layer():
     """Sec. 3.6: starting from the uniform vector replaces the cycle-0 H."""
     circ = supremacy_circuit(3, 4, 12, seed=2)
