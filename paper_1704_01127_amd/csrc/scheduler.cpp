@@ -410,13 +410,13 @@ void dense_sets(int n, const std::vector<SGate>& gates, const std::vector<char>&
 
 }  // namespace
 
-Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& o, const OpCostFn& cost) {
-    Schedule S;
+void mark_skips(int n, const std::vector<SGate>& gates, bool skip_initial_h, bool skip_trailing_diag,
+                std::vector<char>& dropped, bool& uniform_init) {
     const int ng = (int)gates.size();
-    S.dropped.assign(ng, 0);
-
+    dropped.assign(ng, 0);
+    uniform_init = false;
     // Leading H on every qubit -> uniform initialisation (Sec. 3.6).
-    if (o.skip_initial_h && n > 0) {
+    if (skip_initial_h && n > 0) {
         std::vector<int> first(n, -1);
         for (int i = 0; i < ng; ++i)
             for (int j = 0; j < gates[i].nq; ++j)
@@ -424,25 +424,31 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
         bool ok = true;
         for (int q = 0; q < n && ok; ++q) ok = first[q] >= 0 && gates[first[q]].kind == G_H;
         if (ok) {
-            for (int q = 0; q < n; ++q) S.dropped[first[q]] = 1;
-            S.uniform_init = true;
+            for (int q = 0; q < n; ++q) dropped[first[q]] = 1;
+            uniform_init = true;
         }
     }
     // Trailing diagonal gates change phases only (Sec. 3.6).
-    if (o.skip_trailing_diag) {
+    if (skip_trailing_diag) {
         std::vector<char> later_dense(n, 0);
         for (int i = ng - 1; i >= 0; --i) {
-            if (S.dropped[i]) continue;
+            if (dropped[i]) continue;
             const SGate& g = gates[i];
             if (g.diag) {
                 bool any = false;
                 for (int j = 0; j < g.nq; ++j) any |= later_dense[g.q[j]] != 0;
-                if (!any) S.dropped[i] = 1;
+                if (!any) dropped[i] = 1;
             } else {
                 for (int j = 0; j < g.nq; ++j) later_dense[g.q[j]] = 1;
             }
         }
     }
+}
+
+Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& o, const OpCostFn& cost) {
+    Schedule S;
+    const int ng = (int)gates.size();
+    mark_skips(n, gates, o.skip_initial_h, o.skip_trailing_diag, S.dropped, S.uniform_init);
     for (int i = 0; i < ng; ++i) S.n_applied += !S.dropped[i];
 
     if (o.mode == 0) {

@@ -46,9 +46,40 @@ struct Schedule {
     int n_applied = 0;
 };
 
+// Gates a run leaves out (Sec. 3.6): with skip_initial_h, the first gate of
+// every qubit when all of them are H (the run starts from the uniform state
+// instead; uniform_init is then set); with skip_trailing_diag, every diagonal
+// gate that no non-diagonal gate follows on any of its qubits.
+void mark_skips(int n, const std::vector<SGate>& gates, bool skip_initial_h, bool skip_trailing_diag,
+                std::vector<char>& dropped, bool& uniform_init);
+
 // Build the schedule. `cost` is used by mode 2 only: the greedy schedule of
 // every cap k <= kmax is built and the cheapest by predicted total wins
 // (empty cost: the greedy schedule with cap kmax).
 Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& o, const OpCostFn& cost);
+
+// Stage finding for a state spread over 2^(n - n_local) memories
+// (Sec. 3.6.1 steps 1 and 3, Sec. 3.5); stages.cpp.
+struct StageOpts {
+    int n_local = 30;          // bit locations 0 .. n_local - 1 are local
+    bool spec_cz = true;       // CZ on global qubits needs no communication
+    bool spec_diag1 = false;   // nor do diagonal single-qubit gates
+    bool search = true;        // cheap search for the qubits to swap (else the lowest locations)
+    bool early_swaps = true;   // step 3
+    int kmax = 5;              // clusters within each stage (0: none)
+    bool fuse_diag = false;
+    bool skip_initial_h = false;
+    bool skip_trailing_diag = false;
+};
+
+struct StagePlan {
+    bool ok = true;                        // false: a gate gathers more qubits than are local
+    std::vector<int> gate_stage;           // per gate: its stage, -1 when skipped
+    std::vector<std::vector<int>> loc;     // per stage: bit location of every qubit
+    std::vector<int> n_clusters;           // per stage, with kmax > 0
+    int n_moved = 0;                       // clusters moved across a swap by step 3
+};
+
+StagePlan make_stage_plan(int n, const std::vector<SGate>& gates, const StageOpts& o);
 
 }  // namespace qsim
