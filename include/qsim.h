@@ -136,8 +136,10 @@ typedef struct {
  * reduction partial sums. */
 size_t qsim_workspace_bytes(int n_qubits, qsim_dtype dt, int kmax);
 
-/* Create a handle for the state held in dev_amps (2^n amplitudes of dt,
- * >= 256-byte aligned, amps_bytes >= 2^n * sizeof(amplitude)) with the
+/* Create a handle for the state held in dev_amps: the 2^n complex amplitudes
+ * of an n-qubit state, amplitude i belonging to the basis state whose bit q is
+ * the value of qubit q (Sec. 2). dev_amps holds 2^n amplitudes of dt,
+ * >= 256-byte aligned, amps_bytes >= 2^n * sizeof(amplitude), with the
  * workspace dev_workspace (>= qsim_workspace_bytes, 256-byte aligned). Both
  * buffers stay owned by the caller and must outlive the handle. hip_stream
  * is a hipStream_t (NULL = the default stream). n_qubits in [1, 34] for C64,
@@ -189,6 +191,11 @@ qsim_status qsim_probs(qsim_state s, void* dev_out, qsim_dtype out_dt, double* n
  * |psi_i - ref_i|. dev_ref: 2^n amplitudes of ref_dt. Synchronises. */
 qsim_status qsim_compare(qsim_state s, const void* dev_ref, qsim_dtype ref_dt, double* fidelity,
                          double* max_abs_diff);
+
+/* Tell the library that the caller has written the amplitudes itself (a
+ * copy into dev_amps): the float64 sums a fused_stats run left for the next
+ * qsim_probs describe the old state and are dropped. No GPU work. */
+qsim_status qsim_state_changed(qsim_state s);
 
 /* Wait for the state's stream; reports errors of enqueued work. */
 qsim_status qsim_sync(qsim_state s);
@@ -345,6 +352,48 @@ qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates,
                           const qsim_run_opts* opts, int32_t* gate_op, int32_t* gate_role,
                           int32_t* op_kind, int32_t* op_k, int32_t* op_qubits, int op_cap,
                           int* n_ops);
+
+/* ------------------------------------------------------------------ stages
+ * Stage finding for a state spread over 2^g memories (host only, no GPU
+ * work). Qubits sit at bit locations 0..n-1 of the amplitude index; locations
+ * below n_local are local, the g = n - n_local above them global. A gate runs
+ * without communication when every qubit it gathers is local (Sec. 3.4).
+ * Step 1 (Sec. 3.6.1): gates on different qubits commute, so the largest
+ * first stage - every gate that can run before a global qubit is needed - is
+ * taken; then all g global qubits are swapped with g local qubits (one
+ * all-to-all, Sec. 3.4) and the next stage is grown, until the circuit ends.
+ * The local qubits that go global are those at the lowest locations
+ * (search = 0, the paper's upper bound) or the result of a cheap search
+ * (search = 1: candidate sets led by the qubits whose next gather lies
+ * furthest ahead, each played out to the end; fewest swaps wins; the first
+ * layout, free because no state exists yet, is searched too). Sec. 3.5's
+ * specialisation: a CZ on global qubits is a conditional phase or local Z and
+ * needs no swap (specialize bit 0); diagonal single-qubit gates are phases
+ * (bit 1; the paper's stage finding assumes the random gates dense, i.e. bit 1
+ * off). Step 2: each stage's gates are clustered (kmax > 0; only local qubits
+ * count, Table 1). Step 3 (early_swaps): a stage's last cluster moves past the
+ * following swap when its gates can run there and the two stages then need
+ * fewer clusters; the number of swaps does not change. */
+typedef struct {
+    int32_t n_local;            /* n/2 <= n_local <= n */
+    int32_t specialize;         /* bit 0: CZ on global qubits; bit 1: diagonal 1-qubit gates */
+    int32_t search;
+    int32_t early_swaps;
+    int32_t kmax;               /* 0..6; 0 = no clustering (stage_clusters reads -1) */
+    int32_t fuse_diag;          /* clustering option, as in qsim_run_opts */
+    int32_t skip_initial_h;     /* as in qsim_run_opts */
+    int32_t skip_trailing_diag; /* as in qsim_run_opts */
+} qsim_stage_opts;
+
+/* gate_stage (n_gates, nullable): stage of each gate, -1 when skipped.
+ * stage_loc (max_stages * n_qubits, nullable): bit location of qubit q in
+ * stage s at [s * n_qubits + q]; consecutive stages differ by one swap.
+ * stage_clusters (max_stages, nullable): clusters of each stage. *n_stages
+ * receives the number of stages (swaps + 1), also when max_stages is too
+ * small (then QSIM_E_INVALID and nothing else is written). */
+qsim_status qsim_stage_schedule(int n_qubits, const qsim_gate* gates, int n_gates, const qsim_stage_opts* opts,
+                                int32_t* gate_stage, int32_t* stage_loc, int32_t* stage_clusters, int max_stages,
+                                int* n_stages);
 
 /* ------------------------------------------------------------------ batches
  * Many independent circuits in one persistent launch (complex64 states).

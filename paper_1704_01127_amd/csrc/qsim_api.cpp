@@ -929,6 +929,12 @@ qsim_status qsim_compare(qsim_state s, const void* dev_ref, qsim_dtype ref_dt, d
     return QSIM_OK;
 }
 
+qsim_status qsim_state_changed(qsim_state s) {
+    if (qsim_status r = check_state(s)) return r;
+    s->stats_ready = false;  // the sums a fused_stats run left describe the old amplitudes
+    return QSIM_OK;
+}
+
 qsim_status qsim_sync(qsim_state s) {
     if (qsim_status r = check_state(s)) return r;
     HIP_TRY(hipStreamSynchronize(s->st), "stream sync");
@@ -1083,6 +1089,42 @@ qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates, con
             if (gate_op) gate_op[gi] = o;
             if (gate_role) gate_role[gi] = 1;
         }
+    }
+    return QSIM_OK;
+}
+
+qsim_status qsim_stage_schedule(int n_qubits, const qsim_gate* gates, int n_gates, const qsim_stage_opts* opts,
+                                int32_t* gate_stage, int32_t* stage_loc, int32_t* stage_clusters, int max_stages,
+                                int* n_stages) {
+    if (n_qubits < 1 || n_qubits > 64) return fail(QSIM_E_UNSUPPORTED, "n_qubits out of range");
+    if (!opts) return fail(QSIM_E_INVALID, "null options");
+    if (n_gates < 0 || (n_gates && !gates)) return fail(QSIM_E_INVALID, "bad gate list");
+    for (int i = 0; i < n_gates; ++i)
+        if (qsim_status r = check_gate(n_qubits, gates[i], i)) return r;
+    if (opts->n_local < 1 || opts->n_local > n_qubits || 2 * opts->n_local < n_qubits)
+        return fail(QSIM_E_INVALID, "n_local must be in [n_qubits / 2, n_qubits]");
+    if (opts->kmax < 0 || opts->kmax > kMaxK) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [0, 6]");
+    StageOpts so;
+    so.n_local = opts->n_local;
+    so.spec_cz = opts->specialize & 1;
+    so.spec_diag1 = (opts->specialize & 2) != 0;
+    so.search = opts->search != 0;
+    so.early_swaps = opts->early_swaps != 0;
+    so.kmax = opts->kmax;
+    so.fuse_diag = opts->fuse_diag != 0;
+    so.skip_initial_h = opts->skip_initial_h != 0;
+    so.skip_trailing_diag = opts->skip_trailing_diag != 0;
+    const StagePlan P = make_stage_plan(n_qubits, to_sgates(gates, n_gates), so);
+    if (!P.ok) return fail(QSIM_E_INVALID, "a gate gathers more qubits than n_local locations hold");
+    const int ns = (int)P.loc.size();
+    if (n_stages) *n_stages = ns;
+    if (ns > max_stages) return fail(QSIM_E_INVALID, "max_stages too small");
+    if (gate_stage)
+        for (int i = 0; i < n_gates; ++i) gate_stage[i] = P.gate_stage[i];
+    for (int st = 0; st < ns; ++st) {
+        if (stage_loc)
+            for (int q = 0; q < n_qubits; ++q) stage_loc[st * n_qubits + q] = P.loc[st][q];
+        if (stage_clusters) stage_clusters[st] = so.kmax > 0 ? P.n_clusters[st] : -1;
     }
     return QSIM_OK;
 }

@@ -57,6 +57,12 @@ class RunStats(ctypes.Structure):
                     schedule_ms=self.schedule_ms, total_ms=self.total_ms)
 
 
+class StageOpts(ctypes.Structure):
+    _fields_ = [("n_local", ctypes.c_int32), ("specialize", ctypes.c_int32), ("search", ctypes.c_int32),
+                ("early_swaps", ctypes.c_int32), ("kmax", ctypes.c_int32), ("fuse_diag", ctypes.c_int32),
+                ("skip_initial_h", ctypes.c_int32), ("skip_trailing_diag", ctypes.c_int32)]
+
+
 class BatchCircuit(ctypes.Structure):
     _fields_ = [("n_qubits", ctypes.c_int32), ("n_gates", ctypes.c_int32), ("gates", ctypes.POINTER(Gate)),
                 ("dev_amps", ctypes.c_void_p)]
@@ -100,6 +106,7 @@ def lib():
             "qsim_probs": (ctypes.c_int, [vp, vp, ctypes.c_int, dp, dp, dp]),
             "qsim_compare": (ctypes.c_int, [vp, vp, ctypes.c_int, dp, dp]),
             "qsim_sync": (ctypes.c_int, [vp]),
+            "qsim_state_changed": (ctypes.c_int, [vp]),
             "qsim_last_error": (ctypes.c_char_p, []),
             "qsim_op_timings": (ctypes.c_int, [vp, i32p, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_float),
                                                ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -128,6 +135,9 @@ def lib():
                                              ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         }
         sig.update({
+            "qsim_stage_schedule": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(Gate), ctypes.c_int,
+                                                   ctypes.POINTER(StageOpts), i32p, i32p, i32p, ctypes.c_int,
+                                                   ctypes.POINTER(ctypes.c_int)]),
             "qsim_batch_plan": (ctypes.c_int, [ctypes.POINTER(BatchCircuit), ctypes.c_int, ctypes.POINTER(RunOpts),
                                                ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]),
             "qsim_batch_run": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp, ctypes.c_uint32,
@@ -210,6 +220,30 @@ def schedule(n: int, gates: Sequence, dtype: int = C64, **opts) -> dict:
     m = nops.value
     return dict(gate_op=list(gate_op)[:ng], gate_role=list(gate_role)[:ng], op_kind=list(op_kind)[:m],
                 op_k=list(op_k)[:m], op_qubits=[list(op_q[6 * o_:6 * o_ + 6]) for o_ in range(m)])
+
+
+def stage_schedule(n: int, gates: Sequence, n_local: int, specialize: int = 1, search: bool = True,
+                   early_swaps: bool = True, kmax: int = 5, fuse_diag: bool = False, skip_initial_h: bool = True,
+                   skip_trailing_diag: bool = True) -> dict:
+    """Host-only: stages of a circuit on 2^(n - n_local) memories
+    (qsim_stage_schedule). Returns gate_stage, stage_loc (per stage, the bit
+    location of every qubit), stage_clusters and n_swaps."""
+    arr, keep = gate_array(gates)
+    o = StageOpts(n_local, specialize, int(search), int(early_swaps), kmax, int(fuse_diag), int(skip_initial_h),
+                  int(skip_trailing_diag))
+    ng = len(gates)
+    ns = ctypes.c_int()
+    L = lib()
+    st = L.qsim_stage_schedule(n, arr, ng, ctypes.byref(o), None, None, None, 0, ctypes.byref(ns))
+    if st not in (OK, E_INVALID) or ns.value <= 0:
+        _check(st)
+    m = ns.value
+    gate_stage = (ctypes.c_int32 * max(1, ng))()
+    loc = (ctypes.c_int32 * (m * n))()
+    clus = (ctypes.c_int32 * m)()
+    _check(L.qsim_stage_schedule(n, arr, ng, ctypes.byref(o), gate_stage, loc, clus, m, ctypes.byref(ns)))
+    return dict(gate_stage=list(gate_stage)[:ng], stage_loc=[list(loc[s * n:(s + 1) * n]) for s in range(m)],
+                stage_clusters=list(clus)[:m], n_swaps=m - 1)
 
 
 OPT_CLUSTER_VARIANT = 1
@@ -404,6 +438,7 @@ class State:
         import torch
         t = torch.as_tensor(values).to(self.amps.dtype)
         self.amps.copy_(t.to(self.amps.device))
+        _check(lib().qsim_state_changed(self.h))
 
     def to_numpy(self) -> np.ndarray:
         self.sync()

@@ -35,3 +35,20 @@ def _announce_gpu_case(request):
         if tr is not None:
             tr.write_line("[gpu case] %s" % request.node.nodeid, flush=True)
     yield
+
+
+U32 = 2.0 ** -24
+
+
+def fp32_circuit_bound(max_amp, n_ops, kmax):
+    """Largest |d amp| allowed for a complex64 run of n_ops cluster passes
+    (clusters of <= kmax qubits) against the float64 oracle.
+
+    One pass computes every output as a dot product of 2^(kmax+1) real
+    terms. Its rounding errors, of order u = 2^-24 relative each, add up like
+    a random walk, to about sqrt(2^(kmax+1)) u times the output's scale,
+    which is at most max|amp|; unitary passes do not amplify earlier errors,
+    so n_ops passes add at most n_ops such terms. A factor 4 covers the
+    rounding of the inputs and matrices. Arithmetic with fewer significant
+    bits (plain fp16: u = 2^-11) exceeds this bound by orders of magnitude."""
+    return 4.0 * n_ops * (2.0 ** (kmax + 1)) ** 0.5 * U32 * max_amp

@@ -1,0 +1,73 @@
+"""The benchmarked 30-qubit workload against the CPU oracle at full size.
+
+The 5x6-grid depth-25 supremacy circuit (seeds 0-4) is run by every GPU form
+the benchmark times - complex64 fused (6-qubit clusters on fp16 matrix cores
+with operand halves), complex64 fused with 6-qubit clusters on fp32 matrix
+cores, complex128 fused and complex128 one gate at a time - and each final
+state is compared with the float64 oracle's, amplitude by amplitude (in
+float64 on the GPU: the oracle's 16 GiB state is uploaded once per seed).
+The runs skip what the benchmark skips: the leading H layer becomes the
+uniform start (the same state) and trailing diagonal gates are dropped, so the
+oracle is given the circuit without them (Sec. 3.6).
+
+Bars: complex128 max |d amp| <= 1e-12; complex64 fidelity >= 1 - 1e-6 and
+max |d amp| within the stated float32 bound (conftest.fp32_circuit_bound).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from conftest import fp32_circuit_bound
+from paper_1704_01127_amd import qsim
+from supremacy_inputs import supremacy_circuit
+
+pytestmark = pytest.mark.gpu
+
+BENCH_OPTS = dict(kmax=6, scheduler="learned", fuse_diag=True, skip_trailing_diag=True, skip_initial_h=True,
+                  fused_stats=True)
+FORMS = [
+    ("c64", 2, BENCH_OPTS),                                    # the benchmark's form
+    ("c64", 0, BENCH_OPTS),                                    # 6-qubit clusters on fp32 matrix cores
+    ("c128", 2, dict(BENCH_OPTS, kmax=5)),                     # float64 fused
+    ("c128", 2, dict(scheduler="per_gate", skip_trailing_diag=True, skip_initial_h=True)),
+]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_30q_depth25_forms_match_oracle(seed):
+    circ = supremacy_circuit(5, 6, 25, seed)
+    kept, dropped = oracle.drop_trailing_diagonal(circ)
+    assert len(dropped) >= 6  # at least the final CZ layer
+    psi = oracle.run(kept)
+    mx = float(np.max(np.abs(psi)))
+    onorm, _, oent = oracle.stats(psi)
+    ref = torch.from_numpy(psi).cuda()
+    del psi
+    old = qsim.get_option(qsim.OPT_K6_KERNEL)
+    errs = {}
+    try:
+        for dt, k6, opts in FORMS:
+            qsim.set_option(qsim.OPT_K6_KERNEL, k6)
+            s = qsim.State(30, dt)
+            st = s.run_circuit(circ.gates, **opts)
+            norm, _, ent = s.probs()
+            f, d = s.compare(ref)
+            # the run applied exactly the oracle's gates: the H layer it replaced plus the rest
+            assert st["n_gates_applied"] + 30 == len(kept.gates), st
+            tag = (dt, k6, opts.get("scheduler"))
+            errs[tag] = d
+            print("seed %d %s: ops %d fidelity 1-%.2e max|d| %.3e (%.2e of max|amp|) norm-1 %.1e dS %.1e"
+                  % (seed, tag, st["n_ops"], 1 - f, d, d / mx, norm - 1, ent - oent), flush=True)
+            if dt == "c128":
+                assert d <= 1e-12, (tag, d)
+                assert abs(norm - onorm) <= 1e-12 and abs(ent - oent) <= 1e-10, tag
+            else:
+                assert f >= 1 - 1e-6, (tag, f)
+                assert d <= fp32_circuit_bound(mx, st["n_ops"], 6), (tag, d, mx)
+                assert abs(norm - onorm) <= 1e-5 and abs(ent - oent) <= 1e-4, tag
+            del s
+    finally:
+        qsim.set_option(qsim.OPT_K6_KERNEL, old)
+    # fp16-halves 6-qubit products stay at the error level of the fp32 matrix cores
+    assert errs[("c64", 2, "learned")] <= 4 * errs[("c64", 0, "learned")], errs
