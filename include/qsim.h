@@ -165,6 +165,16 @@ qsim_status qsim_apply_cluster(qsim_state s, int k, const int32_t* qubits, const
 qsim_status qsim_apply_diag(qsim_state s, int n_pairs, const int32_t* cz_pairs, int n_phase,
                             const int32_t* phase_qubits, const double* phase_theta);
 
+/* Relabel bit locations in place (the local swap of Sec. 3.4, which moves
+ * the qubits to be exchanged to chosen bit locations): for j < m the bit at
+ * location from[j] moves to location to[j], i.e. the amplitude at index i
+ * goes to the index whose bit to[j] is bit from[j] of i; other bits stay.
+ * from and to list the same m <= 12 distinct locations (< n). One pass over
+ * the state (read and write), in tiles of up to 2^12 amplitudes staged
+ * through LDS. Errors: QSIM_E_UNSUPPORTED for m > 12, QSIM_E_INVALID for
+ * locations out of range, repeated, or differing between from and to. */
+qsim_status qsim_permute_qubits(qsim_state s, int m, const int32_t* from, const int32_t* to);
+
 /* Apply one gate with the per-gate kernels (one launch; the plain method):
  * a 2x2 matrix on the index pairs (i, i + 2^q) (Sec. 2), a sign flip for CZ,
  * a phase on the amplitudes with bit q set for diagonal 1-qubit gates, and
@@ -267,7 +277,15 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * circuit's previous op is done, circuits with the longest remaining chain
  * go first; it shortens the end of the launch, where only the deepest
  * circuits are left, but costs more planning than it saves on the
- * 512-circuit workload). Either order is free of deadlock. Errors:
+ * 512-circuit workload), 2 diagonal order (op j of circuit i gets key i + j,
+ * so only about as many circuits as they have ops are in flight: for circuits
+ * that are pieces of one large state, which then stay in the Infinity Cache
+ * between their ops). Every order is free of deadlock.
+ * QSIM_OPT_CHECK_UNITARY (default 0; a debugging aid): 1 makes every call
+ * that takes a dense matrix (qsim_apply_cluster, DENSE gates of runs,
+ * schedules and batches) check on the host that max_ij |(M M^+ - I)_ij| <=
+ * 1e-10 (the gates of Sec. 2 are unitary) and return QSIM_E_INVALID
+ * otherwise, before anything is enqueued. Errors:
  * QSIM_E_INVALID for an unknown option or an out-of-range value. */
 typedef enum {
     QSIM_OPT_CLUSTER_VARIANT = 1,
@@ -279,7 +297,8 @@ typedef enum {
     QSIM_OPT_PAIR = 7,
     QSIM_OPT_PAIR_TILE = 8,
     QSIM_OPT_CLUSTER_SETS = 9,
-    QSIM_OPT_BATCH_ORDER = 10
+    QSIM_OPT_BATCH_ORDER = 10,
+    QSIM_OPT_CHECK_UNITARY = 11
 } qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);

@@ -145,6 +145,24 @@ def num_threads() -> int:
     return lib().oracle_num_threads()
 
 
+def permute_bits(psi: np.ndarray, src, dst) -> np.ndarray:
+    """Relabel bit locations (Sec. 3.4: qubits are moved between bit
+    locations before and after a global-to-local swap): the amplitude at
+    index i goes to the index whose bit dst[j] is bit src[j] of i, every
+    other bit unchanged. Returns a new array."""
+    n = int(np.log2(psi.size))
+    assert sorted(src) == sorted(dst) and len(set(src)) == len(src)
+    i = np.arange(psi.size, dtype=np.int64)
+    j = i.copy()
+    for s in src:
+        j &= ~(np.int64(1) << s)
+    for s, d in zip(src, dst):
+        j |= ((i >> s) & 1) << d
+    out = np.empty_like(psi)
+    out[j] = psi
+    return out
+
+
 # Gates whose matrix is diagonal in the computational basis (Sec. 2: T and CZ
 # as printed; Z, T^dagger and the phase gate diag(1, e^{i theta})).
 DIAGONAL_GATES = frozenset({"T", "TDG", "Z", "CZ", "PHASE"})

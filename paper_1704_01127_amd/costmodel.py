@@ -151,46 +151,53 @@ def time_run(state, circ, opts, reps=3):
     return best, st
 
 
-def compare(n_list=(28, 29, 30), seeds=range(100, 104), depth=40, log=print):
-    """Time held-out circuits: learned (k <= 6) against fixed-k greedy at k = 5
-    (the fallback's default) and k = 6, and the analytic model; results are
-    checked to agree."""
+def compare(n_list=(28, 29, 30), seeds=range(100, 104), depth=40, dtype="c64", log=print):
+    """Time held-out circuits with the learned scheduler (k <= 6) against the
+    method without the model: the fixed-k greedy scheduler at the k_max the
+    autotuner found best for this dtype and size (qsim.best_opts), and also
+    greedy at k = 5 and k = 6 and the analytic model. The results of every
+    schedule are checked to agree (fidelity against the tuned greedy run)."""
     import torch
     rows = []
     base = dict(fuse_diag=True, skip_trailing_diag=True, skip_initial_h=True)
     for n in n_list:
-        s1 = qsim.State(n, "c64", kmax=6)
-        s2 = qsim.State(n, "c64", kmax=6)
+        tuned = qsim.best_opts(n, dtype)
+        s1 = qsim.State(n, dtype, kmax=6)
+        s2 = qsim.State(n, dtype, kmax=6)
         for seed in seeds:
             circ = workload(n, depth, seed)
-            t5, st5 = time_run(s1, circ, dict(base, scheduler="greedy", kmax=5))
-            t6, st6 = time_run(s1, circ, dict(base, scheduler="greedy", kmax=6))
+            tg, stg = time_run(s1, circ, dict(base, scheduler="greedy", kmax=tuned["kmax"]))
             tl, stl = time_run(s2, circ, dict(base, scheduler="learned", kmax=6))
             fid, maxd = s1.compare(s2.amps)
+            t5, st5 = time_run(s1, circ, dict(base, scheduler="greedy", kmax=5))
+            t6, st6 = time_run(s1, circ, dict(base, scheduler="greedy", kmax=6))
             ta, sta = time_run(s1, circ, dict(base, scheduler="analytic", kmax=6))
-            row = dict(n=n, seed=seed, greedy_ms=t5 * 1e3, greedy6_ms=t6 * 1e3, learned_ms=tl * 1e3,
-                       analytic_ms=ta * 1e3, greedy_ops=st5["n_ops"], greedy6_ops=st6["n_ops"],
+            row = dict(n=n, dtype=dtype, seed=seed, tuned_kmax=tuned["kmax"], tuned_greedy_ms=tg * 1e3,
+                       greedy_ms=t5 * 1e3, greedy6_ms=t6 * 1e3, learned_ms=tl * 1e3, analytic_ms=ta * 1e3,
+                       tuned_greedy_ops=stg["n_ops"], greedy_ops=st5["n_ops"], greedy6_ops=st6["n_ops"],
                        learned_ops=stl["n_ops"], analytic_ops=sta["n_ops"],
-                       learned_clusters_by_k=stl["n_clusters_by_k"], learned_schedule_ms=stl["schedule_ms"],
-                       fidelity_learned_vs_greedy=fid, max_abs_diff=maxd)
+                       tuned_clusters_by_k=stg["n_clusters_by_k"], learned_clusters_by_k=stl["n_clusters_by_k"],
+                       learned_schedule_ms=stl["schedule_ms"], fidelity_learned_vs_greedy=fid, max_abs_diff=maxd)
             rows.append(row)
             log(json.dumps(row))
         del s1, s2
         torch.cuda.empty_cache()
+    tg = sum(r["tuned_greedy_ms"] for r in rows)
     g5 = sum(r["greedy_ms"] for r in rows)
     g6 = sum(r["greedy6_ms"] for r in rows)
     lr = sum(r["learned_ms"] for r in rows)
     an = sum(r["analytic_ms"] for r in rows)
-    log("total: greedy k=5 %.1f ms, greedy k=6 %.1f ms, analytic %.1f ms, learned %.1f ms "
-        "(learned vs greedy k=5: %.1f%% faster, vs k=6: %.1f%% faster)"
-        % (g5, g6, an, lr, 100 * (g5 - lr) / g5, 100 * (g6 - lr) / g6))
+    log("total (%s): tuned greedy %.1f ms, greedy k=5 %.1f ms, greedy k=6 %.1f ms, analytic %.1f ms, "
+        "learned %.1f ms (learned vs tuned greedy: %.1f%% faster)"
+        % (dtype, tg, g5, g6, an, lr, 100 * (tg - lr) / tg))
     return rows
 
 
 def cmd_compare(args):
     import torch  # noqa: F401
     qsim.load_tuning()
-    rows = compare(n_list=[int(x) for x in args.n.split(",")], seeds=range(args.seed0, args.seed0 + args.seeds))
+    rows = compare(n_list=[int(x) for x in args.n.split(",")], seeds=range(args.seed0, args.seed0 + args.seeds),
+                   dtype=args.dtype)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(rows, f, indent=1)
@@ -211,6 +218,7 @@ def main(argv=None):
     c.add_argument("--n", default="28,29,30")
     c.add_argument("--seed0", type=int, default=100)
     c.add_argument("--seeds", type=int, default=4)
+    c.add_argument("--dtype", default="c64", choices=["c64", "c128"])
     c.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     {"record": cmd_record, "train": cmd_train, "compare": cmd_compare}[args.cmd](args)

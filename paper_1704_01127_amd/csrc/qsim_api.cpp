@@ -76,6 +76,7 @@ int g_pair = 0;
 int g_pair_tile = 11;
 int g_cluster_sets = 1;
 int g_batch_order = 0;
+int g_check_unitary = 0;  // host check of every dense matrix: max |M M^+ - I| <= 1e-10
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
@@ -136,6 +137,26 @@ qsim_status qsim::api::check_gate(int n, const qsim_gate& g, int idx) {
     if (g.kind == G_DENSE && (nq < 1 || nq > kMaxK))
         return fail(QSIM_E_UNSUPPORTED, at + "dense gates need 1 <= k <= 6");
     if (g.kind == G_DENSE && !g.mat) return fail(QSIM_E_INVALID, at + "dense gate without a matrix");
+    if (g.kind == G_DENSE && g_check_unitary) {
+        // (M M^+)_{ij} = sum_l M_il conj(M_jl); row-major, (re, im) interleaved
+        const int d = 1 << nq;
+        double worst = 0.0;
+        for (int i = 0; i < d; ++i)
+            for (int j = 0; j < d; ++j) {
+                double re = 0.0, im = 0.0;
+                for (int l = 0; l < d; ++l) {
+                    const double ar = g.mat[2 * (i * d + l)], ai = g.mat[2 * (i * d + l) + 1];
+                    const double br = g.mat[2 * (j * d + l)], bi = g.mat[2 * (j * d + l) + 1];
+                    re += ar * br + ai * bi;
+                    im += ai * br - ar * bi;
+                }
+                if (i == j) re -= 1.0;
+                worst = std::max(worst, std::hypot(re, im));
+            }
+        if (!(worst <= 1e-10))
+            return fail(QSIM_E_INVALID, at + "dense matrix is not unitary (max |M M^+ - I| = " +
+                                            std::to_string(worst) + ")");
+    }
     uint64_t m = 0;
     for (int j = 0; j < nq; ++j) {
         const int q = g.qubits[j];
@@ -775,6 +796,42 @@ qsim_status qsim_apply_diag(qsim_state s, int n_pairs, const int32_t* cz_pairs, 
     return flush(s, c);
 }
 
+qsim_status qsim_permute_qubits(qsim_state s, int m, const int32_t* from, const int32_t* to) {
+    if (qsim_status r = check_state(s)) return r;
+    if (m < 0 || m > kPermMaxBits) return fail(QSIM_E_UNSUPPORTED, "at most 12 bit locations per permutation");
+    if (m && (!from || !to)) return fail(QSIM_E_INVALID, "null argument");
+    uint64_t sf = 0, st = 0;
+    for (int j = 0; j < m; ++j) {
+        if (from[j] < 0 || from[j] >= s->n || to[j] < 0 || to[j] >= s->n)
+            return fail(QSIM_E_INVALID, "bit location out of range");
+        if ((sf >> from[j] & 1) || (st >> to[j] & 1)) return fail(QSIM_E_INVALID, "repeated bit location");
+        sf |= uint64_t(1) << from[j];
+        st |= uint64_t(1) << to[j];
+    }
+    if (sf != st) return fail(QSIM_E_INVALID, "from and to must list the same bit locations");
+    bool identity = true;
+    for (int j = 0; j < m; ++j) identity &= from[j] == to[j];
+    if (identity) return QSIM_OK;
+    s->stats_ready = false;
+    // tile bits: the moving locations and the lowest fixed ones, up to 12 (so
+    // that loads and stores run over the lowest bits)
+    PermGeom pg{};
+    uint64_t tile = sf;
+    const int nt = std::min(s->n, kPermMaxBits);
+    for (int b = 0; b < s->n && __builtin_popcountll(tile) < nt; ++b) tile |= uint64_t(1) << b;
+    pg.nt = 0;
+    int tau_of[64];
+    for (int b = 0; b < s->n; ++b)
+        if (tile >> b & 1) {
+            tau_of[b] = pg.nt;
+            pg.tb[pg.nt++] = b;
+        }
+    for (int j = 0; j < pg.nt; ++j) pg.to[j] = j;
+    for (int j = 0; j < m; ++j) pg.to[tau_of[from[j]]] = tau_of[to[j]];
+    HIP_TRY(launch_permute(s->psi, s->dbl, s->n, pg, s->st), "permute launch");
+    return QSIM_OK;
+}
+
 qsim_status qsim_apply_gate(qsim_state s, const qsim_gate* gate) {
     if (qsim_status r = check_state(s)) return r;
     s->stats_ready = false;
@@ -986,8 +1043,13 @@ qsim_status qsim_set_option(int option, int value) {
         return QSIM_OK;
     }
     if (option == QSIM_OPT_BATCH_ORDER) {
-        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "batch order must be 0 or 1");
+        if (value < 0 || value > 2) return fail(QSIM_E_INVALID, "batch order must be 0, 1 or 2");
         g_batch_order = value;
+        return QSIM_OK;
+    }
+    if (option == QSIM_OPT_CHECK_UNITARY) {
+        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "check_unitary must be 0 or 1");
+        g_check_unitary = value;
         return QSIM_OK;
     }
     if (option == QSIM_OPT_BATCH_ITEM_TILES) {
@@ -1034,6 +1096,7 @@ int qsim_get_option(int option) {
     if (option == QSIM_OPT_PAIR_TILE) return g_pair_tile;
     if (option == QSIM_OPT_CLUSTER_SETS) return g_cluster_sets;
     if (option == QSIM_OPT_BATCH_ORDER) return g_batch_order;
+    if (option == QSIM_OPT_CHECK_UNITARY) return g_check_unitary;
     return -1;
 }
 

@@ -291,6 +291,27 @@ void order_items_critical_path(qsim_batch_s* b, const std::vector<Packed>& packe
     }
 }
 
+// Diagonal order: circuit i's op j gets key i + j (circuits in the order
+// given), items sorted by key, then by circuit. Op j of circuit i runs next
+// to op j - 1 of circuit i + 1, so only about as many circuits as they have
+// ops are in flight at once: when the circuits are pieces of one large state,
+// the pieces in flight stay in the last-level (Infinity) cache between ops.
+void order_items_diagonal(qsim_batch_s* b, const std::vector<Packed>& packed, const std::vector<int>& op0,
+                          int n_circuits) {
+    std::vector<std::pair<size_t, int>> keys;  // (i + j, i)
+    for (int i = 0; i < n_circuits; ++i)
+        for (size_t j = 0; j < packed[i].ops.size(); ++j) keys.emplace_back(i + j, i);
+    std::sort(keys.begin(), keys.end());
+    for (const auto& kv : keys) {
+        const int i = kv.second;
+        const size_t j = kv.first - i;
+        const BatchOp& op = b->ops[op0[i] + j];
+        const uint64_t n_it = (op.tiles + b->item_tiles - 1) / b->item_tiles;
+        for (uint64_t it = 0; it < n_it; ++it)
+            b->items.push_back(BatchItem{(uint32_t)(op0[i] + j), (uint32_t)(it * b->item_tiles)});
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -377,8 +398,10 @@ qsim_status qsim_batch_plan(const qsim_batch_circuit* circuits, int n_circuits, 
     }
     if (g_batch_order == 0)
         order_items_by_level(b, circuits, packed, op0, n_circuits);
-    else
+    else if (g_batch_order == 1)
         order_items_critical_path(b, packed, op0, n_circuits);
+    else
+        order_items_diagonal(b, packed, op0, n_circuits);
     // the order must hand out every item once, each op's items after all items
     // of its circuit's previous op (what keeps the waits of the kernel finite)
     {

@@ -231,6 +231,19 @@ hipError_t launch_batch(const BatchOp* ops, const BatchItem* items, uint32_t n_i
 hipError_t launch_gate1q(void* psi, bool dbl, int n, int q, const double m[8], hipStream_t st);
 hipError_t launch_phase1q(void* psi, bool dbl, int n, int q, double cs, double sn, hipStream_t st);
 hipError_t launch_cz(void* psi, bool dbl, int n, int a, int b, hipStream_t st);
+// Bit permutation of the amplitude index (a relabelling of bit locations,
+// Sec. 3.4's local swap). Tiles are the 2^nt amplitudes whose tile bits
+// tb[0..nt) (ascending state bit positions) vary; tau is the index inside a
+// tile (bit j of tau at state bit tb[j]). The amplitude at tile index tau
+// moves to the tile index whose bit to[j] is bit j of tau.
+constexpr int kPermMaxBits = 12;
+struct PermGeom {
+    int32_t nt;
+    int32_t tb[kPermMaxBits];
+    int32_t to[kPermMaxBits];
+};
+hipError_t launch_permute(void* psi, bool dbl, int n, const PermGeom& pg, hipStream_t st);
+
 // Reductions: partial sums go to `part` (kReduceBlocks * 8 doubles), the
 // final values to `res` (4 doubles).
 constexpr int kReduceBlocks = 2048;

@@ -3220,6 +3220,82 @@ hipError_t launch_stats(const void* psi, bool dbl, int n, void* probs, bool prob
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------ bit permutation
+// One work-group per tile (persistent grid): the whole tile is loaded into
+// registers (every load in flight), written to LDS at its permuted index, and
+// stored back in the original order of addresses, so loads and stores are
+// both runs over the tile's lowest bits (the host puts the lowest non-moving
+// state bits into the tile for that). In place: a tile is read completely
+// before any of it is written, and tiles are disjoint.
+template <typename V2, int NT>
+__global__ __launch_bounds__(256) void k_permute(V2* __restrict__ psi, uint64_t ntiles, PermGeom pg) {
+    constexpr int N = 1 << NT;
+    constexpr int PER = (N + 255) / 256;
+    __shared__ V2 buf[N];
+    for (uint64_t tile = xcd_block(); tile < ntiles; tile += gridDim.x) {
+        uint64_t base = tile;
+#pragma unroll
+        for (int i = 0; i < NT; ++i) base = insert_zero(base, pg.tb[i]);
+        V2 v[PER];
+        uint64_t addr[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int tau = r * 256 + (int)threadIdx.x;
+            uint64_t off = 0;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) off |= uint64_t((tau >> j) & 1) << pg.tb[j];
+            addr[r] = base | off;
+            if (tau < N) v[r] = psi[addr[r]];
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int tau = r * 256 + (int)threadIdx.x;
+            int dst = 0;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) dst |= ((tau >> j) & 1) << pg.to[j];
+            if (tau < N) buf[dst] = v[r];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int tau = r * 256 + (int)threadIdx.x;
+            if (tau < N) psi[addr[r]] = buf[tau];
+        }
+        __syncthreads();
+    }
+}
+
+namespace {
+template <int NT>
+hipError_t launch_permute_nt(void* psi, bool dbl, int n, const PermGeom& pg, hipStream_t st) {
+    const uint64_t tiles = uint64_t(1) << (n - NT);
+    const unsigned grid = grid_for(tiles, 1, kPersistGrid);
+    if (dbl)
+        hipLaunchKernelGGL((k_permute<double2, NT>), dim3(grid), dim3(256), 0, st, (double2*)psi, tiles, pg);
+    else
+        hipLaunchKernelGGL((k_permute<float2, NT>), dim3(grid), dim3(256), 0, st, (float2*)psi, tiles, pg);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_permute(void* psi, bool dbl, int n, const PermGeom& pg, hipStream_t st) {
+    if (pg.nt < 1 || pg.nt > kPermMaxBits || pg.nt > n) return hipErrorInvalidValue;
+    switch (pg.nt) {
+        case 1: return launch_permute_nt<1>(psi, dbl, n, pg, st);
+        case 2: return launch_permute_nt<2>(psi, dbl, n, pg, st);
+        case 3: return launch_permute_nt<3>(psi, dbl, n, pg, st);
+        case 4: return launch_permute_nt<4>(psi, dbl, n, pg, st);
+        case 5: return launch_permute_nt<5>(psi, dbl, n, pg, st);
+        case 6: return launch_permute_nt<6>(psi, dbl, n, pg, st);
+        case 7: return launch_permute_nt<7>(psi, dbl, n, pg, st);
+        case 8: return launch_permute_nt<8>(psi, dbl, n, pg, st);
+        case 9: return launch_permute_nt<9>(psi, dbl, n, pg, st);
+        case 10: return launch_permute_nt<10>(psi, dbl, n, pg, st);
+        case 11: return launch_permute_nt<11>(psi, dbl, n, pg, st);
+        default: return launch_permute_nt<12>(psi, dbl, n, pg, st);
+    }
+}
+
 hipError_t launch_reduce_stats(const double* part, unsigned nblocks, double* res, hipStream_t st) {
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, part, (int)nblocks, 3, 0u, res);
     return hipGetLastError();

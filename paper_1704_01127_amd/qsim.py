@@ -107,6 +107,7 @@ def lib():
             "qsim_compare": (ctypes.c_int, [vp, vp, ctypes.c_int, dp, dp]),
             "qsim_sync": (ctypes.c_int, [vp]),
             "qsim_state_changed": (ctypes.c_int, [vp]),
+            "qsim_permute_qubits": (ctypes.c_int, [vp, ctypes.c_int, i32p, i32p]),
             "qsim_last_error": (ctypes.c_char_p, []),
             "qsim_op_timings": (ctypes.c_int, [vp, i32p, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_float),
                                                ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -256,6 +257,7 @@ OPT_PAIR = 7
 OPT_PAIR_TILE = 8
 OPT_CLUSTER_SETS = 9
 OPT_BATCH_ORDER = 10
+OPT_CHECK_UNITARY = 11
 
 
 def set_option(option: int, value: int):
@@ -460,6 +462,12 @@ class State:
         th = (ctypes.c_double * max(1, len(phases)))(*[float(t) for _, t in phases])
         _check(lib().qsim_apply_diag(self.h, len(pairs), _i32(flat), len(phases),
                                      _i32([q for q, _ in phases]), th))
+
+    def permute_qubits(self, src: Sequence[int], dst: Sequence[int]):
+        """Move the bit at location src[j] to location dst[j] (qsim_permute_qubits)."""
+        if len(src) != len(dst):
+            raise ValueError("src and dst must have the same length")
+        _check(lib().qsim_permute_qubits(self.h, len(src), _i32(src), _i32(dst)))
 
     def apply_gate(self, gate):
         arr, keep = gate_array([gate])

@@ -91,3 +91,28 @@ def test_batch_plan_host_checks():
     assert plan(ptrs=(1 << 20, (2 << 20) + 8))[0] == qsim.E_INVALID  # unaligned
     assert plan(n=11)[0] == qsim.E_INVALID          # the circuit's qubit 11 is out of range
     assert L.qsim_batch_run(None, None, 0, None, 0, None) == qsim.E_INVALID
+
+
+def test_unitarity_check_option():
+    """QSIM_OPT_CHECK_UNITARY: dense matrices are checked on the host before
+    anything runs (the schedule call is host-only)."""
+    import numpy as np
+
+    from paper_1704_01127_amd import qsim
+    from supremacy_inputs import haar_unitary
+    u = haar_unitary(3, 5)
+    bad = u.copy()
+    bad[0, 0] += 1e-6
+    assert qsim.get_option(qsim.OPT_CHECK_UNITARY) == 0
+    qsim.schedule(4, [("U", (0, 1, 3), bad)])  # off by default: accepted
+    qsim.set_option(qsim.OPT_CHECK_UNITARY, 1)
+    try:
+        qsim.schedule(4, [("U", (0, 1, 3), u)])
+        with pytest.raises(qsim.QsimError, match="not unitary"):
+            qsim.schedule(4, [("H", (0,)), ("U", (0, 1, 3), bad)])
+        with pytest.raises(qsim.QsimError, match="not unitary"):
+            qsim.stage_schedule(4, [("U", (0, 1), 2 * np.eye(4, dtype=np.complex128))], 3)
+    finally:
+        qsim.set_option(qsim.OPT_CHECK_UNITARY, 0)
+    with pytest.raises(qsim.QsimError):
+        qsim.set_option(qsim.OPT_CHECK_UNITARY, 2)

@@ -615,6 +615,40 @@ def test_20q_depth25_per_gate_float64(seed):
         assert_fp32_circuit(s3.to_numpy(), ref, st, kmax)
 
 
+# ------------------------------------------------------------------ bit permutation
+PERM_CASES = [
+    (5, [0, 4], [4, 0]), (11, [0, 1, 2], [2, 0, 1]), (12, list(range(12)), list(range(11, -1, -1))),
+    (13, [3, 5, 7, 9, 11, 0], [0, 11, 9, 7, 5, 3]), (21, [20, 0], [0, 20]),
+    (21, [2, 4, 6, 15, 17, 20], [15, 17, 20, 2, 4, 6]),
+    (22, [0, 1, 2, 3, 4, 5, 16, 17, 18, 19, 20, 21], [16, 17, 18, 19, 20, 21, 0, 1, 2, 3, 4, 5]),
+    (23, [9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 22], [22, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19]),
+]
+
+
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("case", range(len(PERM_CASES)))
+def test_permute_qubits(dt, case):
+    """Bit relabelling (data movement only): bit-exact against the oracle's
+    permutation of the same stored amplitudes; tiles of the moving bits plus
+    the lowest fixed ones, any number of tiles."""
+    n, src, dst = PERM_CASES[case]
+    psi = random_state(n, 70 + case)
+    s = make_state(n, dt, psi)
+    held = s.to_numpy().astype(np.complex128)
+    s.permute_qubits(src, dst)
+    got = s.to_numpy().astype(np.complex128)
+    np.testing.assert_array_equal(got, oracle.permute_bits(held, src, dst))
+    s.permute_qubits(dst, src)
+    np.testing.assert_array_equal(s.to_numpy().astype(np.complex128), held)
+
+
+def test_permute_qubits_errors():
+    s = make_state(8, "c64")
+    for src, dst in (([0, 1], [1, 2]), ([0, 0], [1, 1]), ([8], [8]), (list(range(13)), list(range(13)))):
+        with pytest.raises(qsim.QsimError):
+            s.permute_qubits(src, dst)
+
+
 # ------------------------------------------------------------------ reductions
 @pytest.mark.parametrize("dt", ["c64", "c128"])
 def test_probs_and_compare(dt):

@@ -209,6 +209,29 @@ def test_drop_trailing_diagonal():
     assert np.max(np.abs(full - cut)) > 1e-3  # phases changed: the gates really went
 
 
+def test_permute_bits():
+    """Relabelling bit locations: a hand-worked swap of bits 0 and 1, and the
+    identity that moving the bits equals running the circuit with every qubit
+    renamed to its new location (gates on other qubit indices, from |0...0>,
+    which every relabelling leaves unchanged)."""
+    psi = np.array([1, 2, 3, 4], np.complex128)
+    np.testing.assert_array_equal(oracle.permute_bits(psi, [0, 1], [1, 0]), [1, 3, 2, 4])
+    np.testing.assert_array_equal(oracle.permute_bits(psi, [1], [1]), psi)
+    circ = supremacy_circuit(3, 3, 14, seed=9)
+    n = circ.n
+    rng = np.random.default_rng(1)
+    for src_n in (2, 3, 5, 9):
+        src = [int(x) for x in rng.choice(n, src_n, replace=False)]
+        dst = [int(x) for x in rng.permutation(src)]
+        sigma = dict(zip(src, dst))
+        ren = Circuit(n, [Gate(g.name, tuple(sigma.get(q, q) for q in g.qubits), g.mat) for g in circ.gates])
+        want = oracle.run(ren)
+        got = oracle.permute_bits(oracle.run(circ), src, dst)
+        np.testing.assert_array_equal(got, want)
+        back = oracle.permute_bits(got, dst, src)
+        np.testing.assert_array_equal(back, oracle.run(circ))
+
+
 def test_uniform_start_equals_hadamard_layer():
     """Sec. 3.6: starting from the uniform vector replaces the cycle-0 H."""
     circ = supremacy_circuit(3, 4, 12, seed=2)
