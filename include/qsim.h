@@ -207,6 +207,22 @@ qsim_status qsim_compare(qsim_state s, const void* dev_ref, qsim_dtype ref_dt, d
  * qsim_probs describe the old state and are dropped. No GPU work. */
 qsim_status qsim_state_changed(qsim_state s);
 
+/* qsim_probs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results as qsim_probs on the 2^n amplitudes of dt at
+ * dev_amps (amps_bytes >= 2^n * sizeof(amplitude)), with no state handle and
+ * no workspace. The reduction's partial sums go to a fixed device array of
+ * the library (qsim_noalloc_scratch_bytes(), about 128 KiB, one per GPU, held
+ * until the process ends); nothing is allocated. Enqueued on hip_stream (a
+ * hipStream_t, NULL = default) on the current device, then synchronised.
+ * Calls that overlap on one GPU (other host threads, other streams) share the
+ * array and race: the caller serialises them. n_qubits in [1, 34] for C64,
+ * [1, 33] for C128; larger states are rejected with QSIM_E_UNSUPPORTED. */
+qsim_status qsim_probs_noalloc(int n_qubits, qsim_dtype dt, const void* dev_amps, size_t amps_bytes,
+                               void* hip_stream, void* dev_out, qsim_dtype out_dt, double* norm,
+                               double* sum_p2, double* entropy_nats);
+size_t qsim_noalloc_scratch_bytes(void);
+
 /* Wait for the state's stream; reports errors of enqueued work. */
 qsim_status qsim_sync(qsim_state s);
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqsim.so")
-SOURCES = ["qsim_kernels.hip", "qsim_mlp.hip", "qsim_api.cpp", "qsim_batch.cpp", "scheduler.cpp", "stages.cpp", "learned.cpp"]
+SOURCES = ["qsim_kernels.hip", "qsim_mlp.hip", "qsim_api.cpp", "qsim_batch.cpp", "scheduler.cpp", "stages.cpp", "learned.cpp", "qsim_noalloc.hip"]
 ARCH = os.environ.get("QSIM_OFFLOAD_ARCH", "gfx950")
 
 

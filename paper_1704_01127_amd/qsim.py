@@ -108,6 +108,9 @@ def lib():
             "qsim_sync": (ctypes.c_int, [vp]),
             "qsim_state_changed": (ctypes.c_int, [vp]),
             "qsim_permute_qubits": (ctypes.c_int, [vp, ctypes.c_int, i32p, i32p]),
+            "qsim_probs_noalloc": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp, vp,
+                                                  ctypes.c_int, dp, dp, dp]),
+            "qsim_noalloc_scratch_bytes": (ctypes.c_size_t, []),
             "qsim_last_error": (ctypes.c_char_p, []),
             "qsim_op_timings": (ctypes.c_int, [vp, i32p, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_float),
                                                ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -526,6 +529,28 @@ class State:
 
     def sync(self):
         _check(lib().qsim_sync(self.h))
+
+
+def probs_noalloc(amps, out=None, stream=None) -> tuple:
+    """qsim_probs_noalloc on a device tensor of 2^n complex amplitudes: (norm,
+    sum p^2, entropy in nats), and p_i into `out` (float32 / float64, 2^n)
+    when given. Uses the library's fixed device scratch, no workspace."""
+    import torch
+    n = int(amps.numel()).bit_length() - 1
+    if amps.numel() != 2 ** n or not amps.is_contiguous() or amps.dtype not in (torch.complex64, torch.complex128):
+        raise ValueError("amps must be a contiguous complex64/complex128 device tensor of 2^n elements")
+    dt = C64 if amps.dtype == torch.complex64 else C128
+    ptr, odt = None, C64
+    if out is not None:
+        if out.numel() != 2 ** n or out.dtype not in (torch.float32, torch.float64):
+            raise ValueError("out must hold 2^n float32 or float64")
+        ptr, odt = ctypes.c_void_p(out.data_ptr()), (C64 if out.dtype == torch.float32 else C128)
+    st = stream if stream is not None else torch.cuda.current_stream(amps.device)
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().qsim_probs_noalloc(n, dt, ctypes.c_void_p(amps.data_ptr()), amps.numel() * amps.element_size(),
+                                    ctypes.c_void_p(st.cuda_stream), ptr, odt, ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)))
+    return a.value, b.value, c.value
 
 
 class Batch:
