@@ -94,6 +94,8 @@ def parse():
                     help="skip the CPU oracle (and with it every comparison against the oracle)")
     ap.add_argument("--no-fp32-k6", action="store_true",
                     help="skip the form with 6-qubit clusters on the fp32 matrix cores")
+    ap.add_argument("--no-mapped", action="store_true",
+                    help="skip the fused forms with the qubit mapping (QSIM_OPT_MAP_QUBITS)")
     ap.add_argument("--batch-check-every", type=int, default=8,
                     help="compare every n-th circuit of the batch with the oracle (0: none)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batched launch")
@@ -323,6 +325,15 @@ def main():
                                                min(args.warmup, 1), record=True)
         finally:
             qsim.set_option(qsim.OPT_K6_KERNEL, k6_default)
+    if args.only is None and not args.no_mapped:
+        # the same form with the qubit mapping: relabelled qubits, one permutation pass at the end
+        qsim.set_option(qsim.OPT_MAP_QUBITS, 1)
+        try:
+            states["c64_fused_mapped"] = qsim.State(n, "c64", kmax=max(args.kmax, 5))
+            forms["c64_fused_mapped"] = timed(states["c64_fused_mapped"], fused_opts, args.steps,
+                                              min(args.warmup, 1), record=True)
+        finally:
+            qsim.set_option(qsim.OPT_MAP_QUBITS, 0)
     if args.only in (None, "pergate"):
         states["c128_per_gate"] = qsim.State(n, "c128", kmax=max(args.kmax, 5))
         k64 = args.fp64_steps if args.fp64_steps is not None else args.steps
@@ -333,6 +344,14 @@ def main():
         f64_opts = dict(fused_opts, kmax=args.fp64_kmax)
         states["c128_fused"] = qsim.State(n, "c128", kmax=max(args.fp64_kmax, 5))
         forms["c128_fused"] = timed(states["c128_fused"], f64_opts, args.steps, min(args.warmup, 1), record=True)
+        if not args.no_mapped:
+            qsim.set_option(qsim.OPT_MAP_QUBITS, 1)
+            try:
+                states["c128_fused_mapped"] = qsim.State(n, "c128", kmax=max(args.fp64_kmax, 5))
+                forms["c128_fused_mapped"] = timed(states["c128_fused_mapped"], f64_opts, args.steps,
+                                                   min(args.warmup, 1), record=True)
+            finally:
+                qsim.set_option(qsim.OPT_MAP_QUBITS, 0)
 
     main_key = "c64_fused" if "c64_fused" in forms else "c128_per_gate"
     ref = forms[main_key]
@@ -368,13 +387,20 @@ def main():
     desc = {"c64_fused_fp32_k6": "complex64 state, the same schedule with 6-qubit clusters on fp32 matrix "
                                  "cores (real-split product)",
             "c128_fused": "complex128 state, fused clusters of <= %d qubits on fp64 matrix cores" % args.fp64_kmax,
-            "c128_per_gate": "complex128 state, one launch per gate (the plain method)"}
+            "c128_per_gate": "complex128 state, one launch per gate (the plain method)",
+            "c64_fused_mapped": "the complex64 form with the qubit mapping (least used qubits on the slow bit "
+                                "locations, one permutation pass at the end)",
+            "c128_fused_mapped": "the complex128 fused form with the qubit mapping"}
     out["forms"] = {}
     for key, f in forms.items():
         if key == main_key:
             continue
         d = {"form": desc[key], "tts_s": round(f["tts"], 5), "steps": len(f["per"]), "ops": f["st"]["n_ops"],
              "norm": f["res"][0], "entropy_nats": f["res"][2]}
+        if f["recs"]:
+            perm = [r["ms"] for r in f["recs"] if r["kind"] == "permute"]
+            if perm:
+                d["permute_ms"] = round(sum(perm) / len(perm), 4)
         if f["recs"]:
             d["roofline"], _ = cluster_roofline(f["recs"], n, key.startswith("c128"), len(f["per"]),
                                                 0 if key == "c64_fused_fp32_k6" else k6_default, pair_tile)

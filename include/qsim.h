@@ -234,13 +234,16 @@ const char* qsim_last_error(void);
  * order: op_kind (0 cluster, 1 diagonal pass, 2 single-qubit gate, 3
  * single-qubit phase, 4 CZ, 5 cluster-matrix build, 6 uniform initialisation
  * written together with the first cluster, 7 two clusters in one pass, 8 the
- * uniform initialisation and the first two clusters in one pass),
+ * uniform initialisation and the first two clusters in one pass, 9 the
+ * permutation pass of QSIM_OPT_MAP_QUBITS),
  * op_k (cluster size - 5 for a pair, 6 for kind 8; number of matrices for a build),
  * op_qubits[6*i ..] (sorted targets of a cluster - of the first for a pair,
  * of the second for kind 8 -
  * or the gate's qubits, -1 padded), op_epi (flags of a cluster: bit 0 = applies diagonal
  * gates while storing, bit 1 = LDS-staged kernel variant, bit 2 = matrix-core
- * kernel) and ms (milliseconds). Arrays of cap entries (any may be NULL);
+ * kernel, bit 3 = also sums the reductions, bits 8-15 = the number of diagonal
+ * gates the scheduler attached to it, capped at 255 - the epilogue size the
+ * learned cost model is given) and ms (milliseconds). Arrays of cap entries (any may be NULL);
  * *n_ops receives the count. Synchronises the stream. */
 qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32_t* op_qubits,
                             int32_t* op_epi, float* ms, int cap, int* n_ops);
@@ -301,7 +304,15 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * that takes a dense matrix (qsim_apply_cluster, DENSE gates of runs,
  * schedules and batches) check on the host that max_ij |(M M^+ - I)_ij| <=
  * 1e-10 (the gates of Sec. 2 are unitary) and return QSIM_E_INVALID
- * otherwise, before anything is enqueued. Errors:
+ * otherwise, before anything is enqueued.
+ * QSIM_OPT_MAP_QUBITS (default 0; the GPU form of the qubit mapping of
+ * Sec. 3.6.2): 1 lets a fusing run that starts from the uniform state
+ * (skip_initial_h) place the qubits its clusters use least on the bit
+ * locations where the cluster kernels are slowest (the lowest six and the top
+ * three) - free at the start, since every relabelling of the uniform state is
+ * the same state - and restore the caller's order with one permutation pass
+ * at the end (at most twelve moving locations). Read when a run is
+ * scheduled. Errors:
  * QSIM_E_INVALID for an unknown option or an out-of-range value. */
 typedef enum {
     QSIM_OPT_CLUSTER_VARIANT = 1,
@@ -314,7 +325,8 @@ typedef enum {
     QSIM_OPT_PAIR_TILE = 8,
     QSIM_OPT_CLUSTER_SETS = 9,
     QSIM_OPT_BATCH_ORDER = 10,
-    QSIM_OPT_CHECK_UNITARY = 11
+    QSIM_OPT_CHECK_UNITARY = 11,
+    QSIM_OPT_MAP_QUBITS = 12
 } qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);

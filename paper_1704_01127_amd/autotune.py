@@ -188,6 +188,8 @@ def main(argv=None):
                     help="re-tune the cluster kernel variants in an existing table")
     ap.add_argument("--variant-trials", type=int, default=8,
                     help="random target sets per (k, low class) in the variant search")
+    ap.add_argument("--buckets", default="20,24,28,30",
+                    help="size buckets (qubits) of the (scheduler, k_max) search, from 20, 24, 28, 30")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
 
@@ -226,7 +228,8 @@ def main(argv=None):
         out["cost_us"][dt] = tune_costs(args.n, dt, args.reps, args.seed, log)
         qsim.set_cost_table(qsim.C64 if dt == "c64" else qsim.C128, out["cost_us"][dt], args.n)
     if not args.no_kmax:
-        buckets = {20: (4, 5), 24: (4, 6), 28: (4, 7), 30: (5, 6)}
+        grids = {20: (4, 5), 24: (4, 6), 28: (4, 7), 30: (5, 6)}
+        buckets = {int(b): grids[int(b)] for b in args.buckets.split(",")}
         for dt in dts:
             out["best"][dt] = tune_kmax(dt, buckets if dt == "c64" else {k: v for k, v in buckets.items() if k <= 28},
                                         args.seed, log)

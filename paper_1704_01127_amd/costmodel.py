@@ -44,7 +44,7 @@ def op_record_rows(recs, n, dtype_code):
             continue
         k = r["k"] if r["kind"] == "cluster" else 0
         qs = r["qubits"] if k else []
-        f = qsim.cost_features(n, dtype_code, qs, n_epi=1 if r.get("epi") else 0)
+        f = qsim.cost_features(n, dtype_code, qs, n_epi=r["n_epi"])  # what the scheduler passes for the op
         feats.append(f)
         ys.append(math.log(r["ms"] * 1e3 / 2.0 ** (n - 30)))
     return feats, ys
@@ -55,7 +55,7 @@ def cmd_record(args):
     feats, ys, meta = [], [], []
     configs = [dict(kmax=k, fuse_diag=fd) for k in (2, 3, 4, 5, 6) for fd in (False, True)]
     t_start = time.time()
-    for dt, ns in (("c64", [27, 28, 29, 30]), ("c128", [27, 28])):
+    for dt, ns in (("c64", [27, 28, 29, 30]), ("c128", [27, 28, 29, 30])):
         code = qsim.C64 if dt == "c64" else qsim.C128
         for n in ns:
             state = qsim.State(n, dt, kmax=6)

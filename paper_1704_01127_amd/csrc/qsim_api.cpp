@@ -77,6 +77,7 @@ int g_pair_tile = 11;
 int g_cluster_sets = 1;
 int g_batch_order = 0;
 int g_check_unitary = 0;  // host check of every dense matrix: max |M M^+ - I| <= 1e-10
+int g_map_qubits = 0;     // runs from the uniform state: relabel qubits away from the slow bit locations
 double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
@@ -244,6 +245,7 @@ struct Chunk {
         int q0, q1;
         double m[8];
         bool stats;      // kind 0: also sum p, p^2, -p ln p of the stored state (the run's last op)
+        int n_epi;       // diagonal gates the scheduler attached to the cluster (its epilogue)
     };
     std::vector<Item> items;
     int slots_used = 0;
@@ -321,7 +323,7 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
             r.k = it.geom.k;
             for (int j = 0; j < it.geom.k; ++j) r.qubits[j] = it.geom.t[j];
             r.flags = (it.epi >= 0 ? 1 : 0) | (variant == 1 ? 2 : 0) | (it.layout != LAYOUT_PLAIN ? 4 : 0) |
-                      (it.stats ? 8 : 0);
+                      (it.stats ? 8 : 0) | (std::min(it.n_epi, 255) << 8);
         } else if (it.kind >= 2) {
             r.k = it.kind == 4 ? 2 : 1;
             r.qubits[0] = it.q0;
@@ -437,6 +439,7 @@ qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, con
     it.layout = bo.layout;
     it.slot = c.slots_used++;
     it.epi = -1;
+    it.n_epi = (int)epi_gates.size();
     if (e.n_cc || e.n_mix || e.n_ph) {
         it.epi = (int)c.epis.size();
         c.epis.push_back(e);
@@ -796,6 +799,61 @@ qsim_status qsim_apply_diag(qsim_state s, int n_pairs, const int32_t* cz_pairs, 
     return flush(s, c);
 }
 
+namespace {
+// Tile geometry of a bit permutation (m <= kPermMaxBits moving locations):
+// the moving locations and the lowest fixed ones, up to 12 bits, so loads
+// and stores run over the lowest bits.
+PermGeom perm_geom(int n, int m, const int32_t* from, const int32_t* to) {
+    PermGeom pg{};
+    uint64_t tile = 0;
+    for (int j = 0; j < m; ++j) tile |= uint64_t(1) << from[j];
+    const int nt = std::min(n, kPermMaxBits);
+    for (int b = 0; b < n && __builtin_popcountll(tile) < nt; ++b) tile |= uint64_t(1) << b;
+    int tau_of[64];
+    for (int b = 0; b < n; ++b)
+        if (tile >> b & 1) {
+            tau_of[b] = pg.nt;
+            pg.tb[pg.nt++] = b;
+        }
+    for (int j = 0; j < pg.nt; ++j) pg.to[j] = j;
+    for (int j = 0; j < m; ++j) pg.to[tau_of[from[j]]] = tau_of[to[j]];
+    return pg;
+}
+
+// Bit locations for a run that starts from the uniform state (any relabelling
+// of it is the same state, so the first layout is free). Cluster kernels are
+// slowest with targets on the lowest six locations (a scattered gather) or the
+// top three (measured per target position at 28 qubits): the qubits the
+// schedule's clusters use least go there. At most six transpositions (twelve
+// moving locations), so one permutation pass restores the order at the end.
+// Returns loc[q] (the identity when nothing moves).
+std::vector<int> choose_layout(int n, const Schedule& S) {
+    std::vector<int> loc(n);
+    for (int q = 0; q < n; ++q) loc[q] = q;
+    if (n < 16) return loc;
+    std::vector<int> use(n, 0);
+    for (const SOp& op : S.ops)
+        if (op.kind == OP_CLUSTER)
+            for (int j = 0; j < op.k; ++j) use[op.qubits[j]] += 8 - op.k;  // narrower clusters suffer more
+    auto slow = [&](int l) { return l < 6 || l >= n - 3; };
+    int n_slow = 0;
+    for (int l = 0; l < n; ++l) n_slow += slow(l);
+    std::vector<int> order(n);
+    for (int q = 0; q < n; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return use[a] < use[b]; });
+    std::vector<char> want_slow(n, 0);  // the least used qubits
+    for (int i = 0; i < n_slow; ++i) want_slow[order[i]] = 1;
+    std::vector<int> out, in;  // heavily used qubits on slow locations, lightly used ones elsewhere
+    for (int i = n - 1; i >= 0; --i)
+        if (slow(loc[order[i]]) && !want_slow[order[i]]) out.push_back(order[i]);
+    for (int i = 0; i < n; ++i)
+        if (!slow(loc[order[i]]) && want_slow[order[i]]) in.push_back(order[i]);
+    const size_t swaps = std::min<size_t>({out.size(), in.size(), size_t(kPermMaxBits / 2)});
+    for (size_t i = 0; i < swaps; ++i) std::swap(loc[out[i]], loc[in[i]]);
+    return loc;
+}
+}  // namespace
+
 qsim_status qsim_permute_qubits(qsim_state s, int m, const int32_t* from, const int32_t* to) {
     if (qsim_status r = check_state(s)) return r;
     if (m < 0 || m > kPermMaxBits) return fail(QSIM_E_UNSUPPORTED, "at most 12 bit locations per permutation");
@@ -813,22 +871,7 @@ qsim_status qsim_permute_qubits(qsim_state s, int m, const int32_t* from, const 
     for (int j = 0; j < m; ++j) identity &= from[j] == to[j];
     if (identity) return QSIM_OK;
     s->stats_ready = false;
-    // tile bits: the moving locations and the lowest fixed ones, up to 12 (so
-    // that loads and stores run over the lowest bits)
-    PermGeom pg{};
-    uint64_t tile = sf;
-    const int nt = std::min(s->n, kPermMaxBits);
-    for (int b = 0; b < s->n && __builtin_popcountll(tile) < nt; ++b) tile |= uint64_t(1) << b;
-    pg.nt = 0;
-    int tau_of[64];
-    for (int b = 0; b < s->n; ++b)
-        if (tile >> b & 1) {
-            tau_of[b] = pg.nt;
-            pg.tb[pg.nt++] = b;
-        }
-    for (int j = 0; j < pg.nt; ++j) pg.to[j] = j;
-    for (int j = 0; j < m; ++j) pg.to[tau_of[from[j]]] = tau_of[to[j]];
-    HIP_TRY(launch_permute(s->psi, s->dbl, s->n, pg, s->st), "permute launch");
+    HIP_TRY(launch_permute(s->psi, s->dbl, s->n, perm_geom(s->n, m, from, to), s->st), "permute launch");
     return QSIM_OK;
 }
 
@@ -858,8 +901,31 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     for (int i = 0; i < n_gates; ++i)
         if (gates[i].kind == G_DENSE && gates[i].k > s->kmax_ws)
             return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
-    const std::vector<SGate> sg = to_sgates(gates, n_gates);
-    const Schedule S = make_schedule(s->n, sg, so, cost_fn(opts, s->n, s->dbl));
+    Schedule S = make_schedule(s->n, to_sgates(gates, n_gates), so, cost_fn(opts, s->n, s->dbl));
+    // qubit mapping: from the uniform state the first layout is free; the run
+    // applies the relabelled gates and one permutation pass restores the order
+    std::vector<qsim_gate> mapped;
+    int32_t pfrom[kPermMaxBits], pto[kPermMaxBits];
+    int pm = 0;
+    if (g_map_qubits && S.uniform_init && so.mode != 0) {
+        const std::vector<int> loc = choose_layout(s->n, S);
+        for (int q = 0; q < s->n; ++q)
+            if (loc[q] != q) {
+                pfrom[pm] = loc[q];
+                pto[pm] = q;
+                ++pm;
+            }
+        if (pm) {  // the same schedule on the relabelled qubits
+            mapped.assign(gates, gates + n_gates);
+            for (qsim_gate& g : mapped)
+                for (int j = 0; j < gate_nq(g); ++j) g.qubits[j] = loc[g.qubits[j]];
+            gates = mapped.data();
+            for (SOp& op : S.ops) {
+                for (int j = 0; j < op.k; ++j) op.qubits[j] = loc[op.qubits[j]];
+                if (op.kind == OP_CLUSTER) std::sort(op.qubits, op.qubits + op.k);
+            }
+        }
+    }
     const auto t1 = std::chrono::steady_clock::now();
 
     qsim_run_stats st;
@@ -940,6 +1006,17 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
             last.stats = true;
     }
     if (qsim_status r = flush(s, c)) return r;
+    if (pm) {  // back to the caller's qubit order (sums of a fused_stats pass do not change)
+        OpRecord r;
+        std::memset(&r, 0, sizeof(r));
+        r.kind = 9;
+        r.k = pm;
+        for (int j = 0; j < std::min(pm, 6); ++j) r.qubits[j] = pto[j];
+        HIP_TRY(rec_begin(s, r), "event record");
+        HIP_TRY(launch_permute(s->psi, s->dbl, s->n, perm_geom(s->n, pm, pfrom, pto), s->st), "permute launch");
+        HIP_TRY(rec_end(s, r), "event record");
+        st.n_ops++;
+    }
     const auto t2 = std::chrono::steady_clock::now();
     st.schedule_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     st.total_ms = std::chrono::duration<double, std::milli>(t2 - t0).count();
@@ -1052,6 +1129,11 @@ qsim_status qsim_set_option(int option, int value) {
         g_check_unitary = value;
         return QSIM_OK;
     }
+    if (option == QSIM_OPT_MAP_QUBITS) {
+        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "map_qubits must be 0 or 1");
+        g_map_qubits = value;
+        return QSIM_OK;
+    }
     if (option == QSIM_OPT_BATCH_ITEM_TILES) {
         if (value < 1 || value > 4096 || (value & (value - 1)))
             return fail(QSIM_E_INVALID, "tiles per batch item must be a power of two in [1, 4096]");
@@ -1097,6 +1179,7 @@ int qsim_get_option(int option) {
     if (option == QSIM_OPT_CLUSTER_SETS) return g_cluster_sets;
     if (option == QSIM_OPT_BATCH_ORDER) return g_batch_order;
     if (option == QSIM_OPT_CHECK_UNITARY) return g_check_unitary;
+    if (option == QSIM_OPT_MAP_QUBITS) return g_map_qubits;
     return -1;
 }
 

@@ -9,10 +9,12 @@
 // most gates, before the remaining gates are assigned to further clusters.
 //
 // Cost-driven mode (analytic or learned cost model): complete candidate
-// schedules - greedy with caps kmax - 2 .. kmax, and greedy with kmax where a
-// full-width cluster may give way to the (kmax - 1)-qubit cluster of the same
-// seed when that is predicted cheaper per gate - are built, and the one with
-// the smallest predicted total time is kept. (Per-cluster choices alone are
+// schedules - greedy with caps kmax - 2 .. kmax (with and without the
+// candidate qubit sets below), and greedy with kmax where a full-width
+// cluster may give way to the (kmax - 1)-qubit cluster of the same seed when
+// that is predicted cheaper per gate - are built, and the one with the
+// smallest predicted total time is kept. Narrower caps are skipped when the
+// model predicts their clusters no cheaper than full-width ones. (Per-cluster choices alone are
 // myopic: a cluster can look cheap per gate and still leave more total work;
 // the final comparison is between whole schedules.)
 //
@@ -488,26 +490,72 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
         return S;
     }
     // cost-driven: complete candidate schedules, the one with the smallest
-    // predicted total time wins (built in parallel). Candidates: the greedy
-    // schedule for each cap kmax - 2 .. kmax (smaller caps only add passes),
-    // the cost-trimmed greedy schedule for kmax, and the greedy schedules for
-    // kmax with each family of candidate qubit sets.
+    // predicted total time wins (built in parallel). Candidates: for each cap
+    // kmax - 2 .. kmax (smaller caps only add passes) the greedy schedule and
+    // the greedy schedules with each family of candidate qubit sets of that
+    // size - so the schedule the plain greedy scheduler would pick at any of
+    // these caps is always among them - and the cost-trimmed greedy schedule
+    // for kmax.
     const int k_lo = std::max(1, kmax - 2);
     const auto policy = o.parallel ? std::launch::async : std::launch::deferred;
+    // A narrower cap only adds passes, so it can only win when its clusters are
+    // predicted clearly cheaper than full-width ones (complex128: 6-qubit
+    // clusters are bound by the fp64 matrix cores). The predicted cost of a
+    // cluster of each width, averaged over low, middle, high and spread target
+    // sets, decides which caps (and the cost-trimmed schedule, which mixes
+    // widths) are worth building.
+    auto typical = [&](int k) {
+        int sets[4][kMaxK];
+        for (int j = 0; j < k; ++j) {
+            sets[0][j] = j;
+            sets[1][j] = n / 2 - k / 2 + j;
+            sets[2][j] = n - k + j;
+            sets[3][j] = k > 1 ? (int)((long)j * (n - 1) / (k - 1)) : 0;
+        }
+        double c = 0.0;
+        for (auto& q : sets) c += cost(k, q, 0);
+        return c / 4;
+    };
+    std::vector<char> use_cap(kmax + 1, 1);
+    if (n >= kmax + 2) {
+        const double full = typical(kmax);
+        for (int kc = k_lo; kc < kmax; ++kc) use_cap[kc] = typical(kc) < 0.97 * full;
+    }
+    std::vector<std::vector<uint64_t>> fam;  // set families, built before any task reads them
+    std::vector<int> fam_k;
+    if (o.cluster_sets)
+        for (int kc = std::max(2, k_lo); kc <= kmax; ++kc) {
+            if (!use_cap[kc]) continue;
+            std::vector<uint64_t> a, b;
+            if (kc == kmax) {
+                a = sets0;
+                b = sets1;
+            } else {
+                dense_sets(n, gates, S.dropped, kc, a, b);
+            }
+            if (!a.empty()) {
+                fam.push_back(std::move(a));
+                fam_k.push_back(kc);
+            }
+            if (!b.empty()) {
+                fam.push_back(std::move(b));
+                fam_k.push_back(kc);
+            }
+        }
     std::vector<std::future<std::vector<SOp>>> futs;
     for (int kc = k_lo; kc <= kmax; ++kc)
-        futs.push_back(std::async(policy, [&, kc]() {
-            return greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag);
-        }));
-    if (kmax > 1)
+        if (use_cap[kc])
+            futs.push_back(std::async(policy, [&, kc]() {
+                return greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag);
+            }));
+    if (kmax > 1 && use_cap[kmax - 1])
         futs.push_back(std::async(policy, [&]() {
             return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost);
         }));
-    for (const std::vector<uint64_t>* sets : {&sets0, &sets1})
-        if (!sets->empty())
-            futs.push_back(std::async(policy, [&, sets]() {
-                return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, sets);
-            }));
+    for (size_t f = 0; f < fam.size(); ++f)
+        futs.push_back(std::async(policy, [&, f]() {
+            return greedy_ops(n, gates, S.dropped, S.n_applied, fam_k[f], o.fuse_diag, nullptr, &fam[f]);
+        }));
     double best_cost = 0.0;
     for (size_t c = 0; c < futs.size(); ++c) {
         std::vector<SOp> ops = futs[c].get();

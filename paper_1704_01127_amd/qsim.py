@@ -261,6 +261,7 @@ OPT_PAIR_TILE = 8
 OPT_CLUSTER_SETS = 9
 OPT_BATCH_ORDER = 10
 OPT_CHECK_UNITARY = 11
+OPT_MAP_QUBITS = 12
 
 
 def set_option(option: int, value: int):
@@ -521,10 +522,10 @@ class State:
         _check(L.qsim_op_timings(self.h, kind, k, qs, epi, ms, m, ctypes.byref(n)))
         kinds = {0: "cluster", 1: "diag", 2: "gate1q", 3: "phase1q", 4: "cz", 5: "build", 6: "init_cluster",
                  8: "init_cluster2",
-                 7: "pair"}
+                 7: "pair", 9: "permute"}
         return [dict(kind=kinds[kind[i]], k=k[i], qubits=[q for q in qs[6 * i:6 * i + 6] if q >= 0],
                      epi=bool(epi[i] & 1), staged=bool(epi[i] & 2), mfma=bool(epi[i] & 4),
-                     stats=bool(epi[i] & 8), ms=float(ms[i]))
+                     stats=bool(epi[i] & 8), n_epi=(epi[i] >> 8) & 255, ms=float(ms[i]))
                 for i in range(m)]
 
     def sync(self):

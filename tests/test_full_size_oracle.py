@@ -71,3 +71,35 @@ def test_30q_depth25_forms_match_oracle(seed):
         qsim.set_option(qsim.OPT_K6_KERNEL, old)
     # fp16-halves 6-qubit products stay at the error level of the fp32 matrix cores
     assert errs[("c64", 2, "learned")] <= 4 * errs[("c64", 0, "learned")], errs
+
+
+@pytest.mark.parametrize("n", [28, 30])
+def test_learned_and_greedy_match_oracle(n):
+    """The learned-scheduling workload (depth 40 with a Haar 5-qubit gate
+    after every 8th cycle, held-out seed 110): the learned schedule and the
+    fixed-k greedy schedule at the tuned k_max, complex64 (and complex128 at
+    28 qubits), each against the float64 oracle."""
+    from paper_1704_01127_amd.costmodel import workload
+    qsim.load_tuning()
+    circ = workload(n, 40, 110)
+    kept, _ = oracle.drop_trailing_diagonal(circ)
+    psi = oracle.run(kept)
+    mx = float(np.max(np.abs(psi)))
+    ref = torch.from_numpy(psi).cuda()
+    del psi
+    base = dict(fuse_diag=True, skip_trailing_diag=True, skip_initial_h=True)
+    dts = ("c64", "c128") if n <= 28 else ("c64",)
+    for dt in dts:
+        tuned = qsim.best_opts(n, dt)
+        for opts in (dict(base, scheduler="learned", kmax=6), dict(base, scheduler="greedy", kmax=tuned["kmax"])):
+            s = qsim.State(n, dt)
+            st = s.run_circuit(circ.gates, **opts)
+            assert st["n_gates_applied"] + n == len(kept.gates)
+            f, d = s.compare(ref)
+            print("n %d %s %s: ops %d, 1 - F %.2e, max|d| %.3e" % (n, dt, opts["scheduler"], st["n_ops"], 1 - f, d),
+                  flush=True)
+            if dt == "c128":
+                assert d <= 1e-12
+            else:
+                assert f >= 1 - 1e-6 and d <= fp32_circuit_bound(mx, st["n_ops"], 6), (f, d)
+            del s

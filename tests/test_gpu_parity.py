@@ -642,6 +642,35 @@ def test_permute_qubits(dt, case):
     np.testing.assert_array_equal(s.to_numpy().astype(np.complex128), held)
 
 
+@pytest.mark.parametrize("dt", ["c64", "c128"])
+@pytest.mark.parametrize("kmax", [4, 6])
+def test_map_qubits_matches_oracle(dt, kmax):
+    """QSIM_OPT_MAP_QUBITS: the run applies relabelled gates from the uniform
+    state and one permutation pass restores the order; the state (and the
+    fused sums) equal the oracle's."""
+    circ = with_haar_layers(supremacy_circuit(4, 5, 25, seed=3), 8, 5, 9)
+    ref = oracle.run(circ)
+    old = qsim.get_option(qsim.OPT_MAP_QUBITS)
+    qsim.set_option(qsim.OPT_MAP_QUBITS, 1)
+    try:
+        s = make_state(20, dt)
+        st = s.run_circuit(circ.gates, kmax=kmax, fuse_diag=True, skip_initial_h=True, record_timings=True,
+                           fused_stats=True)
+        kinds = [r["kind"] for r in s.op_timings()]
+        norm, s2, ent = s.probs()
+    finally:
+        qsim.set_option(qsim.OPT_MAP_QUBITS, old)
+    assert kinds[-1] == "permute", kinds  # this circuit's layout moves qubits
+    got = s.to_numpy()
+    if dt == "c128":
+        assert np.max(np.abs(got - ref)) <= 1e-12
+    else:
+        assert_fp32_circuit(got, ref, st, kmax)
+    on, os2, oent = oracle.stats(ref)
+    tol = 1e-12 if dt == "c128" else 1e-5
+    assert abs(norm - on) <= tol and abs(s2 - os2) <= tol * os2 * 10 and abs(ent - oent) <= tol * 20
+
+
 def test_permute_qubits_errors():
     s = make_state(8, "c64")
     for src, dst in (([0, 1], [1, 2]), ([0, 0], [1, 1]), ([8], [8]), (list(range(13)), list(range(13)))):

@@ -99,22 +99,60 @@ def test_learned_scheduler_runs_exactly():
 
 
 @pytest.mark.skipif(not os.path.exists(qsim.COST_MODEL_PATH), reason="no trained cost model in the tree")
-def test_learned_vs_greedy_time_to_solution():
-    """What the trained model gains: held-out 28- and 30-qubit depth-40
-    circuits with Haar 5-qubit gates, timed end to end (scheduling included)
-    with the learned scheduler (k <= 6) against the fixed-k greedy scheduler
-    that is used without a model (k = 5, the default) and against fixed-k
-    greedy at k = 6. Results must agree; the learned schedule must beat k = 5
-    by at least 5% in total and be within 3% of k = 6 (the gains are printed)."""
-    from paper_1704_01127_amd.costmodel import compare
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_learned_vs_tuned_greedy_time_to_solution(dtype):
+    """What the trained model gains over the method without it: held-out 28-
+    and 30-qubit depth-40 circuits with Haar 5-qubit gates, timed end to end
+    (scheduling included) with the learned scheduler (k <= 6) against the
+    fixed-k greedy scheduler at the k_max the autotuner picked for that dtype
+    and size (complex64: 6; complex128: 5). Results must agree (float64
+    states to 1e-12). The learned total must not exceed the tuned greedy
+    total by more than the run-to-run spread measured here (the same tuned
+    greedy schedule timed twice): where the model picks the tuned schedule the
+    two times differ by noise only. Gains and losses per circuit are
+    printed."""
+    from paper_1704_01127_amd.costmodel import compare, time_run, workload
     qsim.load_tuning()
     lines = []
-    rows = compare(n_list=(28, 30), seeds=range(110, 113), log=lines.append)
+    rows = compare(n_list=(28, 30), seeds=range(110, 113), dtype=dtype, log=lines.append)
     print("\n".join(lines))
     for r in rows:
-        assert r["fidelity_learned_vs_greedy"] >= 1 - 1e-6
-    g5 = sum(r["greedy_ms"] for r in rows)
-    g6 = sum(r["greedy6_ms"] for r in rows)
+        assert r["fidelity_learned_vs_greedy"] >= (1 - 1e-6 if dtype == "c64" else 1 - 1e-12)
+    tg = sum(r["tuned_greedy_ms"] for r in rows)
     lr = sum(r["learned_ms"] for r in rows)
-    assert lr <= 0.95 * g5, (lr, g5)
-    assert lr <= 1.03 * g6, (lr, g6)
+    # spread of the tuned schedule's own time, summed over the same circuits
+    base = dict(fuse_diag=True, skip_trailing_diag=True, skip_initial_h=True)
+    spread = 0.0
+    for r in rows:
+        s = qsim.State(r["n"], dtype, kmax=6)
+        opts = dict(base, scheduler="greedy", kmax=r["tuned_kmax"])
+        t2, _ = time_run(s, workload(r["n"], 40, r["seed"]), opts)
+        spread += abs(t2 * 1e3 - r["tuned_greedy_ms"])
+        del s
+        torch.cuda.empty_cache()
+    print("learned %.1f ms, tuned greedy %.1f ms, spread %.2f ms" % (lr, tg, spread))
+    assert lr <= tg + spread, (lr, tg, spread)
+
+
+def test_autotuner_writes_a_usable_table(tmp_path):
+    """The autotuner end to end on one small bucket: kernel variants at 16
+    qubits, the cost table, the (scheduler, k_max) choice of the 20-qubit
+    bucket; the table it writes has every entry and loads."""
+    import json
+
+    from paper_1704_01127_amd import autotune
+    out = tmp_path / "tune.json"
+    try:
+        autotune.main(["--n", "16", "--n-variant", "16", "--dtypes", "c64", "--reps", "1", "--variant-trials", "1",
+                       "--buckets", "20", "--no-batch", "--out", str(out)])
+        t = json.loads(out.read_text())
+        assert sorted(t["variants"]["c64"]) == ["4", "5", "6"]
+        assert all(len(row) == 4 and set(row) <= {0, 1} for row in t["variants"]["c64"].values())
+        assert len(t["cost_us"]["c64"]) == 7 and all(x > 0 for x in t["cost_us"]["c64"])
+        b = t["best"]["c64"]["20"]
+        assert b["scheduler"] in ("greedy", "analytic") and 3 <= b["kmax"] <= 6 and b["ms"] > 0
+        qsim.load_tuning(str(out))
+        assert qsim.best_opts(20, "c64") == dict(scheduler=b["scheduler"], kmax=b["kmax"])
+    finally:
+        qsim.set_option(qsim.OPT_CLUSTER_VARIANT, -1)
+        qsim.load_tuning()  # the repository's table again

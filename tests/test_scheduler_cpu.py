@@ -179,11 +179,11 @@ def test_candidate_sets_reduce_passes():
         qsim.set_option(qsim.OPT_CLUSTER_SETS, old)
 
 
-@pytest.mark.parametrize("option", [qsim.OPT_CLUSTER_SETS, qsim.OPT_BATCH_ORDER])
-def test_planning_option_range(option):
+@pytest.mark.parametrize("option,top", [(qsim.OPT_CLUSTER_SETS, 1), (qsim.OPT_BATCH_ORDER, 2), (qsim.OPT_MAP_QUBITS, 1)])
+def test_planning_option_range(option, top):
     old = qsim.get_option(option)
     assert old in (0, 1)
-    for bad in (-1, 2):
+    for bad in (-1, top + 1):
         with pytest.raises(qsim.QsimError):
             qsim.set_option(option, bad)
     assert qsim.get_option(option) == old
