@@ -62,12 +62,20 @@ def cmd_record(args):
             for seed in range(args.seeds):
                 circ = workload(n, args.depth, seed)
                 for ci, cfg in enumerate(configs):
-                    state.init("uniform")
-                    state.run_circuit(circ.gates, record_timings=True, skip_trailing_diag=True, **cfg)
-                    f, y = op_record_rows(state.op_timings(), n, code)
-                    feats += f
-                    ys += y
-                    meta += [(seed, n, code, ci)] * len(y)
+                    # both matrix-core kernel variants (direct gather, LDS-staged
+                    # tiles) on every op, so the model learns which is faster
+                    # for a given target set
+                    for variant in (0, 1):
+                        qsim.set_option(qsim.OPT_CLUSTER_VARIANT, variant)
+                        try:
+                            state.init("uniform")
+                            state.run_circuit(circ.gates, record_timings=True, skip_trailing_diag=True, **cfg)
+                            f, y = op_record_rows(state.op_timings(), n, code)
+                        finally:
+                            qsim.set_option(qsim.OPT_CLUSTER_VARIANT, -1)
+                        feats += f
+                        ys += y
+                        meta += [(seed, n, code, ci)] * len(y)
                 print("recorded %s n=%d seed=%d: %d records (%.0f s)" % (dt, n, seed, len(ys), time.time() - t_start),
                       flush=True)
             del state
@@ -173,6 +181,7 @@ def compare(n_list=(28, 29, 30), seeds=range(100, 104), depth=40, dtype="c64", l
             t6, st6 = time_run(s1, circ, dict(base, scheduler="greedy", kmax=6))
             ta, sta = time_run(s1, circ, dict(base, scheduler="analytic", kmax=6))
             row = dict(n=n, dtype=dtype, seed=seed, tuned_kmax=tuned["kmax"], tuned_greedy_ms=tg * 1e3,
+                       tuned_schedule_ms=stg["schedule_ms"],
                        greedy_ms=t5 * 1e3, greedy6_ms=t6 * 1e3, learned_ms=tl * 1e3, analytic_ms=ta * 1e3,
                        tuned_greedy_ops=stg["n_ops"], greedy_ops=st5["n_ops"], greedy6_ops=st6["n_ops"],
                        learned_ops=stl["n_ops"], analytic_ops=sta["n_ops"],

@@ -5,6 +5,7 @@
 // scheduler's cost is exp(prediction) * 2^(n - 30).
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -19,7 +20,7 @@ constexpr int kFeatures = 16;
 // Features of one op: sizes, FLOP and byte intensity, where the targets sit
 // (low bits break coalescing, high bits stride far), kernel kind and the
 // diagonal epilogue. k = 0 is a standalone diagonal pass.
-void op_features(int n, bool dbl, int k, const int* q, int n_epi, float* f) {
+void op_features(int n, bool dbl, int k, const int* q, int n_epi, float* f, int variant_override) {
     std::memset(f, 0, sizeof(float) * kFeatures);
     int lo = n, hi = -1, below3 = 0, below6 = 0, top3 = 0;
     for (int j = 0; j < k; ++j) {
@@ -36,7 +37,8 @@ void op_features(int n, bool dbl, int k, const int* q, int n_epi, float* f) {
     for (int j = 0; j < k; ++j) g.t[j] = q[j];
     g.k = k;
     g.n = n;
-    const int variant = k == 0 ? 0 : cluster_variant_for(dbl, g, layout);
+    int variant = k == 0 ? 0 : cluster_variant_for(dbl, g, layout);
+    if (variant_override >= 0 && k > 0 && variant_choice(dbl, k, layout)) variant = variant_override;
     f[0] = k / 6.0f;
     f[1] = n / 34.0f;
     f[2] = dbl ? 1.0f : 0.0f;
@@ -63,8 +65,15 @@ struct Model {
     std::vector<float> mean, inv_std; // feature normalisation
     float y_mean = 0.f, y_std = 1.f;
 };
-Model g_model;
+// The loaded model; a load replaces the pointer, so a prediction in flight
+// keeps the model it started with and needs no lock while it evaluates.
+std::shared_ptr<const Model> g_model = std::make_shared<Model>();
 std::mutex g_model_mu;
+
+std::shared_ptr<const Model> current_model() {
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    return g_model;
+}
 }  // namespace
 
 size_t mlp_param_count(int n_in, int h) { return (size_t)h * n_in + h + (size_t)h * h + h + h + 1; }
@@ -107,21 +116,32 @@ float mlp_forward_host(const float* p, int n_in, int h, const float* x) {
     return hw ? mlp_forward_fma(p, n_in, h, x) : mlp_forward_impl<false>(p, n_in, h, x);
 }
 
-bool learned_model_loaded() {
-    std::lock_guard<std::mutex> lk(g_model_mu);
-    return g_model.loaded;
+bool learned_model_loaded() { return current_model()->loaded; }
+
+double learned_cost_us(int n, bool dbl, int k, const int* qubits, int n_epi, int variant) {
+    float f[kFeatures];
+    op_features(n, dbl, k, qubits, n_epi, f, variant);
+    const std::shared_ptr<const Model> m = current_model();
+    if (!m->loaded) return 1.0;
+    float x[kFeatures];
+    for (int i = 0; i < kFeatures; ++i) x[i] = (f[i] - m->mean[i]) * m->inv_std[i];
+    const float y = mlp_forward_host(m->p.data(), m->n_in, m->n_hidden, x);
+    const double log_us = (double)y * m->y_std + m->y_mean;
+    return std::exp(log_us) * std::ldexp(1.0, n - 30);
 }
 
-double learned_cost_us(int n, bool dbl, int k, const int* qubits, int n_epi) {
-    float f[kFeatures];
-    op_features(n, dbl, k, qubits, n_epi, f);
-    std::lock_guard<std::mutex> lk(g_model_mu);
-    if (!g_model.loaded) return 1.0;
-    float x[kFeatures];
-    for (int i = 0; i < kFeatures; ++i) x[i] = (f[i] - g_model.mean[i]) * g_model.inv_std[i];
-    const float y = mlp_forward_host(g_model.p.data(), g_model.n_in, g_model.n_hidden, x);
-    const double log_us = (double)y * g_model.y_std + g_model.y_mean;
-    return std::exp(log_us) * std::ldexp(1.0, n - 30);
+// Predicted time of an op with the faster of the two matrix-core kernel
+// variants (direct gather or LDS-staged tiles) where the op has both and no
+// variant is forced; *variant (nullable) receives the choice (-1: the
+// library's own rule applies).
+double learned_cost_best_us(int n, bool dbl, int k, const int* qubits, int n_epi, int* variant) {
+    if (variant) *variant = -1;
+    if (k == 0 || get_cluster_variant() >= 0 || !variant_choice(dbl, k, cluster_layout(dbl, k, n)))
+        return learned_cost_us(n, dbl, k, qubits, n_epi, -1);
+    const double t0 = learned_cost_us(n, dbl, k, qubits, n_epi, 0);
+    const double t1 = learned_cost_us(n, dbl, k, qubits, n_epi, 1);
+    if (variant) *variant = t1 < t0 ? 1 : 0;
+    return t1 < t0 ? t1 : t0;
 }
 
 }  // namespace qsim
@@ -138,15 +158,15 @@ qsim_status qsim_cost_features(int n_qubits, qsim_dtype dt, int k, const int32_t
         return QSIM_E_INVALID;
     int q[6] = {0, 0, 0, 0, 0, 0};
     for (int j = 0; j < k; ++j) q[j] = qubits[j];
-    op_features(n_qubits, dt == QSIM_C128, k, q, n_epi, out);
+    op_features(n_qubits, dt == QSIM_C128, k, q, n_epi, out, -1);
     return QSIM_OK;
 }
 
 qsim_status qsim_set_cost_model(const float* params, int n_in, int n_hidden, const float* feat_mean,
                                 const float* feat_std, double y_mean, double y_std) {
-    std::lock_guard<std::mutex> lk(g_model_mu);
     if (!params) {  // unload
-        g_model = Model();
+        std::lock_guard<std::mutex> lk(g_model_mu);
+        g_model = std::make_shared<Model>();
         return QSIM_OK;
     }
     if (n_in != kFeatures || n_hidden < 1 || n_hidden > 256 || !feat_mean || !feat_std || !(y_std > 0))
@@ -161,7 +181,8 @@ qsim_status qsim_set_cost_model(const float* params, int n_in, int n_hidden, con
     m.y_mean = (float)y_mean;
     m.y_std = (float)y_std;
     m.loaded = true;
-    g_model = std::move(m);
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    g_model = std::make_shared<const Model>(std::move(m));
     return QSIM_OK;
 }
 
@@ -175,7 +196,7 @@ qsim_status qsim_mlp_predict_host(const float* params, int n_in, int n_hidden, c
 double qsim_cost_model_predict_us(int n_qubits, qsim_dtype dt, int k, const int32_t* qubits, int n_epi) {
     int q[6] = {0, 0, 0, 0, 0, 0};
     for (int j = 0; j < k && j < 6; ++j) q[j] = qubits[j];
-    return learned_cost_us(n_qubits, dt == QSIM_C128, k, q, n_epi);
+    return learned_cost_us(n_qubits, dt == QSIM_C128, k, q, n_epi, -1);
 }
 
 }  // extern "C"

@@ -90,7 +90,8 @@ int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
 
 namespace qsim {
 bool learned_model_loaded();
-double learned_cost_us(int n, bool dbl, int k, const int* qubits, int n_epi);
+double learned_cost_us(int n, bool dbl, int k, const int* qubits, int n_epi, int variant);
+double learned_cost_best_us(int n, bool dbl, int k, const int* qubits, int n_epi, int* variant);
 }  // namespace qsim
 
 struct OpRecord {
@@ -246,6 +247,7 @@ struct Chunk {
         double m[8];
         bool stats;      // kind 0: also sum p, p^2, -p ln p of the stored state (the run's last op)
         int n_epi;       // diagonal gates the scheduler attached to the cluster (its epilogue)
+        int variant;     // kind 0: matrix-core kernel variant chosen by the learned model, -1: the library's rule
     };
     std::vector<Item> items;
     int slots_used = 0;
@@ -318,7 +320,8 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
         OpRecord r;
         std::memset(&r, 0, sizeof(r));
         r.kind = it.kind;
-        const int variant = it.kind == 0 ? cluster_variant_for(s->dbl, it.geom, it.layout) : 0;
+        const int variant =
+            it.kind == 0 ? (it.variant >= 0 ? it.variant : cluster_variant_for(s->dbl, it.geom, it.layout)) : 0;
         if (it.kind == 0 || it.kind == 6 || it.kind == 7 || it.kind == 8) {
             r.k = it.geom.k;
             for (int j = 0; j < it.geom.k; ++j) r.qubits[j] = it.geom.t[j];
@@ -440,6 +443,7 @@ qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, con
     it.slot = c.slots_used++;
     it.epi = -1;
     it.n_epi = (int)epi_gates.size();
+    it.variant = -1;
     if (e.n_cc || e.n_mix || e.n_ph) {
         it.epi = (int)c.epis.size();
         c.epis.push_back(e);
@@ -678,7 +682,7 @@ std::vector<SGate> qsim::api::to_sgates(const qsim_gate* gates, int n_gates) {
 OpCostFn qsim::api::cost_fn(const qsim_run_opts* o, int n, bool dbl) {
     if (!o || o->scheduler == QSIM_SCHED_PER_GATE || o->scheduler == QSIM_SCHED_GREEDY) return OpCostFn();
     if (o->scheduler == QSIM_SCHED_LEARNED && learned_model_loaded()) {
-        return [n, dbl](int k, const int* q, int n_epi) { return learned_cost_us(n, dbl, k, q, n_epi); };
+        return [n, dbl](int k, const int* q, int n_epi) { return learned_cost_us(n, dbl, k, q, n_epi, -1); };
     }
     const double scale = std::ldexp(1.0, n - g_cost_nref[dbl]);
     const double* us = g_cost_us[dbl];
@@ -948,6 +952,9 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     const bool fold = S.uniform_init && g_fold_init && !S.ops.empty() && S.ops[0].kind == OP_CLUSTER;
     const bool fold2 = fold && g_fold_init == 2 && !s->dbl && S.ops.size() >= 2 && S.ops[1].kind == OP_CLUSTER &&
                        S.ops[1].k == 6 && cluster_layout(false, 6, s->n) == LAYOUT_SPLIT16F;
+    // the learned model also picks each cluster's kernel variant (unless one is forced)
+    const bool learned_variants = opts && opts->scheduler == QSIM_SCHED_LEARNED && so.mode == 2 &&
+                                  learned_model_loaded() && get_cluster_variant() < 0;
     // consecutive clusters of <= 5 qubits on a complex64 state go in pairs
     const bool pairing = g_pair && !s->dbl && s->n >= 11 && s->kmax_ws >= 5 && so.mode != 0;
     auto small = [&](size_t i) { return S.ops[i].kind == OP_CLUSTER && S.ops[i].k <= 5; };
@@ -991,6 +998,11 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
             st.n_diag_ops++;
         } else {
             r = add_cluster(s, c, op.k, op.qubits, gates, op.members, op.epi);
+            if (r == QSIM_OK && learned_variants) {  // the variant the model predicts faster for these targets
+                int v = -1;
+                learned_cost_best_us(s->n, s->dbl, op.k, op.qubits, (int)op.epi.size(), &v);
+                c.items.back().variant = v;
+            }
             st.n_clusters_by_k[op.k]++;
             st.n_gates_fused_epilogue += (int)op.epi.size();
         }
@@ -1001,9 +1013,12 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     // sums the quantities qsim_probs reports, so they need no further pass
     if (opts && opts->fused_stats && !c.items.empty()) {
         Chunk::Item& last = c.items.back();
-        if (last.kind == 0 &&
-            cluster_stats_supported(s->dbl, last.geom.k, last.layout, cluster_variant_for(s->dbl, last.geom, last.layout)))
-            last.stats = true;
+        // the sums come from the direct kernels: a staged choice of the model
+        // gives way, since the sums save a whole pass over the state
+        if (last.kind == 0 && last.variant == 1 && cluster_stats_supported(s->dbl, last.geom.k, last.layout, 0))
+            last.variant = 0;
+        const int v = last.variant >= 0 ? last.variant : cluster_variant_for(s->dbl, last.geom, last.layout);
+        if (last.kind == 0 && cluster_stats_supported(s->dbl, last.geom.k, last.layout, v)) last.stats = true;
     }
     if (qsim_status r = flush(s, c)) return r;
     if (pm) {  // back to the caller's qubit order (sums of a fused_stats pass do not change)

@@ -223,6 +223,14 @@ int get_cluster_variant();
 void set_tune_entry(bool dbl, int k, int cls, int variant);
 int get_tune_entry(bool dbl, int k, int cls);
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout);
+// The op can run with either matrix-core kernel variant (direct or staged).
+inline bool variant_choice(bool dbl, int k, int layout) {
+    return layout != LAYOUT_PLAIN && (k <= 5 || (!dbl && layout == LAYOUT_SPLIT16F));
+}
+int get_cluster_variant();
+// Learned cost model: features of an op (variant_override >= 0 replaces the
+// kernel variant the library would pick, where the op has both).
+void op_features(int n, bool dbl, int k, const int* q, int n_epi, float* f, int variant_override);
 hipError_t launch_diag(void* psi, bool dbl, int n, const EpiDesc* epi, hipStream_t st);
 StageGeom make_stage_geom(const ClusterGeom& g, int C, int unit);
 hipError_t launch_batch(const BatchOp* ops, const BatchItem* items, uint32_t n_items, uint32_t* counters,

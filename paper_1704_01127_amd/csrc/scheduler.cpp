@@ -14,7 +14,7 @@
 // cluster may give way to the (kmax - 1)-qubit cluster of the same seed when
 // that is predicted cheaper per gate - are built, and the one with the
 // smallest predicted total time is kept. Narrower caps are skipped when the
-// model predicts their clusters no cheaper than full-width ones. (Per-cluster choices alone are
+// model predicts their clusters not cheap enough to pay for their extra passes. (Per-cluster choices alone are
 // myopic: a cluster can look cheap per gate and still leave more total work;
 // the final comparison is between whole schedules.)
 //
@@ -498,12 +498,13 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     // for kmax.
     const int k_lo = std::max(1, kmax - 2);
     const auto policy = o.parallel ? std::launch::async : std::launch::deferred;
-    // A narrower cap only adds passes, so it can only win when its clusters are
-    // predicted clearly cheaper than full-width ones (complex128: 6-qubit
-    // clusters are bound by the fp64 matrix cores). The predicted cost of a
-    // cluster of each width, averaged over low, middle, high and spread target
-    // sets, decides which caps (and the cost-trimmed schedule, which mixes
-    // widths) are worth building.
+    // A narrower cap only adds passes: a cluster of kc qubits takes roughly
+    // kc / kmax of the gates of a full-width one, so a cap kc is worth building
+    // only when its clusters are predicted cheaper than that fraction of a
+    // full-width cluster's time (complex128: 6-qubit clusters are bound by the
+    // fp64 matrix cores). The predicted cost of a cluster of each width,
+    // averaged over low, middle, high and spread target sets, decides which
+    // caps (and the cost-trimmed schedule, which mixes widths) are built.
     auto typical = [&](int k) {
         int sets[4][kMaxK];
         for (int j = 0; j < k; ++j) {
@@ -519,54 +520,64 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     std::vector<char> use_cap(kmax + 1, 1);
     if (n >= kmax + 2) {
         const double full = typical(kmax);
-        for (int kc = k_lo; kc < kmax; ++kc) use_cap[kc] = typical(kc) < 0.97 * full;
+        for (int kc = k_lo; kc < kmax; ++kc) use_cap[kc] = typical(kc) < full * kc / kmax;
     }
-    std::vector<std::vector<uint64_t>> fam;  // set families, built before any task reads them
-    std::vector<int> fam_k;
+    // set families: kmax's are at hand; a narrower cap's are found inside
+    // its tasks (in parallel), one task per (cap, slack)
+    struct Fam {
+        int k, slack;
+    };
+    std::vector<Fam> fam;
     if (o.cluster_sets)
         for (int kc = std::max(2, k_lo); kc <= kmax; ++kc) {
             if (!use_cap[kc]) continue;
-            std::vector<uint64_t> a, b;
             if (kc == kmax) {
-                a = sets0;
-                b = sets1;
+                if (!sets0.empty()) fam.push_back({kc, 0});
+                if (!sets1.empty()) fam.push_back({kc, 1});
             } else {
-                dense_sets(n, gates, S.dropped, kc, a, b);
-            }
-            if (!a.empty()) {
-                fam.push_back(std::move(a));
-                fam_k.push_back(kc);
-            }
-            if (!b.empty()) {
-                fam.push_back(std::move(b));
-                fam_k.push_back(kc);
+                fam.push_back({kc, 0});
+                fam.push_back({kc, 1});
             }
         }
-    std::vector<std::future<std::vector<SOp>>> futs;
+    // each task builds a candidate and predicts its total (in parallel)
+    using Cand = std::pair<std::vector<SOp>, double>;
+    auto priced = [&](std::vector<SOp> ops) {
+        double total = 0.0;
+        for (const SOp& op : ops)
+            total += op.kind == OP_DIAG ? cost(0, op.qubits, 0) : cost(op.k, op.qubits, (int)op.epi.size());
+        return Cand(std::move(ops), total);
+    };
+    std::vector<std::future<Cand>> futs;
     for (int kc = k_lo; kc <= kmax; ++kc)
         if (use_cap[kc])
             futs.push_back(std::async(policy, [&, kc]() {
-                return greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag);
+                return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag));
             }));
     if (kmax > 1 && use_cap[kmax - 1])
         futs.push_back(std::async(policy, [&]() {
-            return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost);
+            return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost));
         }));
     for (size_t f = 0; f < fam.size(); ++f)
         futs.push_back(std::async(policy, [&, f]() {
-            return greedy_ops(n, gates, S.dropped, S.n_applied, fam_k[f], o.fuse_diag, nullptr, &fam[f]);
+            const Fam& F = fam[f];
+            if (F.k == kmax)
+                return priced(greedy_ops(n, gates, S.dropped, S.n_applied, F.k, o.fuse_diag, nullptr,
+                                         F.slack ? &sets1 : &sets0));
+            std::vector<uint64_t> a, b;
+            dense_sets(n, gates, S.dropped, F.k, a, b);
+            const std::vector<uint64_t>& sets = F.slack ? b : a;
+            if (sets.empty()) return Cand(std::vector<SOp>(), -1.0);  // no such family: not a candidate
+            return priced(greedy_ops(n, gates, S.dropped, S.n_applied, F.k, o.fuse_diag, nullptr, &sets));
         }));
     double best_cost = 0.0;
+    bool have = false;
     for (size_t c = 0; c < futs.size(); ++c) {
-        std::vector<SOp> ops = futs[c].get();
-        double total = 0.0;
-        for (const SOp& op : ops) {
-            if (op.kind == OP_DIAG) total += cost(0, op.qubits, 0);
-            else total += cost(op.k, op.qubits, (int)op.epi.size());
-        }
-        if (c == 0 || total < best_cost) {
-            best_cost = total;
-            S.ops = std::move(ops);
+        Cand cand = futs[c].get();
+        if (cand.second < 0) continue;
+        if (!have || cand.second < best_cost) {
+            best_cost = cand.second;
+            S.ops = std::move(cand.first);
+            have = true;
         }
     }
     return S;
