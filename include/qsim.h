@@ -44,6 +44,14 @@ extern "C" {
 
 typedef struct qsim_state_s* qsim_state;
 
+/* Widest cluster the scheduler forms (a fused k-qubit gate, Sec. 3.6.1) and
+ * widest single gate a caller passes. 7-qubit clusters exist on complex64
+ * states of at least 12 qubits while QSIM_OPT_K6_KERNEL is 2 (fp16 matrix
+ * cores with operand halves); elsewhere the cap is 6. Per-op qubit lists
+ * (qsim_op_timings, qsim_schedule) have QSIM_MAX_CLUSTER entries per op. */
+#define QSIM_MAX_CLUSTER 7
+#define QSIM_MAX_GATE_QUBITS 6
+
 typedef enum { QSIM_C64 = 1, QSIM_C128 = 2 } qsim_dtype;
 
 /* Initial contents of the state at qsim_create / qsim_init_state.
@@ -56,7 +64,8 @@ typedef enum { QSIM_INIT_ZERO = 0, QSIM_INIT_UNIFORM = 1, QSIM_INIT_KEEP = 2 } q
 typedef enum {
     QSIM_OK = 0,
     QSIM_E_INVALID = -1,     /* bad argument: qubit >= n or repeated, null pointer, buffer too small */
-    QSIM_E_UNSUPPORTED = -2, /* k > 6, n out of range, too many entries in a diagonal layer */
+    QSIM_E_UNSUPPORTED = -2, /* a gate over 6 qubits, kmax over 7, n out of range, too many entries in a
+                                diagonal layer */
     QSIM_E_DEVICE = -3       /* a HIP runtime error or a failed GPU launch */
 } qsim_status;
 
@@ -99,7 +108,8 @@ typedef enum {
 } qsim_scheduler;
 
 typedef struct {
-    int32_t kmax;               /* largest cluster, 1..6 (ignored by PER_GATE) */
+    int32_t kmax;               /* largest cluster, 1..7 (ignored by PER_GATE); runs and schedules
+                                   cap it at 6 where no 7-qubit kernel applies (QSIM_MAX_CLUSTER) */
     int32_t scheduler;          /* qsim_scheduler */
     int32_t skip_trailing_diag; /* drop diagonal gates after the last non-diagonal gate on all
                                    their qubits: they change phases, not probabilities (Sec. 3.6) */
@@ -113,7 +123,7 @@ typedef struct {
     int32_t schedule_dtype;     /* qsim_dtype the cost models assume in qsim_schedule
                                    (qsim_run_circuit uses the state's); 0 = C64 */
     int32_t fused_stats;        /* when the run's last op is a cluster on a complex64 state applied
-                                   by a direct matrix-core kernel (k = 4..6), that kernel also sums
+                                   by a direct matrix-core kernel (k = 4..7), that kernel also sums
                                    the float64 norm, sum of p^2 and entropy of the amplitudes it
                                    stores, and the next qsim_probs with dev_out = NULL returns them
                                    without reading the state again. Any library call that changes
@@ -123,7 +133,7 @@ typedef struct {
 
 typedef struct {
     int32_t n_ops;              /* launches of cluster / diagonal / per-gate kernels */
-    int32_t n_clusters_by_k[7]; /* clusters applied, by k */
+    int32_t n_clusters_by_k[8]; /* clusters applied, by k (index 0 unused) */
     int32_t n_diag_ops;         /* standalone diagonal passes */
     int32_t n_gates_applied;    /* gates after trailing / initial skips */
     int32_t n_gates_fused_epilogue;
@@ -237,7 +247,7 @@ const char* qsim_last_error(void);
  * uniform initialisation and the first two clusters in one pass, 9 the
  * permutation pass of QSIM_OPT_MAP_QUBITS),
  * op_k (cluster size - 5 for a pair, 6 for kind 8; number of matrices for a build),
- * op_qubits[6*i ..] (sorted targets of a cluster - of the first for a pair,
+ * op_qubits[QSIM_MAX_CLUSTER*i ..] (sorted targets of a cluster - of the first for a pair,
  * of the second for kind 8 -
  * or the gate's qubits, -1 padded), op_epi (flags of a cluster: bit 0 = applies diagonal
  * gates while storing, bit 1 = LDS-staged kernel variant, bit 2 = matrix-core
@@ -249,7 +259,8 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
                             int32_t* op_epi, float* ms, int cap, int* n_ops);
 
 /* Process-wide tuning (the autotuner's controls).
- * The matrix-core cluster kernels (k <= 5; k = 6 on complex64 states) exist
+ * The matrix-core cluster kernels (k <= 5; k = 6 on complex64 states; k = 7
+ * has the direct form only) exist
  * in two variants: 0 gathers each lane's amplitudes straight from HBM into
  * registers, 1 moves the wave's tile as linear runs and re-orders it through
  * LDS. The variant is looked up per
@@ -267,7 +278,8 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * of 6-qubit clusters on complex64 states: 0 the fp32 real-split product, 1
  * the fp32 three-multiplication complex product, 2 (default) fp16 matrix
  * cores on hi / lo halves of the operands (about 2^-21 relative error, the
- * size of fp32 rounding),
+ * size of fp32 rounding); only with 2 are 7-qubit clusters formed (the same
+ * halves on the matrix's real and imaginary parts),
  * read when a cluster is enqueued. QSIM_OPT_FOLD_INIT (default 2): when a
  * run starts from the uniform state (skip_initial_h) with a cluster, 1
  * writes that state and the cluster - a product state again - in one pass
@@ -334,7 +346,7 @@ qsim_status qsim_set_tune_entry(qsim_dtype dt, int k, int low_class, int variant
 int qsim_get_tune_entry(qsim_dtype dt, int k, int low_class);
 
 /* Cost table of QSIM_SCHED_ANALYTIC: us_by_k[k] = measured microseconds of one
- * op on a state of n_ref qubits (index 0: a diagonal pass, 1..6: a k-qubit
+ * op on a state of n_ref qubits (index 0: a diagonal pass, 1..7: a k-qubit
  * cluster); costs scale as 2^(n - n_ref) because every op streams the whole
  * state (Sec. 3.1: the kernels are memory bound; a compute-bound k shows up as
  * a larger entry). The cost-driven schedulers build the greedy schedule for
@@ -366,7 +378,8 @@ qsim_status qsim_cost_features(int n_qubits, qsim_dtype dt, int k, const int32_t
 size_t qsim_mlp_param_count(int n_in, int n_hidden);
 qsim_status qsim_set_cost_model(const float* params, int n_in, int n_hidden, const float* feat_mean,
                                 const float* feat_std, double y_mean, double y_std);
-/* Predicted microseconds of one op under the loaded model (1.0 if none). */
+/* Predicted microseconds of one op under the loaded model (1.0 if none; -1.0
+ * for k outside 0..QSIM_MAX_CLUSTER or a null qubit list with k > 0). */
 double qsim_cost_model_predict_us(int n_qubits, qsim_dtype dt, int k, const int32_t* qubits, int n_epi);
 /* Host forward pass (float32, fused multiply-adds in index order): y[b] for x[batch][in]. */
 qsim_status qsim_mlp_predict_host(const float* params, int n_in, int n_hidden, const float* x, int batch,
@@ -393,7 +406,7 @@ qsim_status qsim_mlp_adam(int n_params, float* dev_params, const float* dev_grad
  * gate_role[g] = 0 (folded into the op's matrix), 1 (applied while storing,
  * diagonal) or 2 (the op is a standalone diagonal pass). For each op:
  * op_kind[o] (0 cluster, 1 diagonal pass, 2 per-gate), op_k[o] and its sorted
- * qubits op_qubits[6*o ..]. Arrays of op_cap entries; *n_ops receives the
+ * qubits op_qubits[QSIM_MAX_CLUSTER*o ..]. Arrays of op_cap entries; *n_ops receives the
  * count. Returns QSIM_E_INVALID if op_cap is too small. */
 qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates,
                           const qsim_run_opts* opts, int32_t* gate_op, int32_t* gate_role,
@@ -426,7 +439,7 @@ typedef struct {
     int32_t specialize;         /* bit 0: CZ on global qubits; bit 1: diagonal 1-qubit gates */
     int32_t search;
     int32_t early_swaps;
-    int32_t kmax;               /* 0..6; 0 = no clustering (stage_clusters reads -1) */
+    int32_t kmax;               /* 0..7; 0 = no clustering (stage_clusters reads -1) */
     int32_t fuse_diag;          /* clustering option, as in qsim_run_opts */
     int32_t skip_initial_h;     /* as in qsim_run_opts */
     int32_t skip_trailing_diag; /* as in qsim_run_opts */

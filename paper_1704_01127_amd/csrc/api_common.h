@@ -36,6 +36,8 @@ qsim_status split_epilogue(const int* pos_of, const qsim_gate* gates, const std:
 std::vector<SGate> to_sgates(const qsim_gate* gates, int n_gates);
 OpCostFn cost_fn(const qsim_run_opts* o, int n, bool dbl);
 SchedOpts to_sched_opts(const qsim_run_opts* o);
+// SchedOpts::fold_start of a run on a state of n qubits (complex128 if dbl).
+int fold_start_for(bool dbl, int n);
 
 }  // namespace api
 }  // namespace qsim

@@ -156,7 +156,7 @@ qsim_status qsim_cost_features(int n_qubits, qsim_dtype dt, int k, const int32_t
                                float* out) {
     if (!out || k < 0 || k > kMaxK || (k > 0 && !qubits) || n_qubits < 1 || n_qubits > 40)
         return QSIM_E_INVALID;
-    int q[6] = {0, 0, 0, 0, 0, 0};
+    int q[kMaxK] = {};
     for (int j = 0; j < k; ++j) q[j] = qubits[j];
     op_features(n_qubits, dt == QSIM_C128, k, q, n_epi, out, -1);
     return QSIM_OK;
@@ -194,8 +194,9 @@ qsim_status qsim_mlp_predict_host(const float* params, int n_in, int n_hidden, c
 }
 
 double qsim_cost_model_predict_us(int n_qubits, qsim_dtype dt, int k, const int32_t* qubits, int n_epi) {
-    int q[6] = {0, 0, 0, 0, 0, 0};
-    for (int j = 0; j < k && j < 6; ++j) q[j] = qubits[j];
+    if (k < 0 || k > kMaxK || (k > 0 && !qubits)) return -1.0;
+    int q[kMaxK] = {};
+    for (int j = 0; j < k; ++j) q[j] = qubits[j];
     return learned_cost_us(n_qubits, dt == QSIM_C128, k, q, n_epi, -1);
 }
 

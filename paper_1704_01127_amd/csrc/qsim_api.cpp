@@ -55,9 +55,10 @@ int g_cluster_variant = -1;
 // [dtype][k][low_class]: a direct gather when no target is on the low bits,
 // the LDS-staged variant otherwise (k = 6, complex64: from two low targets on;
 // with one the direct kernel's loads still use whole cache lines)
+// (k = 7 has the direct kernel only; its entries are not read)
 int g_tune[2][kMaxK + 1][kLowClasses] = {
-    {{0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 0, 1, 1}},
-    {{0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}}};
+    {{0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 0, 1, 1}, {0, 0, 0, 0}},
+    {{0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 1, 1, 1}, {0, 0, 0, 0}}};
 }  // namespace
 void set_cluster_variant(int v) { g_cluster_variant = v; }
 int get_cluster_variant() { return g_cluster_variant; }
@@ -78,11 +79,11 @@ int g_cluster_sets = 1;
 int g_batch_order = 0;
 int g_check_unitary = 0;  // host check of every dense matrix: max |M M^+ - I| <= 1e-10
 int g_map_qubits = 0;     // runs from the uniform state: relabel qubits away from the slow bit locations
-double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1}};
+double g_cost_us[2][kMaxK + 1] = {{1, 1, 1, 1, 1, 1, 1, 1}, {1, 1, 1, 1, 1, 1, 1, 1}};
 int g_cost_nref[2] = {30, 30};
 int cluster_variant_for(bool dbl, const ClusterGeom& g, int layout) {
     if (layout == LAYOUT_PLAIN) return 0;
-    if (g.k > 5 && (dbl || layout != LAYOUT_SPLIT16F)) return 0;  // k = 6: float, fp16-halves kernel only
+    if (g.k > 5 && (dbl || layout != LAYOUT_SPLIT16F)) return 0;  // k = 6: float, fp16-halves kernel only; k = 7: direct
     if (g_cluster_variant >= 0) return g_cluster_variant;
     return g_tune[dbl][g.k][low_class(g.t, g.k)];
 }
@@ -98,7 +99,7 @@ struct OpRecord {
     int kind;  // 0 cluster, 1 diagonal pass, 2 1-qubit gate, 3 1-qubit phase, 4 CZ, 5 matrix build,
                // 6 uniform initialisation folded into a cluster, 7 two clusters in one pass
     int k;
-    int qubits[6];
+    int qubits[kMaxK];
     int flags;  // bit 0: diagonal epilogue, bit 1: LDS-staged kernel, bit 2: matrix-core kernel
     hipEvent_t ev0, ev1;
 };
@@ -136,7 +137,7 @@ qsim_status qsim::api::check_gate(int n, const qsim_gate& g, int idx) {
     else if (g.kind == G_DENSE) nq = g.k;
     else if (is_named_1q(g.kind)) nq = 1;
     else return fail(QSIM_E_INVALID, at + "unknown gate kind " + std::to_string(g.kind));
-    if (g.kind == G_DENSE && (nq < 1 || nq > kMaxK))
+    if (g.kind == G_DENSE && (nq < 1 || nq > kMaxGateQ))
         return fail(QSIM_E_UNSUPPORTED, at + "dense gates need 1 <= k <= 6");
     if (g.kind == G_DENSE && !g.mat) return fail(QSIM_E_INVALID, at + "dense gate without a matrix");
     if (g.kind == G_DENSE && g_check_unitary) {
@@ -259,6 +260,15 @@ struct Chunk {
         bops.clear(); bgates.clear(); dense.clear(); epis.clear(); items.clear(); slots_used = 0;
     }
 };
+
+// Queue a matrix build; a 7-qubit matrix is built by kBuildParts7 work-groups.
+void push_build(Chunk& c, BuildOp bo) {
+    const int parts = bo.k == 7 ? kBuildParts7 : 1;
+    for (int p = 0; p < parts; ++p) {
+        bo.part = p;
+        c.bops.push_back(bo);
+    }
+}
 
 hipError_t next_event(qsim_state_s* s, hipEvent_t* e) {
     if (s->pool_used == s->pool.size()) {
@@ -408,7 +418,7 @@ qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, con
                         bool fold_init = false) {
     size_t dense_need = 0;
     for (int gi : members) if (gates[gi].kind == G_DENSE) dense_need += size_t(2) << (2 * gates[gi].k);
-    const size_t need = align256((c.bops.size() + 1) * sizeof(BuildOp)) +
+    const size_t need = align256((c.bops.size() + kBuildParts7) * sizeof(BuildOp)) +
                         align256((c.bgates.size() + members.size() + epi_gates.size()) * sizeof(BuildGate)) +
                         align256((c.dense.size() + dense_need) * sizeof(double)) +
                         align256((c.epis.size() + 1) * sizeof(EpiDesc));
@@ -425,13 +435,14 @@ qsim_status add_cluster(qsim_state_s* s, Chunk& c, int k, const int* qubits, con
     bo.gate0 = (int)c.bgates.size();
     bo.is_double = fold_init ? 1 : s->dbl;
     bo.layout = fold_init ? LAYOUT_PLAIN : cluster_layout(s->dbl, k, s->n);
+    if (bo.layout < 0) return fail(QSIM_E_UNSUPPORTED, "no kernel for a cluster of this width on this state");
     bo.out_off = (int64_t)c.slots_used * (int64_t)slot_bytes(s->dbl, s->kmax_ws);
     for (int gi : members) c.bgates.push_back(to_build_gate(gates[gi], pos_of, c.dense));
     // epilogue: terms on target qubits only join the matrix, the rest go to the descriptor
     EpiDesc e;
     if (qsim_status r = split_epilogue(pos_of, gates, epi_gates, c.bgates, c.dense, e)) return r;
     bo.n_gates = (int)c.bgates.size() - bo.gate0;
-    c.bops.push_back(bo);
+    push_build(c, bo);
     Chunk::Item it;
     std::memset(&it, 0, sizeof(it));
     it.kind = fold_init ? 6 : 0;
@@ -463,7 +474,7 @@ qsim_status add_fold2(qsim_state_s* s, Chunk& c, const SOp& A, const SOp& B, con
         for (int gi : op->members) if (gates[gi].kind == G_DENSE) dense_need += size_t(2) << (2 * gates[gi].k);
         ng += op->members.size() + op->epi.size();
     }
-    const size_t need = align256((c.bops.size() + 2) * sizeof(BuildOp)) +
+    const size_t need = align256((c.bops.size() + 2 * kBuildParts7) * sizeof(BuildOp)) +
                         align256((c.bgates.size() + ng) * sizeof(BuildGate)) +
                         align256((c.dense.size() + dense_need) * sizeof(double)) +
                         align256((c.epis.size() + 2) * sizeof(EpiDesc));
@@ -487,7 +498,7 @@ qsim_status add_fold2(qsim_state_s* s, Chunk& c, const SOp& A, const SOp& B, con
     ba.out_off = slotA * sb;
     for (int gi : A.members) c.bgates.push_back(to_build_gate(gates[gi], posA, c.dense));
     ba.n_gates = (int)c.bgates.size() - ba.gate0;
-    c.bops.push_back(ba);
+    push_build(c, ba);
     // B: A's epilogue terms on B's targets, B's gates, B's own epilogue terms on its targets
     BuildOp bb;
     std::memset(&bb, 0, sizeof(bb));
@@ -502,7 +513,7 @@ qsim_status add_fold2(qsim_state_s* s, Chunk& c, const SOp& A, const SOp& B, con
     for (int gi : B.members) c.bgates.push_back(to_build_gate(gates[gi], posB, c.dense));
     if (qsim_status r = split_epilogue(posB, gates, B.epi, c.bgates, c.dense, e2)) return r;
     bb.n_gates = (int)c.bgates.size() - bb.gate0;
-    c.bops.push_back(bb);
+    push_build(c, bb);
     Chunk::Item it;
     std::memset(&it, 0, sizeof(it));
     it.kind = 8;
@@ -611,7 +622,7 @@ qsim_status add_pair(qsim_state_s* s, Chunk& c, const SOp& A, const SOp* Bp, con
         EpiDesc e;
         if (qsim_status r = split_epilogue(pos_of, gates, ops[m]->epi, c.bgates, c.dense, e)) return r;
         bo.n_gates = (int)c.bgates.size() - bo.gate0;
-        c.bops.push_back(bo);
+        push_build(c, bo);
         int epi = -1;
         if (e.n_cc || e.n_mix || e.n_ph) {
             epi = (int)c.epis.size();
@@ -689,6 +700,13 @@ OpCostFn qsim::api::cost_fn(const qsim_run_opts* o, int n, bool dbl) {
     return [scale, us](int k, const int*, int) { return us[k] * scale; };
 }
 
+// The folded start qsim_run_circuit gives a run from the uniform state (see
+// its fold / fold2 conditions), for the scheduler's pricing.
+int qsim::api::fold_start_for(bool dbl, int n) {
+    if (!g_fold_init) return 0;
+    return (g_fold_init == 2 && !dbl && cluster_layout(false, 6, n) == LAYOUT_SPLIT16F) ? 2 : 1;
+}
+
 SchedOpts qsim::api::to_sched_opts(const qsim_run_opts* o) {
     SchedOpts so;
     so.cluster_sets = g_cluster_sets != 0;
@@ -763,7 +781,7 @@ qsim_status qsim_apply_cluster(qsim_state s, int k, const int32_t* qubits, const
     if (qsim_status r = check_state(s)) return r;
     s->stats_ready = false;
     if (!qubits || !mat) return fail(QSIM_E_INVALID, "null argument");
-    if (k < 1 || k > kMaxK) return fail(QSIM_E_UNSUPPORTED, "k must be in [1, 6]");
+    if (k < 1 || k > kMaxGateQ) return fail(QSIM_E_UNSUPPORTED, "k must be in [1, 6]");
     if (k > s->kmax_ws) return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
     if (k > s->n) return fail(QSIM_E_INVALID, "k exceeds the number of qubits");
     qsim_gate g;
@@ -899,7 +917,9 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     for (int i = 0; i < n_gates; ++i)
         if (qsim_status r = check_gate(s->n, gates[i], i)) return r;
     SchedOpts so = to_sched_opts(opts);
-    if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 6]");
+    if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 7]");
+    so.kmax = std::min(so.kmax, max_cluster_k(s->dbl, s->n));  // 7 only where a 7-qubit kernel exists
+    so.fold_start = fold_start_for(s->dbl, s->n);
     if (so.mode != 0 && so.kmax > s->kmax_ws) return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
     s->stats_ready = false;
     for (int i = 0; i < n_gates; ++i)
@@ -950,8 +970,9 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     // the uniform start and a leading cluster are written in one pass; with a
     // second cluster of 6 qubits (complex64, fp16-halves kernel) that one too
     const bool fold = S.uniform_init && g_fold_init && !S.ops.empty() && S.ops[0].kind == OP_CLUSTER;
-    const bool fold2 = fold && g_fold_init == 2 && !s->dbl && S.ops.size() >= 2 && S.ops[1].kind == OP_CLUSTER &&
-                       S.ops[1].k == 6 && cluster_layout(false, 6, s->n) == LAYOUT_SPLIT16F;
+    const bool fold2 = fold && g_fold_init == 2 && !s->dbl && S.ops[0].k <= 6 && S.ops.size() >= 2 &&
+                       S.ops[1].kind == OP_CLUSTER && S.ops[1].k == 6 &&
+                       cluster_layout(false, 6, s->n) == LAYOUT_SPLIT16F;
     // the learned model also picks each cluster's kernel variant (unless one is forced)
     const bool learned_variants = opts && opts->scheduler == QSIM_SCHED_LEARNED && so.mode == 2 &&
                                   learned_model_loaded() && get_cluster_variant() < 0;
@@ -1026,7 +1047,7 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
         std::memset(&r, 0, sizeof(r));
         r.kind = 9;
         r.k = pm;
-        for (int j = 0; j < std::min(pm, 6); ++j) r.qubits[j] = pto[j];
+        for (int j = 0; j < std::min(pm, kMaxK); ++j) r.qubits[j] = pto[j];
         HIP_TRY(rec_begin(s, r), "event record");
         HIP_TRY(launch_permute(s->psi, s->dbl, s->n, perm_geom(s->n, pm, pfrom, pto), s->st), "permute launch");
         HIP_TRY(rec_end(s, r), "event record");
@@ -1209,8 +1230,8 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
         if (op_kind) op_kind[i] = r.kind;
         if (op_k) op_k[i] = r.k;
         if (op_qubits)
-            for (int j = 0; j < 6; ++j)  // diagonal passes and builds have no qubit list
-                op_qubits[6 * i + j] = (r.kind != 1 && r.kind != 5 && j < r.k) ? r.qubits[j] : -1;
+            for (int j = 0; j < QSIM_MAX_CLUSTER; ++j)  // diagonal passes and builds have no qubit list
+                op_qubits[QSIM_MAX_CLUSTER * i + j] = (r.kind != 1 && r.kind != 5 && j < r.k) ? r.qubits[j] : -1;
         if (op_epi) op_epi[i] = r.flags;
         if (ms) {
             float t = 0.f;
@@ -1229,9 +1250,11 @@ qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates, con
     for (int i = 0; i < n_gates; ++i)
         if (qsim_status r = check_gate(n_qubits, gates[i], i)) return r;
     SchedOpts so = to_sched_opts(opts);
-    if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 6]");
-    const Schedule S = make_schedule(n_qubits, to_sgates(gates, n_gates), so,
-                                     cost_fn(opts, n_qubits, opts && opts->schedule_dtype == QSIM_C128));
+    if (so.mode != 0 && (so.kmax < 1 || so.kmax > kMaxK)) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [1, 7]");
+    const bool sdbl = opts && opts->schedule_dtype == QSIM_C128;
+    so.kmax = std::min(so.kmax, max_cluster_k(sdbl, n_qubits));  // as qsim_run_circuit would
+    so.fold_start = fold_start_for(sdbl, n_qubits);
+    const Schedule S = make_schedule(n_qubits, to_sgates(gates, n_gates), so, cost_fn(opts, n_qubits, sdbl));
     if (n_ops) *n_ops = (int)S.ops.size();
     if ((int)S.ops.size() > op_cap) return fail(QSIM_E_INVALID, "op_cap too small");
     if (gate_op)
@@ -1241,7 +1264,7 @@ qsim_status qsim_schedule(int n_qubits, const qsim_gate* gates, int n_gates, con
         if (op_kind) op_kind[o] = op.kind;
         if (op_k) op_k[o] = op.k;
         if (op_qubits)
-            for (int j = 0; j < 6; ++j) op_qubits[6 * o + j] = j < op.k ? op.qubits[j] : -1;
+            for (int j = 0; j < QSIM_MAX_CLUSTER; ++j) op_qubits[QSIM_MAX_CLUSTER * o + j] = j < op.k ? op.qubits[j] : -1;
         for (int gi : op.members) {
             if (gate_op) gate_op[gi] = o;
             if (gate_role) gate_role[gi] = op.kind == OP_DIAG ? 2 : 0;
@@ -1264,7 +1287,7 @@ qsim_status qsim_stage_schedule(int n_qubits, const qsim_gate* gates, int n_gate
         if (qsim_status r = check_gate(n_qubits, gates[i], i)) return r;
     if (opts->n_local < 1 || opts->n_local > n_qubits || 2 * opts->n_local < n_qubits)
         return fail(QSIM_E_INVALID, "n_local must be in [n_qubits / 2, n_qubits]");
-    if (opts->kmax < 0 || opts->kmax > kMaxK) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [0, 6]");
+    if (opts->kmax < 0 || opts->kmax > kMaxK) return fail(QSIM_E_UNSUPPORTED, "kmax must be in [0, 7]");
     StageOpts so;
     so.n_local = opts->n_local;
     so.spec_cz = opts->specialize & 1;

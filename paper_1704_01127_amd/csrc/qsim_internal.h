@@ -7,7 +7,8 @@
 
 namespace qsim {
 
-constexpr int kMaxK = 6;     // largest cluster
+constexpr int kMaxK = 7;     // largest cluster (7: complex64 on the fp16-halves kernel only)
+constexpr int kMaxGateQ = 6; // widest single gate (a dense matrix)
 constexpr int kEpiMax = 64;  // entries of each list of a diagonal descriptor
 
 // Named 2x2 gate matrices, row-major, (re, im) interleaved. Sec. 2 prints H,
@@ -96,16 +97,20 @@ enum : int32_t {
     LAYOUT_MFMA32F = 1,   // real-split, permuted for v_mfma_f32_32x32x2_f32
     LAYOUT_MFMA16D = 2,   // real-split, permuted for v_mfma_f64_16x16x4_f64
     LAYOUT_GAUSS32F = 3,  // k = 6 float: Re M, Im M, Re M + Im M (three-product complex matrix)
-    LAYOUT_SPLIT16F = 4   // k = 6 float: fp16 hi / lo halves of 16 x the real-split matrix
+    LAYOUT_SPLIT16F = 4,  // k = 6 float: fp16 hi / lo halves of 16 x the real-split matrix
+    LAYOUT_SPLIT7 = 5     // k = 7 float: fp16 hi / lo halves of 16 x Re M and 16 x Im M
 };
 
+// A 7-qubit matrix is built by kBuildParts7 work-groups, each owning 32 of
+// its 128 columns (part p: columns 32 p .. 32 p + 31); smaller ones by one.
+constexpr int kBuildParts7 = 4;
 struct BuildOp {
     int32_t k;
     int32_t n_gates;
     int32_t gate0;      // first BuildGate of this op
     int32_t layout;
     int32_t is_double;  // element type of the output
-    int32_t pad;
+    int32_t part;       // k = 7: which quarter of the columns this work-group builds
     int64_t out_off;    // byte offset of the output inside the matrix region
 };
 
@@ -170,8 +175,14 @@ inline int64_t matrix_bytes(int k, int layout, bool dbl) {
     if (layout == LAYOUT_PLAIN) return d * d * 2 * es;
     if (layout == LAYOUT_GAUSS32F) return 3 * d * d * es;
     if (layout == LAYOUT_SPLIT16F) return 2 * (2 * d) * (2 * d) * 2;
+    if (layout == LAYOUT_SPLIT7) return 4 * d * d * 2;
     return (2 * d) * (2 * d) * es;
 }
+
+// Largest cluster a state can take: 7 qubits on complex64 states of at least
+// 12 qubits (a wave tile is 32 columns of 2^7 amplitudes) while 6-qubit
+// clusters use the fp16-halves kernel; 6 otherwise.
+inline int max_cluster_k(bool dbl, int n) { return (!dbl && g_k6_kernel == 2 && n >= 12) ? 7 : 6; }
 
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `st` and return hipSuccess or the launch error.
@@ -204,7 +215,9 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
                           unsigned* stats_blocks = nullptr);
 // Can a cluster launch also produce the sums (see launch_cluster)?
 inline bool cluster_stats_supported(bool dbl, int k, int layout, int variant) {
-    return !dbl && variant == 0 && ((layout == LAYOUT_SPLIT16F && k == 6) || (layout == LAYOUT_MFMA32F && k >= 4));
+    return !dbl && variant == 0 &&
+           ((layout == LAYOUT_SPLIT7 && k == 7) || (layout == LAYOUT_SPLIT16F && k == 6) ||
+            (layout == LAYOUT_MFMA32F && k >= 4));
 }
 // Kernel variant of the matrix-core cluster path: 0 = direct register
 // gather, 1 = LDS-staged linear loads. Chosen per (dtype, k, low_class) from a

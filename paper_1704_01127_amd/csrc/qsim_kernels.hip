@@ -617,6 +617,334 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_split6(float2* __restric
     if constexpr (STATS) block_reduce_store(sv, 3, 0u, part + blockIdx.x * 8);
 }
 
+// A column's diagonal-epilogue factor (col_factor), split for a wave that
+// walks many tiles: terms on the state bits above the tile (uniform in the
+// wave, new each tile) and terms on the column bits (fixed per lane) are
+// separate, and a CZ pair with one qubit of each kind is a mask over the
+// column index, set per tile. Target bits take no part (the host moved such
+// terms into the matrix or the mask over rows).
+// Tile part of base (tile bits zero) for a K-qubit cluster: bit 0 the sign,
+// bits 1..K the mask over rows, the 5 bits above them the mask over the
+// column index; the phase in (cr, ci).
+template <int K = 6>
+__device__ __forceinline__ uint32_t epi_tile_part(c_epi* __restrict__ e, uint64_t base, uint64_t colmask,
+                                                  double& cr, double& ci) {
+    uint32_t sgn = 0, w = 0, cross = 0;
+    const int ncc = e->n_cc;
+    for (int i = 0; i < ncc; ++i) {
+        const int a = e->cc[i][0], b = e->cc[i][1];
+        const bool ca = (colmask >> a) & 1, cb = (colmask >> b) & 1;
+        if (!ca && !cb)
+            sgn ^= (uint32_t)((base >> a) & (base >> b) & 1);
+        else if (ca && !cb)
+            cross ^= (uint32_t)((base >> b) & 1) << __popcll(colmask & ((uint64_t(1) << a) - 1));
+        else if (!ca && cb)
+            cross ^= (uint32_t)((base >> a) & 1) << __popcll(colmask & ((uint64_t(1) << b) - 1));
+    }
+    const int nm = e->n_mix;
+    for (int i = 0; i < nm; ++i) {
+        const int b = e->mix[i][1];
+        if (!((colmask >> b) & 1)) w ^= (uint32_t)((base >> b) & 1) << e->mix[i][0];
+    }
+    cr = 1.0;
+    ci = 0.0;
+    const int np = e->n_ph;
+    for (int i = 0; i < np; ++i) {
+        const int q = e->ph_q[i];
+        if (!((colmask >> q) & 1) && ((base >> q) & 1)) {
+            const double a = e->ph[i][0], b = e->ph[i][1];
+            const double t = cr * a - ci * b;
+            ci = cr * b + ci * a;
+            cr = t;
+        }
+    }
+    return sgn | (w << 1) | (cross << (K + 1));
+}
+
+// Column part of the same factor (cbits: the column's state bits).
+__device__ __forceinline__ void epi_lane_part(c_epi* __restrict__ e, uint64_t cbits, uint64_t colmask, uint32_t& sgn,
+                                              uint32_t& w, double& cr, double& ci) {
+    sgn = 0;
+    w = 0;
+    const int ncc = e->n_cc;
+    for (int i = 0; i < ncc; ++i) {
+        const int a = e->cc[i][0], b = e->cc[i][1];
+        if (((colmask >> a) & 1) && ((colmask >> b) & 1)) sgn ^= (uint32_t)((cbits >> a) & (cbits >> b) & 1);
+    }
+    const int nm = e->n_mix;
+    for (int i = 0; i < nm; ++i) {
+        const int b = e->mix[i][1];
+        if ((colmask >> b) & 1) w ^= (uint32_t)((cbits >> b) & 1) << e->mix[i][0];
+    }
+    cr = 1.0;
+    ci = 0.0;
+    const int np = e->n_ph;
+    for (int i = 0; i < np; ++i) {
+        const int q = e->ph_q[i];
+        if (((colmask >> q) & 1) && ((cbits >> q) & 1)) {
+            const double a = e->ph[i][0], b = e->ph[i][1];
+            const double t = cr * a - ci * b;
+            ci = cr * b + ci * a;
+            cr = t;
+        }
+    }
+}
+
+// Combine the two parts for column index p (tile part read from its lane).
+template <int K = 6>
+__device__ __forceinline__ ColFactor<float> epi_combine(uint32_t tb, double tr, double ti, uint32_t ls, uint32_t lw,
+                                                        double lr, double li, int p) {
+    ColFactor<float> f;
+    f.sgn = ls ^ (tb & 1u) ^ ((uint32_t)__popc((uint32_t)p & (tb >> (K + 1)) & 31u) & 1u);
+    f.w = lw ^ ((tb >> 1) & ((1u << K) - 1u));
+    f.cr = (float)(tr * lr - ti * li);
+    f.ci = (float)(tr * li + ti * lr);
+    return f;
+}
+
+// ------------------------------------------------------------ cluster: float state, k = 7, fp16 matrix cores
+// A 7-qubit cluster doubles the matrix work per byte of state of a 6-qubit
+// one and still stays below the HBM time on the fp16 matrix cores, so it
+// takes the same operand halves (A x ~= A_hi x_hi + A_hi x_lo + A_lo x_hi,
+// fp32 accumulation). Its real-split matrix (2^8 x 2^8 entries) would not fit
+// in LDS, so the complex product is written with the real and imaginary
+// parts of M instead (Sec. 3.2, Eqs. (1)-(3)):
+//   Re y = Re M Re x - Im M Im x,   Im y = Im M Re x + Re M Im x,
+// four real products on two matrices (their halves: 128 KiB of LDS; the
+// minus sign goes onto the halves of Im x, an exact sign flip). One
+// work-group of 4 waves per compute unit.
+// Wave tile: 32 columns x 2^7 targets. Lane l: p = l % 32 (column), h = l / 32
+// owns the amplitudes j | h << 6 (j < 64) of its column, for its loads and
+// its stores. v_mfma_f32_32x32x16_f16: at step s the lane supplies the halves
+// of its amplitudes j = 8 s .. 8 s + 7 (inner index 16 s + 8 h + i <->
+// amplitude (8 s + i) | h << 6); result register r of row block rb holds its
+// amplitude j = 16 rb + r (physical row 8 (r / 4) + 4 h + r % 4). The builder
+// permutes M once to match (LAYOUT_SPLIT7).
+template <bool LOWT, bool STATS = false>
+__global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restrict__ psi,
+                                                               const half8* __restrict__ Ap,
+                                                               const EpiDesc* __restrict__ epi,
+                                                               ClusterGeom g, double* __restrict__ part) {
+    constexpr int K = 7, HX = 64, RB = 4, S = 8, NP = RB * S * 64;
+    // parts: 16 Re M hi, lo, 16 Im M hi, lo; entry (rb, s, lane) of each
+    __shared__ half8 L[4 * NP];
+    load_matrix<4 * NP * 8, 256>(reinterpret_cast<_Float16*>(L), reinterpret_cast<const vf4*>(Ap));
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const uint64_t hoff = h ? (uint64_t(1) << g.t[K - 1]) : 0;
+    const uint64_t ntiles = g.ncols / 32;
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    const bool has_epi = epi != nullptr;
+    const bool has_ph = has_epi && epi->n_ph > 0;
+    // state offset of the lane's amplitude j = 8 a + i: olo[i] | ohi[a] (bits of
+    // j on targets 0..2 and 3..5; target 6 is h)
+    uint64_t olo[8], ohi[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        olo[i] = target_off<3>(i, g);
+        ohi[i] = ((i & 1) ? uint64_t(1) << g.t[3] : 0) | ((i & 2) ? uint64_t(1) << g.t[4] : 0) |
+                 ((i & 4) ? uint64_t(1) << g.t[5] : 0);
+    }
+
+    uint64_t tile = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6);
+    double sv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (tile >= ntiles) {  // uniform in the wave: every wave reaches one reduction
+        if constexpr (STATS) block_reduce_store(sv, 3, 0u, part + blockIdx.x * 8);
+        return;
+    }
+    const uint64_t last = ntiles - 1;
+    // amplitudes 8 a .. 8 a + 7 of the lane for a in [A0, A1)
+    // (the bits are disjoint, so the OR is a sum: one pointer per group a,
+    // then the low offsets added to it)
+    auto load = [&](uint64_t b, float (&X)[2 * HX], int a0, int a1) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            if (a < a0 || a >= a1) continue;
+            const float2* pa = psi + (b | ohi[a]);
+            if (LOWT) {
+#pragma unroll
+                for (int i = 0; i < 8; i += 2) {
+                    const float4 v = *reinterpret_cast<const float4*>(pa + olo[i]);
+                    const int j = 8 * a + i;
+                    X[2 * j] = v.x; X[2 * j + 1] = v.y; X[2 * j + 2] = v.z; X[2 * j + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const float2 v = pa[olo[i]];
+                    const int j = 8 * a + i;
+                    X[2 * j] = v.x; X[2 * j + 1] = v.y;
+                }
+            }
+        }
+    };
+    // real and imaginary parts of amplitudes 8 s + i, scaled, into fp16
+    // halves; returns the factor that undoes the column and matrix scaling
+    half8 rh[S], rl[S], ih[S], il[S];
+    auto split = [&](const float (&X)[2 * HX]) -> float {
+        float mx = 0.0f;  // largest magnitude (|x| is a free operand modifier of the max)
+#pragma unroll
+        for (int i = 0; i < 2 * HX; ++i) mx = fmaxf(mx, fabsf(X[i]));
+        uint32_t mb = __float_as_uint(mx);
+        mb = max(mb, (uint32_t)__shfl_xor((int)mb, 32));  // the other half of the column
+        const int e = (int)(mb >> 23) - 126;               // largest magnitude < 2^e
+        const int se = min(max(14 - e, -100), 100);
+        const float sc = __builtin_ldexpf(1.0f, se);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float vr = X[2 * (8 * s + i)] * sc, vi = X[2 * (8 * s + i) + 1] * sc;
+                const _Float16 hr = (_Float16)vr, hi = (_Float16)vi;
+                rh[s][i] = hr;
+                rl[s][i] = (_Float16)(vr - (float)hr);
+                ih[s][i] = hi;
+                il[s][i] = (_Float16)(vi - (float)hi);
+            }
+        return __builtin_ldexpf(1.0f, -se - 4);
+    };
+    floatx16 ar[RB], ai[RB];
+    // the products of steps s0 .. s1 - 1
+    auto mma = [&](int s0, int s1) {
+        int aoff = lane;
+        asm volatile("" : "+v"(aoff));  // keep the matrix reads inside the loop (not in registers)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s < s0 || s >= s1) continue;
+            // -Im x: the sign bits of both packed halves flipped by one XOR per register
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            const u32x4 sbit = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+            const half8 nh = __builtin_bit_cast(half8, __builtin_bit_cast(u32x4, ih[s]) ^ sbit);
+            const half8 nl = __builtin_bit_cast(half8, __builtin_bit_cast(u32x4, il[s]) ^ sbit);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const int at = (rb * S + s) * 64 + aoff;
+                const half8 Rh = L[at], Rl = L[NP + at], Ih = L[2 * NP + at], Il = L[3 * NP + at];
+                ar[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Rh, rl[s], ar[rb], 0, 0, 0);
+                ai[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ih, rl[s], ai[rb], 0, 0, 0);
+                ar[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Rl, rh[s], ar[rb], 0, 0, 0);
+                ai[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Il, rh[s], ai[rb], 0, 0, 0);
+                ar[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Rh, rh[s], ar[rb], 0, 0, 0);
+                ai[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ih, rh[s], ai[rb], 0, 0, 0);
+                ar[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ih, nl, ar[rb], 0, 0, 0);
+                ai[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Rh, il[s], ai[rb], 0, 0, 0);
+                ar[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Il, nh, ar[rb], 0, 0, 0);
+                ai[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Rl, ih[s], ai[rb], 0, 0, 0);
+                ar[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Ih, nh, ar[rb], 0, 0, 0);
+                ai[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(Rh, ih[s], ai[rb], 0, 0, 0);
+            }
+        }
+    };
+
+    uint64_t base = deposit_cols<K>(tile * 32 + p, g);
+    float unscale;
+    {
+        float B[2 * HX];
+        load(base | hoff, B, 0, 8);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_sched_barrier(0);
+        unscale = split(B);
+    }
+    do {
+        const uint64_t nxt = tile + stride < last ? tile + stride : last;
+        const uint64_t basen = deposit_cols<K>(nxt * 32 + p, g);
+        // the next tile's loads go out in two halves: the second once the
+        // first four steps have freed their operand registers
+        float Bn[2 * HX];
+        load(basen | hoff, Bn, 0, 4);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) ar[rb][i] = ai[rb][i] = 0.0f;
+        mma(0, 4);
+        __builtin_amdgcn_sched_barrier(0);
+        load(basen | hoff, Bn, 4, 8);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(4, 8);
+        // Diagonal epilogue: the column's sign parity and phase are one complex
+        // factor for all its amplitudes, so they join the scale (ucr, uci);
+        // the sign mask over the target index becomes bit j of msk for the
+        // lane's amplitude j (target 6 is the lane's h: its term is the
+        // column's). The store loop is specialised on which parts are present.
+        float ucr = unscale, uci = 0.0f;
+        uint32_t mlo = 0, mhi = 0;  // bit j of mhi:mlo: amplitude j changes sign
+        bool ph = false, sg = false;
+        if (has_epi) {
+            const ColFactor<float> f = col_factor<float>(epi, base);
+            if ((f.sgn ^ ((uint32_t)h & (f.w >> (K - 1)))) & 1u) ucr = -ucr;
+            if (has_ph) {
+                uci = ucr * f.ci;
+                ucr = ucr * f.cr;
+                ph = true;
+            }
+            const uint32_t pat[5] = {0xaaaaaaaau, 0xccccccccu, 0xf0f0f0f0u, 0xff00ff00u, 0xffff0000u};
+#pragma unroll
+            for (int b = 0; b < 5; ++b)
+                if ((f.w >> b) & 1u) {
+                    mlo ^= pat[b];
+                    mhi ^= pat[b];
+                }
+            if ((f.w >> 5) & 1u) mhi = ~mhi;
+            sg = epi->n_mix > 0;  // uniform: the descriptor has sign-mask terms
+        }
+        const uint64_t b0 = base | hoff;
+        auto store_all = [&](auto PH, auto SG) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int r = 0; r < 16; r += 2) {
+                    const int j = 16 * rb + r;
+                    float v[4];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const float xr = ar[rb][r + u], xi = ai[rb][r + u];
+                        if constexpr (decltype(PH)::value) {  // one fixed contraction in every variant
+                            v[2 * u] = fmaf(xr, ucr, -(xi * uci));
+                            v[2 * u + 1] = fmaf(xr, uci, xi * ucr);
+                        } else {
+                            v[2 * u] = xr * ucr;
+                            v[2 * u + 1] = xi * ucr;
+                        }
+                        if constexpr (decltype(SG)::value) {
+                            const int jj = j + u;
+                            const uint32_t m = jj < 32 ? mlo : mhi;
+                            const uint32_t sb = (m << (31 - (jj & 31))) & 0x80000000u;
+                            v[2 * u] = __uint_as_float(__float_as_uint(v[2 * u]) ^ sb);
+                            v[2 * u + 1] = __uint_as_float(__float_as_uint(v[2 * u + 1]) ^ sb);
+                        }
+                    }
+                    if constexpr (STATS) {
+                        stats_acc_f(sv, v[0], v[1]);
+                        stats_acc_f(sv, v[2], v[3]);
+                    }
+                    float2* pa = psi + (b0 | ohi[j >> 3]);
+                    if (LOWT) {
+                        *reinterpret_cast<float4*>(pa + olo[j & 7]) = make_float4(v[0], v[1], v[2], v[3]);
+                    } else {
+                        pa[olo[j & 7]] = make_float2(v[0], v[1]);
+                        pa[olo[(j + 1) & 7]] = make_float2(v[2], v[3]);
+                    }
+                }
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        if constexpr (STATS) {  // once per run: one general path (uci = 0, no mask bits when absent)
+            store_all(T_(), T_());
+        } else if (ph) {
+            if (sg) store_all(T_(), T_()); else store_all(T_(), F_());
+        } else {
+            if (sg) store_all(F_(), T_()); else store_all(F_(), F_());
+        }
+        base = basen;
+        unscale = split(Bn);
+        tile += stride;
+    } while (tile < ntiles);
+    if constexpr (STATS) block_reduce_store(sv, 3, 0u, part + blockIdx.x * 8);
+}
+
 // ------------------------------------------------------------ cluster: MFMA, double
 // v_mfma_f64_16x16x4_f64: lane l: p = l%16 (column), q = l/16 owns target
 // indices x = j | q << (K-2), j < 2^(K-2), of its column(s). Operand A/B: lane
@@ -1460,88 +1788,6 @@ struct FoldIn {
     int k1;
     c_epi* epi1;      // the first epilogue relative to this cluster's targets, or null
 };
-
-// A column's diagonal-epilogue factor (col_factor), split for a wave that
-// walks many tiles: terms on the state bits above the tile (uniform in the
-// wave, new each tile) and terms on the column bits (fixed per lane) are
-// separate, and a CZ pair with one qubit of each kind is a mask over the
-// column index, set per tile. Target bits take no part (the host moved such
-// terms into the matrix or the mask over rows).
-// Tile part of base (tile bits zero): bit 0 the sign, bits 1-6 the mask over
-// rows, bits 7-11 the mask over the column index; the phase in (cr, ci).
-__device__ __forceinline__ uint32_t epi_tile_part(c_epi* __restrict__ e, uint64_t base, uint64_t colmask,
-                                                  double& cr, double& ci) {
-    uint32_t sgn = 0, w = 0, cross = 0;
-    const int ncc = e->n_cc;
-    for (int i = 0; i < ncc; ++i) {
-        const int a = e->cc[i][0], b = e->cc[i][1];
-        const bool ca = (colmask >> a) & 1, cb = (colmask >> b) & 1;
-        if (!ca && !cb)
-            sgn ^= (uint32_t)((base >> a) & (base >> b) & 1);
-        else if (ca && !cb)
-            cross ^= (uint32_t)((base >> b) & 1) << __popcll(colmask & ((uint64_t(1) << a) - 1));
-        else if (!ca && cb)
-            cross ^= (uint32_t)((base >> a) & 1) << __popcll(colmask & ((uint64_t(1) << b) - 1));
-    }
-    const int nm = e->n_mix;
-    for (int i = 0; i < nm; ++i) {
-        const int b = e->mix[i][1];
-        if (!((colmask >> b) & 1)) w ^= (uint32_t)((base >> b) & 1) << e->mix[i][0];
-    }
-    cr = 1.0;
-    ci = 0.0;
-    const int np = e->n_ph;
-    for (int i = 0; i < np; ++i) {
-        const int q = e->ph_q[i];
-        if (!((colmask >> q) & 1) && ((base >> q) & 1)) {
-            const double a = e->ph[i][0], b = e->ph[i][1];
-            const double t = cr * a - ci * b;
-            ci = cr * b + ci * a;
-            cr = t;
-        }
-    }
-    return sgn | (w << 1) | (cross << 7);
-}
-
-// Column part of the same factor (cbits: the column's state bits).
-__device__ __forceinline__ void epi_lane_part(c_epi* __restrict__ e, uint64_t cbits, uint64_t colmask, uint32_t& sgn,
-                                              uint32_t& w, double& cr, double& ci) {
-    sgn = 0;
-    w = 0;
-    const int ncc = e->n_cc;
-    for (int i = 0; i < ncc; ++i) {
-        const int a = e->cc[i][0], b = e->cc[i][1];
-        if (((colmask >> a) & 1) && ((colmask >> b) & 1)) sgn ^= (uint32_t)((cbits >> a) & (cbits >> b) & 1);
-    }
-    const int nm = e->n_mix;
-    for (int i = 0; i < nm; ++i) {
-        const int b = e->mix[i][1];
-        if ((colmask >> b) & 1) w ^= (uint32_t)((cbits >> b) & 1) << e->mix[i][0];
-    }
-    cr = 1.0;
-    ci = 0.0;
-    const int np = e->n_ph;
-    for (int i = 0; i < np; ++i) {
-        const int q = e->ph_q[i];
-        if (((colmask >> q) & 1) && ((cbits >> q) & 1)) {
-            const double a = e->ph[i][0], b = e->ph[i][1];
-            const double t = cr * a - ci * b;
-            ci = cr * b + ci * a;
-            cr = t;
-        }
-    }
-}
-
-// Combine the two parts for column index p (tile part read from its lane).
-__device__ __forceinline__ ColFactor<float> epi_combine(uint32_t tb, double tr, double ti, uint32_t ls, uint32_t lw,
-                                                        double lr, double li, int p) {
-    ColFactor<float> f;
-    f.sgn = ls ^ (tb & 1u) ^ ((uint32_t)__popc((uint32_t)p & (tb >> 7) & 31u) & 1u);
-    f.w = lw ^ ((tb >> 1) & 63u);
-    f.cr = (float)(tr * lr - ti * li);
-    f.ci = (float)(tr * li + ti * lr);
-    return f;
-}
 
 template <bool LOWT, bool FOLD = false>
 __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const half8* Ah, const half8* Al, float2* L,
@@ -2485,48 +2731,57 @@ __global__ __launch_bounds__(256) void k_init_cluster(typename Cplx<T>::type* __
 }
 
 // ------------------------------------------------------------ cluster-matrix builder
-// One work-group (64 threads) per cluster. Thread x owns column x of the
-// cluster matrix: it starts from the basis vector e_x of the 2^k space and
-// applies the cluster's gates in order, in float64 (the matrix is reused for
-// all 2^(n-k) columns of the state, Sec. 3.2, so building it is cheap). The
-// result is then written in the layout of the kernel that will apply it.
+// One work-group (64 threads) per cluster; a 7-qubit cluster takes
+// kBuildParts7 of them, each with 32 of its columns. Thread x owns column x of
+// the cluster matrix: it starts from the basis vector e_x of the 2^k space
+// and applies the cluster's gates in order, in float64 (the matrix is reused
+// for all 2^(n-k) columns of the state, Sec. 3.2, so building it is cheap).
+// The result is then written in the layout of the kernel that will apply it.
 // The columns are interleaved in LDS (real / imaginary part c of entry i of
-// column x at (2 i + c) * kBuildThreads + x): the threads touch consecutive
-// words at every step (a column per contiguous block put them a multiple of
-// 256 words apart, all in one bank).
+// local column x at (2 i + c) * cs + x, cs = the work-group's column count):
+// the threads touch consecutive words at every step (a column per contiguous
+// block put them a multiple of 256 words apart, all in one bank).
 constexpr int kBuildThreads = 64;
-// entry i (2 per amplitude: real, imaginary) of the column at v
-__device__ __forceinline__ double& BV(double* v, int i) { return v[i * kBuildThreads]; }
-__device__ void build_apply_1q(double* v, int D, int a, const double m[8]) {
+// entry i (2 per amplitude: real, imaginary) of the column at v, column stride cs
+__device__ __forceinline__ double& BV(double* v, int i, int cs) { return v[i * cs]; }
+__device__ void build_apply_1q(double* v, int D, int cs, int a, const double m[8]) {
     for (int i = 0; i < D; ++i) {
         if ((i >> a) & 1) continue;
         const int j = i | (1 << a);
-        const double ar = BV(v, 2 * i), ai = BV(v, 2 * i + 1), br = BV(v, 2 * j), bi = BV(v, 2 * j + 1);
-        BV(v, 2 * i) = (m[0] * ar - m[1] * ai) + (m[2] * br - m[3] * bi);
-        BV(v, 2 * i + 1) = (m[0] * ai + m[1] * ar) + (m[2] * bi + m[3] * br);
-        BV(v, 2 * j) = (m[4] * ar - m[5] * ai) + (m[6] * br - m[7] * bi);
-        BV(v, 2 * j + 1) = (m[4] * ai + m[5] * ar) + (m[6] * bi + m[7] * br);
+        const double ar = BV(v, 2 * i, cs), ai = BV(v, 2 * i + 1, cs), br = BV(v, 2 * j, cs),
+                     bi = BV(v, 2 * j + 1, cs);
+        BV(v, 2 * i, cs) = (m[0] * ar - m[1] * ai) + (m[2] * br - m[3] * bi);
+        BV(v, 2 * i + 1, cs) = (m[0] * ai + m[1] * ar) + (m[2] * bi + m[3] * br);
+        BV(v, 2 * j, cs) = (m[4] * ar - m[5] * ai) + (m[6] * br - m[7] * bi);
+        BV(v, 2 * j + 1, cs) = (m[4] * ai + m[5] * ar) + (m[6] * bi + m[7] * br);
     }
 }
 
 __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restrict__ ops,
                                                          const BuildGate* __restrict__ gates,
                                                          const double* __restrict__ dense, char* __restrict__ mat_base) {
+    // 2 doubles per entry, 2^k entries per column, cs columns: 8192 doubles for k <= 6 and for k = 7
     __shared__ double Vs[64 * 2 * kBuildThreads];
     __shared__ double Ws[64 * 2 * kBuildThreads];
     const BuildOp op = ops[blockIdx.x];
-    const int k = op.k, D = 1 << k, x = threadIdx.x;
-    if (x < D) {
-        double* v = Vs + x;
-        double* w = Ws + x;
-        for (int i = 0; i < 2 * D; ++i) BV(v, i) = 0.0;
-        BV(v, 2 * x) = 1.0;
+    const int k = op.k, D = 1 << k, t = threadIdx.x;
+    const int cs = k == 7 ? 32 : kBuildThreads;  // columns held by this work-group
+    const int x0 = k == 7 ? 32 * op.part : 0;    // its first column
+    if (t < D && t < cs) {
+        const int x = x0 + t;
+        double* v = Vs + t;
+        double* w = Ws + t;
+        for (int i = 0; i < 2 * D; ++i) BV(v, i, cs) = 0.0;
+        BV(v, 2 * x, cs) = 1.0;
         for (int gi = 0; gi < op.n_gates; ++gi) {
             const BuildGate bg = gates[op.gate0 + gi];
             if (bg.kind == G_CZ) {
                 const int m = (1 << bg.pos[0]) | (1 << bg.pos[1]);
                 for (int i = 0; i < D; ++i)
-                    if ((i & m) == m) { BV(v, 2 * i) = -BV(v, 2 * i); BV(v, 2 * i + 1) = -BV(v, 2 * i + 1); }
+                    if ((i & m) == m) {
+                        BV(v, 2 * i, cs) = -BV(v, 2 * i, cs);
+                        BV(v, 2 * i + 1, cs) = -BV(v, 2 * i + 1, cs);
+                    }
             } else if (bg.kind == G_DENSE) {
                 const int dq = bg.nq, dd = 1 << dq;
                 const double* u = dense + bg.dense_off;
@@ -2541,24 +2796,25 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restri
                         int src = rest;
                         for (int j = 0; j < dq; ++j) src |= ((xl >> j) & 1) << bg.pos[j];
                         const double mr = u[2 * (yl * dd + xl)], mi = u[2 * (yl * dd + xl) + 1];
-                        sr += mr * BV(v, 2 * src) - mi * BV(v, 2 * src + 1);
-                        si += mr * BV(v, 2 * src + 1) + mi * BV(v, 2 * src);
+                        sr += mr * BV(v, 2 * src, cs) - mi * BV(v, 2 * src + 1, cs);
+                        si += mr * BV(v, 2 * src + 1, cs) + mi * BV(v, 2 * src, cs);
                     }
-                    BV(w, 2 * y) = sr;
-                    BV(w, 2 * y + 1) = si;
+                    BV(w, 2 * y, cs) = sr;
+                    BV(w, 2 * y + 1, cs) = si;
                 }
-                for (int i = 0; i < 2 * D; ++i) BV(v, i) = BV(w, i);
+                for (int i = 0; i < 2 * D; ++i) BV(v, i, cs) = BV(w, i, cs);
             } else {
                 double m[8];
                 gate2x2(bg.kind, bg.theta, m);
-                build_apply_1q(v, D, bg.pos[0], m);
+                build_apply_1q(v, D, cs, bg.pos[0], m);
             }
         }
     }
     __syncthreads();
-    // M[y][x] = entry y of column x
-    auto Mre = [&](int y, int xx) { return Vs[(2 * y) * kBuildThreads + xx]; };
-    auto Mim = [&](int y, int xx) { return Vs[(2 * y + 1) * kBuildThreads + xx]; };
+    // M[y][x] = entry y of column x (a column this work-group holds)
+    auto Mre = [&](int y, int xx) { return Vs[(2 * y) * cs + (xx - x0)]; };
+    auto Mim = [&](int y, int xx) { return Vs[(2 * y + 1) * cs + (xx - x0)]; };
+    const int x = t;  // k <= 6: the thread's column (x0 = 0)
     // entry (R, Kc) of the real-split matrix [[Re, -Im], [Im, Re]]
     auto Ars = [&](int y, int a, int xx, int b) {
         const double re = Mre(y, xx), im = Mim(y, xx);
@@ -2566,14 +2822,39 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restri
     };
     char* out = mat_base + op.out_off;
     if (op.layout == LAYOUT_PLAIN) {
-        if (x < D) {
+        if (t < D && t < cs) {
+            const int xc = x0 + t;
             for (int y = 0; y < D; ++y) {
                 if (op.is_double) {
-                    reinterpret_cast<double2*>(out)[y * D + x] = make_double2(Mre(y, x), Mim(y, x));
+                    reinterpret_cast<double2*>(out)[y * D + xc] = make_double2(Mre(y, xc), Mim(y, xc));
                 } else {
-                    reinterpret_cast<float2*>(out)[y * D + x] = make_float2((float)Mre(y, x), (float)Mim(y, x));
+                    reinterpret_cast<float2*>(out)[y * D + xc] = make_float2((float)Mre(y, xc), (float)Mim(y, xc));
                 }
             }
+        }
+    } else if (op.layout == LAYOUT_SPLIT7) {
+        // k = 7: fp16 halves of 16 Re M and 16 Im M for v_mfma_f32_32x32x16_f16
+        // (k_cluster_f32_split7). Entry (rb, s, lane l, i) of each part:
+        // physical row rho = l % 32 of row block rb is amplitude
+        // (16 rb + 4 (rho / 8) + rho % 4) | ((rho / 4) % 2) << 6; inner element
+        // i of the lanes with l / 32 = hin is amplitude (8 s + i) | hin << 6.
+        // This work-group holds the columns whose bits 5, 6 equal op.part, i.e.
+        // steps s with s / 4 = part % 2 and lanes with l / 32 = part / 2.
+        constexpr int S7 = 8, NP7 = 4 * S7 * 64 * 8;  // halves per part
+        _Float16* A = reinterpret_cast<_Float16*>(out);
+        const int s_lo = 4 * (op.part & 1), hin = op.part >> 1;
+        for (int e = t; e < 4 * 4 * 32 * 8; e += kBuildThreads) {
+            const int i = e & 7, lr = (e >> 3) & 31, sl = (e >> 8) & 3, rb = e >> 10;
+            const int s2 = s_lo + sl, l = lr | (hin << 5), rho = lr;
+            const int y = (16 * rb + 4 * (rho >> 3) + (rho & 3)) | (((rho >> 2) & 1) << 6);
+            const int xin = (8 * s2 + i) | (hin << 6);
+            const float vr = (float)(16.0 * Mre(y, xin)), vi = (float)(16.0 * Mim(y, xin));
+            const _Float16 hr = (_Float16)vr, hi = (_Float16)vi;
+            const size_t at = ((size_t)(rb * S7 + s2) * 64 + l) * 8 + i;
+            A[at] = hr;
+            A[NP7 + at] = (_Float16)(vr - (float)hr);
+            A[2 * NP7 + at] = hi;
+            A[3 * NP7 + at] = (_Float16)(vi - (float)hi);
         }
     } else if (op.layout == LAYOUT_MFMA32F) {
         // entry (rb, s, lane l): row rho = l % 32 of row block rb, inner index 2 s + l / 32
@@ -2768,6 +3049,7 @@ constexpr unsigned kStreamGrid = 8192;  // blocks of 256 threads for grid-stride
 constexpr unsigned kPersistGrid = 2048; // work-groups of the persistent cluster kernels
 constexpr unsigned kPairGrid = 256;     // one 12-wave work-group per compute unit (LDS-limited)
 constexpr unsigned kStagedGrid = 256;   // one 8-wave work-group per compute unit (LDS-limited)
+constexpr unsigned kSplit7Grid = 256;   // one 4-wave work-group per compute unit (LDS-limited)
 }  // namespace
 
 hipError_t launch_init(void* psi, int n, bool dbl, int mode, hipStream_t st) {
@@ -2891,6 +3173,7 @@ hipError_t launch_init_cluster(void* psi, bool dbl, const ClusterGeom& g, const 
         case 4: go(std::integral_constant<int, 4>()); break;
         case 5: go(std::integral_constant<int, 5>()); break;
         case 6: go(std::integral_constant<int, 6>()); break;
+        case 7: go(std::integral_constant<int, 7>()); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2956,6 +3239,7 @@ StageGeom make_stage_geom(const ClusterGeom& g, int C, int unit) {
 }
 
 int cluster_layout(bool dbl, int k, int n) {
+    if (k == 7) return (!dbl && k <= max_cluster_k(dbl, n)) ? LAYOUT_SPLIT7 : -1;  // no other 7-qubit kernel
     if (!dbl) {
         if (k == 6) {
             if (n - k < 5) return LAYOUT_PLAIN;
@@ -3074,6 +3358,27 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
             case 6: return launch_valu_k<6>(psi, dbl, g, mat, epi, st);
             default: return hipErrorInvalidValue;
         }
+    }
+    if (layout == LAYOUT_SPLIT7 && !dbl && g.k == 7 && g.n >= 12) {
+        const uint64_t tiles = g.ncols / 32;
+        const unsigned grid = grid_for(tiles, 4, kSplit7Grid);
+        if (stats_part) {
+            *stats_blocks = grid;
+            if (g.t[0] == 0)
+                hipLaunchKernelGGL((k_cluster_f32_split7<true, true>), dim3(grid), dim3(256), 0, st, (float2*)psi,
+                                   (const half8*)mat, epi, g, stats_part);
+            else
+                hipLaunchKernelGGL((k_cluster_f32_split7<false, true>), dim3(grid), dim3(256), 0, st,
+                                   (float2*)psi, (const half8*)mat, epi, g, stats_part);
+            return hipGetLastError();
+        }
+        if (g.t[0] == 0)
+            hipLaunchKernelGGL(k_cluster_f32_split7<true>, dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const half8*)mat, epi, g, nullptr);
+        else
+            hipLaunchKernelGGL(k_cluster_f32_split7<false>, dim3(grid), dim3(256), 0, st, (float2*)psi,
+                               (const half8*)mat, epi, g, nullptr);
+        return hipGetLastError();
     }
     if (layout == LAYOUT_SPLIT16F && !dbl && g.k == 6 && variant == 1) {
         const StageGeom sg = make_stage_geom(g, 5, 7);  // 11 tile bits; chunks of 2^7 amplitudes

@@ -18,6 +18,12 @@
 // myopic: a cluster can look cheap per gate and still leave more total work;
 // the final comparison is between whole schedules.)
 //
+// Runs from the uniform state write their start in one write-only pass with
+// the first cluster, or with the first two when the second has 6 qubits
+// (SchedOpts::fold_start); candidates are compared with that pass priced as
+// write-only (kFold1Share, kFold2Share of a pass), and with clusters wider
+// than 6 also in a form whose first two clusters have at most 6 qubits.
+//
 // Candidate clusters besides the seeded ones: the closure of a dense qubit
 // set of the interaction graph (every ready gate inside the set joins, until
 // none is left). Growing gate by gate from a seed tends to give chains of
@@ -40,6 +46,7 @@
 #include "qsim_internal.h"
 
 namespace qsim {
+static_assert(kSchedMaxK == kMaxK, "schedule ops hold the widest cluster");
 namespace {
 
 inline int popc(uint64_t x) { return __builtin_popcountll(x); }
@@ -232,9 +239,11 @@ double grown_cost(const OpCostFn& cost, const Grown& c, int n) {
 // a cluster that reached kcap qubits is compared with the cluster the same
 // seed grows under kcap - 1, and the one with the smaller predicted time per
 // gate is taken.
+// first_cap > 0: the first two clusters have at most first_cap qubits (so
+// that a folded start can take them both).
 std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::vector<char>& dropped, int n_applied,
                             int kcap_in, bool fuse_diag, const OpCostFn* trim = nullptr,
-                            const std::vector<uint64_t>* sets = nullptr) {
+                            const std::vector<uint64_t>* sets = nullptr, int first_cap = 0) {
     const int ng = (int)gates.size();
     std::vector<SOp> out;
     Dag d;
@@ -256,6 +265,7 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
     std::vector<int> csize(sets ? sets->size() : 0, 0);
     uint64_t moved = ~uint64_t(0);
     std::vector<int> head_before;
+    int n_clusters = 0;
 
     while (remaining > 0) {
         d.ready_list(head, rl);
@@ -263,11 +273,12 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
         for (int q = 0; q < n; ++q) f0.head[q] = head[q];
         f0.nrl = (int)rl.size();
         std::copy(rl.begin(), rl.end(), f0.rl);
-        int best_score = -1, best_seed = -1, best_cap = kmax;
+        const int kcur = (first_cap > 0 && n_clusters < 2) ? std::min(kmax, first_cap) : kmax;
+        int best_score = -1, best_seed = -1, best_cap = kcur;
         uint64_t best_within = 0;
         for (int seed : rl) {
-            // a gate wider than kmax (a dense gate) forms a cluster of its own width
-            const int khi = std::max(kmax, popc(d.mask[seed]));
+            // a gate wider than the cap (a dense gate) forms a cluster of its own width
+            const int khi = std::max(kcur, popc(d.mask[seed]));
             const int c = grow(d, f0, seed, khi, fuse_diag, 0, nullptr);
             if (c > best_score) {
                 best_score = c;
@@ -290,20 +301,21 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
             const size_t top = std::min(kTopSets, ranked.size());
             std::partial_sort(ranked.begin(), ranked.begin() + top, ranked.end());
             for (size_t i = 0; i < top; ++i) {
-                const int c = grow(d, f0, -1, kmax, fuse_diag, ranked[i].second, nullptr);
+                if (popc(ranked[i].second) > kcur) continue;
+                const int c = grow(d, f0, -1, kcur, fuse_diag, ranked[i].second, nullptr);
                 if (c > best_score) {  // c > 0: the closure took a matrix gate
                     best_score = c;
                     best_seed = -1;
-                    best_cap = kmax;
+                    best_cap = kcur;
                     best_within = ranked[i].second;
                 }
             }
         }
         Grown best;
         grow(d, f0, best_seed, best_cap, fuse_diag, best_within, &best);
-        if (trim && best_seed >= 0 && kmax > 1 && popc(best.Q) == kmax && popc(d.mask[best_seed]) < kmax) {
+        if (trim && best_seed >= 0 && kcur > 1 && popc(best.Q) == kcur && popc(d.mask[best_seed]) < kcur) {
             Grown small;
-            grow(d, f0, best_seed, kmax - 1, fuse_diag, 0, &small);
+            grow(d, f0, best_seed, kcur - 1, fuse_diag, 0, &small);
             if (!all_diag(gates, small) && !all_diag(gates, best)) {
                 const double per_big = grown_cost(*trim, best, n) / best.n_gates();
                 const double per_small = grown_cost(*trim, small, n) / small.n_gates();
@@ -342,6 +354,7 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
             std::sort(op.epi.begin(), op.epi.end());
             head = best.head;
             remaining -= best.n_gates();
+            ++n_clusters;
         }
         out.push_back(std::move(op));
         moved = 0;
@@ -410,6 +423,24 @@ void dense_sets(int n, const std::vector<SGate>& gates, const std::vector<char>&
     }
 }
 
+// The start a schedule gets from a folded initialisation (SchedOpts::
+// fold_start): 2 when its first two ops are clusters of <= 6 and 6 qubits
+// (one write-only pass for both), 1 when its first op is a cluster, else 0.
+int fold_kind(const std::vector<SOp>& ops, int fold) {
+    if (fold <= 0 || ops.empty() || ops[0].kind != OP_CLUSTER) return 0;
+    if (fold >= 2 && ops.size() >= 2 && ops[0].k <= 6 && ops[1].kind == OP_CLUSTER && ops[1].k == 6) return 2;
+    return 1;
+}
+
+// Passes of a schedule with its start counted as the write-only pass it becomes.
+double effective_passes(const std::vector<SOp>& ops, int fold) {
+    switch (fold_kind(ops, fold)) {
+        case 2: return (double)ops.size() - 2 + kFold2Share;
+        case 1: return (double)ops.size() - 1 + kFold1Share;
+        default: return (double)ops.size();
+    }
+}
+
 }  // namespace
 
 void mark_skips(int n, const std::vector<SGate>& gates, bool skip_initial_h, bool skip_trailing_diag,
@@ -470,23 +501,38 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     // candidate qubit sets (dense sets of the interaction graph, two slacks)
     std::vector<uint64_t> sets0, sets1;
     if (o.cluster_sets && kmax >= 2) dense_sets(n, gates, S.dropped, kmax, sets0, sets1);
+    // with a two-cluster folded start and clusters wider than 6, candidates
+    // whose first two clusters have at most 6 qubits are built as well
+    const int fold = S.uniform_init ? o.fold_start : 0;
+    const int first_caps = (fold >= 2 && kmax > 6) ? 2 : 1;
     if (o.mode == 1 || !cost) {
-        if (sets0.empty()) {
-            S.ops = greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag);
-            return S;
-        }
-        // the greedy schedules with and without the candidate sets; the one
-        // with the fewest ops wins (ties: the earlier)
+        // the greedy schedules with and without the candidate sets (and with
+        // a 6-qubit start); the one with the fewest passes wins, the start
+        // counted as the write-only pass it becomes (ties: the earlier)
         const auto policy = o.parallel ? std::launch::async : std::launch::deferred;
-        auto f0 = std::async(policy, [&]() { return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag); });
-        auto f1 = std::async(policy, [&]() {
-            return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, &sets0);
-        });
-        std::vector<SOp> c2 = greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, &sets1);
-        S.ops = f0.get();
-        std::vector<SOp> c1 = f1.get();
-        if (c1.size() < S.ops.size()) S.ops = std::move(c1);
-        if (c2.size() < S.ops.size()) S.ops = std::move(c2);
+        std::vector<std::future<std::vector<SOp>>> futs;
+        for (int fc = 0; fc < first_caps; ++fc) {
+            const int cap = fc ? 6 : 0;
+            futs.push_back(std::async(policy, [&, cap]() {
+                return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, nullptr, cap);
+            }));
+            if (sets0.empty()) continue;
+            futs.push_back(std::async(policy, [&, cap]() {
+                return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, &sets0, cap);
+            }));
+            futs.push_back(std::async(policy, [&, cap]() {
+                return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, &sets1, cap);
+            }));
+        }
+        double best = 0.0;
+        for (size_t c = 0; c < futs.size(); ++c) {
+            std::vector<SOp> ops = futs[c].get();
+            const double p = effective_passes(ops, fold);
+            if (c == 0 || p < best) {
+                best = p;
+                S.ops = std::move(ops);
+            }
+        }
         return S;
     }
     // cost-driven: complete candidate schedules, the one with the smallest
@@ -542,9 +588,18 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     // each task builds a candidate and predicts its total (in parallel)
     using Cand = std::pair<std::vector<SOp>, double>;
     auto priced = [&](std::vector<SOp> ops) {
-        double total = 0.0;
-        for (const SOp& op : ops)
-            total += op.kind == OP_DIAG ? cost(0, op.qubits, 0) : cost(op.k, op.qubits, (int)op.epi.size());
+        double total = 0.0, c0 = 0.0, c1 = 0.0;
+        for (size_t i = 0; i < ops.size(); ++i) {
+            const SOp& op = ops[i];
+            const double c = op.kind == OP_DIAG ? cost(0, op.qubits, 0) : cost(op.k, op.qubits, (int)op.epi.size());
+            total += c;
+            if (i == 0) c0 = c;
+            if (i == 1) c1 = c;
+        }
+        // the start's share: its clusters written by one write-only pass
+        const int fk = fold_kind(ops, fold);
+        if (fk == 2) total -= c0 + (1.0 - kFold2Share) * c1;
+        if (fk == 1) total -= (1.0 - kFold1Share) * c0;
         return Cand(std::move(ops), total);
     };
     std::vector<std::future<Cand>> futs;
@@ -553,6 +608,16 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
             futs.push_back(std::async(policy, [&, kc]() {
                 return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag));
             }));
+    if (first_caps > 1) {  // the widest cap after a 6-qubit start, with and without the candidate sets
+        futs.push_back(std::async(policy, [&]() {
+            return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, nullptr, 6));
+        }));
+        for (const std::vector<uint64_t>* fs : {&sets0, &sets1})
+            if (!fs->empty())
+                futs.push_back(std::async(policy, [&, fs]() {
+                    return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, fs, 6));
+                }));
+    }
     if (kmax > 1 && use_cap[kmax - 1])
         futs.push_back(std::async(policy, [&]() {
             return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost));

@@ -17,10 +17,12 @@ struct SGate {
 
 enum : int { OP_CLUSTER = 0, OP_DIAG = 1, OP_GATE = 2 };
 
+constexpr int kSchedMaxK = 7;  // widest cluster (the library's kMaxK)
+
 struct SOp {
     int kind = OP_CLUSTER;
     int k = 0;
-    int qubits[6] = {0, 0, 0, 0, 0, 0};  // sorted (clusters); the gate's qubits (per-gate ops)
+    int qubits[kSchedMaxK] = {};  // sorted (clusters); the gate's qubits (per-gate ops)
     std::vector<int> members;            // gates folded into the matrix / the pass / the single gate
     std::vector<int> epi;                // diagonal gates applied while storing
 };
@@ -37,7 +39,19 @@ struct SchedOpts {
     bool skip_initial_h = false;
     bool cluster_sets = true;  // also offer closures of dense qubit sets (greedy and cost-driven)
     bool parallel = true;      // build candidate schedules on threads of their own
+    // How a run from the uniform state (skip_initial_h) writes its start:
+    // 0 an initialisation pass; 1 the first cluster with it, in one write-only
+    // pass; 2 also a second cluster of 6 qubits. Schedules are compared with
+    // that pass priced as write-only, and with 2 and kmax > 6 candidates whose
+    // first two clusters have at most 6 qubits are offered as well.
+    int fold_start = 0;
 };
+
+// Cost of the write-only start relative to the full passes it replaces:
+// measured on the 30-qubit complex64 state, the uniform start with one cluster
+// takes 0.41-0.49 of a cluster pass, with two clusters 0.69 of one.
+constexpr double kFold1Share = 0.45;
+constexpr double kFold2Share = 0.70;
 
 struct Schedule {
     std::vector<SOp> ops;

@@ -32,6 +32,10 @@ class QsimError(RuntimeError):
         self.status = status
 
 
+MAX_CLUSTER = 7       # widest cluster (QSIM_MAX_CLUSTER): per-op qubit lists have this many entries
+MAX_GATE_QUBITS = 6   # widest single gate
+
+
 class Gate(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("qubits", ctypes.c_int32 * 6),
                 ("theta", ctypes.c_double), ("mat", ctypes.POINTER(ctypes.c_double))]
@@ -45,7 +49,7 @@ class RunOpts(ctypes.Structure):
 
 
 class RunStats(ctypes.Structure):
-    _fields_ = [("n_ops", ctypes.c_int32), ("n_clusters_by_k", ctypes.c_int32 * 7),
+    _fields_ = [("n_ops", ctypes.c_int32), ("n_clusters_by_k", ctypes.c_int32 * 8),
                 ("n_diag_ops", ctypes.c_int32), ("n_gates_applied", ctypes.c_int32),
                 ("n_gates_fused_epilogue", ctypes.c_int32), ("schedule_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double)]
@@ -180,6 +184,8 @@ def gate_array(gates: Sequence) -> tuple:
             name, qubits, extra = g.name, tuple(g.qubits), getattr(g, "mat", None)
         arr[i].kind = GATE_KIND[name]
         arr[i].k = len(qubits)
+        if len(qubits) > MAX_GATE_QUBITS:
+            raise ValueError("a gate acts on at most %d qubits" % MAX_GATE_QUBITS)
         for j, q in enumerate(qubits):
             arr[i].qubits[j] = int(q)
         if name == "U":
@@ -217,13 +223,14 @@ def schedule(n: int, gates: Sequence, dtype: int = C64, **opts) -> dict:
     gate_role = (ctypes.c_int32 * max(1, ng))()
     op_kind = (ctypes.c_int32 * cap)()
     op_k = (ctypes.c_int32 * cap)()
-    op_q = (ctypes.c_int32 * (6 * cap))()
+    op_q = (ctypes.c_int32 * (MAX_CLUSTER * cap))()
     nops = ctypes.c_int()
     _check(lib().qsim_schedule(n, arr, ng, ctypes.byref(o), gate_op, gate_role, op_kind, op_k, op_q,
                                cap, ctypes.byref(nops)))
     m = nops.value
     return dict(gate_op=list(gate_op)[:ng], gate_role=list(gate_role)[:ng], op_kind=list(op_kind)[:m],
-                op_k=list(op_k)[:m], op_qubits=[list(op_q[6 * o_:6 * o_ + 6]) for o_ in range(m)])
+                op_k=list(op_k)[:m],
+                op_qubits=[list(op_q[MAX_CLUSTER * o_:MAX_CLUSTER * (o_ + 1)]) for o_ in range(m)])
 
 
 def stage_schedule(n: int, gates: Sequence, n_local: int, specialize: int = 1, search: bool = True,
@@ -273,8 +280,15 @@ def get_option(option: int) -> int:
 
 
 def set_cost_table(dtype: int, us_by_k, n_ref: int):
-    """Analytic scheduler costs: us_by_k[k] microseconds per op at n_ref qubits (k = 0: diagonal pass)."""
-    a = (ctypes.c_double * 7)(*[float(x) for x in us_by_k])
+    """Analytic scheduler costs: us_by_k[k] microseconds per op at n_ref qubits
+    (k = 0: diagonal pass, 1..7). A table without the k = 7 entry (7 values)
+    prices 7-qubit clusters as 6-qubit ones."""
+    us = [float(x) for x in us_by_k]
+    if len(us) == MAX_CLUSTER:
+        us.append(us[-1])
+    if len(us) != MAX_CLUSTER + 1:
+        raise ValueError("cost table needs %d or %d entries" % (MAX_CLUSTER, MAX_CLUSTER + 1))
+    a = (ctypes.c_double * (MAX_CLUSTER + 1))(*us)
     _check(lib().qsim_set_cost_table(dtype, a, n_ref))
 
 
@@ -355,7 +369,7 @@ def mlp_adam(params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, e
                                beta2, eps, ctypes.c_void_p(st.cuda_stream)))
 
 
-def workspace_bytes(n: int, dtype: int, kmax: int = 6) -> int:
+def workspace_bytes(n: int, dtype: int, kmax: int = MAX_CLUSTER) -> int:
     return int(lib().qsim_workspace_bytes(n, dtype, kmax))
 
 
@@ -411,7 +425,7 @@ def best_opts(n: int, dtype: str = "c64") -> dict:
 class State:
     """An n-qubit state vector in HBM (torch complex64 / complex128 tensor)."""
 
-    def __init__(self, n: int, dtype: str = "c64", init: str = "zero", kmax: int = 6,
+    def __init__(self, n: int, dtype: str = "c64", init: str = "zero", kmax: int = MAX_CLUSTER,
                  amps=None, stream=None, device: int = 0):
         import torch
         if not _tuning["loaded"] and not os.environ.get("QSIM_NO_TUNING"):
@@ -518,12 +532,12 @@ class State:
         if m == 0:
             return []
         kind, k, epi = (ctypes.c_int32 * m)(), (ctypes.c_int32 * m)(), (ctypes.c_int32 * m)()
-        qs, ms = (ctypes.c_int32 * (6 * m))(), (ctypes.c_float * m)()
+        qs, ms = (ctypes.c_int32 * (MAX_CLUSTER * m))(), (ctypes.c_float * m)()
         _check(L.qsim_op_timings(self.h, kind, k, qs, epi, ms, m, ctypes.byref(n)))
         kinds = {0: "cluster", 1: "diag", 2: "gate1q", 3: "phase1q", 4: "cz", 5: "build", 6: "init_cluster",
                  8: "init_cluster2",
                  7: "pair", 9: "permute"}
-        return [dict(kind=kinds[kind[i]], k=k[i], qubits=[q for q in qs[6 * i:6 * i + 6] if q >= 0],
+        return [dict(kind=kinds[kind[i]], k=k[i], qubits=[q for q in qs[MAX_CLUSTER * i:MAX_CLUSTER * (i + 1)] if q >= 0],
                      epi=bool(epi[i] & 1), staged=bool(epi[i] & 2), mfma=bool(epi[i] & 4),
                      stats=bool(epi[i] & 8), n_epi=(epi[i] >> 8) & 255, ms=float(ms[i]))
                 for i in range(m)]

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from conftest import ROOT
@@ -51,7 +52,44 @@ def test_schedule_rejects_bad_gates():
     with pytest.raises(qsim.QsimError, match="repeated"):
         qsim.schedule(4, [("CZ", (1, 1))])
     with pytest.raises(qsim.QsimError, match="kmax"):
-        qsim.schedule(4, [("H", (0,))], kmax=7)
+        qsim.schedule(4, [("H", (0,))], kmax=8)
+    with pytest.raises(ValueError, match="at most 6"):
+        qsim.gate_array([("U", tuple(range(7)), np.eye(128, dtype=np.complex128))])
+    # the library's own check: a dense gate of 7 qubits is refused
+    arr, keep = qsim.gate_array([("U", tuple(range(6)), np.eye(64, dtype=np.complex128))])
+    arr[0].k = 7
+    nops = ctypes.c_int()
+    o = qsim.run_opts(kmax=7)
+    cap = 4
+    i32 = lambda m: (ctypes.c_int32 * m)()
+    assert qsim.lib().qsim_schedule(8, arr, 1, ctypes.byref(o), i32(1), i32(1), i32(cap), i32(cap),
+                                    i32(cap * qsim.MAX_CLUSTER), cap, ctypes.byref(nops)) == qsim.E_UNSUPPORTED
+    assert b"dense gates" in qsim.lib().qsim_last_error()
+
+
+def test_seven_qubit_cap():
+    """kmax = 7 forms 7-qubit clusters only where a kernel exists for them:
+    complex64 states of >= 12 qubits with the fp16-halves 6-qubit kernel;
+    elsewhere schedules are capped at 6 qubits."""
+    from paper_1704_01127_amd import qsim
+    from supremacy_inputs import supremacy_circuit
+    circ = supremacy_circuit(5, 6, 25, 0)
+
+    def widest(n=circ.n, gates=circ.gates, dtype=qsim.C64):
+        sch = qsim.schedule(n, gates, dtype=dtype, kmax=7, fuse_diag=True, skip_initial_h=True,
+                            skip_trailing_diag=True)
+        return max(k for k, kind in zip(sch["op_k"], sch["op_kind"]) if kind == 0)
+
+    assert widest() == 7
+    assert widest(dtype=qsim.C128) == 6
+    small = supremacy_circuit(3, 3, 20, 0)  # 9 qubits
+    assert widest(small.n, small.gates) <= 6
+    old = qsim.get_option(qsim.OPT_K6_KERNEL)
+    try:
+        qsim.set_option(qsim.OPT_K6_KERNEL, 0)
+        assert widest() == 6
+    finally:
+        qsim.set_option(qsim.OPT_K6_KERNEL, old)
 
 
 def test_batch_plan_host_checks():

@@ -536,6 +536,137 @@ def test_phase_gate():
     assert np.max(np.abs(s.to_numpy() - ref)) <= 1e-15
 
 
+# ------------------------------------------------------------------ 7-qubit clusters
+def seven_qubit_gates(qs, others, seed, epilogue=True):
+    """Gates on the seven qubits qs only (random named single-qubit gates, CZ
+    layers on random pairings, a Haar 4-qubit gate, a closing H layer), which
+    a kmax = 7 schedule fuses into one cluster; then diagonal gates on other
+    qubits and between qs and others (its epilogue with fuse_diag)."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for layer in range(5):
+        for q in qs:
+            gates.append(Gate(str(rng.choice(["H", "SX", "SY", "T", "X", "Y", "Z", "TDG"])), (q,)))
+        perm = [int(x) for x in rng.permutation(qs)]
+        gates.extend(Gate("CZ", (a, b)) for a, b in zip(perm[0::2], perm[1::2]))
+    sub = tuple(int(x) for x in rng.choice(qs, 4, replace=False))
+    gates.append(Gate("U", sub, haar_unitary(4, seed)))
+    gates.extend(Gate("H", (q,)) for q in qs)
+    if epilogue and len(others) >= 3:
+        gates += [Gate("CZ", (qs[1], others[0])), Gate("T", (others[1],)), Gate("CZ", (others[1], others[2])),
+                  Gate("Z", (others[2],)),
+                  Gate("CZ", (others[0], qs[5])), Gate("TDG", (others[0],))]
+    return gates
+
+
+SEVEN_SETS = {
+    "middle": lambda n: list(range(n // 2 - 3, n // 2 + 4)),
+    "low": lambda n: list(range(7)),                        # qubit 0 a target (16-byte accesses), columns spread
+    "high": lambda n: list(range(n - 7, n)),
+    "spread": lambda n: sorted({0, 2, n // 3, n // 2, n // 2 + 1, n - 2, n - 1}),
+    "nolow": lambda n: sorted({1, 3, 4, n // 2, n - 4, n - 3, n - 1}),
+}
+
+
+@pytest.mark.parametrize("n", [12, 13, 17, 21])
+@pytest.mark.parametrize("pat", sorted(SEVEN_SETS))
+@pytest.mark.parametrize("fuse", [False, True])
+def test_seven_qubit_cluster(n, pat, fuse):
+    """One 7-qubit cluster (fp16 halves of Re M and Im M on the matrix cores)
+    on a random state, with and without a diagonal epilogue, against the
+    oracle's gate-by-gate result at the one-cluster bound for k = 7. n = 12
+    is the smallest state (one wave tile of 32 columns); 21 gives every wave
+    several tiles."""
+    qs = SEVEN_SETS[pat](n)
+    others = [q for q in range(n) if q not in qs]
+    gates = seven_qubit_gates(qs, others, 100 * n + len(pat), epilogue=True)
+    psi = random_state(n, 13 * n + len(pat))
+    ref = oracle.apply(psi.copy(), Circuit(n, gates))
+    s = make_state(n, "c64", psi)
+    st = s.run_circuit(gates, scheduler="greedy", kmax=7, fuse_diag=fuse, record_timings=True)
+    assert st["n_clusters_by_k"][7] == 1 and sum(st["n_clusters_by_k"]) == 1, st
+    assert st["n_ops"] == (1 if fuse else 2), st
+    ops = [r for r in s.op_timings() if r["kind"] == "cluster"]
+    assert ops[0]["k"] == 7 and ops[0]["qubits"] == qs and ops[0]["epi"] == fuse, ops
+    got = s.to_numpy()
+    err = np.max(np.abs(got - ref))
+    # the epilogue pass (without fuse) is exact up to fp32 products
+    bound = kernel_tol("c64", 7, np.max(np.abs(ref))) + (0 if fuse else 4 * U32 * np.max(np.abs(ref)))
+    assert err <= bound, (err, bound, qs)
+
+
+@pytest.mark.parametrize("pat", sorted(SEVEN_SETS))
+def test_seven_qubit_cluster_precision(pat):
+    """The 7-qubit kernel's error on a state complex64 holds exactly (no input
+    rounding): max and RMS error against the oracle stay within a factor 2 of
+    the 6-qubit fp16-halves kernel's on the same kind of input, scaled by the
+    square root of the dot-product length (sqrt 2); both far below plain fp16
+    arithmetic (2^-11 relative)."""
+    n = 16
+    qs = SEVEN_SETS[pat](n)
+    gates = seven_qubit_gates(qs, [], 7 + len(pat), epilogue=False)
+    psi = random_state(n, 5 + len(pat)).astype(np.complex64).astype(np.complex128)
+    ref = oracle.apply(psi.copy(), Circuit(n, gates))
+    s = make_state(n, "c64", psi)
+    st = s.run_circuit(gates, scheduler="greedy", kmax=7)
+    assert st["n_clusters_by_k"][7] == 1
+    d7 = np.abs(s.to_numpy() - ref)
+    # the same gates without the last qubit's share: a 6-qubit cluster
+    q6 = qs[:6]
+    g6 = [g for g in gates if set(g.qubits) <= set(q6)]
+    ref6 = oracle.apply(psi.copy(), Circuit(n, g6))
+    s6 = make_state(n, "c64", psi)
+    st6 = s6.run_circuit(g6, scheduler="greedy", kmax=6)
+    assert st6["n_clusters_by_k"][6] == 1
+    d6 = np.abs(s6.to_numpy() - ref6)
+    mx = float(np.max(np.abs(ref)))
+    assert d7.max() <= 2 * np.sqrt(2) * max(d6.max(), 2 * U32 * mx), (d7.max(), d6.max())
+    rms7, rms6 = np.sqrt(np.mean(d7 ** 2)), np.sqrt(np.mean(d6 ** 2))
+    assert rms7 <= 2 * np.sqrt(2) * rms6, (rms7, rms6)
+    assert d7.max() <= 2.0 ** -16 * mx
+
+
+def test_seven_qubit_fused_stats():
+    """The 7-qubit kernel's STATS form: a run whose last op is a 7-qubit
+    cluster returns the same norm, sum p^2 and entropy from the kernel's own
+    sums as the separate reduction."""
+    n = 18
+    qs = SEVEN_SETS["middle"](n)
+    gates = seven_qubit_gates(qs, [0, 1, 2], 3, epilogue=True)
+    psi = random_state(n, 3)
+    ref = make_state(n, "c64", psi)
+    ref.run_circuit(gates, kmax=7, fuse_diag=True)
+    want = ref.probs()
+    s = make_state(n, "c64", psi)
+    s.run_circuit(gates, kmax=7, fuse_diag=True, fused_stats=True)
+    s.amps.zero_()
+    torch.cuda.synchronize()
+    got = s.probs()
+    for a, b in zip(got, want):
+        assert abs(a - b) <= 1e-12 * max(1.0, abs(b)), (got, want)
+    onorm, osp2, oent = oracle.stats(oracle.apply(psi.copy(), Circuit(n, gates)))
+    assert abs(got[0] - onorm) <= 1e-5 and abs(got[2] - oent) <= 1e-4
+
+
+def test_seven_qubit_circuits():
+    """Whole circuits with kmax = 7 against the oracle: a 20-qubit depth-25
+    grid circuit (greedy and learned schedules, diagonal epilogues, the
+    uniform start folded into a first 7-qubit cluster) and one with Haar
+    5-qubit gates; the same runs on a complex128 state are capped at 6 qubits."""
+    for circ in (supremacy_circuit(4, 5, 25, 3), with_haar_layers(supremacy_circuit(4, 5, 24, 4), 6, 5, 9)):
+        ref = oracle.run(circ)
+        for sched in ("greedy", "learned"):
+            s = make_state(circ.n, "c64")
+            st = s.run_circuit(circ.gates, scheduler=sched, kmax=7, fuse_diag=True, skip_initial_h=True)
+            assert_fp32_circuit(s.to_numpy(), ref, st, 7)
+            if sched == "greedy":
+                assert st["n_clusters_by_k"][7] > 0, st
+        s = make_state(circ.n, "c128")
+        st = s.run_circuit(circ.gates, scheduler="greedy", kmax=7, fuse_diag=True, skip_initial_h=True)
+        assert st["n_clusters_by_k"][7] == 0 and st["n_clusters_by_k"][6] > 0, st
+        assert np.max(np.abs(s.to_numpy() - ref)) <= 1e-12
+
+
 # ------------------------------------------------------------------ whole circuits
 RUN_CASES = [
     dict(scheduler="per_gate"),
@@ -550,6 +681,8 @@ RUN_CASES = [
     dict(scheduler="greedy", kmax=5, fuse_diag=True),
     dict(scheduler="greedy", kmax=6, fuse_diag=True),
     dict(scheduler="greedy", kmax=5, fuse_diag=True, skip_initial_h=True),
+    dict(scheduler="greedy", kmax=7),                    # complex128: capped at 6
+    dict(scheduler="greedy", kmax=7, fuse_diag=True, skip_initial_h=True),
 ]
 
 
@@ -897,7 +1030,7 @@ def test_argument_errors():
     with pytest.raises(qsim.QsimError, match="INVALID"):
         s.apply_cluster([1, 1], np.eye(4))
     with pytest.raises(qsim.QsimError, match="UNSUPPORTED"):
-        s.apply_cluster(list(range(7)), np.eye(128)) if False else s.run_circuit([("H", (0,))], kmax=7)
+        s.run_circuit([("H", (0,))], kmax=8)
     with pytest.raises(qsim.QsimError, match="INVALID"):
         s.apply_diag([(2, 2)])
     s.sync()

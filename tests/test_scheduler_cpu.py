@@ -67,7 +67,7 @@ def cluster_sets(request):
     qsim.set_option(qsim.OPT_CLUSTER_SETS, old)
 
 
-@pytest.mark.parametrize("kmax", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("kmax", [1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("fuse", [False, True])
 def test_supremacy_schedule_valid(kmax, fuse, cluster_sets):
     circ = supremacy_circuit(5, 6, 25, seed=kmax)
