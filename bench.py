@@ -56,6 +56,8 @@ def kernel_name(rec, k6_kernel=2, pair_tile=11, dbl=False) -> str:
     if not rec.get("mfma"):
         return "k_cluster_valu<float, %d>" % k
     b = lambda x: "true" if x else "false"  # noqa: E731
+    if k == 7:  # the direct kernel only; its second flag sums the reductions
+        return "k_cluster_f32_split7<%s, %s>" % (b(lowt), b(rec.get("stats")))
     if k == 6 and k6_kernel in (1, 2):
         if k6_kernel == 2 and rec.get("staged"):
             return "k_cluster_f32_split6s<%s>" % b(lowt)
@@ -78,7 +80,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--drop-corner", action="store_true",
                     help="leave out the grid's last site (34 qubits: 5x7 minus site (4, 6))")
-    ap.add_argument("--kmax", type=int, default=6)
+    ap.add_argument("--kmax", type=int, default=7)
     ap.add_argument("--scheduler", default="learned")
     ap.add_argument("--no-fuse-diag", action="store_true")
     ap.add_argument("--pair-tile", type=int, default=None, choices=[10, 11],
@@ -94,6 +96,8 @@ def parse():
                     help="skip the CPU oracle (and with it every comparison against the oracle)")
     ap.add_argument("--no-fp32-k6", action="store_true",
                     help="skip the form with 6-qubit clusters on the fp32 matrix cores")
+    ap.add_argument("--no-k6", action="store_true",
+                    help="skip the form whose clusters have at most 6 qubits (with --kmax 7)")
     ap.add_argument("--no-mapped", action="store_true",
                     help="skip the fused forms with the qubit mapping (QSIM_OPT_MAP_QUBITS)")
     ap.add_argument("--batch-check-every", type=int, default=8,
@@ -281,6 +285,7 @@ def main():
     fused_opts = dict(kmax=args.kmax, scheduler=args.scheduler, fuse_diag=not args.no_fuse_diag,
                       skip_trailing_diag=True, skip_initial_h=True, fused_stats=True)
     pergate_opts = dict(scheduler="per_gate", skip_trailing_diag=True, skip_initial_h=True)
+    k6_opts = dict(fused_opts, kmax=6)
 
     def timed(state, opts, steps, warmup, record):
         fresh = writes_whole_state(qsim, n, gates, opts, state.dt)
@@ -316,8 +321,13 @@ def main():
     if args.only in (None, "fused"):
         states["c64_fused"] = qsim.State(n, "c64", kmax=max(args.kmax, 5))
         forms["c64_fused"] = timed(states["c64_fused"], fused_opts, args.steps, args.warmup, record=True)
+    if args.only is None and not args.no_k6 and args.kmax >= 7:
+        # the same scheduler with clusters of at most 6 qubits (fp16-halves 6-qubit kernel)
+        states["c64_fused_k6"] = qsim.State(n, "c64", kmax=6)
+        forms["c64_fused_k6"] = timed(states["c64_fused_k6"], k6_opts, args.steps, min(args.warmup, 1), record=True)
     if args.only is None and not args.no_fp32_k6 and args.kmax >= 6:
-        # the same schedule with 6-qubit clusters on the fp32 matrix cores
+        # 6-qubit clusters on the fp32 matrix cores (7-qubit clusters need the
+        # fp16 kernel, so the cap is 6 there)
         qsim.set_option(qsim.OPT_K6_KERNEL, 0)
         try:
             states["c64_fused_fp32_k6"] = qsim.State(n, "c64", kmax=max(args.kmax, 5))
@@ -360,11 +370,12 @@ def main():
     out["unit"] = "s"
     out["ms_per_step"] = round(tts * 1e3, 3)
     if main_key == "c64_fused":
-        out["dtype"] = "f32 (6-qubit clusters: f16 hi/lo operand halves, f32 accumulate)"
+        out["dtype"] = "f32 (6- and 7-qubit clusters: f16 hi/lo operand halves, f32 accumulate)"
         form = ("complex64 state; clusters of <= %d qubits (scheduler %s, diagonal fusion %s) built in "
-                "float64 on the GPU; 6-qubit clusters on fp16 matrix cores with hi/lo halves of both "
-                "operands (three products, fp32 accumulation), smaller ones on fp32 matrix cores; "
-                "float64 reductions" % (args.kmax, args.scheduler, "on" if not args.no_fuse_diag else "off"))
+                "float64 on the GPU; 6- and 7-qubit clusters on fp16 matrix cores with hi/lo halves of both "
+                "operands (three products, fp32 accumulation; 7-qubit ones on the real and imaginary parts "
+                "of the matrix), smaller ones on fp32 matrix cores; float64 reductions"
+                % (args.kmax, args.scheduler, "on" if not args.no_fuse_diag else "off"))
     else:
         out["dtype"] = "f64"
         form = "complex128 state, one launch per gate"
@@ -384,7 +395,9 @@ def main():
         roof, ck = cluster_roofline(ref["recs"], n, False, args.steps, k6_default, pair_tile)
         out["roofline"] = roof
         out["cluster_kernels"] = ck
-    desc = {"c64_fused_fp32_k6": "complex64 state, the same schedule with 6-qubit clusters on fp32 matrix "
+    desc = {"c64_fused_k6": "complex64 state, the same scheduler with clusters of <= 6 qubits (6-qubit ones "
+                            "on fp16 matrix cores with operand halves)",
+            "c64_fused_fp32_k6": "complex64 state, clusters of <= 6 qubits with the 6-qubit ones on fp32 matrix "
                                  "cores (real-split product)",
             "c128_fused": "complex128 state, fused clusters of <= %d qubits on fp64 matrix cores" % args.fp64_kmax,
             "c128_per_gate": "complex128 state, one launch per gate (the plain method)",
@@ -426,7 +439,7 @@ def main():
         for key, f in forms.items():
             fid, md = states[key].compare(ref_dev)
             # every form applies the oracle's gates: those not skipped, plus the H layer it replaces
-            opts = pergate_opts if key == "c128_per_gate" else fused_opts
+            opts = pergate_opts if key == "c128_per_gate" else (k6_opts if key == "c64_fused_k6" else fused_opts)
             fresh = writes_whole_state(qsim, n, gates, opts, states[key].dt)
             same = f["st"]["n_gates_applied"] + (n if fresh else 0) == len(kept.gates)
             vs[key] = {"fidelity": fid, "max_abs_diff": md, "max_abs_diff_over_max_amp": md / mx,

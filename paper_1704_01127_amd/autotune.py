@@ -43,6 +43,18 @@ def op_ms(state, qubits, mat, reps):
     return statistics.median(r["ms"] for r in state.op_timings() if r["kind"] == "cluster")
 
 
+def op7_ms(state, qubits, reps, seed):
+    """Median time of one 7-qubit cluster: a single gate has at most 6 qubits,
+    so two dense gates over the 7 qubits, which a k_max = 7 schedule fuses
+    into one cluster (one run per repetition)."""
+    g = [("U", tuple(qubits[:6]), haar(6, seed)), ("U", (qubits[5], qubits[6]), haar(2, seed + 1))]
+    ts = []
+    for _ in range(reps):
+        state.run_circuit(g, scheduler="greedy", kmax=7, record_timings=True)
+        ts += [r["ms"] for r in state.op_timings() if r["kind"] == "cluster" and r["k"] == 7]
+    return statistics.median(ts)
+
+
 def diag_ms(state, n, reps):
     gates = [("CZ", (2 * i, 2 * i + 1)) for i in range(n // 2)] + [("T", (q,)) for q in range(0, n, 3)]
     ts = []
@@ -87,12 +99,19 @@ def apply_variants(table_by_dtype):
 
 
 def tune_costs(n, dt, reps, seed, log):
+    """us_by_k for k = 0..7 (k = 7: complex64 only; a complex128 table repeats
+    its k = 6 entry, which its runs never exceed)."""
     rng = np.random.default_rng(seed + 1)
-    state = qsim.State(n, dt, init="uniform", kmax=6)
+    state = qsim.State(n, dt, init="uniform", kmax=7)
     us = [diag_ms(state, n, reps) * 1e3]
-    for k in range(1, 7):
-        mat = haar(k, k)
-        ts = [op_ms(state, sorted(int(q) for q in rng.choice(n, k, replace=False)), mat, reps) for _ in range(3)]
+    for k in range(1, 8):
+        if k == 7 and dt != "c64":
+            us.append(us[-1])
+            break
+        ts = []
+        for _ in range(3):
+            qs = sorted(int(q) for q in rng.choice(n, k, replace=False))
+            ts.append(op7_ms(state, qs, reps, k) if k == 7 else op_ms(state, qs, haar(k, k), reps))
         us.append(statistics.mean(ts) * 1e3)
         log("cost %s k=%d: %.1f us" % (dt, k, us[-1]))
     del state
@@ -104,10 +123,10 @@ def tune_kmax(dt, buckets, seed, log):
     res = {}
     for n, (R, C) in buckets.items():
         circ = supremacy_circuit(R, C, 25, seed)
-        state = qsim.State(circ.n, dt, kmax=6)
+        state = qsim.State(circ.n, dt, kmax=7)
         best = None
         for sched in ("greedy", "analytic"):
-            for kmax in (3, 4, 5, 6):
+            for kmax in ((3, 4, 5, 6, 7) if dt == "c64" else (3, 4, 5, 6)):
                 opts = dict(kmax=kmax, scheduler=sched, fuse_diag=True, skip_trailing_diag=True,
                             skip_initial_h=True)
                 state.init("zero")

@@ -53,12 +53,14 @@ def op_record_rows(recs, n, dtype_code):
 def cmd_record(args):
     import torch  # noqa: F401
     feats, ys, meta = [], [], []
-    configs = [dict(kmax=k, fuse_diag=fd) for k in (2, 3, 4, 5, 6) for fd in (False, True)]
     t_start = time.time()
     for dt, ns in (("c64", [27, 28, 29, 30]), ("c128", [27, 28, 29, 30])):
         code = qsim.C64 if dt == "c64" else qsim.C128
+        # 7-qubit clusters exist on complex64 only (complex128 runs cap k_max at 6)
+        configs = [dict(kmax=k, fuse_diag=fd) for k in ((2, 3, 4, 5, 6, 7) if dt == "c64" else (2, 3, 4, 5, 6))
+                   for fd in (False, True)]
         for n in ns:
-            state = qsim.State(n, dt, kmax=6)
+            state = qsim.State(n, dt, kmax=7)
             for seed in range(args.seeds):
                 circ = workload(n, args.depth, seed)
                 for ci, cfg in enumerate(configs):
@@ -160,7 +162,8 @@ def time_run(state, circ, opts, reps=3):
 
 
 def compare(n_list=(28, 29, 30), seeds=range(100, 104), depth=40, dtype="c64", log=print):
-    """Time held-out circuits with the learned scheduler (k <= 6) against the
+    """Time held-out circuits with the learned scheduler (k <= 7; 6 on
+    complex128 states) against the
     method without the model: the fixed-k greedy scheduler at the k_max the
     autotuner found best for this dtype and size (qsim.best_opts), and also
     greedy at k = 5 and k = 6 and the analytic model. The results of every
@@ -170,20 +173,23 @@ def compare(n_list=(28, 29, 30), seeds=range(100, 104), depth=40, dtype="c64", l
     base = dict(fuse_diag=True, skip_trailing_diag=True, skip_initial_h=True)
     for n in n_list:
         tuned = qsim.best_opts(n, dtype)
-        s1 = qsim.State(n, dtype, kmax=6)
-        s2 = qsim.State(n, dtype, kmax=6)
+        s1 = qsim.State(n, dtype, kmax=7)
+        s2 = qsim.State(n, dtype, kmax=7)
         for seed in seeds:
             circ = workload(n, depth, seed)
             tg, stg = time_run(s1, circ, dict(base, scheduler="greedy", kmax=tuned["kmax"]))
-            tl, stl = time_run(s2, circ, dict(base, scheduler="learned", kmax=6))
+            tl, stl = time_run(s2, circ, dict(base, scheduler="learned", kmax=7))
             fid, maxd = s1.compare(s2.amps)
             t5, st5 = time_run(s1, circ, dict(base, scheduler="greedy", kmax=5))
             t6, st6 = time_run(s1, circ, dict(base, scheduler="greedy", kmax=6))
-            ta, sta = time_run(s1, circ, dict(base, scheduler="analytic", kmax=6))
+            t7, st7 = time_run(s1, circ, dict(base, scheduler="greedy", kmax=7))
+            ta, sta = time_run(s1, circ, dict(base, scheduler="analytic", kmax=7))
             row = dict(n=n, dtype=dtype, seed=seed, tuned_kmax=tuned["kmax"], tuned_greedy_ms=tg * 1e3,
                        tuned_schedule_ms=stg["schedule_ms"],
-                       greedy_ms=t5 * 1e3, greedy6_ms=t6 * 1e3, learned_ms=tl * 1e3, analytic_ms=ta * 1e3,
+                       greedy_ms=t5 * 1e3, greedy6_ms=t6 * 1e3, greedy7_ms=t7 * 1e3, learned_ms=tl * 1e3,
+                       analytic_ms=ta * 1e3,
                        tuned_greedy_ops=stg["n_ops"], greedy_ops=st5["n_ops"], greedy6_ops=st6["n_ops"],
+                       greedy7_ops=st7["n_ops"],
                        learned_ops=stl["n_ops"], analytic_ops=sta["n_ops"],
                        tuned_clusters_by_k=stg["n_clusters_by_k"], learned_clusters_by_k=stl["n_clusters_by_k"],
                        learned_schedule_ms=stl["schedule_ms"], fidelity_learned_vs_greedy=fid, max_abs_diff=maxd)
@@ -194,11 +200,12 @@ def compare(n_list=(28, 29, 30), seeds=range(100, 104), depth=40, dtype="c64", l
     tg = sum(r["tuned_greedy_ms"] for r in rows)
     g5 = sum(r["greedy_ms"] for r in rows)
     g6 = sum(r["greedy6_ms"] for r in rows)
+    g7 = sum(r["greedy7_ms"] for r in rows)
     lr = sum(r["learned_ms"] for r in rows)
     an = sum(r["analytic_ms"] for r in rows)
-    log("total (%s): tuned greedy %.1f ms, greedy k=5 %.1f ms, greedy k=6 %.1f ms, analytic %.1f ms, "
-        "learned %.1f ms (learned vs tuned greedy: %.1f%% faster)"
-        % (dtype, tg, g5, g6, an, lr, 100 * (tg - lr) / tg))
+    log("total (%s): tuned greedy %.1f ms, greedy k=5 %.1f ms, greedy k=6 %.1f ms, greedy k=7 %.1f ms, "
+        "analytic %.1f ms, learned %.1f ms (learned vs tuned greedy: %.1f%% faster)"
+        % (dtype, tg, g5, g6, g7, an, lr, 100 * (tg - lr) / tg))
     return rows
 
 

@@ -2783,24 +2783,43 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restri
                         BV(v, 2 * i + 1, cs) = -BV(v, 2 * i + 1, cs);
                     }
             } else if (bg.kind == G_DENSE) {
+                // for each assignment `rest` of the entry bits outside the
+                // gate, the dd entries rest | dep(xl) are multiplied by the
+                // gate's matrix; 16 outputs at a time are summed in registers
+                // (dep puts bit j of a gate index at the gate's position j)
                 const int dq = bg.nq, dd = 1 << dq;
                 const double* u = dense + bg.dense_off;
                 int pm = 0;
                 for (int j = 0; j < dq; ++j) pm |= 1 << bg.pos[j];
-                for (int y = 0; y < D; ++y) {
-                    int yl = 0;
-                    for (int j = 0; j < dq; ++j) yl |= ((y >> bg.pos[j]) & 1) << j;
-                    const int rest = y & ~pm;
-                    double sr = 0.0, si = 0.0;
-                    for (int xl = 0; xl < dd; ++xl) {
-                        int src = rest;
-                        for (int j = 0; j < dq; ++j) src |= ((xl >> j) & 1) << bg.pos[j];
-                        const double mr = u[2 * (yl * dd + xl)], mi = u[2 * (yl * dd + xl) + 1];
-                        sr += mr * BV(v, 2 * src, cs) - mi * BV(v, 2 * src + 1, cs);
-                        si += mr * BV(v, 2 * src + 1, cs) + mi * BV(v, 2 * src, cs);
+                auto dep = [&](int xl) {
+                    int o = 0;
+                    for (int j = 0; j < dq; ++j) o |= ((xl >> j) & 1) << bg.pos[j];
+                    return o;
+                };
+                for (int rest = 0; rest < D; rest = ((rest | pm) + 1) & ~pm) {
+                    for (int y0 = 0; y0 < dd; y0 += 16) {
+                        double sr[16], si[16];
+#pragma unroll
+                        for (int t2 = 0; t2 < 16; ++t2) sr[t2] = si[t2] = 0.0;
+                        for (int xl = 0; xl < dd; ++xl) {
+                            const int src = rest | dep(xl);
+                            const double vr = BV(v, 2 * src, cs), vi = BV(v, 2 * src + 1, cs);
+#pragma unroll
+                            for (int t2 = 0; t2 < 16; ++t2) {
+                                if (y0 + t2 >= dd) break;
+                                const double mr = u[2 * ((y0 + t2) * dd + xl)], mi = u[2 * ((y0 + t2) * dd + xl) + 1];
+                                sr[t2] += mr * vr - mi * vi;
+                                si[t2] += mr * vi + mi * vr;
+                            }
+                        }
+#pragma unroll
+                        for (int t2 = 0; t2 < 16; ++t2) {
+                            if (y0 + t2 >= dd) break;
+                            const int dst = rest | dep(y0 + t2);
+                            BV(w, 2 * dst, cs) = sr[t2];
+                            BV(w, 2 * dst + 1, cs) = si[t2];
+                        }
                     }
-                    BV(w, 2 * y, cs) = sr;
-                    BV(w, 2 * y + 1, cs) = si;
                 }
                 for (int i = 0; i < 2 * D; ++i) BV(v, i, cs) = BV(w, i, cs);
             } else {

@@ -36,7 +36,9 @@
 //     then absorbs every ready diagonal gate;
 //   * with fuse_diag, once no gate fits a cluster any more, ready diagonal
 //     gates are attached to it and applied while its results are stored; a
-//     qubit touched by such a gate accepts only diagonal gates afterwards.
+//     qubit touched by such a gate accepts only diagonal gates afterwards;
+//     when the schedule is complete, such a gate moves into the matrix of the
+//     next cluster on its qubits where that cluster holds them all.
 #include "scheduler.h"
 
 #include <algorithm>
@@ -226,6 +228,44 @@ bool all_diag(const std::vector<SGate>& G, const Grown& c) {
     return true;
 }
 
+// Diagonal gates a cluster carries to its store (fuse_diag) move into the
+// matrix of the next cluster that holds all their qubits, when that is the
+// first later op with a non-diagonal gate on any of them: in between they
+// meet only gates on other qubits and diagonal gates, which commute with them
+// (Sec. 3.5). In a matrix they cost nothing; at a store, a phase or a sign
+// that depends on a target bit is arithmetic on every amplitude.
+void absorb_epilogues(std::vector<SOp>& ops, const std::vector<SGate>& gates) {
+    const size_t no = ops.size();
+    auto mask_of = [&](int gi) {
+        uint64_t m = 0;
+        for (int j = 0; j < gates[gi].nq; ++j) m |= uint64_t(1) << gates[gi].q[j];
+        return m;
+    };
+    std::vector<uint64_t> nondiag(no, 0), held(no, 0);
+    for (size_t o = 0; o < no; ++o) {
+        for (int gi : ops[o].members)
+            if (!gates[gi].diag) nondiag[o] |= mask_of(gi);
+        if (ops[o].kind == OP_CLUSTER)
+            for (int j = 0; j < ops[o].k; ++j) held[o] |= uint64_t(1) << ops[o].qubits[j];
+    }
+    for (size_t i = 0; i < no; ++i) {
+        if (ops[i].kind != OP_CLUSTER || ops[i].epi.empty()) continue;
+        std::vector<int> keep;
+        for (int gi : ops[i].epi) {
+            const uint64_t Q = mask_of(gi);
+            size_t t = i + 1;
+            while (t < no && !(nondiag[t] & Q)) ++t;
+            if (t < no && ops[t].kind == OP_CLUSTER && (Q & ~held[t]) == 0) {
+                auto& m = ops[t].members;
+                m.insert(std::lower_bound(m.begin(), m.end(), gi), gi);  // program order in the matrix
+            } else {
+                keep.push_back(gi);
+            }
+        }
+        ops[i].epi = std::move(keep);
+    }
+}
+
 // Predicted time of a grown cluster (sorted qubits from its mask).
 double grown_cost(const OpCostFn& cost, const Grown& c, int n) {
     int q[64], k = 0;
@@ -361,6 +401,7 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
         for (int q = 0; q < n; ++q)
             if (head[q] != head_before[q]) moved |= uint64_t(1) << q;
     }
+    if (fuse_diag) absorb_epilogues(out, gates);
     return out;
 }
 

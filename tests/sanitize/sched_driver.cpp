@@ -61,7 +61,7 @@ int check_schedule(const Schedule& S, const std::vector<SGate>& g, int n, int km
         // a cluster holds at most kmax qubits, or one dense gate wider than that
         int widest = 0;
         for (int m : op.members) widest = std::max(widest, g.at(m).nq);
-        if (op.kind == OP_CLUSTER && (op.k < 1 || op.k > std::max(kmax, widest) || op.k > 6)) return 1;
+        if (op.kind == OP_CLUSTER && (op.k < 1 || op.k > std::max(kmax, widest) || op.k > kMaxK)) return 1;
         for (int j = 0; j < op.k && op.kind != OP_GATE; ++j)
             if (op.qubits[j] < 0 || op.qubits[j] >= n || (j && op.qubits[j] <= op.qubits[j - 1])) return 2;
         for (int m : op.members) seen.at(m)++;
@@ -95,10 +95,11 @@ int main() {
         const int n = 2 + below(30);
         const std::vector<SGate> g = random_gates(n, 10 + below(150), trial % 2 == 0);
         for (int mode = 0; mode <= 2 && !bad; ++mode)
-            for (int kmax = 1; kmax <= 6 && !bad; ++kmax) {
+            for (int kmax = 1; kmax <= kMaxK && !bad; ++kmax) {
                 SchedOpts o;
                 o.mode = mode;
                 o.kmax = kmax;
+                o.fold_start = below(3);
                 o.fuse_diag = below(2);
                 o.skip_trailing_diag = below(2);
                 o.skip_initial_h = below(2);
@@ -117,7 +118,7 @@ int main() {
             so.spec_diag1 = below(2);
             so.search = below(2);
             so.early_swaps = below(2);
-            so.kmax = below(7);
+            so.kmax = below(kMaxK + 1);
             so.skip_initial_h = below(2);
             so.skip_trailing_diag = below(2);
             const StagePlan P = make_stage_plan(n, g, so);

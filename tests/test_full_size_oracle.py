@@ -1,9 +1,10 @@
 """The benchmarked 30-qubit workload against the CPU oracle at full size.
 
 The 5x6-grid depth-25 supremacy circuit (seeds 0-4) is run by every GPU form
-the benchmark times - complex64 fused (6-qubit clusters on fp16 matrix cores
-with operand halves), complex64 fused with 6-qubit clusters on fp32 matrix
-cores, complex128 fused and complex128 one gate at a time - and each final
+the benchmark times - complex64 fused with clusters of up to 7 qubits (6- and
+7-qubit ones on fp16 matrix cores with operand halves), the same with up to 6
+qubits, complex64 fused with 6-qubit clusters on fp32 matrix cores,
+complex128 fused and complex128 one gate at a time - and each final
 state is compared with the float64 oracle's, amplitude by amplitude (in
 float64 on the GPU: the oracle's 16 GiB state is uploaded once per seed).
 The runs skip what the benchmark skips: the leading H layer becomes the
@@ -24,11 +25,12 @@ from supremacy_inputs import supremacy_circuit
 
 pytestmark = pytest.mark.gpu
 
-BENCH_OPTS = dict(kmax=6, scheduler="learned", fuse_diag=True, skip_trailing_diag=True, skip_initial_h=True,
+BENCH_OPTS = dict(kmax=7, scheduler="learned", fuse_diag=True, skip_trailing_diag=True, skip_initial_h=True,
                   fused_stats=True)
 FORMS = [
     ("c64", 2, BENCH_OPTS),                                    # the benchmark's form
-    ("c64", 0, BENCH_OPTS),                                    # 6-qubit clusters on fp32 matrix cores
+    ("c64", 2, dict(BENCH_OPTS, kmax=6)),                      # clusters of at most 6 qubits
+    ("c64", 0, BENCH_OPTS),                                    # 6-qubit clusters on fp32 matrix cores (cap 6)
     ("c128", 2, dict(BENCH_OPTS, kmax=5)),                     # float64 fused
     ("c128", 2, dict(scheduler="per_gate", skip_trailing_diag=True, skip_initial_h=True)),
 ]
@@ -55,7 +57,7 @@ def test_30q_depth25_forms_match_oracle(seed):
             f, d = s.compare(ref)
             # the run applied exactly the oracle's gates: the H layer it replaced plus the rest
             assert st["n_gates_applied"] + 30 == len(kept.gates), st
-            tag = (dt, k6, opts.get("scheduler"))
+            tag = (dt, k6, opts.get("scheduler"), opts.get("kmax"))
             errs[tag] = d
             print("seed %d %s: ops %d fidelity 1-%.2e max|d| %.3e (%.2e of max|amp|) norm-1 %.1e dS %.1e"
                   % (seed, tag, st["n_ops"], 1 - f, d, d / mx, norm - 1, ent - oent), flush=True)
@@ -64,13 +66,15 @@ def test_30q_depth25_forms_match_oracle(seed):
                 assert abs(norm - onorm) <= 1e-12 and abs(ent - oent) <= 1e-10, tag
             else:
                 assert f >= 1 - 1e-6, (tag, f)
-                assert d <= fp32_circuit_bound(mx, st["n_ops"], 6), (tag, d, mx)
+                kw = max(k for k in range(8) if st["n_clusters_by_k"][k])
+                assert d <= fp32_circuit_bound(mx, st["n_ops"], kw), (tag, d, mx)
                 assert abs(norm - onorm) <= 1e-5 and abs(ent - oent) <= 1e-4, tag
             del s
     finally:
         qsim.set_option(qsim.OPT_K6_KERNEL, old)
-    # fp16-halves 6-qubit products stay at the error level of the fp32 matrix cores
-    assert errs[("c64", 2, "learned")] <= 4 * errs[("c64", 0, "learned")], errs
+    # fp16-halves products (6- and 7-qubit) stay at the error level of the fp32 matrix cores
+    assert errs[("c64", 2, "learned", 7)] <= 4 * errs[("c64", 0, "learned", 7)], errs
+    assert errs[("c64", 2, "learned", 6)] <= 4 * errs[("c64", 0, "learned", 7)], errs
 
 
 @pytest.mark.parametrize("n", [28, 30])
@@ -91,7 +95,7 @@ def test_learned_and_greedy_match_oracle(n):
     dts = ("c64", "c128") if n <= 28 else ("c64",)
     for dt in dts:
         tuned = qsim.best_opts(n, dt)
-        for opts in (dict(base, scheduler="learned", kmax=6), dict(base, scheduler="greedy", kmax=tuned["kmax"])):
+        for opts in (dict(base, scheduler="learned", kmax=7), dict(base, scheduler="greedy", kmax=tuned["kmax"])):
             s = qsim.State(n, dt)
             st = s.run_circuit(circ.gates, **opts)
             assert st["n_gates_applied"] + n == len(kept.gates)
@@ -101,5 +105,5 @@ def test_learned_and_greedy_match_oracle(n):
             if dt == "c128":
                 assert d <= 1e-12
             else:
-                assert f >= 1 - 1e-6 and d <= fp32_circuit_bound(mx, st["n_ops"], 6), (f, d)
+                assert f >= 1 - 1e-6 and d <= fp32_circuit_bound(mx, st["n_ops"], 7), (f, d)
             del s

@@ -309,21 +309,23 @@ def test_k6_kernels_circuit(k6_kernel, k6_variant):
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("kmax", [1, 3, 5, 6])
+@pytest.mark.parametrize("kmax", [1, 3, 5, 6, 7])
 def test_fold_init_matches_oracle(dt, kmax):
     """The uniform start written together with the first cluster (and its
     diagonal epilogue) in one pass gives the oracle's state, as does the
     unfolded form."""
     circ = supremacy_circuit(4, 4, 18, seed=40 + kmax)
     ref = oracle.run(circ)
-    sc = qsim.schedule(circ.n, circ.gates, kmax=kmax, fuse_diag=True, skip_initial_h=True)
-    first_is_cluster = sc["op_kind"][0] == 0
-    two = (dt == "c64" and first_is_cluster and len(sc["op_kind"]) > 1 and sc["op_kind"][1] == 0
-           and sc["op_k"][1] == 6)
     old = qsim.get_option(qsim.OPT_FOLD_INIT)
     try:
         for fold in (2, 1, 0):
             qsim.set_option(qsim.OPT_FOLD_INIT, fold)
+            # the schedule depends on the folded start it is priced with
+            sc = qsim.schedule(circ.n, circ.gates, qsim.C64 if dt == "c64" else qsim.C128, kmax=kmax,
+                               fuse_diag=True, skip_initial_h=True)
+            first_is_cluster = sc["op_kind"][0] == 0
+            two = (dt == "c64" and first_is_cluster and len(sc["op_kind"]) > 1 and sc["op_kind"][1] == 0
+                   and sc["op_k"][1] == 6 and sc["op_k"][0] <= 6)
             s = make_state(circ.n, dt)
             st = s.run_circuit(circ.gates, kmax=kmax, fuse_diag=True, skip_initial_h=True, record_timings=True)
             kinds = [r["kind"] for r in s.op_timings()]
@@ -742,7 +744,7 @@ def test_20q_depth25_per_gate_float64(seed):
     s2 = make_state(20, "c128")
     s2.run_circuit(circ.gates, kmax=5, fuse_diag=True)
     assert np.max(np.abs(s2.to_numpy() - ref)) <= 1e-12
-    for kmax in (5, 6):
+    for kmax in (5, 6, 7):
         s3 = make_state(20, "c64")
         st = s3.run_circuit(circ.gates, kmax=kmax, scheduler="learned", fuse_diag=True, skip_initial_h=True)
         assert_fp32_circuit(s3.to_numpy(), ref, st, kmax)
@@ -776,7 +778,7 @@ def test_permute_qubits(dt, case):
 
 
 @pytest.mark.parametrize("dt", ["c64", "c128"])
-@pytest.mark.parametrize("kmax", [4, 6])
+@pytest.mark.parametrize("kmax", [4, 6, 7])
 def test_map_qubits_matches_oracle(dt, kmax):
     """QSIM_OPT_MAP_QUBITS: the run applies relabelled gates from the uniform
     state and one permutation pass restores the order; the state (and the
@@ -847,7 +849,7 @@ def test_22q_full_circuit_float32():
     circ = supremacy_circuit(4, 6, 25, 11, drop=[(3, 5), (3, 4)])
     assert circ.n == 22
     ref = oracle.run(circ)
-    for opts in (dict(kmax=5, fuse_diag=True), dict(kmax=4), dict(kmax=6, fuse_diag=True)):
+    for opts in (dict(kmax=5, fuse_diag=True), dict(kmax=4), dict(kmax=6, fuse_diag=True), dict(kmax=7, fuse_diag=True)):
         s = make_state(22, "c64")
         st = s.run_circuit(circ.gates, **opts)
         assert_fp32_circuit(s.to_numpy(), ref, st, opts["kmax"])
@@ -873,6 +875,7 @@ def _product_amplitudes(circ, groups, idx):
 
 
 @pytest.mark.parametrize("dt,opts", [("c64", dict(kmax=5, fuse_diag=True)), ("c64", dict(kmax=6)),
+                                     ("c64", dict(kmax=7, scheduler="learned", fuse_diag=True, skip_initial_h=True)),
                                      ("c128", dict(kmax=5, fuse_diag=True)), ("c128", dict(scheduler="per_gate"))])
 def test_30q_product_state_sampled(dt, opts):
     """30 qubits in five independent 6-qubit groups interleaved across all
@@ -895,7 +898,8 @@ def test_30q_product_state_sampled(dt, opts):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("opts", [dict(kmax=6, scheduler="learned", fuse_diag=True, skip_initial_h=True),
+@pytest.mark.parametrize("opts", [dict(kmax=7, scheduler="learned", fuse_diag=True, skip_initial_h=True),
+                                  dict(kmax=6, scheduler="learned", fuse_diag=True, skip_initial_h=True),
                                   dict(kmax=5, fuse_diag=True)])
 def test_34q_product_state_sampled(opts):
     """34 qubits (the largest complex64 state: 128 GiB) in six independent
@@ -1000,10 +1004,11 @@ BENCH_FORM = dict(scheduler="learned", fuse_diag=True, skip_initial_h=True)
 
 
 @pytest.mark.parametrize("R,C,drop,dt,kmax,bar", [
+    (5, 6, (), "c64", 7, 1e-6),
     (5, 6, (), "c64", 6, 1e-6),
     (5, 6, (), "c128", 5, 1e-12),
-    (5, 7, ((4, 6),), "c64", 6, 1e-6),
-], ids=["30q-f32", "30q-f64", "34q-f32"])
+    (5, 7, ((4, 6),), "c64", 7, 1e-6),
+], ids=["30q-f32", "30q-f32-k6", "30q-f64", "34q-f32"])
 def test_mirror_bench_form(R, C, drop, dt, kmax, bar):
     """The depth-25 grid circuits followed by their inverse, run the way the
     benchmark runs them (learned schedule, diagonal epilogues, the leading H
