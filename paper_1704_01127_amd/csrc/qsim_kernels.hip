@@ -508,6 +508,53 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_gauss6(float2* __restric
 // floats 8 s .. 8 s + 7 (amplitudes 4 s .. 4 s + 3, re / im interleaved).
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
+// fp16 halves of two scaled floats, packed: H = (f16(x0 sc), f16(x1 sc)),
+// L = (f16(x0 sc - H.lo), f16(x1 sc - H.hi)), rounded to nearest even - the
+// arithmetic of (_Float16)(x * sc) and (_Float16)(x * sc - hi), four
+// mixed-precision FMAs per pair (checked bit for bit against that form; the
+// compiler's own code computed the high halves twice to pack them).
+__device__ __forceinline__ void split_pair_f16(float x0, float x1, float sc, uint32_t& H, uint32_t& L) {
+    __asm__("v_fma_mixlo_f16 %0, %2, %4, 0\n\t"
+            "v_fma_mixhi_f16 %0, %3, %4, 0\n\t"
+            "v_fma_mixlo_f16 %1, %2, %4, -%0 op_sel_hi:[0,0,1]\n\t"
+            "v_fma_mixhi_f16 %1, %3, %4, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+            : "=&v"(H), "=&v"(L)
+            : "v"(x0), "v"(x1), "v"(sc));
+}
+
+// The fp16 halves (hi, lo) of a lane's N floats of one column, scaled by the
+// power of two that puts the column's largest magnitude (over this lane and
+// its partner lane, lane ^ 32) just below 2^14: exact scaling, no fp16
+// overflow for any input, zero columns stay zero. Returns the exponent se
+// of that scale (the results are scaled back by 2^(-se) times the matrix's
+// own 2^-4). Float i of the lane is element i % 8 of xh / xl[i / 8].
+template <int N>
+__device__ __forceinline__ int split_halves(const float (&X)[N], half8 (&xh)[N / 8], half8 (&xl)[N / 8]) {
+    float mx = 0.0f;  // |x| is a free operand modifier of the max
+#pragma unroll
+    for (int i = 0; i < N; ++i) mx = fmaxf(mx, fabsf(X[i]));
+    const uint32_t mb = max(__float_as_uint(mx), (uint32_t)__shfl_xor((int)__float_as_uint(mx), 32));
+    const int e = (int)(mb >> 23) - 126;  // largest magnitude < 2^e
+    const int se = min(max(14 - e, -100), 100);
+    const float sc = __builtin_ldexpf(1.0f, se);
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int st = 0; st < N / 8; ++st) {
+        u32x4 h, l;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t a, b;
+            split_pair_f16(X[8 * st + 2 * q], X[8 * st + 2 * q + 1], sc, a, b);
+            h[q] = a;
+            l[q] = b;
+        }
+        xh[st] = __builtin_bit_cast(half8, h);
+        xl[st] = __builtin_bit_cast(half8, l);
+    }
+    return se;
+}
+
+
 // STATS: as in k_cluster_f32_mfma (sums of the stored amplitudes' p, p^2,
 // -p ln p into part, per work-group).
 template <bool LOWT, bool STATS = false>
@@ -542,23 +589,7 @@ __global__ __launch_bounds__(256, 2) void k_cluster_f32_split6(float2* __restric
     // split the column's amplitudes (scaled) into fp16 halves; returns the
     // factor that undoes the column and matrix scaling
     auto split = [&](const float (&X)[2 * HX], half8 (&xh)[S], half8 (&xl)[S]) -> float {
-        uint32_t mb = 0;  // largest magnitude (as bits: monotonic for non-negative floats)
-#pragma unroll
-        for (int i = 0; i < 2 * HX; ++i) mb = max(mb, __float_as_uint(X[i]) & 0x7fffffffu);
-        mb = max(mb, (uint32_t)__shfl_xor((int)mb, 32));  // the other half of the column
-        const int e = (int)(mb >> 23) - 126;               // largest magnitude < 2^e
-        const int se = min(max(14 - e, -100), 100);
-        const float sc = __builtin_ldexpf(1.0f, se);
-#pragma unroll
-        for (int st = 0; st < S; ++st)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float v = X[8 * st + i] * sc;
-                const _Float16 hi = (_Float16)v;
-                xh[st][i] = hi;
-                xl[st][i] = (_Float16)(v - (float)hi);
-            }
-        return __builtin_ldexpf(1.0f, -se - 4);
+        return __builtin_ldexpf(1.0f, -split_halves<2 * HX>(X, xh, xl) - 4);
     };
 
     float B[1][2 * HX];
@@ -791,17 +822,26 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
         const int e = (int)(mb >> 23) - 126;               // largest magnitude < 2^e
         const int se = min(max(14 - e, -100), 100);
         const float sc = __builtin_ldexpf(1.0f, se);
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+        for (int s = 0; s < S; ++s) {
+            u32x4 hr, lr, hi4, li4;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float vr = X[2 * (8 * s + i)] * sc, vi = X[2 * (8 * s + i) + 1] * sc;
-                const _Float16 hr = (_Float16)vr, hi = (_Float16)vi;
-                rh[s][i] = hr;
-                rl[s][i] = (_Float16)(vr - (float)hr);
-                ih[s][i] = hi;
-                il[s][i] = (_Float16)(vi - (float)hi);
+            for (int q = 0; q < 4; ++q) {  // amplitudes j, j + 1: halves q of the registers
+                const int j = 8 * s + 2 * q;
+                uint32_t a, b, c, d;
+                split_pair_f16(X[2 * j], X[2 * j + 2], sc, a, b);
+                split_pair_f16(X[2 * j + 1], X[2 * j + 3], sc, c, d);
+                hr[q] = a;
+                lr[q] = b;
+                hi4[q] = c;
+                li4[q] = d;
             }
+            rh[s] = __builtin_bit_cast(half8, hr);
+            rl[s] = __builtin_bit_cast(half8, lr);
+            ih[s] = __builtin_bit_cast(half8, hi4);
+            il[s] = __builtin_bit_cast(half8, li4);
+        }
         return __builtin_ldexpf(1.0f, -se - 4);
     };
     floatx16 ar[RB], ai[RB];
@@ -1533,24 +1573,8 @@ __global__ __launch_bounds__(WAVES * 64, 8 / WAVES) void k_cluster_f32_multi(flo
                     X[2 * j + 1] = v.y;
                 }
                 // fp16 halves, the column scaled by a power of two (shared by lanes p, p + 32)
-                uint32_t mb = 0;
-#pragma unroll
-                for (int i = 0; i < 2 * HX; ++i) mb = max(mb, __float_as_uint(X[i]) & 0x7fffffffu);
-                mb = max(mb, (uint32_t)__shfl_xor((int)mb, 32));
-                const int e = (int)(mb >> 23) - 126;
-                const int se = min(max(14 - e, -100), 100);
-                const float sc = __builtin_ldexpf(1.0f, se);
-                const float unscale = __builtin_ldexpf(1.0f, -se - 4);
                 half8 xh[S], xl[S];
-#pragma unroll
-                for (int st = 0; st < S; ++st)
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        const float v = X[8 * st + i] * sc;
-                        const _Float16 hi = (_Float16)v;
-                        xh[st][i] = hi;
-                        xl[st][i] = (_Float16)(v - (float)hi);
-                    }
+                const float unscale = __builtin_ldexpf(1.0f, -split_halves<2 * HX>(X, xh, xl) - 4);
                 floatx16 acc[RB];
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
@@ -1690,23 +1714,8 @@ __global__ __launch_bounds__(WAVES * 64, 1) void k_cluster_f32_pair10(float2* __
                 X[2 * j] = v.x;
                 X[2 * j + 1] = v.y;
             }
-            uint32_t mb = 0;
-#pragma unroll
-            for (int i = 0; i < 2 * HX; ++i) mb = max(mb, __float_as_uint(X[i]) & 0x7fffffffu);
-            mb = max(mb, (uint32_t)__shfl_xor((int)mb, 32));
-            const int e = (int)(mb >> 23) - 126;
-            const int se = min(max(14 - e, -100), 100);
-            const float sc = __builtin_ldexpf(1.0f, se);
             half8 xh[S], xl[S];
-#pragma unroll
-            for (int st = 0; st < S; ++st)
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const float v = X[8 * st + i] * sc;
-                    const _Float16 hi = (_Float16)v;
-                    xh[st][i] = hi;
-                    xl[st][i] = (_Float16)(v - (float)hi);
-                }
+            const int se = split_halves<2 * HX>(X, xh, xl);
             floatx16 acc[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
@@ -1965,23 +1974,8 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
         }
         }
         // fp16 halves of the scaled column (shared scale with lane p + 32)
-        uint32_t mb = 0;
-#pragma unroll
-        for (int i = 0; i < 2 * HX; ++i) mb = max(mb, __float_as_uint(X[i]) & 0x7fffffffu);
-        mb = max(mb, (uint32_t)__shfl_xor((int)mb, 32));
-        const int e = (int)(mb >> 23) - 126;
-        const int se = min(max(14 - e, -100), 100);
-        const float sc = __builtin_ldexpf(1.0f, se);
         half8 xh[S], xl[S];
-#pragma unroll
-        for (int st = 0; st < S; ++st)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float v = X[8 * st + i] * sc;
-                const _Float16 hi = (_Float16)v;
-                xh[st][i] = hi;
-                xl[st][i] = (_Float16)(v - (float)hi);
-            }
+        const int se = split_halves<2 * HX>(X, xh, xl);
         // the column is in registers: prefetch the next tile (issued here, the
         // peak register use is the halves + accumulators + the tile in flight)
         if constexpr (!FOLD) {
