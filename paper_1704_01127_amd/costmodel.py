@@ -53,13 +53,17 @@ def op_record_rows(recs, n, dtype_code):
 def cmd_record(args):
     import torch  # noqa: F401
     feats, ys, meta = [], [], []
+    if args.append:  # extend an earlier record file (its rows come first)
+        old = np.load(args.append, allow_pickle=False)
+        feats, ys, meta = list(old["x"]), list(old["y"]), [tuple(m) for m in old["meta"]]
     t_start = time.time()
-    for dt, ns in (("c64", [27, 28, 29, 30]), ("c128", [27, 28, 29, 30])):
+    sizes = [int(x) for x in args.n.split(",")]
+    kmaxes = [int(x) for x in args.kmax.split(",")]
+    for dt in args.dtypes.split(","):
         code = qsim.C64 if dt == "c64" else qsim.C128
         # 7-qubit clusters exist on complex64 only (complex128 runs cap k_max at 6)
-        configs = [dict(kmax=k, fuse_diag=fd) for k in ((2, 3, 4, 5, 6, 7) if dt == "c64" else (2, 3, 4, 5, 6))
-                   for fd in (False, True)]
-        for n in ns:
+        configs = [dict(kmax=k, fuse_diag=fd) for k in kmaxes if dt == "c64" or k <= 6 for fd in (False, True)]
+        for n in sizes:
             state = qsim.State(n, dt, kmax=7)
             for seed in range(args.seeds):
                 circ = workload(n, args.depth, seed)
@@ -225,6 +229,10 @@ def main(argv=None):
     r = sub.add_parser("record")
     r.add_argument("--seeds", type=int, default=10)
     r.add_argument("--depth", type=int, default=40)
+    r.add_argument("--n", default="27,28,29,30", help="state sizes")
+    r.add_argument("--dtypes", default="c64,c128")
+    r.add_argument("--kmax", default="2,3,4,5,6,7", help="k_max of the recorded schedules")
+    r.add_argument("--append", default=None, help="record file to extend")
     r.add_argument("--out", required=True)
     t = sub.add_parser("train")
     t.add_argument("--data", required=True)

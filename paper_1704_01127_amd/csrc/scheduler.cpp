@@ -199,25 +199,26 @@ int closure_size(const Dag& d, const std::vector<int>& head, uint64_t S) {
     const auto& G = *d.g;
     int h[64];
     for (uint64_t m = S; m; m &= m - 1) h[__builtin_ctzll(m)] = head[__builtin_ctzll(m)];
+    // taking a gate never makes another one unready, so the closure is the
+    // same in any order: a worklist of qubits whose queue head moved
     int cnt = 0;
-    for (bool prog = true; prog;) {
-        prog = false;
-        for (uint64_t m = S; m; m &= m - 1) {
-            const int q = __builtin_ctzll(m);
-            const auto& qq = d.queue[q];
-            while (h[q] < (int)qq.size()) {
-                const int gi = qq[h[q]];
-                if (d.mask[gi] & ~S) break;
-                bool at_head = true;
-                for (int j = 0; j < G[gi].nq && at_head; ++j) {
-                    const int p = G[gi].q[j];
-                    at_head = h[p] < (int)d.queue[p].size() && d.queue[p][h[p]] == gi;
-                }
-                if (!at_head) break;
-                for (int j = 0; j < G[gi].nq; ++j) h[G[gi].q[j]]++;
-                ++cnt;
-                prog = true;
+    for (uint64_t pending = S; pending;) {
+        const int q = __builtin_ctzll(pending);
+        pending &= pending - 1;
+        const auto& qq = d.queue[q];
+        while (h[q] < (int)qq.size()) {
+            const int gi = qq[h[q]];
+            const uint64_t gm = d.mask[gi];
+            if (gm & ~S) break;
+            bool at_head = true;
+            for (int j = 0; j < G[gi].nq && at_head; ++j) {
+                const int p = G[gi].q[j];
+                at_head = h[p] < (int)d.queue[p].size() && d.queue[p][h[p]] == gi;
             }
+            if (!at_head) break;
+            for (int j = 0; j < G[gi].nq; ++j) h[G[gi].q[j]]++;
+            ++cnt;
+            pending |= gm & ~(uint64_t(1) << q);
         }
     }
     return cnt;
@@ -433,14 +434,14 @@ void dense_sets(int n, const std::vector<SGate>& gates, const std::vector<char>&
         std::vector<uint64_t> next;
         for (uint64_t S : level) {
             uint64_t nb = 0;
-            for (int q = 0; q < n; ++q)
-                if (S >> q & 1) nb |= adj[q];
+            for (uint64_t m = S; m; m &= m - 1) nb |= adj[__builtin_ctzll(m)];
             nb &= ~S;
             int top = -1;
-            for (int q = 0; q < n; ++q)
-                if (nb >> q & 1) top = std::max(top, popc(adj[q] & S));
-            for (int q = 0; q < n; ++q)
-                if ((nb >> q & 1) && popc(adj[q] & S) == top) next.push_back(S | (uint64_t(1) << q));
+            for (uint64_t m = nb; m; m &= m - 1) top = std::max(top, popc(adj[__builtin_ctzll(m)] & S));
+            for (uint64_t m = nb; m; m &= m - 1) {
+                const int q = __builtin_ctzll(m);
+                if (popc(adj[q] & S) == top) next.push_back(S | (uint64_t(1) << q));
+            }
         }
         std::sort(next.begin(), next.end());
         next.erase(std::unique(next.begin(), next.end()), next.end());
@@ -449,8 +450,7 @@ void dense_sets(int n, const std::vector<SGate>& gates, const std::vector<char>&
     }
     auto edges = [&](uint64_t S) {
         int e = 0;
-        for (int q = 0; q < n; ++q)
-            if (S >> q & 1) e += popc(adj[q] & S);
+        for (uint64_t m = S; m; m &= m - 1) e += popc(adj[__builtin_ctzll(m)] & S);
         return e / 2;
     };
     int top = 0;
@@ -585,48 +585,6 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     // for kmax.
     const int k_lo = std::max(1, kmax - 2);
     const auto policy = o.parallel ? std::launch::async : std::launch::deferred;
-    // A narrower cap only adds passes: a cluster of kc qubits takes roughly
-    // kc / kmax of the gates of a full-width one, so a cap kc is worth building
-    // only when its clusters are predicted cheaper than that fraction of a
-    // full-width cluster's time (complex128: 6-qubit clusters are bound by the
-    // fp64 matrix cores). The predicted cost of a cluster of each width,
-    // averaged over low, middle, high and spread target sets, decides which
-    // caps (and the cost-trimmed schedule, which mixes widths) are built.
-    auto typical = [&](int k) {
-        int sets[4][kMaxK];
-        for (int j = 0; j < k; ++j) {
-            sets[0][j] = j;
-            sets[1][j] = n / 2 - k / 2 + j;
-            sets[2][j] = n - k + j;
-            sets[3][j] = k > 1 ? (int)((long)j * (n - 1) / (k - 1)) : 0;
-        }
-        double c = 0.0;
-        for (auto& q : sets) c += cost(k, q, 0);
-        return c / 4;
-    };
-    std::vector<char> use_cap(kmax + 1, 1);
-    if (n >= kmax + 2) {
-        const double full = typical(kmax);
-        for (int kc = k_lo; kc < kmax; ++kc) use_cap[kc] = typical(kc) < full * kc / kmax;
-    }
-    // set families: kmax's are at hand; a narrower cap's are found inside
-    // its tasks (in parallel), one task per (cap, slack)
-    struct Fam {
-        int k, slack;
-    };
-    std::vector<Fam> fam;
-    if (o.cluster_sets)
-        for (int kc = std::max(2, k_lo); kc <= kmax; ++kc) {
-            if (!use_cap[kc]) continue;
-            if (kc == kmax) {
-                if (!sets0.empty()) fam.push_back({kc, 0});
-                if (!sets1.empty()) fam.push_back({kc, 1});
-            } else {
-                fam.push_back({kc, 0});
-                fam.push_back({kc, 1});
-            }
-        }
-    // each task builds a candidate and predicts its total (in parallel)
     using Cand = std::pair<std::vector<SOp>, double>;
     auto priced = [&](std::vector<SOp> ops) {
         double total = 0.0, c0 = 0.0, c1 = 0.0;
@@ -643,42 +601,72 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
         if (fk == 1) total -= (1.0 - kFold1Share) * c0;
         return Cand(std::move(ops), total);
     };
-    std::vector<std::future<Cand>> futs;
+    // A narrower cap usually only adds passes, so its set families and the
+    // cost-trimmed schedule (which mixes widths) count only where the cap's
+    // plain greedy schedule is predicted cheaper than the full-width one: a
+    // circuit whose gates do not pack into full-width clusters (or
+    // complex128, whose 6-qubit clusters are bound by the fp64 matrix cores)
+    // gets them, while prediction noise alone cannot make a narrower cap win
+    // on the other circuits. All candidates are started together (one round
+    // of latency); the gated ones are read only where their cap qualifies.
+    struct Task {
+        int gate;  // 0: always a candidate; kc: only where cap kc qualifies
+        std::future<Cand> fut;
+    };
+    std::vector<Task> tasks;
     for (int kc = k_lo; kc <= kmax; ++kc)
-        if (use_cap[kc])
-            futs.push_back(std::async(policy, [&, kc]() {
-                return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag));
-            }));
+        tasks.push_back({0, std::async(policy, [&, kc]() {
+                             return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag));
+                         })});
     if (first_caps > 1) {  // the widest cap after a 6-qubit start, with and without the candidate sets
-        futs.push_back(std::async(policy, [&]() {
-            return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, nullptr, 6));
-        }));
+        tasks.push_back({0, std::async(policy, [&]() {
+                             return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr,
+                                                      nullptr, 6));
+                         })});
         for (const std::vector<uint64_t>* fs : {&sets0, &sets1})
             if (!fs->empty())
-                futs.push_back(std::async(policy, [&, fs]() {
-                    return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, fs, 6));
-                }));
+                tasks.push_back({0, std::async(policy, [&, fs]() {
+                                     return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag,
+                                                              nullptr, fs, 6));
+                                 })});
     }
-    if (kmax > 1 && use_cap[kmax - 1])
-        futs.push_back(std::async(policy, [&]() {
-            return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost));
-        }));
-    for (size_t f = 0; f < fam.size(); ++f)
-        futs.push_back(std::async(policy, [&, f]() {
-            const Fam& F = fam[f];
-            if (F.k == kmax)
-                return priced(greedy_ops(n, gates, S.dropped, S.n_applied, F.k, o.fuse_diag, nullptr,
-                                         F.slack ? &sets1 : &sets0));
-            std::vector<uint64_t> a, b;
-            dense_sets(n, gates, S.dropped, F.k, a, b);
-            const std::vector<uint64_t>& sets = F.slack ? b : a;
-            if (sets.empty()) return Cand(std::vector<SOp>(), -1.0);  // no such family: not a candidate
-            return priced(greedy_ops(n, gates, S.dropped, S.n_applied, F.k, o.fuse_diag, nullptr, &sets));
-        }));
+    if (kmax > 1)
+        tasks.push_back({kmax - 1, std::async(policy, [&]() {
+                             return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost));
+                         })});
+    // set families: kmax's are at hand; a narrower cap's are found inside
+    // its tasks, one task per (cap, slack)
+    if (o.cluster_sets)
+        for (int kc = std::max(2, k_lo); kc <= kmax; ++kc)
+            for (int slack = 0; slack < 2; ++slack) {
+                if (kc == kmax) {
+                    const std::vector<uint64_t>* fs = slack ? &sets1 : &sets0;
+                    if (fs->empty()) continue;
+                    tasks.push_back({0, std::async(policy, [&, fs]() {
+                                         return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax,
+                                                                  o.fuse_diag, nullptr, fs));
+                                     })});
+                } else {
+                    tasks.push_back({kc, std::async(policy, [&, kc, slack]() {
+                                         std::vector<uint64_t> a, b;
+                                         dense_sets(n, gates, S.dropped, kc, a, b);
+                                         const std::vector<uint64_t>& sets = slack ? b : a;
+                                         if (sets.empty()) return Cand(std::vector<SOp>(), -1.0);  // no such family
+                                         return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag,
+                                                                  nullptr, &sets));
+                                     })});
+                }
+            }
+    // the plain schedules come first: their prices decide which caps qualify
+    std::vector<Cand> cands;
+    for (int kc = k_lo; kc <= kmax; ++kc) cands.push_back(tasks[kc - k_lo].fut.get());
+    std::vector<char> use_cap(kmax + 1, 1);
+    for (int kc = k_lo; kc < kmax; ++kc) use_cap[kc] = cands[kc - k_lo].second < cands[kmax - k_lo].second;
+    for (size_t t = kmax - k_lo + 1; t < tasks.size(); ++t)
+        if (tasks[t].gate == 0 || use_cap[tasks[t].gate]) cands.push_back(tasks[t].fut.get());
     double best_cost = 0.0;
     bool have = false;
-    for (size_t c = 0; c < futs.size(); ++c) {
-        Cand cand = futs[c].get();
+    for (Cand& cand : cands) {
         if (cand.second < 0) continue;
         if (!have || cand.second < best_cost) {
             best_cost = cand.second;
