@@ -251,7 +251,8 @@ const char* qsim_last_error(void);
  * of the second for kind 8 -
  * or the gate's qubits, -1 padded), op_epi (flags of a cluster: bit 0 = applies diagonal
  * gates while storing, bit 1 = LDS-staged kernel variant, bit 2 = matrix-core
- * kernel, bit 3 = also sums the reductions, bits 8-15 = the number of diagonal
+ * kernel, bit 3 = also sums the reductions, bit 4 = kind 8 in its table form
+ * (QSIM_OPT_FOLD_TABLE), bits 8-15 = the number of diagonal
  * gates the scheduler attached to it, capped at 255 - the epilogue size the
  * learned cost model is given) and ms (milliseconds). Arrays of cap entries (any may be NULL);
  * *n_ops receives the count. Synchronises the stream. */
@@ -286,7 +287,17 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * instead of an initialisation pass and a cluster pass; 2 also takes in the
  * second op when it is a 6-qubit cluster on a complex64 state: its inputs are
  * computed from that closed form instead of read, so one write-only pass
- * stands for three; 0 keeps them apart. QSIM_OPT_PAIR
+ * stands for three; 0 keeps them apart. QSIM_OPT_FOLD_TABLE (default 1):
+ * with QSIM_OPT_FOLD_INIT 2, the second cluster's input column is w (the
+ * first cluster applied to the uniform vector) at an index that varies over
+ * the rows only through the qubits both clusters share, with the signs of the
+ * first cluster's diagonal gates that couple a column qubit to a row. When at
+ * most 2 qubits are shared and 2^(shared + sign-flipped rows) <= 128, the
+ * second cluster's outputs for every such (shared pattern, sign mask) are
+ * computed once, in float64, into a table of at most 64 KiB, and the
+ * write-only pass combines at most 4 of its rows per column instead of
+ * multiplying the column on the matrix cores; 0 always multiplies.
+ * QSIM_OPT_PAIR
  * (default 0): on complex64 states of >= 11 qubits, two consecutive clusters
  * of <= 5 qubits are applied in one pass over the state (their qubits fit one
  * tile held in LDS; fp16 matrix cores on operand halves); 2 sends every such
@@ -338,7 +349,8 @@ typedef enum {
     QSIM_OPT_CLUSTER_SETS = 9,
     QSIM_OPT_BATCH_ORDER = 10,
     QSIM_OPT_CHECK_UNITARY = 11,
-    QSIM_OPT_MAP_QUBITS = 12
+    QSIM_OPT_MAP_QUBITS = 12,
+    QSIM_OPT_FOLD_TABLE = 13
 } qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);

@@ -73,6 +73,7 @@ int g_batch_pad = 0;
 int g_batch_item_tiles = 128;
 int g_k6_kernel = 2;
 int g_fold_init = 2;
+int g_fold_table = 1;
 int g_pair = 0;
 int g_pair_tile = 11;
 int g_cluster_sets = 1;
@@ -249,6 +250,8 @@ struct Chunk {
         bool stats;      // kind 0: also sum p, p^2, -p ln p of the stored state (the run's last op)
         int n_epi;       // diagonal gates the scheduler attached to the cluster (its epilogue)
         int variant;     // kind 0: matrix-core kernel variant chosen by the learned model, -1: the library's rule
+        int omask, rmask;  // kind 8: the table form's shared and sign-flipped rows, omask -1: matrix cores
+        int slot3;         // kind 8 table form: the table's slot
     };
     std::vector<Item> items;
     int slots_used = 0;
@@ -336,7 +339,7 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
             r.k = it.geom.k;
             for (int j = 0; j < it.geom.k; ++j) r.qubits[j] = it.geom.t[j];
             r.flags = (it.epi >= 0 ? 1 : 0) | (variant == 1 ? 2 : 0) | (it.layout != LAYOUT_PLAIN ? 4 : 0) |
-                      (it.stats ? 8 : 0) | (std::min(it.n_epi, 255) << 8);
+                      (it.stats ? 8 : 0) | (it.kind == 8 && it.omask >= 0 ? 16 : 0) | (std::min(it.n_epi, 255) << 8);
         } else if (it.kind >= 2) {
             r.k = it.kind == 4 ? 2 : 1;
             r.qubits[0] = it.q0;
@@ -366,7 +369,8 @@ qsim_status flush(qsim_state_s* s, Chunk& c) {
                 break;
             case 8:
                 e = launch_fold2(s->psi, it.geom, mats + it.slot * sb, it.epi >= 0 ? epis + it.epi : nullptr,
-                                 it.epi2 >= 0 ? epis + it.epi2 : nullptr, it.geom2, mats + it.slot2 * sb, s->st);
+                                 it.epi2 >= 0 ? epis + it.epi2 : nullptr, it.geom2, mats + it.slot2 * sb, it.omask,
+                                 it.rmask, it.omask >= 0 ? mats + it.slot3 * sb : nullptr, s->st);
                 break;
             case 7: {
                 int32_t t[2][5];
@@ -478,7 +482,7 @@ qsim_status add_fold2(qsim_state_s* s, Chunk& c, const SOp& A, const SOp& B, con
                         align256((c.bgates.size() + ng) * sizeof(BuildGate)) +
                         align256((c.dense.size() + dense_need) * sizeof(double)) +
                         align256((c.epis.size() + 2) * sizeof(EpiDesc));
-    if (c.slots_used + 2 > kSlots || need > kDescBytes) {
+    if (c.slots_used + 3 > kSlots || need > kDescBytes) {
         qsim_status r = flush(s, c);
         if (r != QSIM_OK) return r;
     }
@@ -513,6 +517,21 @@ qsim_status add_fold2(qsim_state_s* s, Chunk& c, const SOp& A, const SOp& B, con
     for (int gi : B.members) c.bgates.push_back(to_build_gate(gates[gi], posB, c.dense));
     if (qsim_status r = split_epilogue(posB, gates, B.epi, c.bgates, c.dense, e2)) return r;
     bb.n_gates = (int)c.bgates.size() - bb.gate0;
+    // B's inputs vary with its rows shared with A (omask) and A's epilogue
+    // signs on its rows (rmask): with few of these, B's outputs for each
+    // pattern go into a table (B then built in plain complex128)
+    int omask = 0, rmask = 0;
+    for (int m = 0; m < B.k; ++m)
+        if (posA[B.qubits[m]] >= 0) omask |= 1 << m;
+    for (int i = 0; i < e1.n_mix; ++i) rmask |= 1 << e1.mix[i][0];
+    const int tab_bits = __builtin_popcount((unsigned)omask) + __builtin_popcount((unsigned)rmask);
+    const bool table = g_fold_table && B.k == 6 && __builtin_popcount((unsigned)omask) <= 2 &&
+                       (1 << tab_bits) <= kFoldTabRows && sb >= (int64_t(512) << tab_bits) &&
+                       sb >= (int64_t)matrix_bytes(6, LAYOUT_PLAIN, true);
+    if (table) {
+        bb.is_double = 1;
+        bb.layout = LAYOUT_PLAIN;
+    }
     push_build(c, bb);
     Chunk::Item it;
     std::memset(&it, 0, sizeof(it));
@@ -528,6 +547,12 @@ qsim_status add_fold2(qsim_state_s* s, Chunk& c, const SOp& A, const SOp& B, con
     it.geom2.ncols = uint64_t(1) << (s->n - A.k);
     it.slot = slotB;
     it.slot2 = slotA;
+    it.omask = it.rmask = -1;
+    if (table) {
+        it.omask = omask;
+        it.rmask = rmask;
+        it.slot3 = c.slots_used++;
+    }
     it.epi = it.epi2 = -1;
     if (e2.n_cc || e2.n_mix || e2.n_ph) {
         it.epi = (int)c.epis.size();
@@ -704,7 +729,8 @@ OpCostFn qsim::api::cost_fn(const qsim_run_opts* o, int n, bool dbl) {
 // its fold / fold2 conditions), for the scheduler's pricing.
 int qsim::api::fold_start_for(bool dbl, int n) {
     if (!g_fold_init) return 0;
-    return (g_fold_init == 2 && !dbl && cluster_layout(false, 6, n) == LAYOUT_SPLIT16F) ? 2 : 1;
+    if (g_fold_init == 2 && !dbl && cluster_layout(false, 6, n) == LAYOUT_SPLIT16F) return g_fold_table ? 3 : 2;
+    return 1;
 }
 
 SchedOpts qsim::api::to_sched_opts(const qsim_run_opts* o) {
@@ -1140,6 +1166,11 @@ qsim_status qsim_set_option(int option, int value) {
         g_fold_init = value;
         return QSIM_OK;
     }
+    if (option == QSIM_OPT_FOLD_TABLE) {
+        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "fold_table must be 0 or 1");
+        g_fold_table = value;
+        return QSIM_OK;
+    }
     if (option == QSIM_OPT_PAIR_TILE) {
         if (value != 10 && value != 11) return fail(QSIM_E_INVALID, "pair tile bits must be 10 or 11");
         g_pair_tile = value;
@@ -1210,6 +1241,7 @@ int qsim_get_option(int option) {
     if (option == QSIM_OPT_BATCH_ITEM_TILES) return g_batch_item_tiles;
     if (option == QSIM_OPT_K6_KERNEL) return g_k6_kernel;
     if (option == QSIM_OPT_FOLD_INIT) return g_fold_init;
+    if (option == QSIM_OPT_FOLD_TABLE) return g_fold_table;
     if (option == QSIM_OPT_PAIR) return g_pair;
     if (option == QSIM_OPT_PAIR_TILE) return g_pair_tile;
     if (option == QSIM_OPT_CLUSTER_SETS) return g_cluster_sets;

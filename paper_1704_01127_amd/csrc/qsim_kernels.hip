@@ -1796,9 +1796,25 @@ struct FoldIn {
     int t1[6];        // the first cluster's qubits
     int k1;
     c_epi* epi1;      // the first epilogue relative to this cluster's targets, or null
+    // table form (FOLD 2): the second cluster's outputs split by the row bits
+    // it shares with the first cluster (sigma: their pattern) and by the
+    // first epilogue's row signs w. Row sigma + Wc[w] of Y (kFoldRow float2
+    // each, in LDS) holds M2 applied to the sign vector of w restricted to
+    // the rows of pattern sigma; a column's outputs are the sum over sigma of
+    // W[ic | iys[sigma]] times that row.
+    const float2* Y;
+    const int* Wc;  // per row-sign mask w: its compressed index << (shared bits)
+    int no;         // patterns sigma: 2^(shared row bits), at most 4
+    int iys[4];     // w index of each pattern's shared rows
 };
+// LDS row of one table pattern: 64 outputs and a 16-byte pad, so that the
+// rows of different patterns start on different banks
+constexpr int kFoldRow = 66;
 
-template <bool LOWT, bool FOLD = false>
+// FOLD: 0 the tile is loaded; 1 the column's inputs are computed from the
+// first cluster's closed form and multiplied on the matrix cores; 2 the
+// column's outputs are combined from the table of FoldIn::Y.
+template <bool LOWT, int FOLD = 0>
 __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const half8* Ah, const half8* Al, float2* L,
                                               c_epi* __restrict__ epi, const StageGeom& sg, uint64_t tile,
                                               uint64_t tile_end, uint64_t stride, const FoldIn* fin = nullptr) {
@@ -1811,7 +1827,7 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
     vf4* L4 = reinterpret_cast<vf4*>(L);
     bool has_epi = epi != nullptr;
     bool has_ph = has_epi && epi->n_ph > 0;
-    if constexpr (FOLD) {
+    if constexpr (FOLD != 0) {
         has_epi = has_epi || fin->epi1 != nullptr;
         has_ph = has_ph || (fin->epi1 != nullptr && fin->epi1->n_ph > 0);
     }
@@ -1877,7 +1893,7 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
     uint32_t l1s = 0, l1w = 0, l2s = 0, l2w = 0, t1b = 0, t2b = 0;
     double l1r = 1.0, l1i = 0.0, l2r = 1.0, l2i = 0.0, t1r = 1.0, t1i = 0.0, t2r = 1.0, t2i = 0.0;
     int icl = 0, it = 0;
-    if constexpr (FOLD) {
+    if constexpr (FOLD != 0) {
 #pragma unroll
         for (int b = 0; b < C; ++b) colmask |= uint64_t(1) << sg.tb[sg.cpos[b]];
         if (fin->epi1 != nullptr) epi_lane_part(fin->epi1, cbits, colmask, l1s, l1w, l1r, l1i);
@@ -1891,7 +1907,7 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
 #pragma unroll
         for (int i = 0; i < NL; ++i) R[i] = *reinterpret_cast<const g_vf4*>(gpsi + ((t0 | ioff(i)) | lane_off));
     };
-    if constexpr (!FOLD) {
+    if constexpr (FOLD == 0) {
         load_tile(tile_base<NT>(tile, sg));
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_waitcnt(0);
@@ -1906,7 +1922,7 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
         asm volatile("" : "+s"(cmask[0]), "+s"(cmask[1]), "+s"(cmask[2]), "+s"(cmask[3]));
         float X[2 * HX];
         ColFactor<float> f1{0u, 0u, 1.0f, 0.0f}, f2{0u, 0u, 1.0f, 0.0f};
-        if constexpr (FOLD) {
+        if constexpr (FOLD != 0) {
             // the column's inputs from the closed form: w at the first cluster's
             // index (its qubits among the column bits, then among the row bits),
             // negated where a gate of the first epilogue couples a row bit with
@@ -1933,17 +1949,40 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
                 f2 = epi_combine((uint32_t)__builtin_amdgcn_readlane((int)t2b, sl), readlane_f64(t2r, sl),
                                  readlane_f64(t2i, sl), l2s, l2w, l2r, l2i, p);
             ++it;
-            const int yh = h ? fin->ymask[K - 1] : 0;
+            if constexpr (FOLD == 1) {
+                const int yh = h ? fin->ymask[K - 1] : 0;
 #pragma unroll
-            for (int j = 0; j < HX; ++j) {
-                int iy = yh;
+                for (int j = 0; j < HX; ++j) {
+                    int iy = yh;
 #pragma unroll
-                for (int b = 0; b < K - 1; ++b)
-                    if ((j >> b) & 1) iy |= fin->ymask[b];
-                const float2 v = fin->W[ic | iy];
-                const bool neg = (__popc(((uint32_t)j | h5) & f1.w) & 1u) != 0;
-                X[2 * j] = neg ? -v.x : v.x;
-                X[2 * j + 1] = neg ? -v.y : v.y;
+                    for (int b = 0; b < K - 1; ++b)
+                        if ((j >> b) & 1) iy |= fin->ymask[b];
+                    const float2 v = fin->W[ic | iy];
+                    const bool neg = (__popc(((uint32_t)j | h5) & f1.w) & 1u) != 0;
+                    X[2 * j] = neg ? -v.x : v.x;
+                    X[2 * j + 1] = neg ? -v.y : v.y;
+                }
+            } else {
+                // its half of the outputs (rows j | h << 5): the table rows of
+                // its row-sign mask, weighted by w at its shared-row patterns
+                const int pb = fin->Wc[f1.w & 63u];
+#pragma unroll
+                for (int j = 0; j < 2 * HX; ++j) X[j] = 0.0f;
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp) {
+                    if (sp < fin->no) {
+                        const float2 a = fin->W[ic | fin->iys[sp]];
+                        const vf4* row = reinterpret_cast<const vf4*>(fin->Y + (pb + sp) * kFoldRow + h * HX);
+#pragma unroll
+                        for (int q = 0; q < HX / 2; ++q) {
+                            const vf4 v = row[q];
+                            X[4 * q] = fmaf(a.x, v.x, fmaf(-a.y, v.y, X[4 * q]));
+                            X[4 * q + 1] = fmaf(a.x, v.y, fmaf(a.y, v.x, X[4 * q + 1]));
+                            X[4 * q + 2] = fmaf(a.x, v.z, fmaf(-a.y, v.w, X[4 * q + 2]));
+                            X[4 * q + 3] = fmaf(a.x, v.w, fmaf(a.y, v.z, X[4 * q + 3]));
+                        }
+                    }
+                }
             }
         } else {
         // tile -> LDS, half by half; each lane reads its column in its half
@@ -1973,46 +2012,48 @@ __device__ __forceinline__ void split6s_tiles(g_float2* __restrict__ gpsi, const
             wave_lds_fence();
         }
         }
-        // fp16 halves of the scaled column (shared scale with lane p + 32)
-        half8 xh[S], xl[S];
-        const int se = split_halves<2 * HX>(X, xh, xl);
-        // the column is in registers: prefetch the next tile (issued here, the
-        // peak register use is the halves + accumulators + the tile in flight)
-        if constexpr (!FOLD) {
-            const uint64_t nxt = tile + stride < last ? tile + stride : last;
-            __builtin_amdgcn_sched_barrier(0);
-            load_tile(tile_base<NT>(nxt, sg));
-            __builtin_amdgcn_sched_barrier(0);
+        if constexpr (FOLD != 2) {
+            // fp16 halves of the scaled column (shared scale with lane p + 32)
+            half8 xh[S], xl[S];
+            const int se = split_halves<2 * HX>(X, xh, xl);
+            // the column is in registers: prefetch the next tile (issued here, the
+            // peak register use is the halves + accumulators + the tile in flight)
+            if constexpr (FOLD == 0) {
+                const uint64_t nxt = tile + stride < last ? tile + stride : last;
+                __builtin_amdgcn_sched_barrier(0);
+                load_tile(tile_base<NT>(nxt, sg));
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            floatx16 acc[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[rb][i] = 0.0f;
+            int aoff = lane;
+            asm volatile("" : "+v"(aoff));  // keep the matrix reads inside the loop (not in registers)
+#pragma unroll
+            for (int st = 0; st < S; ++st)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const half8 ah = Ah[(rb * S + st) * 64 + aoff];
+                    const half8 al = Al[(rb * S + st) * 64 + aoff];
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xl[st], acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, xh[st], acc[rb], 0, 0, 0);
+                    acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xh[st], acc[rb], 0, 0, 0);
+                }
+            const float unscale = __builtin_ldexpf(1.0f, -se - 4);
+#pragma unroll
+            for (int j = 0; j < 2 * HX; ++j) X[j] = acc[j / 16][j % 16] * unscale;
         }
         const uint64_t tb0 = tile_base<NT>(tile, sg);
-        floatx16 acc[RB];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) acc[rb][i] = 0.0f;
-        int aoff = lane;
-        asm volatile("" : "+v"(aoff));  // keep the matrix reads inside the loop (not in registers)
-#pragma unroll
-        for (int st = 0; st < S; ++st)
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                const half8 ah = Ah[(rb * S + st) * 64 + aoff];
-                const half8 al = Al[(rb * S + st) * 64 + aoff];
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xl[st], acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, xh[st], acc[rb], 0, 0, 0);
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, xh[st], acc[rb], 0, 0, 0);
-            }
-        const float unscale = __builtin_ldexpf(1.0f, -se - 4);
-#pragma unroll
-        for (int j = 0; j < 2 * HX; ++j) X[j] = acc[j / 16][j % 16] * unscale;
         if (has_epi) {
             ColFactor<float> f{0u, 0u, 1.0f, 0.0f};
-            if constexpr (FOLD) {
+            if constexpr (FOLD != 0) {
                 f = f2;
             } else {
                 if (epi != nullptr) f = col_factor<float>(epi, tb0 | cbits);
             }
-            if constexpr (FOLD) {  // the first epilogue's column-only sign and phase
+            if constexpr (FOLD != 0) {  // the first epilogue's column-only sign and phase
                 f.sgn ^= f1.sgn;
                 const float r = f.cr * f1.cr - f.ci * f1.ci;
                 f.ci = f.cr * f1.ci + f.ci * f1.cr;
@@ -2119,8 +2160,111 @@ __global__ __launch_bounds__(512, 1) void k_fold2_f32(float2* __restrict__ psi, 
         fin.ymask[m2] = b;
     }
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    split6s_tiles<LOWT, true>((g_float2*)psi, Ah, Al, Ls[w], (c_epi*)epi2, sg, (uint64_t)xcd_block() * WAVES + w,
+    split6s_tiles<LOWT, 1>((g_float2*)psi, Ah, Al, Ls[w], (c_epi*)epi2, sg, (uint64_t)xcd_block() * WAVES + w,
                               ntiles, (uint64_t)gridDim.x * WAVES, &fin);
+}
+
+// Table form: the second cluster's inputs are x[r] = w[ic | iy(r)] s(r) -
+// w at the first cluster's index (ic from the column bits, iy from the rows
+// the two clusters share), s the first epilogue's row signs. Split by the
+// pattern sigma of the shared rows, M2 x = sum over sigma of
+// w[ic | iy(sigma)] M2 (s restricted to the rows of pattern sigma), and s is
+// fixed by the mask of its sign-flipped rows. One work-group per (sigma,
+// compressed mask) forms M2 times that signed indicator in float64; the pass
+// below weights and sums its rows per column.
+struct FoldTabArgs {
+    const double2* M2;  // second cluster: plain complex128 64 x 64, row-major
+    int32_t omask;      // rows (second cluster's target bits) shared with the first cluster
+    int32_t rmask;      // rows the first epilogue's mixed terms sign-flip
+};
+
+__device__ __forceinline__ int pext6(int v, int mask) {
+    int o = 0, k = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if ((mask >> b) & 1) o |= ((v >> b) & 1) << k++;
+    return o;
+}
+__device__ __forceinline__ int pdep6(int v, int mask) {
+    int o = 0, k = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        if ((mask >> b) & 1) o |= ((v >> k++) & 1) << b;
+    return o;
+}
+
+__global__ __launch_bounds__(64) void k_fold2_table(float2* __restrict__ Y, FoldTabArgs a) {
+    __shared__ double x[64];
+    const int t = threadIdx.x;
+    const int no = __popc(a.omask);
+    const int P = blockIdx.x;
+    const int sigma = P & ((1 << no) - 1);
+    const int w = pdep6(P >> no, a.rmask);
+    x[t] = pext6(t, a.omask) != sigma ? 0.0 : ((__popc(t & w) & 1) ? -1.0 : 1.0);
+    __syncthreads();
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < 64; ++s) {
+        const double2 m = a.M2[t * 64 + s];
+        re = fma(m.x, x[s], re);
+        im = fma(m.y, x[s], im);
+    }
+    Y[P * 64 + t] = make_float2((float)re, (float)im);
+}
+
+template <bool LOWT>
+__global__ __launch_bounds__(512, 1) void k_fold2t_f32(float2* __restrict__ psi, const float2* __restrict__ Yg,
+                                                       const EpiDesc* __restrict__ epi2,
+                                                       const EpiDesc* __restrict__ epi1, StageGeom sg, Fold2Args f,
+                                                       FoldTabArgs a, uint64_t ntiles) {
+    constexpr int WAVES = 8;
+    __shared__ float2 Y[kFoldTabRows * kFoldRow];
+    __shared__ float2 Ls[WAVES][1024];
+    __shared__ float2 W[64];
+    __shared__ int Wc[64];
+    const int no = __popc(a.omask);
+    // the table into LDS, rows padded to kFoldRow
+    const int nq = 32 << (no + __popc(a.rmask));  // 16-byte pieces
+    for (int i = (int)threadIdx.x; i < nq; i += (int)blockDim.x)
+        reinterpret_cast<vf4*>(Y + (i >> 5) * kFoldRow)[i & 31] = reinterpret_cast<const vf4*>(Yg)[i];
+    if ((int)threadIdx.x < 64) {
+        W[threadIdx.x] = make_float2(0.0f, 0.0f);
+        Wc[threadIdx.x] = pext6((int)threadIdx.x, a.rmask) << no;
+    }
+    __syncthreads();
+    row_sums(f.M1, 1 << f.k1, f.amp, W);  // w: the first cluster applied to the uniform vector
+    __syncthreads();
+    FoldIn fin;
+    fin.W = W;
+    fin.k1 = f.k1;
+    fin.epi1 = (c_epi*)epi1;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) fin.t1[m] = f.t1[m];
+    int ymask[6];
+#pragma unroll
+    for (int m2 = 0; m2 < 6; ++m2) {
+        const int q = sg.tb[sg.tpos[m2]];
+        int b = 0;
+#pragma unroll
+        for (int m1 = 0; m1 < 6; ++m1)
+            if (m1 < f.k1 && f.t1[m1] == q) b = 1 << m1;
+        ymask[m2] = b;
+        fin.ymask[m2] = b;
+    }
+    fin.Y = Y;
+    fin.Wc = Wc;
+    fin.no = 1 << no;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int rows = pdep6(s, a.omask);
+        int iy = 0;
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+            if ((rows >> m) & 1) iy |= ymask[m];
+        fin.iys[s] = iy;
+    }
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    split6s_tiles<LOWT, 2>((g_float2*)psi, nullptr, nullptr, Ls[w], (c_epi*)epi2, sg, (uint64_t)xcd_block() * WAVES + w,
+                           ntiles, (uint64_t)gridDim.x * WAVES, &fin);
 }
 
 // ------------------------------------------------------------ batched persistent launch
@@ -3146,7 +3290,8 @@ hipError_t launch_multi(void* psi, int n, int m, const int32_t (*targets)[5], co
 }
 
 hipError_t launch_fold2(void* psi, const ClusterGeom& g2, const void* mat2, const EpiDesc* epi2, const EpiDesc* epi1,
-                        const ClusterGeom& g1, const void* mat1, hipStream_t st) {
+                        const ClusterGeom& g1, const void* mat1, int omask, int rmask, void* table,
+                        hipStream_t st) {
     if (g2.k != 6 || g2.n < 11 || g1.k < 1 || g1.k > 6) return hipErrorInvalidValue;
     Fold2Args f;
     std::memset(&f, 0, sizeof(f));
@@ -3157,6 +3302,23 @@ hipError_t launch_fold2(void* psi, const ClusterGeom& g2, const void* mat2, cons
     const StageGeom sg = make_stage_geom(g2, 5, 7);
     const uint64_t tiles = g2.ncols >> 5;
     const unsigned grid = grid_for(tiles, 8, kStagedGrid);
+    if (omask >= 0) {
+        const int no = __builtin_popcount((unsigned)omask), nr = __builtin_popcount((unsigned)rmask);
+        if (table == nullptr || omask > 63 || rmask < 0 || rmask > 63 || no > 2 || (1 << (no + nr)) > kFoldTabRows)
+            return hipErrorInvalidValue;
+        FoldTabArgs a;
+        a.M2 = reinterpret_cast<const double2*>(mat2);
+        a.omask = omask;
+        a.rmask = rmask;
+        hipLaunchKernelGGL(k_fold2_table, dim3(1u << (no + nr)), dim3(64), 0, st, (float2*)table, a);
+        if (g2.t[0] == 0)
+            hipLaunchKernelGGL(k_fold2t_f32<true>, dim3(grid), dim3(512), 0, st, (float2*)psi, (const float2*)table,
+                               epi2, epi1, sg, f, a, tiles);
+        else
+            hipLaunchKernelGGL(k_fold2t_f32<false>, dim3(grid), dim3(512), 0, st, (float2*)psi,
+                               (const float2*)table, epi2, epi1, sg, f, a, tiles);
+        return hipGetLastError();
+    }
     if (g2.t[0] == 0)
         hipLaunchKernelGGL(k_fold2_f32<true>, dim3(grid), dim3(512), 0, st, (float2*)psi, (const half8*)mat2, epi2,
                            epi1, sg, f, tiles);

@@ -466,16 +466,33 @@ void dense_sets(int n, const std::vector<SGate>& gates, const std::vector<char>&
 
 // The start a schedule gets from a folded initialisation (SchedOpts::
 // fold_start): 2 when its first two ops are clusters of <= 6 and 6 qubits
-// (one write-only pass for both), 1 when its first op is a cluster, else 0.
-int fold_kind(const std::vector<SOp>& ops, int fold) {
+// (one write-only pass for both), 3 when that start takes the table form, 1
+// when its first op is a cluster, else 0.
+int fold_kind(const std::vector<SOp>& ops, const std::vector<SGate>& gates, int fold) {
     if (fold <= 0 || ops.empty() || ops[0].kind != OP_CLUSTER) return 0;
-    if (fold >= 2 && ops.size() >= 2 && ops[0].k <= 6 && ops[1].kind == OP_CLUSTER && ops[1].k == 6) return 2;
+    if (fold >= 2 && ops.size() >= 2 && ops[0].k <= 6 && ops[1].kind == OP_CLUSTER && ops[1].k == 6) {
+        if (fold < 3) return 2;
+        // the table form: rows of the second cluster shared with the first,
+        // and rows the first one's diagonal gates couple to a column qubit
+        uint64_t t1 = 0, t2 = 0, flipped = 0;
+        for (int j = 0; j < ops[0].k; ++j) t1 |= uint64_t(1) << ops[0].qubits[j];
+        for (int j = 0; j < ops[1].k; ++j) t2 |= uint64_t(1) << ops[1].qubits[j];
+        for (int gi : ops[0].epi) {
+            const SGate& g = gates[gi];
+            if (g.nq != 2) continue;
+            const uint64_t a = uint64_t(1) << g.q[0], b = uint64_t(1) << g.q[1];
+            if (((t2 & a) != 0) != ((t2 & b) != 0)) flipped |= t2 & (a | b);
+        }
+        const int shared = popc(t1 & t2);
+        return shared <= 2 && shared + popc(flipped) <= 7 ? 3 : 2;
+    }
     return 1;
 }
 
 // Passes of a schedule with its start counted as the write-only pass it becomes.
-double effective_passes(const std::vector<SOp>& ops, int fold) {
-    switch (fold_kind(ops, fold)) {
+double effective_passes(const std::vector<SOp>& ops, const std::vector<SGate>& gates, int fold) {
+    switch (fold_kind(ops, gates, fold)) {
+        case 3: return (double)ops.size() - 2 + kFold2TableShare;
         case 2: return (double)ops.size() - 2 + kFold2Share;
         case 1: return (double)ops.size() - 1 + kFold1Share;
         default: return (double)ops.size();
@@ -568,7 +585,7 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
         double best = 0.0;
         for (size_t c = 0; c < futs.size(); ++c) {
             std::vector<SOp> ops = futs[c].get();
-            const double p = effective_passes(ops, fold);
+            const double p = effective_passes(ops, gates, fold);
             if (c == 0 || p < best) {
                 best = p;
                 S.ops = std::move(ops);
@@ -596,7 +613,8 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
             if (i == 1) c1 = c;
         }
         // the start's share: its clusters written by one write-only pass
-        const int fk = fold_kind(ops, fold);
+        const int fk = fold_kind(ops, gates, fold);
+        if (fk == 3) total -= c0 + (1.0 - kFold2TableShare) * c1;
         if (fk == 2) total -= c0 + (1.0 - kFold2Share) * c1;
         if (fk == 1) total -= (1.0 - kFold1Share) * c0;
         return Cand(std::move(ops), total);

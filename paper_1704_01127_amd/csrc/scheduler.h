@@ -41,17 +41,24 @@ struct SchedOpts {
     bool parallel = true;      // build candidate schedules on threads of their own
     // How a run from the uniform state (skip_initial_h) writes its start:
     // 0 an initialisation pass; 1 the first cluster with it, in one write-only
-    // pass; 2 also a second cluster of 6 qubits. Schedules are compared with
-    // that pass priced as write-only, and with 2 and kmax > 6 candidates whose
-    // first two clusters have at most 6 qubits are offered as well.
+    // pass; 2 also a second cluster of 6 qubits, multiplied per column on the
+    // matrix cores; 3 as 2, in the table form where it applies (the second
+    // cluster shares at most 2 qubits with the first, and 2^(shared + rows the
+    // first cluster's diagonal gates sign-flip) <= 128). Schedules are
+    // compared with that pass priced as write-only, and with 2 or 3 and
+    // kmax > 6 candidates whose first two clusters have at most 6 qubits are
+    // offered as well.
     int fold_start = 0;
 };
 
 // Cost of the write-only start relative to the full passes it replaces:
 // measured on the 30-qubit complex64 state, the uniform start with one cluster
-// takes 0.41-0.49 of a cluster pass, with two clusters 0.69 of one.
+// takes 0.41-0.49 of a cluster pass, with two clusters 0.69 of a 6-qubit pass
+// on the matrix cores and 0.47 in the table form (1.63 ms, the write
+// ceiling, against 3.48 ms).
 constexpr double kFold1Share = 0.45;
 constexpr double kFold2Share = 0.70;
+constexpr double kFold2TableShare = 0.47;
 
 struct Schedule {
     std::vector<SOp> ops;

@@ -269,6 +269,7 @@ OPT_CLUSTER_SETS = 9
 OPT_BATCH_ORDER = 10
 OPT_CHECK_UNITARY = 11
 OPT_MAP_QUBITS = 12
+OPT_FOLD_TABLE = 13
 
 
 def set_option(option: int, value: int):
@@ -524,7 +525,8 @@ class State:
 
     def op_timings(self) -> list:
         """Per-launch records of the last run with record_timings=True:
-        dicts with kind, k, qubits, epi and ms (HIP events on the state's stream)."""
+        dicts with kind, k, qubits, epi flags, n_epi and ms (HIP events on the
+        state's stream); table: a folded start in its table form."""
         n = ctypes.c_int()
         L = lib()
         L.qsim_op_timings(self.h, None, None, None, None, None, 0, ctypes.byref(n))  # count only
@@ -539,7 +541,8 @@ class State:
                  7: "pair", 9: "permute"}
         return [dict(kind=kinds[kind[i]], k=k[i], qubits=[q for q in qs[MAX_CLUSTER * i:MAX_CLUSTER * (i + 1)] if q >= 0],
                      epi=bool(epi[i] & 1), staged=bool(epi[i] & 2), mfma=bool(epi[i] & 4),
-                     stats=bool(epi[i] & 8), n_epi=(epi[i] >> 8) & 255, ms=float(ms[i]))
+                     stats=bool(epi[i] & 8), table=bool(epi[i] & 16), n_epi=(epi[i] >> 8) & 255,
+                     ms=float(ms[i]))
                 for i in range(m)]
 
     def sync(self):

@@ -99,7 +99,7 @@ int main() {
                 SchedOpts o;
                 o.mode = mode;
                 o.kmax = kmax;
-                o.fold_start = below(3);
+                o.fold_start = below(4);
                 o.fuse_diag = below(2);
                 o.skip_trailing_diag = below(2);
                 o.skip_initial_h = below(2);

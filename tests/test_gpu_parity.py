@@ -388,7 +388,9 @@ def test_fold_init_first_cluster(dt, case):
 
 # (n, seed, Haar gate size): the second cluster's targets with qubit 0 or not,
 # the first cluster of 6 qubits or fewer, the two overlapping or not
-FOLD2_CASES = [(16, 19, 6), (11, 1, 2), (13, 7, 6), (11, 0, 6), (11, 2, 3), (11, 4, 6)]
+# (with the table form: no, 2 and 1 shared qubits in the first cases, 4 - the
+# matrix-core form - in (11, 1, 2) and (11, 2, 3), target 0 in (11, 4, 6))
+FOLD2_CASES = [(16, 19, 6), (11, 1, 2), (13, 7, 6), (11, 0, 6), (11, 2, 3), (11, 4, 6), (12, 21, 6), (14, 20, 6)]
 
 
 @pytest.mark.parametrize("case", range(len(FOLD2_CASES)))
@@ -396,27 +398,69 @@ def test_fold2_matches_oracle(case):
     """The uniform start, a first cluster and a second 6-qubit cluster in one
     write-only pass (the second's inputs computed from the closed form, the
     first epilogue split by the second's targets) against the oracle, and
-    against the same run with the three passes apart."""
+    against the same run with the three passes apart: the second cluster
+    multiplied per column on the matrix cores, and (where its inputs depend on
+    few column qubits) read from a table of its outputs."""
     from supremacy_inputs.circuits import batch_grid
     n, seed, hk = FOLD2_CASES[case]
     R, C, drop = batch_grid(n)
     circ = with_haar_layers(supremacy_circuit(R, C, 16, 300 + seed, drop), 4, hk, 400 + seed)
     ref = oracle.run(circ)
     opts = dict(kmax=6, fuse_diag=True, skip_initial_h=True, record_timings=True)
-    old = qsim.get_option(qsim.OPT_FOLD_INIT)
+    old = qsim.get_option(qsim.OPT_FOLD_INIT), qsim.get_option(qsim.OPT_FOLD_TABLE)
     try:
-        got = {}
-        for fold in (2, 0):
+        got, table = {}, {}
+        for fold, tab in ((2, 1), (2, 0), (0, 1)):
             qsim.set_option(qsim.OPT_FOLD_INIT, fold)
+            qsim.set_option(qsim.OPT_FOLD_TABLE, tab)
             s = make_state(n, "c64")
             st = s.run_circuit(circ.gates, **opts)
-            kinds = [r["kind"] for r in s.op_timings() if r["kind"] != "build"]
-            assert (kinds[0] == "init_cluster2") == (fold == 2), kinds
-            got[fold] = s.to_numpy()
+            recs = [r for r in s.op_timings() if r["kind"] != "build"]
+            assert (recs[0]["kind"] == "init_cluster2") == (fold == 2), [r["kind"] for r in recs]
+            table[(fold, tab)] = recs[0]["table"]
+            got[(fold, tab)] = s.to_numpy()
     finally:
-        qsim.set_option(qsim.OPT_FOLD_INIT, old)
-    assert_fp32_circuit(got[2], ref, st, 6)
-    assert np.max(np.abs(got[2] - got[0])) <= 2 * fp32_circuit_bound(float(np.max(np.abs(ref))), st["n_ops"] + 2, 6)
+        qsim.set_option(qsim.OPT_FOLD_INIT, old[0])
+        qsim.set_option(qsim.OPT_FOLD_TABLE, old[1])
+    print("case", case, "table form:", table[(2, 1)])
+    assert not table[(2, 0)] and not table[(0, 1)]
+    bound = 2 * fp32_circuit_bound(float(np.max(np.abs(ref))), st["n_ops"] + 2, 6)
+    for key in ((2, 1), (2, 0)):
+        assert_fp32_circuit(got[key], ref, st, 6)
+        assert np.max(np.abs(got[key] - got[(0, 1)])) <= bound
+
+
+def test_fold2_table_form_full_size():
+    """The benchmarked 30-qubit grid circuit (5 x 6, depth 25, seed 0) in its
+    complex64 form (learned schedule, k <= 7) starts with the table form of
+    the folded start (its first two clusters share one qubit), and the whole
+    run agrees with the same run whose folded start multiplies every column on
+    the matrix cores, element by element within the float32 bound."""
+    circ = supremacy_circuit(5, 6, 25, 0)
+    opts = dict(kmax=7, scheduler="learned", fuse_diag=True, skip_initial_h=True, skip_trailing_diag=True,
+                record_timings=True)
+    old = qsim.get_option(qsim.OPT_FOLD_TABLE)
+    states, table = {}, {}
+    try:
+        for tab in (1, 0):
+            qsim.set_option(qsim.OPT_FOLD_TABLE, tab)
+            s = qsim.State(circ.n, "c64", kmax=7)
+            st = s.run_circuit(circ.gates, **opts)
+            recs = [r for r in s.op_timings() if r["kind"] != "build"]
+            assert recs[0]["kind"] == "init_cluster2", [r["kind"] for r in recs]
+            table[tab] = recs[0]["table"]
+            states[tab] = s
+    finally:
+        qsim.set_option(qsim.OPT_FOLD_TABLE, old)
+    assert table[1] and not table[0]
+    a, b = states[1].amps, states[0].amps
+    mx = float(b.abs().max())
+    d = float((a - b).abs().max())
+    n_ops = st["n_ops"] + 1
+    print("max |d amp| %.3g, max |amp| %.3g, %d passes" % (d, mx, n_ops))
+    assert d <= 2 * fp32_circuit_bound(mx, n_ops, 7), (d, mx)
+    del states, a, b
+    torch.cuda.empty_cache()
 
 
 # ------------------------------------------------------------------ two clusters per pass (complex64)
