@@ -2879,63 +2879,61 @@ __global__ __launch_bounds__(256) void k_init_cluster(typename Cplx<T>::type* __
 // local column x at (2 i + c) * cs + x, cs = the work-group's column count):
 // the threads touch consecutive words at every step (a column per contiguous
 // block put them a multiple of 256 words apart, all in one bank).
-constexpr int kBuildThreads = 64;
-// entry i (2 per amplitude: real, imaginary) of the column at v, column stride cs
+// 4 waves per matrix (a quarter of a 7-qubit matrix): each column is worked
+// on by kBuildThreads / (columns held) threads, every gate split over them
+constexpr int kBuildThreads = 256;
+constexpr int kBuildCols = 64;  // columns held for k <= 6 (32 for k = 7)
+// entry i of a column: its doubles lie cs apart (the columns side by side)
 __device__ __forceinline__ double& BV(double* v, int i, int cs) { return v[i * cs]; }
-__device__ void build_apply_1q(double* v, int D, int cs, int a, const double m[8]) {
-    for (int i = 0; i < D; ++i) {
-        if ((i >> a) & 1) continue;
-        const int j = i | (1 << a);
-        const double ar = BV(v, 2 * i, cs), ai = BV(v, 2 * i + 1, cs), br = BV(v, 2 * j, cs),
-                     bi = BV(v, 2 * j + 1, cs);
-        BV(v, 2 * i, cs) = (m[0] * ar - m[1] * ai) + (m[2] * br - m[3] * bi);
-        BV(v, 2 * i + 1, cs) = (m[0] * ai + m[1] * ar) + (m[2] * bi + m[3] * br);
-        BV(v, 2 * j, cs) = (m[4] * ar - m[5] * ai) + (m[6] * br - m[7] * bi);
-        BV(v, 2 * j + 1, cs) = (m[4] * ai + m[5] * ar) + (m[6] * bi + m[7] * br);
-    }
-}
 
 __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restrict__ ops,
                                                          const BuildGate* __restrict__ gates,
                                                          const double* __restrict__ dense, char* __restrict__ mat_base) {
     // 2 doubles per entry, 2^k entries per column, cs columns: 8192 doubles for k <= 6 and for k = 7
-    __shared__ double Vs[64 * 2 * kBuildThreads];
-    __shared__ double Ws[64 * 2 * kBuildThreads];
+    __shared__ double Vs[64 * 2 * kBuildCols];
+    __shared__ double Ws[64 * 2 * kBuildCols];
     const BuildOp op = ops[blockIdx.x];
     const int k = op.k, D = 1 << k, t = threadIdx.x;
-    const int cs = k == 7 ? 32 : kBuildThreads;  // columns held by this work-group
-    const int x0 = k == 7 ? 32 * op.part : 0;    // its first column
-    if (t < D && t < cs) {
-        const int x = x0 + t;
-        double* v = Vs + t;
-        double* w = Ws + t;
-        for (int i = 0; i < 2 * D; ++i) BV(v, i, cs) = 0.0;
-        BV(v, 2 * x, cs) = 1.0;
-        for (int gi = 0; gi < op.n_gates; ++gi) {
-            const BuildGate bg = gates[op.gate0 + gi];
-            if (bg.kind == G_CZ) {
-                const int m = (1 << bg.pos[0]) | (1 << bg.pos[1]);
-                for (int i = 0; i < D; ++i)
+    const int cs = k == 7 ? 32 : kBuildCols;   // columns held by this work-group
+    const int x0 = k == 7 ? 32 * op.part : 0;  // its first column
+    // thread t: column c, share sub of T
+    const int T = kBuildThreads / cs, c = t % cs, sub = t / cs;
+    const bool act = c < D;
+    double* v = Vs + c;
+    double* w = Ws + c;
+    if (act)
+        for (int i = sub; i < 2 * D; i += T) BV(v, i, cs) = i == 2 * (x0 + c) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int gi = 0; gi < op.n_gates; ++gi) {
+        const BuildGate bg = gates[op.gate0 + gi];
+        if (bg.kind == G_CZ) {
+            const int m = (1 << bg.pos[0]) | (1 << bg.pos[1]);
+            if (act)
+                for (int i = sub; i < D; i += T)
                     if ((i & m) == m) {
                         BV(v, 2 * i, cs) = -BV(v, 2 * i, cs);
                         BV(v, 2 * i + 1, cs) = -BV(v, 2 * i + 1, cs);
                     }
-            } else if (bg.kind == G_DENSE) {
-                // for each assignment `rest` of the entry bits outside the
-                // gate, the dd entries rest | dep(xl) are multiplied by the
-                // gate's matrix; 16 outputs at a time are summed in registers
-                // (dep puts bit j of a gate index at the gate's position j)
-                const int dq = bg.nq, dd = 1 << dq;
-                const double* u = dense + bg.dense_off;
-                int pm = 0;
-                for (int j = 0; j < dq; ++j) pm |= 1 << bg.pos[j];
-                auto dep = [&](int xl) {
-                    int o = 0;
-                    for (int j = 0; j < dq; ++j) o |= ((xl >> j) & 1) << bg.pos[j];
-                    return o;
-                };
+        } else if (bg.kind == G_DENSE) {
+            // for each assignment `rest` of the entry bits outside the gate,
+            // the dd entries rest | dep(xl) are multiplied by the gate's
+            // matrix; 16 outputs at a time (one work item, dealt round-robin
+            // to the column's threads) are summed in registers (dep puts bit j
+            // of a gate index at the gate's position j)
+            const int dq = bg.nq, dd = 1 << dq;
+            const double* u = dense + bg.dense_off;
+            int pm = 0;
+            for (int j = 0; j < dq; ++j) pm |= 1 << bg.pos[j];
+            auto dep = [&](int xl) {
+                int o = 0;
+                for (int j = 0; j < dq; ++j) o |= ((xl >> j) & 1) << bg.pos[j];
+                return o;
+            };
+            if (act) {
+                int item = 0;
                 for (int rest = 0; rest < D; rest = ((rest | pm) + 1) & ~pm) {
-                    for (int y0 = 0; y0 < dd; y0 += 16) {
+                    for (int y0 = 0; y0 < dd; y0 += 16, ++item) {
+                        if (item % T != sub) continue;
                         double sr[16], si[16];
 #pragma unroll
                         for (int t2 = 0; t2 < 16; ++t2) sr[t2] = si[t2] = 0.0;
@@ -2959,19 +2957,34 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restri
                         }
                     }
                 }
-                for (int i = 0; i < 2 * D; ++i) BV(v, i, cs) = BV(w, i, cs);
-            } else {
-                double m[8];
-                gate2x2(bg.kind, bg.theta, m);
-                build_apply_1q(v, D, cs, bg.pos[0], m);
             }
+            __syncthreads();
+            if (act)
+                for (int i = sub; i < 2 * D; i += T) BV(v, i, cs) = BV(w, i, cs);
+        } else {
+            double m[8];
+            gate2x2(bg.kind, bg.theta, m);
+            const int a = bg.pos[0], lo = (1 << a) - 1;
+            if (act)
+                for (int pr = sub; pr < D / 2; pr += T) {
+                    const int i = ((pr & ~lo) << 1) | (pr & lo), j = i | (1 << a);
+                    const double ar = BV(v, 2 * i, cs), ai = BV(v, 2 * i + 1, cs), br = BV(v, 2 * j, cs),
+                                 bi = BV(v, 2 * j + 1, cs);
+                    BV(v, 2 * i, cs) = (m[0] * ar - m[1] * ai) + (m[2] * br - m[3] * bi);
+                    BV(v, 2 * i + 1, cs) = (m[0] * ai + m[1] * ar) + (m[2] * bi + m[3] * br);
+                    BV(v, 2 * j, cs) = (m[4] * ar - m[5] * ai) + (m[6] * br - m[7] * bi);
+                    BV(v, 2 * j + 1, cs) = (m[4] * ai + m[5] * ar) + (m[6] * bi + m[7] * br);
+                }
         }
+        __syncthreads();
     }
     __syncthreads();
     // M[y][x] = entry y of column x (a column this work-group holds)
     auto Mre = [&](int y, int xx) { return Vs[(2 * y) * cs + (xx - x0)]; };
     auto Mim = [&](int y, int xx) { return Vs[(2 * y + 1) * cs + (xx - x0)]; };
-    const int x = t;  // k <= 6: the thread's column (x0 = 0)
+    // k <= 6 layouts: lane l = t % 64 of the MFMA operand, the (row block,
+    // step) pairs dealt to the 4 waves
+    const int lane = t & 63, wv = t >> 6, NW = kBuildThreads / 64;
     // entry (R, Kc) of the real-split matrix [[Re, -Im], [Im, Re]]
     auto Ars = [&](int y, int a, int xx, int b) {
         const double re = Mre(y, xx), im = Mim(y, xx);
@@ -2979,14 +2992,13 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restri
     };
     char* out = mat_base + op.out_off;
     if (op.layout == LAYOUT_PLAIN) {
-        if (t < D && t < cs) {
-            const int xc = x0 + t;
-            for (int y = 0; y < D; ++y) {
-                if (op.is_double) {
-                    reinterpret_cast<double2*>(out)[y * D + xc] = make_double2(Mre(y, xc), Mim(y, xc));
-                } else {
-                    reinterpret_cast<float2*>(out)[y * D + xc] = make_float2((float)Mre(y, xc), (float)Mim(y, xc));
-                }
+        const int nc = D < cs ? D : cs;  // columns held
+        for (int e = t; e < D * nc; e += kBuildThreads) {
+            const int y = e / nc, xc = x0 + e % nc;
+            if (op.is_double) {
+                reinterpret_cast<double2*>(out)[y * D + xc] = make_double2(Mre(y, xc), Mim(y, xc));
+            } else {
+                reinterpret_cast<float2*>(out)[y * D + xc] = make_float2((float)Mre(y, xc), (float)Mim(y, xc));
             }
         }
     } else if (op.layout == LAYOUT_SPLIT7) {
@@ -3015,17 +3027,16 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restri
         }
     } else if (op.layout == LAYOUT_MFMA32F) {
         // entry (rb, s, lane l): row rho = l % 32 of row block rb, inner index 2 s + l / 32
-        const int RB = 2 * D / 32, S = D, l = x;
+        const int RB = 2 * D / 32, S = D, l = lane;
         const int rho = l & 31, hin = l >> 5;
         float* A = reinterpret_cast<float*>(out);
-        for (int rb = 0; rb < RB; ++rb) {
+        for (int it = wv; it < RB * S; it += NW) {
+            const int rb = it / S, s = it % S;
             const int jout = rb * 8 + 2 * (rho >> 3) + ((rho & 3) >> 1);
             const int hout = (rho >> 2) & 1;
             const int y = jout | (hout << (k - 1)), a = rho & 1;
-            for (int s = 0; s < S; ++s) {
-                const int xin = (s >> 1) | (hin << (k - 1)), b = s & 1;
-                A[(rb * S + s) * 64 + l] = (float)Ars(y, a, xin, b);
-            }
+            const int xin = (s >> 1) | (hin << (k - 1)), b = s & 1;
+            A[(rb * S + s) * 64 + l] = (float)Ars(y, a, xin, b);
         }
     } else if (op.layout == LAYOUT_GAUSS32F) {
         // k = 6: three 64 x 64 real matrices P = 0: Re M, 1: Im M, 2: Re M + Im M,
@@ -3033,17 +3044,16 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restri
         // i = l % 16 of row block rb, inner index s | (l / 16) << 4. The result
         // of physical row i lands in register i % 4 of the lanes with l / 16 =
         // i / 4, which own amplitude (4 rb + i % 4) | (i / 4) << 4.
-        const int l = x, i = l & 15, qin = l >> 4;
+        const int l = lane, i = l & 15, qin = l >> 4;
         float* A = reinterpret_cast<float*>(out);
-        for (int rb = 0; rb < 4; ++rb) {
+        for (int it = wv; it < 4 * 16; it += NW) {
+            const int rb = it / 16, s2 = it % 16;
             const int y = (4 * rb + (i & 3)) | ((i >> 2) << 4);
-            for (int s2 = 0; s2 < 16; ++s2) {
-                const int xin = s2 | (qin << 4);
-                const double re = Mre(y, xin), im = Mim(y, xin);
-                A[((0 * 4 + rb) * 16 + s2) * 64 + l] = (float)re;
-                A[((1 * 4 + rb) * 16 + s2) * 64 + l] = (float)im;
-                A[((2 * 4 + rb) * 16 + s2) * 64 + l] = (float)(re + im);
-            }
+            const int xin = s2 | (qin << 4);
+            const double re = Mre(y, xin), im = Mim(y, xin);
+            A[((0 * 4 + rb) * 16 + s2) * 64 + l] = (float)re;
+            A[((1 * 4 + rb) * 16 + s2) * 64 + l] = (float)im;
+            A[((2 * 4 + rb) * 16 + s2) * 64 + l] = (float)(re + im);
         }
     } else if (op.layout == LAYOUT_SPLIT16F) {
         // k = 5 or 6, fp16 halves of 16 x the real-split matrix for
@@ -3052,37 +3062,36 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(const BuildOp* __restri
         // l % 32 of row block rb (result rows as in LAYOUT_MFMA32F), inner index
         // float 8 s + i of the lanes with l / 32 = hin, i.e. component i % 2 of
         // amplitude (4 s + i / 2) | hin << (k - 1). hi block, then lo block.
-        const int l = x, rho = l & 31, hin = l >> 5;
+        const int l = lane, rho = l & 31, hin = l >> 5;
         const int RB = 1 << (k - 4), S = 1 << (k - 3);
         _Float16* Ahi = reinterpret_cast<_Float16*>(out);
         _Float16* Alo = Ahi + (size_t)RB * S * 64 * 8;
-        for (int rb = 0; rb < RB; ++rb) {
+        for (int it = wv; it < RB * S; it += NW) {
+            const int rb = it / S, s2 = it % S;
             const int jout = rb * 8 + 2 * (rho >> 3) + ((rho & 3) >> 1);
             const int hout = (rho >> 2) & 1;
             const int y = jout | (hout << (k - 1)), a = rho & 1;
-            for (int s2 = 0; s2 < S; ++s2)
-                for (int i = 0; i < 8; ++i) {
-                    const int xin = (4 * s2 + (i >> 1)) | (hin << (k - 1)), b = i & 1;
-                    const float v = (float)(16.0 * Ars(y, a, xin, b));
-                    const _Float16 hi = (_Float16)v;
-                    const size_t at = ((size_t)(rb * S + s2) * 64 + l) * 8 + i;
-                    Ahi[at] = hi;
-                    Alo[at] = (_Float16)(v - (float)hi);
-                }
+            for (int i = 0; i < 8; ++i) {
+                const int xin = (4 * s2 + (i >> 1)) | (hin << (k - 1)), b = i & 1;
+                const float v = (float)(16.0 * Ars(y, a, xin, b));
+                const _Float16 hi = (_Float16)v;
+                const size_t at = ((size_t)(rb * S + s2) * 64 + l) * 8 + i;
+                Ahi[at] = hi;
+                Alo[at] = (_Float16)(v - (float)hi);
+            }
         }
     } else {  // LAYOUT_MFMA16D
         // entry (rb, s, lane l): row rho = l % 16 of row block rb, inner index 4 s + l / 16.
         // The result row rho lands in register rho / 4 of the lanes with l / 16 = rho % 4.
-        const int RB = 2 * D / 16, S = 2 * D / 4, l = x;
+        const int RB = 2 * D / 16, S = 2 * D / 4, l = lane;
         const int rho = l & 15, qin = l >> 4;
         double* A = reinterpret_cast<double*>(out);
-        for (int rb = 0; rb < RB; ++rb) {
+        for (int it = wv; it < RB * S; it += NW) {
+            const int rb = it / S, s = it % S;
             const int qout = rho & 3, ir = rho >> 2;
             const int y = (rb * 2 + (ir >> 1)) | (qout << (k - 2)), a = ir & 1;
-            for (int s = 0; s < S; ++s) {
-                const int xin = (s >> 1) | (qin << (k - 2)), b = s & 1;
-                A[(rb * S + s) * 64 + l] = Ars(y, a, xin, b);
-            }
+            const int xin = (s >> 1) | (qin << (k - 2)), b = s & 1;
+            A[(rb * S + s) * 64 + l] = Ars(y, a, xin, b);
         }
     }
 }
