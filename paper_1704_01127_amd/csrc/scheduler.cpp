@@ -159,7 +159,11 @@ int grow(const Dag& d, const Frontier& f0, int seed, int kcap, bool fuse_diag, u
             const uint64_t m = d.mask[gi];
             if (within ? (m & ~within) != 0 : popc(Q | m) > kcap) continue;
             const int nw = popc(m & ~Q);
-            if (nw < best_new) { best = gi; best_new = nw; }
+            if (nw < best_new) {
+                best = gi;
+                best_new = nw;
+                if (nw == 0) break;  // nothing beats it, and later gates have higher indices
+            }
         }
         if (best < 0) break;
         ++n_mat;
