@@ -41,9 +41,18 @@
 //     next cluster on its qubits where that cluster holds them all.
 #include "scheduler.h"
 
+#include <pthread.h>
+
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstring>
-#include <future>
+#include <deque>
+#include <exception>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <thread>
 
 #include "qsim_internal.h"
 
@@ -52,6 +61,115 @@ static_assert(kSchedMaxK == kMaxK, "schedule ops hold the widest cluster");
 namespace {
 
 inline int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+// Candidate schedules are built on a process-wide pool of worker threads,
+// started on first use: starting a thread per candidate cost as much host
+// time as building the candidates. A call hands over a batch of tasks and
+// works on it too; a task's exception is rethrown in the caller. Batches are
+// shared: a worker that comes late to a finished batch only reads its task
+// counter, never the caller's data. After fork() the child starts a pool of
+// its own.
+class TaskPool {
+  public:
+    static TaskPool& get() {
+        static std::once_flag once;
+        std::call_once(once, [] { pthread_atfork(nullptr, nullptr, [] { instance() = nullptr; }); });
+        std::lock_guard<std::mutex> l(create_mutex());
+        if (!instance()) {
+            const int hw = (int)std::thread::hardware_concurrency();
+            instance() = new TaskPool(std::max(1, std::min(15, hw - 1)));  // kept until the process ends
+        }
+        return *instance();
+    }
+    void run(std::vector<std::function<void()>> fs) {
+        if (fs.empty()) return;
+        auto b = std::make_shared<Batch>();
+        b->n = (int)fs.size();
+        b->fs = std::move(fs);
+        {
+            std::lock_guard<std::mutex> l(m_);
+            q_.push_back(b);
+        }
+        cv_.notify_all();
+        work(*b);
+        std::unique_lock<std::mutex> l(b->m);
+        b->cv.wait(l, [&] { return b->done == b->n; });
+        if (b->error) std::rethrow_exception(b->error);
+    }
+
+  private:
+    struct Batch {
+        std::vector<std::function<void()>> fs;
+        int n = 0;
+        std::atomic<int> next{0};
+        std::mutex m;
+        std::condition_variable cv;
+        int done = 0;  // under m
+        std::exception_ptr error;
+    };
+    static TaskPool*& instance() {
+        static TaskPool* p = nullptr;
+        return p;
+    }
+    static std::mutex& create_mutex() {
+        static std::mutex m;
+        return m;
+    }
+    static void work(Batch& b) {
+        for (;;) {
+            const int i = b.next.fetch_add(1);
+            if (i >= b.n) return;
+            std::exception_ptr e;
+            try {
+                b.fs[i]();
+            } catch (...) {
+                e = std::current_exception();
+            }
+            std::lock_guard<std::mutex> l(b.m);
+            if (e && !b.error) b.error = e;
+            if (++b.done == b.n) b.cv.notify_all();
+        }
+    }
+    explicit TaskPool(int workers) {
+        for (int i = 0; i < workers; ++i) std::thread([this] { loop(); }).detach();
+    }
+    void loop() {
+        for (;;) {
+            std::shared_ptr<Batch> b;
+            {
+                std::unique_lock<std::mutex> l(m_);
+                cv_.wait(l, [&] { return !q_.empty(); });
+                b = q_.front();
+                if (b->next.load() >= b->n) {  // every task taken: the batch leaves the queue
+                    q_.pop_front();
+                    continue;
+                }
+            }
+            work(*b);
+        }
+    }
+    std::mutex m_;
+    std::condition_variable cv_;
+    std::deque<std::shared_ptr<Batch>> q_;
+};
+
+// Results of the tasks, in order: on the pool when parallel, else one after
+// another on this thread. Only tasks with want[i] (all when want is null) run.
+template <typename T>
+std::vector<T> run_tasks(bool parallel, const std::vector<std::function<T()>>& fns,
+                         const std::vector<char>* want = nullptr) {
+    std::vector<T> out(fns.size());
+    if (!parallel) {
+        for (size_t i = 0; i < fns.size(); ++i)
+            if (!want || (*want)[i]) out[i] = fns[i]();
+        return out;
+    }
+    std::vector<std::function<void()>> jobs;
+    for (size_t i = 0; i < fns.size(); ++i)
+        if (!want || (*want)[i]) jobs.push_back([&fns, &out, i] { out[i] = fns[i](); });
+    TaskPool::get().run(std::move(jobs));
+    return out;
+}
 
 struct Dag {
     int n;
@@ -571,24 +689,24 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
         // the greedy schedules with and without the candidate sets (and with
         // a 6-qubit start); the one with the fewest passes wins, the start
         // counted as the write-only pass it becomes (ties: the earlier)
-        const auto policy = o.parallel ? std::launch::async : std::launch::deferred;
-        std::vector<std::future<std::vector<SOp>>> futs;
+        std::vector<std::function<std::vector<SOp>()>> fns;
         for (int fc = 0; fc < first_caps; ++fc) {
             const int cap = fc ? 6 : 0;
-            futs.push_back(std::async(policy, [&, cap]() {
+            fns.push_back([&, cap]() {
                 return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, nullptr, cap);
-            }));
+            });
             if (sets0.empty()) continue;
-            futs.push_back(std::async(policy, [&, cap]() {
+            fns.push_back([&, cap]() {
                 return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, &sets0, cap);
-            }));
-            futs.push_back(std::async(policy, [&, cap]() {
+            });
+            fns.push_back([&, cap]() {
                 return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, &sets1, cap);
-            }));
+            });
         }
+        std::vector<std::vector<SOp>> res = run_tasks(o.parallel, fns);
         double best = 0.0;
-        for (size_t c = 0; c < futs.size(); ++c) {
-            std::vector<SOp> ops = futs[c].get();
+        for (size_t c = 0; c < res.size(); ++c) {
+            std::vector<SOp>& ops = res[c];
             const double p = effective_passes(ops, gates, fold);
             if (c == 0 || p < best) {
                 best = p;
@@ -605,7 +723,6 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     // these caps is always among them - and the cost-trimmed greedy schedule
     // for kmax.
     const int k_lo = std::max(1, kmax - 2);
-    const auto policy = o.parallel ? std::launch::async : std::launch::deferred;
     using Cand = std::pair<std::vector<SOp>, double>;
     auto priced = [&](std::vector<SOp> ops) {
         double total = 0.0, c0 = 0.0, c1 = 0.0;
@@ -629,33 +746,30 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     // circuit whose gates do not pack into full-width clusters (or
     // complex128, whose 6-qubit clusters are bound by the fp64 matrix cores)
     // gets them, while prediction noise alone cannot make a narrower cap win
-    // on the other circuits. All candidates are started together (one round
-    // of latency); the gated ones are read only where their cap qualifies.
-    struct Task {
-        int gate;  // 0: always a candidate; kc: only where cap kc qualifies
-        std::future<Cand> fut;
+    // on the other circuits. In parallel all candidates are built together
+    // (one round of latency) and the gate applies when choosing; one after
+    // another, the gated ones are built only where their cap qualifies.
+    std::vector<std::function<Cand()>> fns;
+    std::vector<int> gate;  // 0: always a candidate; kc: only where cap kc qualifies
+    auto add = [&](int g, std::function<Cand()> f) {
+        gate.push_back(g);
+        fns.push_back(std::move(f));
     };
-    std::vector<Task> tasks;
-    for (int kc = k_lo; kc <= kmax; ++kc)
-        tasks.push_back({0, std::async(policy, [&, kc]() {
-                             return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag));
-                         })});
+    for (int kc = k_lo; kc <= kmax; ++kc)  // the plain schedules first: their prices decide which caps qualify
+        add(0, [&, kc]() { return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag)); });
     if (first_caps > 1) {  // the widest cap after a 6-qubit start, with and without the candidate sets
-        tasks.push_back({0, std::async(policy, [&]() {
-                             return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr,
-                                                      nullptr, 6));
-                         })});
+        add(0, [&]() {
+            return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, nullptr, 6));
+        });
         for (const std::vector<uint64_t>* fs : {&sets0, &sets1})
             if (!fs->empty())
-                tasks.push_back({0, std::async(policy, [&, fs]() {
-                                     return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag,
-                                                              nullptr, fs, 6));
-                                 })});
+                add(0, [&, fs]() {
+                    return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, fs, 6));
+                });
     }
     if (kmax > 1)
-        tasks.push_back({kmax - 1, std::async(policy, [&]() {
-                             return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost));
-                         })});
+        add(kmax - 1,
+            [&]() { return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost)); });
     // set families: kmax's are at hand; a narrower cap's are found inside
     // its tasks, one task per (cap, slack)
     if (o.cluster_sets)
@@ -664,28 +778,36 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
                 if (kc == kmax) {
                     const std::vector<uint64_t>* fs = slack ? &sets1 : &sets0;
                     if (fs->empty()) continue;
-                    tasks.push_back({0, std::async(policy, [&, fs]() {
-                                         return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax,
-                                                                  o.fuse_diag, nullptr, fs));
-                                     })});
+                    add(0, [&, fs]() {
+                        return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, fs));
+                    });
                 } else {
-                    tasks.push_back({kc, std::async(policy, [&, kc, slack]() {
-                                         std::vector<uint64_t> a, b;
-                                         dense_sets(n, gates, S.dropped, kc, a, b);
-                                         const std::vector<uint64_t>& sets = slack ? b : a;
-                                         if (sets.empty()) return Cand(std::vector<SOp>(), -1.0);  // no such family
-                                         return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag,
-                                                                  nullptr, &sets));
-                                     })});
+                    add(kc, [&, kc, slack]() {
+                        std::vector<uint64_t> a, b;
+                        dense_sets(n, gates, S.dropped, kc, a, b);
+                        const std::vector<uint64_t>& sets = slack ? b : a;
+                        if (sets.empty()) return Cand(std::vector<SOp>(), -1.0);  // no such family: not a candidate
+                        return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag, nullptr, &sets));
+                    });
                 }
             }
-    // the plain schedules come first: their prices decide which caps qualify
-    std::vector<Cand> cands;
-    for (int kc = k_lo; kc <= kmax; ++kc) cands.push_back(tasks[kc - k_lo].fut.get());
+    const size_t nplain = (size_t)(kmax - k_lo + 1);
+    std::vector<char> want(fns.size(), 0);
+    for (size_t i = 0; i < fns.size(); ++i) want[i] = o.parallel || i < nplain;
+    std::vector<Cand> res = run_tasks(o.parallel, fns, &want);
     std::vector<char> use_cap(kmax + 1, 1);
-    for (int kc = k_lo; kc < kmax; ++kc) use_cap[kc] = cands[kc - k_lo].second < cands[kmax - k_lo].second;
-    for (size_t t = kmax - k_lo + 1; t < tasks.size(); ++t)
-        if (tasks[t].gate == 0 || use_cap[tasks[t].gate]) cands.push_back(tasks[t].fut.get());
+    for (int kc = k_lo; kc < kmax; ++kc) use_cap[kc] = res[kc - k_lo].second < res[kmax - k_lo].second;
+    for (size_t i = nplain; i < fns.size(); ++i) want[i] = gate[i] == 0 || use_cap[gate[i]];
+    if (!o.parallel) {
+        std::vector<char> rest(want);
+        for (size_t i = 0; i < nplain; ++i) rest[i] = 0;
+        std::vector<Cand> more = run_tasks(false, fns, &rest);
+        for (size_t i = nplain; i < fns.size(); ++i)
+            if (rest[i]) res[i] = std::move(more[i]);
+    }
+    std::vector<Cand> cands;
+    for (size_t i = 0; i < fns.size(); ++i)
+        if (want[i]) cands.push_back(std::move(res[i]));
     double best_cost = 0.0;
     bool have = false;
     for (Cand& cand : cands) {
