@@ -130,6 +130,41 @@ def test_prepared_gates_schedule_like_the_list():
         assert a == b
 
 
+def test_concurrent_schedules_match_sequential():
+    """Schedules built from several host threads at once (each call hands its
+    candidates to the library's shared worker pool) equal the ones built one
+    at a time: cost-driven and greedy, complex64 and complex128."""
+    import threading
+    qsim.load_tuning()  # the trained model and the cost table, when present: cost-driven candidates
+    circs = [supremacy_circuit(4, 5, 20, seed=s) for s in range(4)] + [supremacy_circuit(5, 6, 25, seed=0)]
+    jobs = [(c, dt, sched) for c in circs for dt in (qsim.C64, qsim.C128)
+            for sched in ("learned", "analytic", "greedy")]
+    opts = dict(kmax=7, fuse_diag=True, skip_initial_h=True, skip_trailing_diag=True)
+    want = [qsim.schedule(c.n, c.gates, dt, scheduler=sched, **opts) for c, dt, sched in jobs]
+    got = [None] * len(jobs)
+    errors = []
+
+    def worker(w):
+        try:
+            for rep in range(3):
+                for i in range(w, len(jobs), 8):
+                    c, dt, sched = jobs[i]
+                    r = qsim.schedule(c.n, c.gates, dt, scheduler=sched, **opts)
+                    if got[i] is None:
+                        got[i] = r
+                    elif got[i] != r:
+                        errors.append(i)
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(repr(e))
+    threads = [threading.Thread(target=worker, args=(w,)) for w in range(8)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    assert got == want
+
+
 def test_per_gate_schedule_is_one_op_per_gate():
     circ = supremacy_circuit(4, 5, 25, seed=0)
     sch = qsim.schedule(circ.n, circ.gates, scheduler="per_gate")
