@@ -264,7 +264,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: the whole state vector lives in one MI355X's HBM and "
-              "this build has no multi-GPU path (use --gpus 1).", file=sys.stderr)
+              "the library runs on one GPU (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
