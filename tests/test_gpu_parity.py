@@ -430,6 +430,45 @@ def test_fold2_matches_oracle(case):
         assert np.max(np.abs(got[key] - got[(0, 1)])) <= bound
 
 
+# two dense 6-qubit gates after the H layer (the whole circuit is the folded
+# start): shared qubits 0, 1, 2 (the table form) and 4 (the matrix-core
+# form); with a trailing CZ layer across both gates' qubits or without
+FOLD2_DENSE = [((0, 2, 4, 6, 8, 10), (1, 3, 5, 7, 9, 11)),
+               ((0, 1, 2, 3, 4, 5), (5, 6, 7, 8, 9, 10)),
+               ((2, 4, 6, 8, 10, 12), (1, 4, 7, 10, 11, 13)),
+               ((3, 4, 5, 6, 7, 8), (0, 3, 4, 5, 6, 13))]
+
+
+@pytest.mark.parametrize("trailing_cz", [False, True])
+@pytest.mark.parametrize("case", range(len(FOLD2_DENSE)))
+def test_fold2_dense_start(case, trailing_cz):
+    """The folded start of two dense 6-qubit gates without a first epilogue
+    (and with or without a second one, CZ gates the schedule attaches to the
+    second cluster), in the table form where the gates share at most 2 qubits
+    and on the matrix cores otherwise, against the oracle."""
+    n = 14
+    a, b = FOLD2_DENSE[case]
+    gates = [Gate("H", (q,)) for q in range(n)]
+    gates.append(Gate("U", a, haar_unitary(6, 700 + case)))
+    gates.append(Gate("U", b, haar_unitary(6, 710 + case)))
+    if trailing_cz:
+        free = [q for q in range(n) if q not in a and q not in b][0]
+        only_a = [q for q in a if q not in b][0]
+        only_b = [q for q in b if q not in a]
+        gates += [Gate("CZ", (only_b[0], free)), Gate("CZ", (only_a, only_b[1])), Gate("CZ", (b[3], b[4]))]
+        gates.append(Gate("T", (b[5],)))
+        gates.append(Gate("H", (b[5],)))  # keeps the diagonal gates before it from being dropped as trailing
+    circ = Circuit(n, gates)
+    ref = oracle.run(circ)
+    shared = len(set(a) & set(b))
+    s = make_state(n, "c64")
+    st = s.run_circuit(circ.gates, kmax=6, fuse_diag=True, skip_initial_h=True, record_timings=True)
+    recs = [r for r in s.op_timings() if r["kind"] != "build"]
+    assert recs[0]["kind"] == "init_cluster2", [r["kind"] for r in recs]
+    assert recs[0]["table"] == (shared <= 2), (shared, recs[0])
+    assert_fp32_circuit(s.to_numpy(), ref, st, 6)
+
+
 def test_fold2_table_form_full_size():
     """The benchmarked 30-qubit grid circuit (5 x 6, depth 25, seed 0) in its
     complex64 form (learned schedule, k <= 7) starts with the table form of
