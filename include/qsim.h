@@ -312,6 +312,13 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * grown gate by gate from a seed, and keep the schedule with fewer ops
  * (greedy) or the smaller predicted time (cost-driven); 0 grows from seeds
  * only (Sec. 3.6.1's greedy), read when a schedule is built.
+ * QSIM_OPT_DEVIATIONS (default 1): on states of at least 29 qubits, runs that
+ * build their candidate schedules in parallel (qsim_run_circuit,
+ * qsim_schedule) also build the schedules that differ from the greedy choice
+ * at one of the first 3 steps, taking one of the 4 next-best clusters there
+ * (with the larger family of dense qubit sets), and keep them if they need
+ * fewer passes or are predicted faster (a limited-discrepancy search, about
+ * 0.7 ms of host time); 0 skips them. Read when a schedule is built.
  * QSIM_OPT_BATCH_ORDER: the order in which a batch's work items are handed
  * out, read when a batch is planned: 0 (default) level order (the j-th op
  * of every circuit before any (j+1)-th), 1 critical path first (a list
@@ -350,7 +357,8 @@ typedef enum {
     QSIM_OPT_BATCH_ORDER = 10,
     QSIM_OPT_CHECK_UNITARY = 11,
     QSIM_OPT_MAP_QUBITS = 12,
-    QSIM_OPT_FOLD_TABLE = 13
+    QSIM_OPT_FOLD_TABLE = 13,
+    QSIM_OPT_DEVIATIONS = 14
 } qsim_option;
 qsim_status qsim_set_option(int option, int value);
 int qsim_get_option(int option);

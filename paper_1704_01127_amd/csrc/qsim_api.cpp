@@ -74,6 +74,7 @@ int g_batch_item_tiles = 128;
 int g_k6_kernel = 2;
 int g_fold_init = 2;
 int g_fold_table = 1;
+int g_deviations = 1;
 int g_pair = 0;
 int g_pair_tile = 11;
 int g_cluster_sets = 1;
@@ -525,9 +526,11 @@ qsim_status add_fold2(qsim_state_s* s, Chunk& c, const SOp& A, const SOp& B, con
         if (posA[B.qubits[m]] >= 0) omask |= 1 << m;
     for (int i = 0; i < e1.n_mix; ++i) rmask |= 1 << e1.mix[i][0];
     const int tab_bits = __builtin_popcount((unsigned)omask) + __builtin_popcount((unsigned)rmask);
-    const bool table = g_fold_table && B.k == 6 && __builtin_popcount((unsigned)omask) <= 2 &&
-                       (1 << tab_bits) <= kFoldTabRows && sb >= (int64_t(512) << tab_bits) &&
-                       sb >= (int64_t)matrix_bytes(6, LAYOUT_PLAIN, true);
+    const bool table = g_fold_table && __builtin_popcount((unsigned)omask) <= 2 &&
+                       (1 << tab_bits) <= (B.k == 7 ? kFoldTab7Rows : kFoldTabRows) &&
+                       sb >= (int64_t(8) << (B.k + tab_bits)) && sb >= (int64_t)matrix_bytes(B.k, LAYOUT_PLAIN, true);
+    if (B.k == 7 && !table)  // the scheduler folds a 7-qubit second cluster only where the table form applies
+        return fail(QSIM_E_UNSUPPORTED, "two-cluster start with a 7-qubit second cluster needs the table form");
     if (table) {
         bb.is_double = 1;
         bb.layout = LAYOUT_PLAIN;
@@ -736,6 +739,7 @@ int qsim::api::fold_start_for(bool dbl, int n) {
 SchedOpts qsim::api::to_sched_opts(const qsim_run_opts* o) {
     SchedOpts so;
     so.cluster_sets = g_cluster_sets != 0;
+    so.deviations = g_deviations != 0;
     if (!o) return so;
     so.kmax = o->kmax;
     so.mode = o->scheduler == QSIM_SCHED_PER_GATE ? 0 : (o->scheduler == QSIM_SCHED_GREEDY ? 1 : 2);
@@ -951,7 +955,10 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     for (int i = 0; i < n_gates; ++i)
         if (gates[i].kind == G_DENSE && gates[i].k > s->kmax_ws)
             return fail(QSIM_E_UNSUPPORTED, "workspace sized for smaller clusters");
-    Schedule S = make_schedule(s->n, to_sgates(gates, n_gates), so, cost_fn(opts, s->n, s->dbl));
+    const std::vector<SGate> sgates = to_sgates(gates, n_gates);
+    Schedule S = make_schedule(s->n, sgates, so, cost_fn(opts, s->n, s->dbl));
+    // the folded start (the relabelling below keeps it)
+    const int fold_kind = S.uniform_init && g_fold_init ? schedule_fold_kind(S.ops, sgates, so.fold_start) : 0;
     // qubit mapping: from the uniform state the first layout is free; the run
     // applies the relabelled gates and one permutation pass restores the order
     std::vector<qsim_gate> mapped;
@@ -995,10 +1002,8 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
     } rec_off{s};
     // the uniform start and a leading cluster are written in one pass; with a
     // second cluster of 6 qubits (complex64, fp16-halves kernel) that one too
-    const bool fold = S.uniform_init && g_fold_init && !S.ops.empty() && S.ops[0].kind == OP_CLUSTER;
-    const bool fold2 = fold && g_fold_init == 2 && !s->dbl && S.ops[0].k <= 6 && S.ops.size() >= 2 &&
-                       S.ops[1].kind == OP_CLUSTER && S.ops[1].k == 6 &&
-                       cluster_layout(false, 6, s->n) == LAYOUT_SPLIT16F;
+    const bool fold = fold_kind >= 1;
+    const bool fold2 = fold_kind >= 2;  // kinds 2-4: complex64, 6-qubit clusters on the fp16-halves kernel
     // the learned model also picks each cluster's kernel variant (unless one is forced)
     const bool learned_variants = opts && opts->scheduler == QSIM_SCHED_LEARNED && so.mode == 2 &&
                                   learned_model_loaded() && get_cluster_variant() < 0;
@@ -1166,6 +1171,11 @@ qsim_status qsim_set_option(int option, int value) {
         g_fold_init = value;
         return QSIM_OK;
     }
+    if (option == QSIM_OPT_DEVIATIONS) {
+        if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "deviations must be 0 or 1");
+        g_deviations = value;
+        return QSIM_OK;
+    }
     if (option == QSIM_OPT_FOLD_TABLE) {
         if (value < 0 || value > 1) return fail(QSIM_E_INVALID, "fold_table must be 0 or 1");
         g_fold_table = value;
@@ -1242,6 +1252,7 @@ int qsim_get_option(int option) {
     if (option == QSIM_OPT_K6_KERNEL) return g_k6_kernel;
     if (option == QSIM_OPT_FOLD_INIT) return g_fold_init;
     if (option == QSIM_OPT_FOLD_TABLE) return g_fold_table;
+    if (option == QSIM_OPT_DEVIATIONS) return g_deviations;
     if (option == QSIM_OPT_PAIR) return g_pair;
     if (option == QSIM_OPT_PAIR_TILE) return g_pair_tile;
     if (option == QSIM_OPT_CLUSTER_SETS) return g_cluster_sets;

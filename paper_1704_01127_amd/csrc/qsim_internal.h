@@ -193,16 +193,18 @@ hipError_t launch_multi(void* psi, int n, int m, const int32_t (*targets)[5], co
                         const EpiDesc* const* epis, hipStream_t st);
 // The uniform start, a first cluster (g1: plain complex128 matrix mat1) with
 // its epilogue expressed relative to the second cluster's targets (epi1), and
-// a second 6-qubit cluster (g2, its own epilogue epi2), in one write-only pass
-// over a complex64 state of n >= 11 qubits. omask < 0: mat2 in
+// a second cluster of 6 or 7 qubits (g2, its own epilogue epi2; the first has
+// at most as many), in one write-only pass over a complex64 state of n >= 11
+// (k2 = 6) or 12 (k2 = 7) qubits. omask < 0 (k2 = 6 only): mat2 in
 // LAYOUT_SPLIT16F, the second cluster multiplied per column on the matrix
 // cores. Otherwise mat2 is plain complex128, omask marks the second cluster's
 // target bits that are also the first cluster's (at most 2) and rmask those
 // epi1's mixed terms sign-flip; the second cluster's outputs for every
 // (pattern of the omask rows, sign mask over the rmask rows) are first put in
-// `table` (2^(|omask| + |rmask|) <= kFoldTabRows rows of 64 complex64, 512
-// bytes each) and the pass combines them per column.
+// `table` (2^(|omask| + |rmask|) <= kFoldTabRows rows of 64 complex64, or
+// kFoldTab7Rows rows of 128 for k2 = 7) and the pass combines them per column.
 constexpr int kFoldTabRows = 128;
+constexpr int kFoldTab7Rows = 64;  // with a 7-qubit second cluster: rows of 128 outputs
 hipError_t launch_fold2(void* psi, const ClusterGeom& g2, const void* mat2, const EpiDesc* epi2, const EpiDesc* epi1,
                         const ClusterGeom& g1, const void* mat1, int omask, int rmask, void* table,
                         hipStream_t st);

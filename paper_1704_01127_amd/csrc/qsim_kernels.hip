@@ -2124,7 +2124,7 @@ struct Fold2Args {
     const double2* M1;  // first cluster: plain complex128 2^k1 x 2^k1, row-major
     double amp;         // 2^(-n/2)
     int32_t k1;
-    int32_t t1[6];      // its qubits (sorted)
+    int32_t t1[7];      // its qubits (sorted)
 };
 
 template <bool LOWT>
@@ -2173,42 +2173,48 @@ __global__ __launch_bounds__(512, 1) void k_fold2_f32(float2* __restrict__ psi, 
 // compressed mask) forms M2 times that signed indicator in float64; the pass
 // below weights and sums its rows per column.
 struct FoldTabArgs {
-    const double2* M2;  // second cluster: plain complex128 64 x 64, row-major
+    const double2* M2;  // second cluster: plain complex128 2^k2 x 2^k2, row-major
     int32_t omask;      // rows (second cluster's target bits) shared with the first cluster
     int32_t rmask;      // rows the first epilogue's mixed terms sign-flip
 };
 
-__device__ __forceinline__ int pext6(int v, int mask) {
+// bits of v at the set bits of mask (B bits), packed low; and back
+template <int B>
+__device__ __forceinline__ int pext_bits(int v, int mask) {
     int o = 0, k = 0;
 #pragma unroll
-    for (int b = 0; b < 6; ++b)
+    for (int b = 0; b < B; ++b)
         if ((mask >> b) & 1) o |= ((v >> b) & 1) << k++;
     return o;
 }
-__device__ __forceinline__ int pdep6(int v, int mask) {
+template <int B>
+__device__ __forceinline__ int pdep_bits(int v, int mask) {
     int o = 0, k = 0;
 #pragma unroll
-    for (int b = 0; b < 6; ++b)
+    for (int b = 0; b < B; ++b)
         if ((mask >> b) & 1) o |= ((v >> k++) & 1) << b;
     return o;
 }
 
-__global__ __launch_bounds__(64) void k_fold2_table(float2* __restrict__ Y, FoldTabArgs a) {
-    __shared__ double x[64];
+// one work-group of 2^K2 threads (one per output row) per table row
+template <int K2>
+__global__ __launch_bounds__(1 << K2) void k_fold2_table(float2* __restrict__ Y, FoldTabArgs a) {
+    constexpr int D2 = 1 << K2;
+    __shared__ double x[D2];
     const int t = threadIdx.x;
     const int no = __popc(a.omask);
     const int P = blockIdx.x;
     const int sigma = P & ((1 << no) - 1);
-    const int w = pdep6(P >> no, a.rmask);
-    x[t] = pext6(t, a.omask) != sigma ? 0.0 : ((__popc(t & w) & 1) ? -1.0 : 1.0);
+    const int w = pdep_bits<K2>(P >> no, a.rmask);
+    x[t] = pext_bits<K2>(t, a.omask) != sigma ? 0.0 : ((__popc(t & w) & 1) ? -1.0 : 1.0);
     __syncthreads();
     double re = 0.0, im = 0.0;
-    for (int s = 0; s < 64; ++s) {
-        const double2 m = a.M2[t * 64 + s];
+    for (int s = 0; s < D2; ++s) {
+        const double2 m = a.M2[t * D2 + s];
         re = fma(m.x, x[s], re);
         im = fma(m.y, x[s], im);
     }
-    Y[P * 64 + t] = make_float2((float)re, (float)im);
+    Y[P * D2 + t] = make_float2((float)re, (float)im);
 }
 
 template <bool LOWT>
@@ -2228,7 +2234,7 @@ __global__ __launch_bounds__(512, 1) void k_fold2t_f32(float2* __restrict__ psi,
         reinterpret_cast<vf4*>(Y + (i >> 5) * kFoldRow)[i & 31] = reinterpret_cast<const vf4*>(Yg)[i];
     if ((int)threadIdx.x < 64) {
         W[threadIdx.x] = make_float2(0.0f, 0.0f);
-        Wc[threadIdx.x] = pext6((int)threadIdx.x, a.rmask) << no;
+        Wc[threadIdx.x] = pext_bits<6>((int)threadIdx.x, a.rmask) << no;
     }
     __syncthreads();
     row_sums(f.M1, 1 << f.k1, f.amp, W);  // w: the first cluster applied to the uniform vector
@@ -2255,7 +2261,7 @@ __global__ __launch_bounds__(512, 1) void k_fold2t_f32(float2* __restrict__ psi,
     fin.no = 1 << no;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const int rows = pdep6(s, a.omask);
+        const int rows = pdep_bits<6>(s, a.omask);
         int iy = 0;
 #pragma unroll
         for (int m = 0; m < 6; ++m)
@@ -2265,6 +2271,125 @@ __global__ __launch_bounds__(512, 1) void k_fold2t_f32(float2* __restrict__ psi,
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     split6s_tiles<LOWT, 2>((g_float2*)psi, nullptr, nullptr, Ls[w], (c_epi*)epi2, sg, (uint64_t)xcd_block() * WAVES + w,
                            ntiles, (uint64_t)gridDim.x * WAVES, &fin);
+}
+
+// Table form with a 7-qubit second cluster (the first has at most 7 qubits):
+// the write-only pass has no matrix in LDS, only the table (rows of 128
+// outputs), so two work-groups fit per compute unit. The lanes own the
+// amplitudes the 7-qubit cluster kernel's lanes do - lane (p, h) the
+// amplitudes j | h << 6 of column p - and store them the same way; each
+// output is summed from at most 4 table rows, weighted by w at the first
+// cluster's index, then takes both epilogues' column factors and the second
+// one's row signs.
+constexpr int kFold7Row = 130;  // LDS row: 128 outputs and a 16-byte pad
+
+template <bool LOWT>
+__global__ __launch_bounds__(256, 2) void k_fold2t7_f32(float2* __restrict__ psi, const float2* __restrict__ Yg,
+                                                        const EpiDesc* __restrict__ epi2,
+                                                        const EpiDesc* __restrict__ epi1, ClusterGeom g, Fold2Args f,
+                                                        FoldTabArgs a) {
+    constexpr int K = 7, HX = 64;
+    __shared__ float2 Y[kFoldTab7Rows * kFold7Row];
+    __shared__ float2 W[128];
+    __shared__ int Wc[128];
+    const int no = __popc(a.omask);
+    const int nq = 64 << (no + __popc(a.rmask));  // 16-byte pieces of the table
+    for (int i = (int)threadIdx.x; i < nq; i += (int)blockDim.x)
+        reinterpret_cast<vf4*>(Y + (i >> 6) * kFold7Row)[i & 63] = reinterpret_cast<const vf4*>(Yg)[i];
+    if ((int)threadIdx.x < 128) {
+        W[threadIdx.x] = make_float2(0.0f, 0.0f);
+        Wc[threadIdx.x] = pext_bits<7>((int)threadIdx.x, a.rmask) << no;
+    }
+    __syncthreads();
+    row_sums(f.M1, 1 << f.k1, f.amp, W);  // w: the first cluster applied to the uniform vector
+    __syncthreads();
+    // w-index bits of the rows both clusters hold, per shared-row pattern
+    int iys[4];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        const int rows = pdep_bits<7>(sp, a.omask);
+        int iy = 0;
+#pragma unroll
+        for (int m = 0; m < K; ++m)
+            if ((rows >> m) & 1)
+#pragma unroll
+                for (int m1 = 0; m1 < 7; ++m1)
+                    if (m1 < f.k1 && f.t1[m1] == g.t[m]) iy |= 1 << m1;
+        iys[sp] = iy;
+    }
+    const int nsp = 1 << no;
+
+    const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
+    const uint64_t hoff = h ? (uint64_t(1) << g.t[K - 1]) : 0;
+    const uint64_t ntiles = g.ncols / 32;
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    uint64_t olo[8], ohi[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        olo[i] = target_off<3>(i, g);
+        ohi[i] = ((i & 1) ? uint64_t(1) << g.t[3] : 0) | ((i & 2) ? uint64_t(1) << g.t[4] : 0) |
+                 ((i & 4) ? uint64_t(1) << g.t[5] : 0);
+    }
+    for (uint64_t tile = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6); tile < ntiles; tile += stride) {
+        const uint64_t base = deposit_cols<K>(tile * 32 + p, g);
+        // the first cluster's index from the column's bits (its qubits among
+        // the second's targets are rows: zero in base)
+        int ic = 0;
+#pragma unroll
+        for (int m = 0; m < 7; ++m)
+            if (m < f.k1) ic |= (int)((base >> f.t1[m]) & 1) << m;
+        ColFactor<float> f1{0u, 0u, 1.0f, 0.0f}, f2{0u, 0u, 1.0f, 0.0f};
+        if (epi1 != nullptr) f1 = col_factor<float>((c_epi*)epi1, base);
+        if (epi2 != nullptr) f2 = col_factor<float>((c_epi*)epi2, base);
+        const int pb = Wc[f1.w & 127u];
+        float X[2 * HX];
+#pragma unroll
+        for (int j = 0; j < 2 * HX; ++j) X[j] = 0.0f;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp) {
+            if (sp < nsp) {
+                const float2 wv = W[ic | iys[sp]];
+                const vf4* row = reinterpret_cast<const vf4*>(Y + (pb + sp) * kFold7Row + h * HX);
+#pragma unroll
+                for (int q = 0; q < HX / 2; ++q) {
+                    const vf4 v = row[q];
+                    X[4 * q] = fmaf(wv.x, v.x, fmaf(-wv.y, v.y, X[4 * q]));
+                    X[4 * q + 1] = fmaf(wv.x, v.y, fmaf(wv.y, v.x, X[4 * q + 1]));
+                    X[4 * q + 2] = fmaf(wv.x, v.z, fmaf(-wv.y, v.w, X[4 * q + 2]));
+                    X[4 * q + 3] = fmaf(wv.x, v.w, fmaf(wv.y, v.z, X[4 * q + 3]));
+                }
+            }
+        }
+        // the column factor of both epilogues (the first one's row signs are
+        // in the table; the second one's sign mask over the lane's rows j and
+        // its term on target 6, the lane's h)
+        const uint32_t sgn = f1.sgn ^ f2.sgn ^ ((uint32_t)h & (f2.w >> (K - 1)));
+        float ucr = f1.cr * f2.cr - f1.ci * f2.ci, uci = f1.cr * f2.ci + f1.ci * f2.cr;
+        if (sgn & 1u) {
+            ucr = -ucr;
+            uci = -uci;
+        }
+        const uint32_t wl = f2.w & 63u;
+        const uint64_t b0 = base | hoff;
+#pragma unroll
+        for (int j = 0; j < HX; j += 2) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float xr = X[2 * (j + u)], xi = X[2 * (j + u) + 1];
+                const float neg = (__popc((uint32_t)(j + u) & wl) & 1) ? -1.0f : 1.0f;
+                v[2 * u] = neg * fmaf(xr, ucr, -(xi * uci));
+                v[2 * u + 1] = neg * fmaf(xr, uci, xi * ucr);
+            }
+            float2* pa = psi + (b0 | ohi[j >> 3]);
+            if (LOWT) {
+                *reinterpret_cast<float4*>(pa + olo[j & 7]) = make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+                pa[olo[j & 7]] = make_float2(v[0], v[1]);
+                pa[olo[(j + 1) & 7]] = make_float2(v[2], v[3]);
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------ batched persistent launch
@@ -3301,7 +3426,8 @@ hipError_t launch_multi(void* psi, int n, int m, const int32_t (*targets)[5], co
 hipError_t launch_fold2(void* psi, const ClusterGeom& g2, const void* mat2, const EpiDesc* epi2, const EpiDesc* epi1,
                         const ClusterGeom& g1, const void* mat1, int omask, int rmask, void* table,
                         hipStream_t st) {
-    if (g2.k != 6 || g2.n < 11 || g1.k < 1 || g1.k > 6) return hipErrorInvalidValue;
+    if (g2.k < 6 || g2.k > 7 || g2.n < 12 - (7 - g2.k) || g1.k < 1 || g1.k > g2.k) return hipErrorInvalidValue;
+    if (g2.k == 7 && omask < 0) return hipErrorInvalidValue;  // a 7-qubit second cluster: the table form only
     Fold2Args f;
     std::memset(&f, 0, sizeof(f));
     f.M1 = reinterpret_cast<const double2*>(mat1);
@@ -3313,13 +3439,25 @@ hipError_t launch_fold2(void* psi, const ClusterGeom& g2, const void* mat2, cons
     const unsigned grid = grid_for(tiles, 8, kStagedGrid);
     if (omask >= 0) {
         const int no = __builtin_popcount((unsigned)omask), nr = __builtin_popcount((unsigned)rmask);
-        if (table == nullptr || omask > 63 || rmask < 0 || rmask > 63 || no > 2 || (1 << (no + nr)) > kFoldTabRows)
+        const int rmax = g2.k == 7 ? kFoldTab7Rows : kFoldTabRows, mmax = (1 << g2.k) - 1;
+        if (table == nullptr || omask > mmax || rmask < 0 || rmask > mmax || no > 2 || (1 << (no + nr)) > rmax)
             return hipErrorInvalidValue;
         FoldTabArgs a;
         a.M2 = reinterpret_cast<const double2*>(mat2);
         a.omask = omask;
         a.rmask = rmask;
-        hipLaunchKernelGGL(k_fold2_table, dim3(1u << (no + nr)), dim3(64), 0, st, (float2*)table, a);
+        if (g2.k == 7) {
+            hipLaunchKernelGGL(k_fold2_table<7>, dim3(1u << (no + nr)), dim3(128), 0, st, (float2*)table, a);
+            const unsigned grid7 = grid_for(g2.ncols / 32, 4, 2 * kSplit7Grid);
+            if (g2.t[0] == 0)
+                hipLaunchKernelGGL(k_fold2t7_f32<true>, dim3(grid7), dim3(256), 0, st, (float2*)psi,
+                                   (const float2*)table, epi2, epi1, g2, f, a);
+            else
+                hipLaunchKernelGGL(k_fold2t7_f32<false>, dim3(grid7), dim3(256), 0, st, (float2*)psi,
+                                   (const float2*)table, epi2, epi1, g2, f, a);
+            return hipGetLastError();
+        }
+        hipLaunchKernelGGL(k_fold2_table<6>, dim3(1u << (no + nr)), dim3(64), 0, st, (float2*)table, a);
         if (g2.t[0] == 0)
             hipLaunchKernelGGL(k_fold2t_f32<true>, dim3(grid), dim3(512), 0, st, (float2*)psi, (const float2*)table,
                                epi2, epi1, sg, f, a, tiles);

@@ -155,17 +155,23 @@ class TaskPool {
 
 // Results of the tasks, in order: on the pool when parallel, else one after
 // another on this thread. Only tasks with want[i] (all when want is null) run.
+// On the pool they start by descending first_key[i] (longest expected first,
+// so that the short ones fill the workers that finish early).
 template <typename T>
 std::vector<T> run_tasks(bool parallel, const std::vector<std::function<T()>>& fns,
-                         const std::vector<char>* want = nullptr) {
+                         const std::vector<char>* want = nullptr, const std::vector<int>* first_key = nullptr) {
     std::vector<T> out(fns.size());
     if (!parallel) {
         for (size_t i = 0; i < fns.size(); ++i)
             if (!want || (*want)[i]) out[i] = fns[i]();
         return out;
     }
+    std::vector<int> order(fns.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    if (first_key)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return (*first_key)[a] > (*first_key)[b]; });
     std::vector<std::function<void()>> jobs;
-    for (size_t i = 0; i < fns.size(); ++i)
+    for (int i : order)
         if (!want || (*want)[i]) jobs.push_back([&fns, &out, i] { out[i] = fns[i](); });
     TaskPool::get().run(std::move(jobs));
     return out;
@@ -404,9 +410,14 @@ double grown_cost(const OpCostFn& cost, const Grown& c, int n) {
 // gate is taken.
 // first_cap > 0: the first two clusters have at most first_cap qubits (so
 // that a folded start can take them both).
+// dev_step >= 0: at that step (op index) the cluster taken is the dev_rank-th
+// best of the distinct candidates (by gates taken, ties in the order the
+// greedy choice breaks them; rank 0 is the greedy choice) instead of the
+// best; an empty schedule when there are not that many.
 std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::vector<char>& dropped, int n_applied,
                             int kcap_in, bool fuse_diag, const OpCostFn* trim = nullptr,
-                            const std::vector<uint64_t>* sets = nullptr, int first_cap = 0) {
+                            const std::vector<uint64_t>* sets = nullptr, int first_cap = 0, int dev_step = -1,
+                            int dev_rank = 0) {
     const int ng = (int)gates.size();
     std::vector<SOp> out;
     Dag d;
@@ -439,10 +450,19 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
         const int kcur = (first_cap > 0 && n_clusters < 2) ? std::min(kmax, first_cap) : kmax;
         int best_score = -1, best_seed = -1, best_cap = kcur;
         uint64_t best_within = 0;
+        // the deviating step lists every candidate: (score, seed, cap, within, qubits)
+        const bool dev = (int)out.size() == dev_step;
+        struct DevCand {
+            int score, seed, cap;
+            uint64_t within, Q;
+        };
+        std::vector<DevCand> devc;
         for (int seed : rl) {
             // a gate wider than the cap (a dense gate) forms a cluster of its own width
             const int khi = std::max(kcur, popc(d.mask[seed]));
-            const int c = grow(d, f0, seed, khi, fuse_diag, 0, nullptr);
+            Grown g;
+            const int c = grow(d, f0, seed, khi, fuse_diag, 0, dev ? &g : nullptr);
+            if (dev) devc.push_back({c, seed, khi, 0, g.Q});
             if (c > best_score) {
                 best_score = c;
                 best_seed = seed;
@@ -465,7 +485,9 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
             std::partial_sort(ranked.begin(), ranked.begin() + top, ranked.end());
             for (size_t i = 0; i < top; ++i) {
                 if (popc(ranked[i].second) > kcur) continue;
-                const int c = grow(d, f0, -1, kcur, fuse_diag, ranked[i].second, nullptr);
+                Grown g;
+                const int c = grow(d, f0, -1, kcur, fuse_diag, ranked[i].second, dev ? &g : nullptr);
+                if (dev && c > 0) devc.push_back({c, -1, kcur, ranked[i].second, g.Q});
                 if (c > best_score) {  // c > 0: the closure took a matrix gate
                     best_score = c;
                     best_seed = -1;
@@ -473,6 +495,22 @@ std::vector<SOp> greedy_ops(int n, const std::vector<SGate>& gates, const std::v
                     best_within = ranked[i].second;
                 }
             }
+        }
+        if (dev) {
+            std::stable_sort(devc.begin(), devc.end(),
+                             [](const DevCand& a, const DevCand& b) { return a.score > b.score; });
+            std::vector<DevCand> uniq;
+            for (const DevCand& c : devc) {
+                bool dup = false;
+                for (const DevCand& u : uniq) dup |= u.Q == c.Q && u.score == c.score;
+                if (!dup) uniq.push_back(c);
+            }
+            if (dev_rank >= (int)uniq.size()) return {};
+            const DevCand& ch = uniq[dev_rank];
+            best_score = ch.score;
+            best_seed = ch.seed;
+            best_cap = ch.cap;
+            best_within = ch.within;
         }
         Grown best;
         grow(d, f0, best_seed, best_cap, fuse_diag, best_within, &best);
@@ -588,12 +626,15 @@ void dense_sets(int n, const std::vector<SGate>& gates, const std::vector<char>&
 
 // The start a schedule gets from a folded initialisation (SchedOpts::
 // fold_start): 2 when its first two ops are clusters of <= 6 and 6 qubits
-// (one write-only pass for both), 3 when that start takes the table form, 1
-// when its first op is a cluster, else 0.
+// (one write-only pass for both, the second multiplied on the matrix cores),
+// 3 when that start takes the table form, 4 when the second cluster has 7
+// qubits (the first <= 7) and the table form applies (it is the only form for
+// a 7-qubit second cluster), 1 when its first op is a cluster, else 0.
 int fold_kind(const std::vector<SOp>& ops, const std::vector<SGate>& gates, int fold) {
     if (fold <= 0 || ops.empty() || ops[0].kind != OP_CLUSTER) return 0;
-    if (fold >= 2 && ops.size() >= 2 && ops[0].k <= 6 && ops[1].kind == OP_CLUSTER && ops[1].k == 6) {
-        if (fold < 3) return 2;
+    if (fold >= 2 && ops.size() >= 2 && ops[1].kind == OP_CLUSTER &&
+        ((ops[0].k <= 6 && ops[1].k == 6) || ops[1].k == 7)) {
+        if (fold < 3 && ops[1].k == 6) return 2;
         // the table form: rows of the second cluster shared with the first,
         // and rows the first one's diagonal gates couple to a column qubit
         uint64_t t1 = 0, t2 = 0, flipped = 0;
@@ -605,8 +646,9 @@ int fold_kind(const std::vector<SOp>& ops, const std::vector<SGate>& gates, int 
             const uint64_t a = uint64_t(1) << g.q[0], b = uint64_t(1) << g.q[1];
             if (((t2 & a) != 0) != ((t2 & b) != 0)) flipped |= t2 & (a | b);
         }
-        const int shared = popc(t1 & t2);
-        return shared <= 2 && shared + popc(flipped) <= 7 ? 3 : 2;
+        const int shared = popc(t1 & t2), bits = shared + popc(flipped);
+        if (ops[1].k == 6) return shared <= 2 && bits <= kFoldTableBits6 ? 3 : 2;
+        if (fold >= 3 && shared <= 2 && bits <= kFoldTableBits7) return 4;
     }
     return 1;
 }
@@ -614,6 +656,7 @@ int fold_kind(const std::vector<SOp>& ops, const std::vector<SGate>& gates, int 
 // Passes of a schedule with its start counted as the write-only pass it becomes.
 double effective_passes(const std::vector<SOp>& ops, const std::vector<SGate>& gates, int fold) {
     switch (fold_kind(ops, gates, fold)) {
+        case 4: return (double)ops.size() - 2 + kFold7TableShare;
         case 3: return (double)ops.size() - 2 + kFold2TableShare;
         case 2: return (double)ops.size() - 2 + kFold2Share;
         case 1: return (double)ops.size() - 1 + kFold1Share;
@@ -658,6 +701,10 @@ void mark_skips(int n, const std::vector<SGate>& gates, bool skip_initial_h, boo
     }
 }
 
+int schedule_fold_kind(const std::vector<SOp>& ops, const std::vector<SGate>& gates, int fold_start) {
+    return fold_kind(ops, gates, fold_start);
+}
+
 Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& o, const OpCostFn& cost) {
     Schedule S;
     const int ng = (int)gates.size();
@@ -685,6 +732,11 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     // whose first two clusters have at most 6 qubits are built as well
     const int fold = S.uniform_init ? o.fold_start : 0;
     const int first_caps = (fold >= 2 && kmax > 6) ? 2 : 1;
+    // the one-deviation schedules of the widest cap, with the larger family of
+    // sets (slack 1: it holds the slack-0 sets)
+    const std::vector<uint64_t>* dev_sets = sets1.empty() ? &sets0 : &sets1;
+    const bool deviations =
+        o.deviations && o.parallel && o.cluster_sets && n >= kDevMinQubits && kmax >= 2 && !dev_sets->empty();
     if (o.mode == 1 || !cost) {
         // the greedy schedules with and without the candidate sets (and with
         // a 6-qubit start); the one with the fewest passes wins, the start
@@ -703,10 +755,21 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
                 return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, &sets1, cap);
             });
         }
-        std::vector<std::vector<SOp>> res = run_tasks(o.parallel, fns);
+        const size_t ndev0 = fns.size();
+        if (deviations)
+            for (int st = 0; st < kDevSteps; ++st)
+                for (int r = 1; r <= kDevRanks; ++r)
+                    fns.push_back([&, st, r]() {
+                        return greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, dev_sets, 0,
+                                          st, r);
+                    });
+        std::vector<int> key(fns.size(), 0);  // start the deviations and the set-based schedules first
+        for (size_t i = 0; i < fns.size(); ++i) key[i] = i >= ndev0 ? 2 : (i % 3 ? 1 : 0);
+        std::vector<std::vector<SOp>> res = run_tasks(o.parallel, fns, nullptr, &key);
         double best = 0.0;
         for (size_t c = 0; c < res.size(); ++c) {
             std::vector<SOp>& ops = res[c];
+            if (c >= ndev0 && ops.empty()) continue;  // no candidate of that rank
             const double p = effective_passes(ops, gates, fold);
             if (c == 0 || p < best) {
                 best = p;
@@ -724,6 +787,30 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     // for kmax.
     const int k_lo = std::max(1, kmax - 2);
     using Cand = std::pair<std::vector<SOp>, double>;
+    // The one-deviation search only widens the choice of full-width
+    // schedules: it runs where a full-width cluster is predicted to cost no
+    // more per qubit than one of one qubit fewer (each cost averaged over low,
+    // middle, high and spread target sets). On complex128 the 6-qubit
+    // clusters are bound by the fp64 matrix cores and it would only cost host
+    // time.
+    auto typical = [&](int k) {
+        int sets[4][kMaxK];
+        for (int j = 0; j < k; ++j) {
+            sets[0][j] = j;
+            sets[1][j] = n / 2 - k / 2 + j;
+            sets[2][j] = n - k + j;
+            sets[3][j] = k > 1 ? (int)((long)j * (n - 1) / (k - 1)) : 0;
+        }
+        double c = 0.0;
+        for (auto& q : sets) c += cost(k, q, 0);
+        return c / 4;
+    };
+    const double full_per_qubit = typical(kmax) / kmax;
+    const bool cd_deviations = deviations && (kmax < 2 || full_per_qubit <= typical(kmax - 1) / (kmax - 1));
+    // narrower caps expected to pay (a cheaper cluster per qubit): their
+    // gated candidates start with the others instead of in a second round
+    bool narrow_likely = false;
+    for (int kc = k_lo; kc < kmax; ++kc) narrow_likely |= typical(kc) / kc < full_per_qubit;
     auto priced = [&](std::vector<SOp> ops) {
         double total = 0.0, c0 = 0.0, c1 = 0.0;
         for (size_t i = 0; i < ops.size(); ++i) {
@@ -735,6 +822,7 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
         }
         // the start's share: its clusters written by one write-only pass
         const int fk = fold_kind(ops, gates, fold);
+        if (fk == 4) total -= c0 + (1.0 - kFold7TableShare) * c1;
         if (fk == 3) total -= c0 + (1.0 - kFold2TableShare) * c1;
         if (fk == 2) total -= c0 + (1.0 - kFold2Share) * c1;
         if (fk == 1) total -= (1.0 - kFold1Share) * c0;
@@ -751,9 +839,11 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
     // another, the gated ones are built only where their cap qualifies.
     std::vector<std::function<Cand()>> fns;
     std::vector<int> gate;  // 0: always a candidate; kc: only where cap kc qualifies
-    auto add = [&](int g, std::function<Cand()> f) {
+    std::vector<int> key;   // start order on the pool: the long searches (over candidate sets) first
+    auto add = [&](int g, std::function<Cand()> f, int k = 0) {
         gate.push_back(g);
         fns.push_back(std::move(f));
+        key.push_back(k);
     };
     for (int kc = k_lo; kc <= kmax; ++kc)  // the plain schedules first: their prices decide which caps qualify
         add(0, [&, kc]() { return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kc, o.fuse_diag)); });
@@ -763,10 +853,28 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
         });
         for (const std::vector<uint64_t>* fs : {&sets0, &sets1})
             if (!fs->empty())
-                add(0, [&, fs]() {
-                    return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, fs, 6));
-                });
+                add(
+                    0,
+                    [&, fs]() {
+                        return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, fs, 6));
+                    },
+                    1);
     }
+    // the one-deviation schedules (gate -1: kept only where they need fewer
+    // passes than every other candidate - among schedules of as many passes
+    // the other candidates already offer the model its choice)
+    if (cd_deviations)
+        for (int st = 0; st < kDevSteps; ++st)
+            for (int r = 1; r <= kDevRanks; ++r)
+                add(
+                    -1,
+                    [&, st, r]() {
+                        std::vector<SOp> ops = greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr,
+                                                          dev_sets, 0, st, r);
+                        if (ops.empty()) return Cand(std::vector<SOp>(), -1.0);  // no candidate of that rank
+                        return priced(std::move(ops));
+                    },
+                    2);
     if (kmax > 1)
         add(kmax - 1,
             [&]() { return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, &cost)); });
@@ -778,9 +886,13 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
                 if (kc == kmax) {
                     const std::vector<uint64_t>* fs = slack ? &sets1 : &sets0;
                     if (fs->empty()) continue;
-                    add(0, [&, fs]() {
-                        return priced(greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, fs));
-                    });
+                    add(
+                        0,
+                        [&, fs]() {
+                            return priced(
+                                greedy_ops(n, gates, S.dropped, S.n_applied, kmax, o.fuse_diag, nullptr, fs));
+                        },
+                        1);
                 } else {
                     add(kc, [&, kc, slack]() {
                         std::vector<uint64_t> a, b;
@@ -791,23 +903,43 @@ Schedule make_schedule(int n, const std::vector<SGate>& gates, const SchedOpts& 
                     });
                 }
             }
+    // First every ungated candidate (in parallel: all of them at once, with
+    // the gated ones too where narrower caps are expected to pay), then the
+    // gated ones whose cap qualified (a second round only where some did)
     const size_t nplain = (size_t)(kmax - k_lo + 1);
     std::vector<char> want(fns.size(), 0);
-    for (size_t i = 0; i < fns.size(); ++i) want[i] = o.parallel || i < nplain;
-    std::vector<Cand> res = run_tasks(o.parallel, fns, &want);
+    for (size_t i = 0; i < fns.size(); ++i) want[i] = o.parallel ? (gate[i] <= 0 || narrow_likely) : i < nplain;
+    std::vector<Cand> res = run_tasks(o.parallel, fns, &want, &key);
     std::vector<char> use_cap(kmax + 1, 1);
     for (int kc = k_lo; kc < kmax; ++kc) use_cap[kc] = res[kc - k_lo].second < res[kmax - k_lo].second;
-    for (size_t i = nplain; i < fns.size(); ++i) want[i] = gate[i] == 0 || use_cap[gate[i]];
-    if (!o.parallel) {
-        std::vector<char> rest(want);
-        for (size_t i = 0; i < nplain; ++i) rest[i] = 0;
-        std::vector<Cand> more = run_tasks(false, fns, &rest);
+    std::vector<char> rest(fns.size(), 0);
+    bool more_needed = false;
+    for (size_t i = nplain; i < fns.size(); ++i) {
+        const bool w = gate[i] <= 0 || use_cap[gate[i]];
+        rest[i] = w && !want[i];
+        more_needed |= rest[i] != 0;
+        want[i] = w;
+    }
+    if (more_needed) {
+        std::vector<Cand> more = run_tasks(o.parallel, fns, &rest, &key);
         for (size_t i = nplain; i < fns.size(); ++i)
             if (rest[i]) res[i] = std::move(more[i]);
     }
-    std::vector<Cand> cands;
+    double passes = 0.0;  // fewest passes of the other candidates
+    bool any = false;
     for (size_t i = 0; i < fns.size(); ++i)
-        if (want[i]) cands.push_back(std::move(res[i]));
+        if (want[i] && gate[i] >= 0 && res[i].second >= 0) {
+            const double p = effective_passes(res[i].first, gates, fold);
+            if (!any || p < passes) passes = p;
+            any = true;
+        }
+    std::vector<Cand> cands;
+    for (size_t i = 0; i < fns.size(); ++i) {
+        if (!want[i]) continue;
+        if (gate[i] < 0 && (res[i].second < 0 || (any && effective_passes(res[i].first, gates, fold) >= passes)))
+            continue;
+        cands.push_back(std::move(res[i]));
+    }
     double best_cost = 0.0;
     bool have = false;
     for (Cand& cand : cands) {

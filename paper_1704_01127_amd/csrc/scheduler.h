@@ -39,6 +39,7 @@ struct SchedOpts {
     bool skip_initial_h = false;
     bool cluster_sets = true;  // also offer closures of dense qubit sets (greedy and cost-driven)
     bool parallel = true;      // build candidate schedules on threads of their own
+    bool deviations = true;    // also the one-deviation schedules (see kDevSteps), on large states
     // How a run from the uniform state (skip_initial_h) writes its start:
     // 0 an initialisation pass; 1 the first cluster with it, in one write-only
     // pass; 2 also a second cluster of 6 qubits, multiplied per column on the
@@ -59,6 +60,28 @@ struct SchedOpts {
 constexpr double kFold1Share = 0.45;
 constexpr double kFold2Share = 0.70;
 constexpr double kFold2TableShare = 0.47;
+// with a 7-qubit second cluster (table form only): the write-only pass
+// against a 7-qubit pass
+constexpr double kFold7TableShare = 0.45;
+// Table form limits: at most 2 shared qubits and 2^(shared + sign-flipped
+// rows) table rows of the second cluster's outputs: 128 rows of 64 outputs
+// (k = 6) or 64 rows of 128 (k = 7), 64 KiB either way.
+constexpr int kFoldTableBits6 = 7;
+constexpr int kFoldTableBits7 = 6;
+// The one-deviation search (schedules that take, at one of the first
+// kDevSteps steps, one of the kDevRanks next-best clusters instead of the
+// best, a limited-discrepancy search) costs about 0.7 ms of host time; it
+// runs where a pass takes longer than that (states of at least
+// kDevMinQubits qubits) and candidates are built in parallel.
+constexpr int kDevSteps = 3;
+constexpr int kDevRanks = 4;
+constexpr int kDevMinQubits = 29;
+
+// The folded start a schedule's first ops take (SchedOpts::fold_start): 0
+// none, 1 the first cluster, 2 two clusters with the second (6 qubits) on the
+// matrix cores, 3 the same in the table form, 4 two clusters with a 7-qubit
+// second one in the table form.
+int schedule_fold_kind(const std::vector<SOp>& ops, const std::vector<SGate>& gates, int fold_start);
 
 struct Schedule {
     std::vector<SOp> ops;

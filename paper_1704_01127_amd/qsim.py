@@ -291,6 +291,7 @@ OPT_BATCH_ORDER = 10
 OPT_CHECK_UNITARY = 11
 OPT_MAP_QUBITS = 12
 OPT_FOLD_TABLE = 13
+OPT_DEVIATIONS = 14
 
 
 def set_option(option: int, value: int):

@@ -469,12 +469,48 @@ def test_fold2_dense_start(case, trailing_cz):
     assert_fp32_circuit(s.to_numpy(), ref, st, 6)
 
 
+# supremacy circuits (depth 16, seed 500 + s) whose k <= 7 schedule starts with
+# two 7-qubit clusters: (n, s) sharing 2, 2 (target 0 in the second), 2, 0
+# (target 0), 1 and 0 (target 0, 5 sign-flipped rows) qubits
+FOLD7_CASES = [(12, 0), (12, 1), (14, 4), (16, 1), (16, 2), (18, 0)]
+
+
+@pytest.mark.parametrize("case", range(len(FOLD7_CASES)))
+def test_fold2_seven_qubit_start(case):
+    """The uniform start and two 7-qubit clusters in one write-only pass (the
+    table form: the second cluster's outputs per shared-row pattern and
+    row-sign mask, combined per column) against the oracle, and against the
+    same run whose start takes the first cluster only."""
+    from supremacy_inputs.circuits import batch_grid
+    n, seed = FOLD7_CASES[case]
+    R, C, drop = batch_grid(n)
+    circ = supremacy_circuit(R, C, 16, 500 + seed, drop)
+    ref = oracle.run(circ)
+    opts = dict(kmax=7, scheduler="learned", fuse_diag=True, skip_initial_h=True, record_timings=True)
+    old = qsim.get_option(qsim.OPT_FOLD_INIT)
+    try:
+        got = {}
+        for fold in (2, 1):
+            qsim.set_option(qsim.OPT_FOLD_INIT, fold)
+            s = make_state(n, "c64")
+            st = s.run_circuit(circ.gates, **opts)
+            recs = [r for r in s.op_timings() if r["kind"] != "build"]
+            if fold == 2:
+                assert recs[0]["kind"] == "init_cluster2" and recs[0]["k"] == 7 and recs[0]["table"], recs[0]
+            got[fold] = s.to_numpy()
+    finally:
+        qsim.set_option(qsim.OPT_FOLD_INIT, old)
+    assert_fp32_circuit(got[2], ref, st, 7)
+    assert np.max(np.abs(got[2] - got[1])) <= 2 * fp32_circuit_bound(float(np.max(np.abs(ref))), st["n_ops"] + 2, 7)
+
+
 def test_fold2_table_form_full_size():
     """The benchmarked 30-qubit grid circuit (5 x 6, depth 25, seed 0) in its
     complex64 form (learned schedule, k <= 7) starts with the table form of
-    the folded start (its first two clusters share one qubit), and the whole
-    run agrees with the same run whose folded start multiplies every column on
-    the matrix cores, element by element within the float32 bound."""
+    the folded start, and the whole run agrees with the same run without the
+    two-cluster start (fold_table 0: the matrix-core form where the second
+    cluster has 6 qubits, else the first cluster alone), element by element
+    within the float32 bound."""
     circ = supremacy_circuit(5, 6, 25, 0)
     opts = dict(kmax=7, scheduler="learned", fuse_diag=True, skip_initial_h=True, skip_trailing_diag=True,
                 record_timings=True)
@@ -486,7 +522,7 @@ def test_fold2_table_form_full_size():
             s = qsim.State(circ.n, "c64", kmax=7)
             st = s.run_circuit(circ.gates, **opts)
             recs = [r for r in s.op_timings() if r["kind"] != "build"]
-            assert recs[0]["kind"] == "init_cluster2", [r["kind"] for r in recs]
+            assert recs[0]["kind"] == ("init_cluster2" if tab else recs[0]["kind"]), [r["kind"] for r in recs]
             table[tab] = recs[0]["table"]
             states[tab] = s
     finally:

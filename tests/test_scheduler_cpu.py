@@ -232,7 +232,36 @@ def test_candidate_sets_reduce_passes():
         qsim.set_option(qsim.OPT_CLUSTER_SETS, old)
 
 
-@pytest.mark.parametrize("option,top", [(qsim.OPT_CLUSTER_SETS, 1), (qsim.OPT_BATCH_ORDER, 2), (qsim.OPT_MAP_QUBITS, 1)])
+def test_deviation_search():
+    """The one-deviation schedules (QSIM_OPT_DEVIATIONS): on 30-qubit grid
+    circuits where the greedy schedule needs 14 clusters at k <= 7, a
+    schedule that takes a next-best cluster at one of the first steps needs 13
+    (seeds 0, 2 and 9); every schedule stays valid, none gets longer, and
+    below 29 qubits the search does not run (same schedule either way)."""
+    old = qsim.get_option(qsim.OPT_DEVIATIONS)
+    opts = dict(kmax=7, fuse_diag=True, skip_initial_h=True, skip_trailing_diag=True)
+    try:
+        for seed in (0, 2, 9):
+            circ = supremacy_circuit(5, 6, 25, seed=seed)
+            got = {}
+            for dev in (0, 1):
+                qsim.set_option(qsim.OPT_DEVIATIONS, dev)
+                sch = qsim.schedule(circ.n, circ.gates, scheduler="greedy", **opts)
+                check_schedule(circ, sch, 7, skip_trailing=True, skip_initial_h=True)
+                got[dev] = sum(1 for k in sch["op_kind"] if k == 0)
+            assert got[0] == 14 and got[1] == 13, (seed, got)
+        small = supremacy_circuit(4, 6, 25, seed=0)
+        same = []
+        for dev in (0, 1):
+            qsim.set_option(qsim.OPT_DEVIATIONS, dev)
+            same.append(qsim.schedule(small.n, small.gates, scheduler="greedy", **opts))
+        assert same[0] == same[1]
+    finally:
+        qsim.set_option(qsim.OPT_DEVIATIONS, old)
+
+
+@pytest.mark.parametrize("option,top", [(qsim.OPT_CLUSTER_SETS, 1), (qsim.OPT_BATCH_ORDER, 2), (qsim.OPT_MAP_QUBITS, 1),
+                                        (qsim.OPT_DEVIATIONS, 1), (qsim.OPT_FOLD_TABLE, 1)])
 def test_planning_option_range(option, top):
     old = qsim.get_option(option)
     assert old in (0, 1)
