@@ -733,6 +733,15 @@ __device__ __forceinline__ ColFactor<float> epi_combine(uint32_t tb, double tr, 
     return f;
 }
 
+// Swap a (in the odd 16-lane rows of the wave) with b (in the even rows):
+// afterwards lane l of an even row holds in b what lane l + 16 held in a, and
+// lane l + 16 holds in a what lane l held in b.
+__device__ __forceinline__ void lane_swap16(float& a, float& b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
 // ------------------------------------------------------------ cluster: float state, k = 7, fp16 matrix cores
 // A 7-qubit cluster doubles the matrix work per byte of state of a 6-qubit
 // one and still stays below the HBM time on the fp16 matrix cores, so it
@@ -764,6 +773,21 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
 
     const int lane = threadIdx.x & 63, p = lane & 31, h = lane >> 5;
     const uint64_t hoff = h ? (uint64_t(1) << g.t[K - 1]) : 0;
+    // Without a target on qubit 0 the tile's columns are neighbouring
+    // amplitudes. Lanes p and p + 16 (p < 16 within each half-wave) then hold
+    // columns 2 p and 2 p + 1: each accesses both columns of every other row
+    // (even rows in the lower lane, odd ones in the upper) as one 16 byte
+    // access, and one lane swap per 32-bit value (v_permlane16_swap, between
+    // the two 16-lane rows) gives each lane its own column after a load and
+    // the pair of columns before a store. Half the memory instructions of
+    // 8-byte accesses, for the same 256-byte runs: 2 % off the pass. Not in
+    // the STATS form, whose store phase is bound by its float64 sums (the
+    // swaps made it 3 % slower). With a target on qubit 0 the 16 byte
+    // accesses are two rows of the lane's own column.
+    constexpr bool PAIR = !LOWT && !STATS;
+    const int cpair = PAIR ? 2 * (p & 15) : p;                  // first column of the lane's accesses
+    const uint64_t cown = PAIR ? (uint64_t)((p >> 4) & 1) : 0;  // the lane's own column: cpair + cown
+    const uint64_t roff = cown ? (uint64_t(1) << g.t[0]) : 0;   // odd rows
     const uint64_t ntiles = g.ncols / 32;
     const uint64_t stride = (uint64_t)gridDim.x * 4;
     const bool has_epi = epi != nullptr;
@@ -788,12 +812,13 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
     // amplitudes 8 a .. 8 a + 7 of the lane for a in [A0, A1)
     // (the bits are disjoint, so the OR is a sum: one pointer per group a,
     // then the low offsets added to it)
+    // (b: the lane's access base, odd-row offset included)
     auto load = [&](uint64_t b, float (&X)[2 * HX], int a0, int a1) {
 #pragma unroll
         for (int a = 0; a < 8; ++a) {
             if (a < a0 || a >= a1) continue;
             const float2* pa = psi + (b | ohi[a]);
-            if (LOWT) {
+            if (LOWT || PAIR) {
 #pragma unroll
                 for (int i = 0; i < 8; i += 2) {
                     const float4 v = *reinterpret_cast<const float4*>(pa + olo[i]);
@@ -813,7 +838,14 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
     // real and imaginary parts of amplitudes 8 s + i, scaled, into fp16
     // halves; returns the factor that undoes the column and matrix scaling
     half8 rh[S], rl[S], ih[S], il[S];
-    auto split = [&](const float (&X)[2 * HX]) -> float {
+    auto split = [&](float (&X)[2 * HX]) -> float {
+        if constexpr (PAIR) {  // rows j, j + 1 of the lane's own column
+#pragma unroll
+            for (int j = 0; j < HX; j += 2) {
+                lane_swap16(X[2 * j], X[2 * j + 2]);
+                lane_swap16(X[2 * j + 1], X[2 * j + 3]);
+            }
+        }
         float mx = 0.0f;  // largest magnitude (|x| is a free operand modifier of the max)
 #pragma unroll
         for (int i = 0; i < 2 * HX; ++i) mx = fmaxf(mx, fabsf(X[i]));
@@ -877,11 +909,11 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
         }
     };
 
-    uint64_t base = deposit_cols<K>(tile * 32 + p, g);
+    uint64_t base = deposit_cols<K>(tile * 32 + cpair, g);
     float unscale;
     {
         float B[2 * HX];
-        load(base | hoff, B, 0, 8);
+        load(base | hoff | roff, B, 0, 8);
         __builtin_amdgcn_sched_barrier(0);
         __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_sched_barrier(0);
@@ -889,11 +921,11 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
     }
     do {
         const uint64_t nxt = tile + stride < last ? tile + stride : last;
-        const uint64_t basen = deposit_cols<K>(nxt * 32 + p, g);
+        const uint64_t basen = deposit_cols<K>(nxt * 32 + cpair, g);
         // the next tile's loads go out in two halves: the second once the
         // first four steps have freed their operand registers
         float Bn[2 * HX];
-        load(basen | hoff, Bn, 0, 4);
+        load(basen | hoff | roff, Bn, 0, 4);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -901,7 +933,7 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
             for (int i = 0; i < 16; ++i) ar[rb][i] = ai[rb][i] = 0.0f;
         mma(0, 4);
         __builtin_amdgcn_sched_barrier(0);
-        load(basen | hoff, Bn, 4, 8);
+        load(basen | hoff | roff, Bn, 4, 8);
         __builtin_amdgcn_sched_barrier(0);
         mma(4, 8);
         // Diagonal epilogue: the column's sign parity and phase are one complex
@@ -913,7 +945,7 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
         uint32_t mlo = 0, mhi = 0;  // bit j of mhi:mlo: amplitude j changes sign
         bool ph = false, sg = false;
         if (has_epi) {
-            const ColFactor<float> f = col_factor<float>(epi, base);
+            const ColFactor<float> f = col_factor<float>(epi, base | cown);
             if ((f.sgn ^ ((uint32_t)h & (f.w >> (K - 1)))) & 1u) ucr = -ucr;
             if (has_ph) {
                 uci = ucr * f.ci;
@@ -930,7 +962,7 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
             if ((f.w >> 5) & 1u) mhi = ~mhi;
             sg = epi->n_mix > 0;  // uniform: the descriptor has sign-mask terms
         }
-        const uint64_t b0 = base | hoff;
+        const uint64_t b0 = base | hoff | roff;
         auto store_all = [&](auto PH, auto SG) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
@@ -960,8 +992,12 @@ __global__ __launch_bounds__(256, 1) void k_cluster_f32_split7(float2* __restric
                         stats_acc_f(sv, v[0], v[1]);
                         stats_acc_f(sv, v[2], v[3]);
                     }
+                    if constexpr (PAIR) {  // row j of both columns (lower lane), row j + 1 (upper)
+                        lane_swap16(v[0], v[2]);
+                        lane_swap16(v[1], v[3]);
+                    }
                     float2* pa = psi + (b0 | ohi[j >> 3]);
-                    if (LOWT) {
+                    if (LOWT || PAIR) {
                         *reinterpret_cast<float4*>(pa + olo[j & 7]) = make_float4(v[0], v[1], v[2], v[3]);
                     } else {
                         pa[olo[j & 7]] = make_float2(v[0], v[1]);
