@@ -316,9 +316,10 @@ qsim_status qsim_op_timings(qsim_state s, int32_t* op_kind, int32_t* op_k, int32
  * build their candidate schedules in parallel (qsim_run_circuit,
  * qsim_schedule) also build the schedules that differ from the greedy choice
  * at one of the first 3 steps, taking one of the 4 next-best clusters there
- * (with the larger family of dense qubit sets), and keep them if they need
- * fewer passes or are predicted faster (a limited-discrepancy search, about
- * 0.7 ms of host time); 0 skips them. Read when a schedule is built.
+ * (with the larger family of dense qubit sets), and keep one only if it
+ * needs fewer passes than every other candidate (a limited-discrepancy
+ * search, about 0.3 ms of host time); 0 skips them. Read when a schedule is
+ * built.
  * QSIM_OPT_BATCH_ORDER: the order in which a batch's work items are handed
  * out, read when a batch is planned: 0 (default) level order (the j-th op
  * of every circuit before any (j+1)-th), 1 critical path first (a list
