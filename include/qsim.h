@@ -123,7 +123,9 @@ typedef struct {
     int32_t schedule_dtype;     /* qsim_dtype the cost models assume in qsim_schedule
                                    (qsim_run_circuit uses the state's); 0 = C64 */
     int32_t fused_stats;        /* when the run's last op is a cluster on a complex64 state applied
-                                   by a direct matrix-core kernel (k = 4..7), that kernel also sums
+                                   by a direct matrix-core kernel (k = 4..7) or, for k = 2, 3 on a
+                                   state of at least k + 6 qubits, by the staged vector-ALU kernel,
+                                   that kernel also sums
                                    the float64 norm, sum of p^2 and entropy of the amplitudes it
                                    stores, and the next qsim_probs with dev_out = NULL returns them
                                    without reading the state again. Any library call that changes

@@ -219,16 +219,17 @@ int cluster_layout(bool dbl, int k, int n);
 // variant (matrix-core layouts, k <= 5): 0 = direct register gather, 1 = LDS-staged.
 // stats_part: also sum p, p^2 and -p ln p of the stored amplitudes into
 // stats_part (per work-group, 8 doubles each; *stats_blocks receives their
-// number); only the direct float matrix-core kernels (k = 4..6) do this,
-// other cases return hipErrorInvalidValue.
+// number); the direct float matrix-core kernels (k = 4..7) and the staged
+// vector-ALU kernel (float, k = 2, 3) do this, other cases return
+// hipErrorInvalidValue.
 hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void* mat, int layout,
                           const EpiDesc* epi, int variant, hipStream_t st, double* stats_part = nullptr,
                           unsigned* stats_blocks = nullptr);
 // Can a cluster launch also produce the sums (see launch_cluster)?
-inline bool cluster_stats_supported(bool dbl, int k, int layout, int variant) {
+inline bool cluster_stats_supported(bool dbl, int n, int k, int layout, int variant) {
     return !dbl && variant == 0 &&
            ((layout == LAYOUT_SPLIT7 && k == 7) || (layout == LAYOUT_SPLIT16F && k == 6) ||
-            (layout == LAYOUT_MFMA32F && k >= 4));
+            (layout == LAYOUT_MFMA32F && k >= 4) || (layout == LAYOUT_PLAIN && (k == 2 || k == 3) && n - k >= 6));
 }
 // Kernel variant of the matrix-core cluster path: 0 = direct register
 // gather, 1 = LDS-staged linear loads. Chosen per (dtype, k, low_class) from a

@@ -2675,12 +2675,15 @@ __global__ __launch_bounds__(256) void k_cluster_valu(typename Cplx<T>::type* __
 // 64 columns: the k targets and the 6 lowest non-target bits, whose lowest 6
 // positions are always state bits 0..5. Chunk x of the tile (tau = 64 x +
 // lane) is one contiguous run of 64 amplitudes; LDS hands each thread its
-// column, then takes the results back for contiguous stores.
-template <typename T, int K>
+// column, then takes the results back for contiguous stores. STATS (float
+// only): also sum p, p^2 and -p ln p of the stored amplitudes into part (per
+// work-group), as the matrix-core kernels' STATS forms do.
+template <typename T, int K, bool STATS = false>
 __global__ __launch_bounds__(256) void k_cluster_valu_staged(typename Cplx<T>::type* __restrict__ psi,
                                                              const typename Cplx<T>::type* __restrict__ M,
                                                              const EpiDesc* __restrict__ epi, StageGeom sg,
-                                                             uint64_t tiles) {
+                                                             uint64_t tiles, double* __restrict__ part) {
+    static_assert(!STATS || std::is_same<T, float>::value, "sums of float states only");
     using V = typename Cplx<T>::type;
     constexpr int D = 1 << K, RS = D + 1;  // LDS row of a column, padded
     __shared__ V Ms[D * D];
@@ -2715,6 +2718,7 @@ __global__ __launch_bounds__(256) void k_cluster_valu_staged(typename Cplx<T>::t
         if ((lane >> b) & 1) coff |= uint64_t(1) << sg.tb[sg.cpos[b]];
     const bool has_epi = epi != nullptr;
     const bool has_ph = has_epi && epi->n_ph > 0;
+    double sv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (uint64_t tile = (uint64_t)xcd_block() * 4 + (threadIdx.x >> 6); tile < tiles;
          tile += (uint64_t)gridDim.x * 4) {
         const uint64_t tb0 = tile_base<K + 6>(tile, sg);
@@ -2738,6 +2742,7 @@ __global__ __launch_bounds__(256) void k_cluster_valu_staged(typename Cplx<T>::t
                 ai += m.x * v[x].y + m.y * v[x].x;
             }
             if (has_epi) apply_factor(ar, ai, f, (uint32_t)y, has_ph);
+            if constexpr (STATS) stats_acc_f(sv, ar, ai);
             V o;
             o.x = ar;
             o.y = ai;
@@ -2748,6 +2753,7 @@ __global__ __launch_bounds__(256) void k_cluster_valu_staged(typename Cplx<T>::t
         for (int x = 0; x < D; ++x) psi[tb0 | sg.ioff[x] | (uint64_t)lane] = L[(cl | cx[x]) * RS + (yl | yx[x])];
         wave_lds_fence();  // the next tile's writes come after these reads
     }
+    if constexpr (STATS) block_reduce_store(sv, 3, 0u, part + blockIdx.x * 8);  // every thread gets here
 }
 
 // ------------------------------------------------------------ diagonal pass
@@ -3612,22 +3618,31 @@ int cluster_layout(bool dbl, int k, int n) {
 namespace {
 template <int K>
 hipError_t launch_valu_k(void* psi, bool dbl, const ClusterGeom& g, const void* mat, const EpiDesc* epi,
-                         hipStream_t st) {
+                         hipStream_t st, double* stats_part = nullptr, unsigned* stats_blocks = nullptr) {
     if (K >= 2 && K <= 3 && g.n - K >= 6) {
         constexpr int KS = K >= 2 && K <= 3 ? K : 2;
         const StageGeom sg = make_stage_geom(g, 6, 6);  // tile: the targets and 6 column bits
         for (int i = 0; i < 6; ++i)
             if (sg.tb[i] != i) return hipErrorInvalidValue;  // cannot happen: bits 0..5 are tile bits
         const uint64_t tiles = g.ncols >> 6;
+        if (stats_part) {  // float (checked by the caller); the partials area holds kReduceBlocks work-groups
+            if (dbl) return hipErrorInvalidValue;
+            const unsigned grid = grid_for(tiles, 4, kReduceBlocks);
+            *stats_blocks = grid;
+            hipLaunchKernelGGL((k_cluster_valu_staged<float, KS, true>), dim3(grid), dim3(256), 0, st,
+                               (float2*)psi, (const float2*)mat, epi, sg, tiles, stats_part);
+            return hipGetLastError();
+        }
         const unsigned grid = grid_for(tiles, 4, kStreamGrid);
         if (dbl)
             hipLaunchKernelGGL((k_cluster_valu_staged<double, KS>), dim3(grid), dim3(256), 0, st, (double2*)psi,
-                               (const double2*)mat, epi, sg, tiles);
+                               (const double2*)mat, epi, sg, tiles, nullptr);
         else
             hipLaunchKernelGGL((k_cluster_valu_staged<float, KS>), dim3(grid), dim3(256), 0, st, (float2*)psi,
-                               (const float2*)mat, epi, sg, tiles);
+                               (const float2*)mat, epi, sg, tiles, nullptr);
         return hipGetLastError();
     }
+    if (stats_part) return hipErrorInvalidValue;  // no sums in the plain form
     const unsigned grid = grid_for(g.ncols, 256, kStreamGrid);
     if (dbl)
         hipLaunchKernelGGL((k_cluster_valu<double, K>), dim3(grid), dim3(256), 0, st, (double2*)psi,
@@ -3704,13 +3719,13 @@ hipError_t launch_cluster(void* psi, bool dbl, const ClusterGeom& g, const void*
                           const EpiDesc* epi, int variant, hipStream_t st, double* stats_part,
                           unsigned* stats_blocks) {
     // the sums of the stored amplitudes come from the direct float matrix-core kernels only
-    if (stats_part && (!cluster_stats_supported(dbl, g.k, layout, variant) || !stats_blocks))
+    if (stats_part && (!cluster_stats_supported(dbl, g.n, g.k, layout, variant) || !stats_blocks))
         return hipErrorInvalidValue;
     if (layout == LAYOUT_PLAIN) {
         switch (g.k) {
             case 1: return launch_valu_k<1>(psi, dbl, g, mat, epi, st);
-            case 2: return launch_valu_k<2>(psi, dbl, g, mat, epi, st);
-            case 3: return launch_valu_k<3>(psi, dbl, g, mat, epi, st);
+            case 2: return launch_valu_k<2>(psi, dbl, g, mat, epi, st, stats_part, stats_blocks);
+            case 3: return launch_valu_k<3>(psi, dbl, g, mat, epi, st, stats_part, stats_blocks);
             case 4: return launch_valu_k<4>(psi, dbl, g, mat, epi, st);
             case 5: return launch_valu_k<5>(psi, dbl, g, mat, epi, st);
             case 6: return launch_valu_k<6>(psi, dbl, g, mat, epi, st);

@@ -1062,6 +1062,7 @@ FUSED_CASES = [
     (5, [9, 10, 11, 12, 13], 0), (5, [0, 4, 8, 12, 14], 0),          # direct k = 5
     (4, [3, 8, 11, 15], 0), (4, [0, 5, 9, 13], 0),                   # direct k = 4 (forced)
     (4, [3, 8, 11, 15], 1),                                          # staged: not fused, recomputed
+    (3, [3, 8, 11], 0), (3, [0, 5, 9], 0), (2, [4, 10], 0),          # staged vector-ALU kernel, k = 2, 3
 ]
 
 
@@ -1069,6 +1070,7 @@ FUSED_CASES = [
 @pytest.mark.parametrize("k,qs,variant", FUSED_CASES)
 def test_fused_stats(n, k, qs, variant):
     """A run whose last op is a cluster applied by a direct matrix-core kernel
+    (k = 4..6) or the staged vector-ALU kernel (k = 2, 3)
     with fused_stats: the norm, sum p^2 and entropy of the stored state come
     from that kernel and equal the separate reduction's. The probe: the state
     is then overwritten directly; the fused path still reports the run's sums
