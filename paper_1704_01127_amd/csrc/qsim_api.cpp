@@ -1067,10 +1067,11 @@ qsim_status qsim_run_circuit(qsim_state s, const qsim_gate* gates, int n_gates, 
         Chunk::Item& last = c.items.back();
         // the sums come from the direct kernels: a staged choice of the model
         // gives way, since the sums save a whole pass over the state
-        if (last.kind == 0 && last.variant == 1 && cluster_stats_supported(s->dbl, last.geom.n, last.geom.k, last.layout, 0))
+        const ClusterGeom& lg = last.geom;
+        if (last.kind == 0 && last.variant == 1 && cluster_stats_supported(s->dbl, lg.n, lg.k, last.layout, 0))
             last.variant = 0;
-        const int v = last.variant >= 0 ? last.variant : cluster_variant_for(s->dbl, last.geom, last.layout);
-        if (last.kind == 0 && cluster_stats_supported(s->dbl, last.geom.n, last.geom.k, last.layout, v)) last.stats = true;
+        const int v = last.variant >= 0 ? last.variant : cluster_variant_for(s->dbl, lg, last.layout);
+        if (last.kind == 0 && cluster_stats_supported(s->dbl, lg.n, lg.k, last.layout, v)) last.stats = true;
     }
     if (qsim_status r = flush(s, c)) return r;
     if (pm) {  // back to the caller's qubit order (sums of a fused_stats pass do not change)
