@@ -40,12 +40,14 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def kernel_name(rec, k6_kernel=2, pair_tile=11, dbl=False) -> str:
-    """Name (as rocprofv3 reports it) of the cluster kernel a launch used."""
+def kernel_name(rec, k6_kernel=2, pair_tile=11, dbl=False, n=None) -> str:
+    """Name (as rocprofv3 reports it) of the cluster kernel a launch used (n:
+    the state's qubits, which decide the vector-ALU kernel's form)."""
     k, lowt = rec["k"], rec["qubits"][0] == 0
+    staged_valu = n is not None and 2 <= k <= 3 and n - k >= 6 and not rec.get("mfma")
     if dbl:
         if not rec.get("mfma"):
-            return "k_cluster_valu<double, %d>" % k
+            return ("k_cluster_valu_staged<double, %d, false>" if staged_valu else "k_cluster_valu<double, %d>") % k
         if rec.get("staged"):
             return "k_cluster_f64_stage<%d, 5, %d>" % (k, 512 if k == 5 else 256)
         return "k_cluster_f64_mfma<%d, %d, %d>" % (k, 1 if k == 6 else 2, 512 if k == 6 else 256)
@@ -53,9 +55,11 @@ def kernel_name(rec, k6_kernel=2, pair_tile=11, dbl=False) -> str:
         q = set(rec["qubits"])
         ten = pair_tile == 10 and (0 in q or len(q) < 10)  # the 10-qubit tile holds qubit 0
         return "k_cluster_f32_pair10<12>" if ten else "k_cluster_f32_multi<2, 8>"
+    b = lambda x: "true" if x else "false"  # noqa: E731
+    if staged_valu:  # its second flag sums the reductions
+        return "k_cluster_valu_staged<float, %d, %s>" % (k, b(rec.get("stats")))
     if not rec.get("mfma"):
         return "k_cluster_valu<float, %d>" % k
-    b = lambda x: "true" if x else "false"  # noqa: E731
     if k == 7:  # the direct kernel only; its second flag sums the reductions
         return "k_cluster_f32_split7<%s, %s>" % (b(lowt), b(rec.get("stats")))
     if k == 6 and k6_kernel in (1, 2):
@@ -215,7 +219,7 @@ def cluster_roofline(recs, n, dbl, steps, k6_kernel, pair_tile):
     total_ms = sum(r["ms"] for r in recs)
     groups = {}
     for r in clusters:
-        groups.setdefault(kernel_name(r, k6_kernel, pair_tile, dbl), []).append(r["ms"])
+        groups.setdefault(kernel_name(r, k6_kernel, pair_tile, dbl, n), []).append(r["ms"])
     kname, times = max(groups.items(), key=lambda kv: sum(kv[1]))
     bytes_per_launch = 2 * 2 ** n * amp_bytes
     avg_ms = sum(times) / len(times)

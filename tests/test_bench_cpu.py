@@ -35,6 +35,11 @@ def test_kernel_names_of_launch_records():
     assert b.kernel_name(rec(5, [0, 9, 14, 16, 26], mfma=True)) == "k_cluster_f32_mfma<5, 2, true, false>"
     assert b.kernel_name(rec(5, [1, 9, 14, 16, 26], mfma=True, stats=True)) == "k_cluster_f32_mfma<5, 2, false, true>"
     assert b.kernel_name(rec(3, [2, 5, 9])) == "k_cluster_valu<float, 3>"
+    # with the state's size: 2- and 3-qubit clusters on >= k + 6 qubits take the staged form
+    assert b.kernel_name(rec(3, [2, 5, 9]), n=34) == "k_cluster_valu_staged<float, 3, false>"
+    assert b.kernel_name(rec(2, [2, 5], stats=True), n=34) == "k_cluster_valu_staged<float, 2, true>"
+    assert b.kernel_name(rec(3, [2, 5, 6]), n=8) == "k_cluster_valu<float, 3>"
+    assert b.kernel_name(rec(2, [2, 9]), dbl=True, n=30) == "k_cluster_valu_staged<double, 2, false>"
     assert b.kernel_name(rec(6, [1, 3, 9, 12, 20, 25], mfma=True), k6_kernel=1) == "k_cluster_f32_gauss6<false>"
     # 6-qubit clusters on the fp32 matrix cores (the real-split kernel, direct only)
     assert b.kernel_name(rec(6, [1, 3, 9, 12, 20, 25], mfma=True), k6_kernel=0) == \
